@@ -1,0 +1,164 @@
+/*
+ * dqz.h -- C ABI of libdqz, an error-bounded lossy compressor for fp32
+ * fields on AMD MI355X (gfx950), implementing the dual-quantization +
+ * Huffman method of cuSZ (Tian et al., PACT'20).
+ *
+ * Compression (Sec. 3.1-3.2 of the paper):
+ *   value-range-relative error bound (footnote in Sec. 3.2.2)
+ *   -> prequantization d° = round(d / 2eb) (Sec. 3.1.2, Algorithm 2)
+ *   -> 1-layer Lorenzo prediction inside zero-padded blocks of 32 (1D),
+ *      16x16 (2D) or 8x8x8 (3D) points (Sec. 3.1.1)
+ *   -> postquantization delta = d° - p° with a cap of +-radius; values
+ *      outside the cap are outliers stored verbatim (Algorithm 2)
+ *   -> histogram of quantization codes (Sec. 3.2.1)
+ *   -> Huffman code lengths + canonical codebook (Sec. 3.2.2-3.2.3)
+ *   -> encode + deflate into one bit-dense stream (Sec. 3.2.4).
+ * Decompression (Sec. 3.3): inflate, then reversed dual-quantization.
+ *
+ * Guarantee: every finite input element comes back within eb_abs,
+ * |x - x'| <= eb_abs evaluated in double precision; non-finite elements
+ * come back bit-exact.  Elements whose fp32 reconstruction would miss the
+ * bound are stored verbatim ("patches", the paper's rehearsal/watchdog idea
+ * of Algorithm 1 applied to the final fp32 value).
+ *
+ * Conventions for every entry point:
+ *   - Pointers named d_* are device pointers on the context's GPU; h_* are
+ *     host pointers.  The caller owns all of them; the library never frees
+ *     caller memory and never writes outside [ptr, ptr + capacity).
+ *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Work is
+ *     stream-ordered; dqz_compress blocks only to read back the archive
+ *     size and status (a few hundred bytes) at its end.
+ *   - Calls on one context must not overlap (the context owns the device
+ *     scratch); separate contexts are independent.
+ *   - Every function returns DQZ_OK (0) or a negative dqz_status; no C++
+ *     exception crosses this boundary.  On error, output buffers hold
+ *     unspecified bytes and the context stays usable.
+ *
+ * Archive layout (little-endian), fixed 128-byte header followed by
+ *   lengths   u8[2R]                          Huffman code length per code
+ *   chunks    u64[n_chunks]                   stream bit offset of each chunk
+ *   subchunks u16[n_sub]                      stream bits of each subchunk
+ *   exceptions {u32 key, u32 payload}[n_out + n_patch], ascending key,
+ *             key = 2*position + kind; kind 0: outlier, payload = delta
+ *             (int32); kind 1: patch, payload = raw fp32 bits of the input
+ *   stream    u32[ceil(total_bits / 32)]      codewords MSB-first; stream
+ *             bit i is bit (31 - i % 32) of word i / 32
+ * Positions are indices in the padded block-major order: blocks in
+ * row-major order of block coordinates, points row-major inside a full-size
+ * block (points outside the field are skipped by the stream).  A subchunk is
+ * `sub_size` consecutive positions, a chunk `chunk_subs` subchunks.  The
+ * lengths and chunk sections start 8-byte aligned (after padding), as does
+ * the exception section.
+ */
+#ifndef DQZ_H
+#define DQZ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dqz_status;
+
+#define DQZ_OK 0
+#define DQZ_EINVAL (-1)       /* bad argument: shape, eb, radius, sizes, null pointer */
+#define DQZ_ETOOSMALL (-2)    /* archive or field capacity too small */
+#define DQZ_ENOMEM (-3)       /* device or pinned host allocation failed */
+#define DQZ_ECORRUPT (-4)     /* archive fails validation */
+#define DQZ_EUNSUPPORTED (-5) /* valid request outside this build's limits */
+#define DQZ_EHIP (-6)         /* a HIP runtime call failed (message in dqz_ctx_last_error) */
+
+#define DQZ_EB_ABS 0     /* eb is the absolute bound */
+#define DQZ_EB_VALREL 1  /* eb is relative to (max - min) of the finite values */
+
+#define DQZ_HEADER_BYTES 128
+
+/* Field shape: ndim in {1,2,3}; dims[0..ndim-1] slowest -> fastest (C
+ * row-major); entries past ndim are ignored.  An extent of 0 is an empty
+ * field.  The padded position count (blocks * block volume) must stay below
+ * 2^31. */
+typedef struct {
+    uint32_t ndim;
+    uint32_t reserved;
+    uint64_t dims[3];
+} dqz_shape;
+
+/* Compression parameters.  Zero fields take the defaults noted. */
+typedef struct {
+    double eb;           /* error bound, finite and > 0 */
+    int32_t eb_mode;     /* DQZ_EB_ABS or DQZ_EB_VALREL */
+    uint32_t radius;     /* code cap R: power of two in [1, 4096]; 2R quantization bins (default 512) */
+    uint32_t sub_size;   /* positions per subchunk: power of two in [32, 1024] (default 128) */
+    uint32_t chunk_subs; /* subchunks per chunk: power of two in [1, 65536] (default 64) */
+} dqz_params;
+
+typedef struct dqz_ctx dqz_ctx;
+
+/* Create a context on HIP device `device`; device scratch is allocated on
+ * first use and kept (grown on demand) until dqz_ctx_destroy. */
+dqz_status dqz_ctx_create(int device, dqz_ctx **out);
+void dqz_ctx_destroy(dqz_ctx *ctx);
+
+/* Host-only: worst-case archive size for this shape and parameters (every
+ * element an outlier and a patch, longest codes) and the device scratch the
+ * context will hold for it.  Either output pointer may be NULL. */
+dqz_status dqz_compress_bound(const dqz_shape *shape, const dqz_params *params,
+                              uint64_t *archive_max, uint64_t *workspace_bytes);
+
+/* Compress the fp32 field at d_field (row-major, `shape`) into d_archive
+ * (capacity archive_cap bytes).  On success *archive_bytes holds the archive
+ * size; if h_header is non-NULL the 128-byte header is copied there too.  If
+ * the archive does not fit, returns DQZ_ETOOSMALL and *archive_bytes holds
+ * the size that would have been needed when it is known (0 otherwise). */
+dqz_status dqz_compress(dqz_ctx *ctx, const float *d_field, const dqz_shape *shape,
+                        const dqz_params *params, void *d_archive, uint64_t archive_cap,
+                        uint64_t *archive_bytes, void *h_header, void *stream);
+
+/* Host-only: parse and validate a 128-byte header.  Any output may be NULL.
+ * field_elems = product of the dims. */
+dqz_status dqz_archive_info(const void *h_header, uint64_t header_bytes, dqz_shape *shape,
+                            dqz_params *params, uint64_t *field_elems, uint64_t *archive_bytes);
+
+/* Decompress the archive at d_archive (archive_bytes long) into d_field
+ * (capacity field_cap_elems floats, row-major).  h_header may point to a
+ * host copy of the archive's 128-byte header (skips a device->host read);
+ * NULL reads it from d_archive.  Returns DQZ_ECORRUPT for an archive that
+ * fails validation (the field then holds unspecified values). */
+dqz_status dqz_decompress(dqz_ctx *ctx, const void *d_archive, uint64_t archive_bytes,
+                          const void *h_header, float *d_field, uint64_t field_cap_elems,
+                          void *stream);
+
+const char *dqz_status_str(dqz_status status);
+/* Text of the last error on this context ("" if none). */
+const char *dqz_ctx_last_error(const dqz_ctx *ctx);
+
+/* Per-stage timing.  While enabled, every dqz_compress / dqz_decompress on
+ * this context records HIP events on its stream between its kernels (a small
+ * per-call cost); dqz_stage_times then returns the elapsed microseconds of
+ * each stage of the most recent call of that kind:
+ *   compress   (which = 0): [0] init, [1] value range + eb (0 in absolute
+ *              mode), [2] dual-quantization + histogram + exceptions,
+ *              [3] codebook + header, [4] stream clear, [5] encode + deflate
+ *   decompress (which = 1): [0] decoding tables, [1] inflate + reconstruct
+ * `us` must hold DQZ_MAX_STAGES doubles; *n_stages receives the count. */
+#define DQZ_MAX_STAGES 8
+dqz_status dqz_ctx_set_timing(dqz_ctx *ctx, int enable);
+dqz_status dqz_stage_times(dqz_ctx *ctx, int which, double *us, int *n_stages);
+
+/* Stage dumps for parity testing: copy an intermediate buffer of the most
+ * recent dqz_compress on this context to host memory.
+ *   DQZ_DBG_CODES      u16 per padded position (0xFFFF outside the field)
+ *   DQZ_DBG_HISTOGRAM  u32[2R]
+ *   DQZ_DBG_CODEBOOK   u64[2R], (length << 56) | canonical code
+ * `bytes` must equal the buffer's size. */
+#define DQZ_DBG_CODES 1
+#define DQZ_DBG_HISTOGRAM 2
+#define DQZ_DBG_CODEBOOK 3
+dqz_status dqz_debug_copy(dqz_ctx *ctx, int what, void *h_dst, uint64_t bytes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DQZ_H */

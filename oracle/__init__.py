@@ -155,7 +155,7 @@ def canonical_codes(lengths) -> np.ndarray:
 
 
 def compress(x: np.ndarray, eb: float, mode: int = EB_VALREL, radius: int = 512,
-             sub_size: int = 256, chunk_subs: int = 64) -> np.ndarray:
+             sub_size: int = 128, chunk_subs: int = 64) -> np.ndarray:
     """Archive bytes (uint8) of ``x`` (float32, 1-3 dims)."""
     lib = _load()
     x = np.ascontiguousarray(x, dtype=np.float32)

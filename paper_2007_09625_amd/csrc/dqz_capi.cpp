@@ -1,0 +1,501 @@
+// dqz_capi.cpp -- the C ABI of libdqz: argument validation, geometry and
+// archive layout, device scratch, and the stream-ordered launch sequence.
+//
+// Compression:   init -> [range + eb (valrel)] -> quantize -> codebook ->
+//                zero stream + encode -> one small readback (status, size,
+//                header).
+// Decompression: decoding tables -> inflate + reconstruct -> status readback.
+#include "../../include/dqz.h"
+#include "dqz_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+using namespace dqz;
+
+struct dqz_ctx {
+    int device = 0;
+    int ncu = 256;
+    void *ws = nullptr;        // device scratch
+    size_t ws_bytes = 0;
+    Ctl *h_ctl = nullptr;      // pinned readback of the control block
+    std::string last_error;
+    // most recent compression, for the stage dumps
+    uint16_t *last_codes = nullptr;
+    uint32_t *last_hist = nullptr;
+    uint64_t *last_book = nullptr;
+    uint64_t last_padded = 0;
+    uint32_t last_nsym = 0;
+    // per-stage timing
+    bool timing = false;
+    hipEvent_t ev[2][DQZ_MAX_STAGES + 1] = {};
+    int n_ev[2] = {0, 0};
+    bool ev_ready[2] = {false, false};
+};
+
+namespace {
+
+constexpr uint32_t kDefaultRadius = 512;
+constexpr uint32_t kDefaultSub = 128;
+constexpr uint32_t kDefaultChunkSubs = 64;
+
+bool is_pow2(uint64_t v) { return v && !(v & (v - 1)); }
+uint64_t align_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
+uint32_t log2u(uint32_t v) {
+    uint32_t s = 0;
+    while ((1u << s) < v) s++;
+    return s;
+}
+
+dqz_status fail(dqz_ctx *ctx, dqz_status st, const std::string &msg) {
+    if (ctx) ctx->last_error = msg;
+    return st;
+}
+
+dqz_status hip_fail(dqz_ctx *ctx, hipError_t e, const char *what) {
+    return fail(ctx, DQZ_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(ctx, expr)                                   \
+    do {                                                     \
+        hipError_t e_ = (expr);                              \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
+    } while (0)
+
+struct Plan {
+    Geom g;
+    Layout L;
+    uint32_t tiles_q = 0, tiles_e = 0;
+};
+
+dqz_status make_geom(const dqz_shape *s, Geom &g, std::string &why) {
+    if (!s) { why = "shape is NULL"; return DQZ_EINVAL; }
+    if (s->ndim < 1 || s->ndim > 3) { why = "ndim must be 1, 2 or 3"; return DQZ_EINVAL; }
+    uint64_t n3[3] = {1, 1, 1};
+    for (uint32_t i = 0; i < s->ndim; i++) n3[3 - s->ndim + i] = s->dims[i];
+    for (int a = 0; a < 3; a++)
+        if (n3[a] >= (1ull << 31)) { why = "extent too large"; return DQZ_EUNSUPPORTED; }
+    const uint32_t b3[3][3] = {{1, 1, 32}, {1, 16, 16}, {8, 8, 8}};
+    uint64_t nblocks = 1, nelem = 1;
+    for (int a = 0; a < 3; a++) {
+        g.n[a] = (uint32_t)n3[a];
+        g.b[a] = b3[s->ndim - 1][a];
+        g.nb[a] = (uint32_t)((n3[a] + g.b[a] - 1) / g.b[a]);
+        nblocks *= g.nb[a];
+        nelem *= n3[a];
+    }
+    g.bvol = g.b[0] * g.b[1] * g.b[2];
+    g.ndim = s->ndim;
+    g.nelem = nelem;
+    const uint64_t padded = nblocks * g.bvol;
+    if (padded >= (1ull << 31)) { why = "field too large: padded positions must stay below 2^31"; return DQZ_EUNSUPPORTED; }
+    g.padded = (uint32_t)padded;
+    return DQZ_OK;
+}
+
+dqz_status make_layout(const Geom &g, uint32_t radius, uint32_t sub, uint32_t csubs, Layout &L, std::string &why) {
+    if (!is_pow2(radius) || radius > 4096) { why = "radius must be a power of two <= 4096"; return DQZ_EINVAL; }
+    if (radius > kMaxRadius) { why = "radius above 1024 is not supported by this build"; return DQZ_EUNSUPPORTED; }
+    if (!is_pow2(sub) || sub < 32 || sub > 1024) { why = "sub_size must be a power of two in [32, 1024]"; return DQZ_EINVAL; }
+    if (!is_pow2(csubs) || csubs > 65536) { why = "chunk_subs must be a power of two <= 65536"; return DQZ_EINVAL; }
+    L.radius = radius;
+    L.nsym = 2 * radius;
+    L.sub_size = sub;
+    L.sub_shift = log2u(sub);
+    L.chunk_subs = csubs;
+    const uint64_t n_sub = (g.padded + (uint64_t)sub - 1) / sub;
+    const uint64_t n_chunks = (n_sub + csubs - 1) / csubs;
+    L.n_sub = (uint32_t)n_sub;
+    L.n_chunks = (uint32_t)n_chunks;
+    L.off_len = kHeaderBytes;
+    L.off_chunk = align_up(L.off_len + L.nsym, 8);
+    L.off_sub = L.off_chunk + 8 * n_chunks;
+    L.off_exc = align_up(L.off_sub + 2 * n_sub, 8);
+    L.cap = 0;
+    L.pad = 0;
+    return DQZ_OK;
+}
+
+void fill_params(const dqz_params *p, uint32_t &radius, uint32_t &sub, uint32_t &csubs) {
+    radius = p->radius ? p->radius : kDefaultRadius;
+    sub = p->sub_size ? p->sub_size : kDefaultSub;
+    csubs = p->chunk_subs ? p->chunk_subs : kDefaultChunkSubs;
+}
+
+// device scratch layout
+struct WsLayout {
+    uint64_t ctl, hist, lbq, lbe, zero_end, book, codes, tab, total;
+};
+
+// control block and decoding tables at fixed offsets, then the compression
+// buffers (so a decompression never overwrites the last compression's stage
+// buffers kept for dqz_debug_copy)
+WsLayout ws_layout(const Plan &P, bool compress) {
+    WsLayout w;
+    w.ctl = 0;
+    w.tab = align_up(sizeof(Ctl), 256);
+    w.hist = align_up(w.tab + sizeof(DecodeTables), 256);
+    w.lbq = align_up(w.hist + 4ull * P.L.nsym, 256);
+    w.lbe = align_up(w.lbq + 8ull * P.tiles_q, 256);
+    w.zero_end = align_up(w.lbe + 8ull * P.tiles_e, 256);
+    w.book = w.zero_end;
+    w.codes = align_up(w.book + 8ull * P.L.nsym, 256);
+    w.total = compress ? align_up(w.codes + 2ull * P.g.padded, 256) : w.hist;
+    return w;
+}
+
+dqz_status ensure_ws(dqz_ctx *ctx, size_t bytes) {
+    if (ctx->ws_bytes >= bytes) return DQZ_OK;
+    if (ctx->ws) {
+        (void)hipFree(ctx->ws);
+        ctx->ws = nullptr;
+        ctx->ws_bytes = 0;
+    }
+    size_t want = bytes + bytes / 8;
+    hipError_t e = hipMalloc(&ctx->ws, want);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        ctx->ws = nullptr;
+        return fail(ctx, DQZ_ENOMEM, "device scratch allocation failed");
+    }
+    ctx->ws_bytes = want;
+    return DQZ_OK;
+}
+
+// stage marks: mark(ctx, which, i) records event i of call kind `which`
+void mark(dqz_ctx *ctx, int which, int i, hipStream_t s) {
+    if (!ctx->timing) return;
+    (void)hipEventRecord(ctx->ev[which][i], s);
+    ctx->n_ev[which] = i + 1;
+}
+
+dqz_status status_from_device(dqz_ctx *ctx, uint32_t st) {
+    if (st & ST_EINVAL) return fail(ctx, DQZ_EINVAL, "error bound out of range for this field");
+    if (st & ST_EUNSUPPORTED) return fail(ctx, DQZ_EUNSUPPORTED, "code length above 64 bits");
+    if (st & ST_ECORRUPT) return fail(ctx, DQZ_ECORRUPT, "archive failed validation");
+    if (st & ST_ETOOSMALL) return fail(ctx, DQZ_ETOOSMALL, "archive capacity too small");
+    return DQZ_OK;
+}
+
+uint32_t rd_u32(const uint8_t *p, int off) {
+    uint32_t v;
+    memcpy(&v, p + off, 4);
+    return v;
+}
+uint64_t rd_u64(const uint8_t *p, int off) {
+    uint64_t v;
+    memcpy(&v, p + off, 8);
+    return v;
+}
+
+// Parse and validate a header; fills the plan (with the archive-dependent
+// counts) when `P` is non-NULL.
+struct HeaderInfo {
+    dqz_shape shape;
+    dqz_params params;
+    uint64_t nelem, n_exc, total_bits, archive_bytes, off_str, n_words;
+    uint32_t max_len;
+    float h;
+};
+
+dqz_status parse_header(const uint8_t *hb, uint64_t n, HeaderInfo &hi, Plan *P, std::string &why) {
+    if (!hb || n < kHeaderBytes) { why = "header too short"; return DQZ_ECORRUPT; }
+    if (rd_u32(hb, 0) != kMagic || (hb[4] | (hb[5] << 8)) != (int)kVersion) { why = "bad magic or version"; return DQZ_ECORRUPT; }
+    const uint32_t ndim = hb[6], mode = hb[7];
+    if (ndim < 1 || ndim > 3 || mode > 1) { why = "bad ndim or eb mode"; return DQZ_ECORRUPT; }
+    memset(&hi, 0, sizeof(hi));
+    hi.shape.ndim = ndim;
+    const uint64_t n3[3] = {rd_u64(hb, 8), rd_u64(hb, 16), rd_u64(hb, 24)};
+    for (uint32_t a = 0; a < 3 - ndim; a++)
+        if (n3[a] != 1) { why = "bad dims"; return DQZ_ECORRUPT; }
+    for (uint32_t i = 0; i < ndim; i++) hi.shape.dims[i] = n3[3 - ndim + i];
+    Plan local;
+    Plan &pl = P ? *P : local;
+    std::string w2;
+    if (make_geom(&hi.shape, pl.g, w2) != DQZ_OK) { why = "bad dims: " + w2; return DQZ_ECORRUPT; }
+    for (int a = 0; a < 3; a++)
+        if (rd_u32(hb, 32 + 4 * a) != pl.g.b[a]) { why = "bad block dims"; return DQZ_ECORRUPT; }
+    const uint32_t radius = rd_u32(hb, 44), sub = rd_u32(hb, 104), csubs = rd_u32(hb, 108);
+    if (make_layout(pl.g, radius, sub, csubs, pl.L, w2) != DQZ_OK) { why = "bad parameters: " + w2; return DQZ_ECORRUPT; }
+    double ebp;
+    memcpy(&ebp, hb + 48, 8);
+    hi.params.eb = ebp;
+    hi.params.eb_mode = (int32_t)mode;
+    hi.params.radius = radius;
+    hi.params.sub_size = sub;
+    hi.params.chunk_subs = csubs;
+    hi.nelem = rd_u64(hb, 80);
+    if (hi.nelem != pl.g.nelem) { why = "element count mismatch"; return DQZ_ECORRUPT; }
+    const uint64_t n_out = rd_u32(hb, 88), n_patch = rd_u32(hb, 92);
+    if (n_out > hi.nelem || n_patch > hi.nelem) { why = "bad exception counts"; return DQZ_ECORRUPT; }
+    hi.n_exc = n_out + n_patch;
+    hi.total_bits = rd_u64(hb, 96);
+    if (hi.total_bits > 64ull * hi.nelem) { why = "bad stream length"; return DQZ_ECORRUPT; }
+    if (rd_u32(hb, 112) != pl.L.n_chunks) { why = "chunk count mismatch"; return DQZ_ECORRUPT; }
+    hi.max_len = hb[116];
+    if (hi.max_len > 63 || (hi.nelem > 0 && hi.max_len == 0)) { why = "bad max code length"; return DQZ_ECORRUPT; }
+    hi.n_words = (hi.total_bits + 31) / 32;
+    hi.off_str = pl.L.off_exc + 8 * hi.n_exc;
+    const uint64_t end = hi.off_str + 4 * hi.n_words;
+    hi.archive_bytes = rd_u64(hb, 120);
+    if (hi.archive_bytes != end) { why = "archive size mismatch"; return DQZ_ECORRUPT; }
+    uint32_t hbits = rd_u32(hb, 64);
+    memcpy(&hi.h, &hbits, 4);
+    if (!std::isfinite(hi.h) || !(hi.h > 0.0f)) { why = "bad quantization step"; return DQZ_ECORRUPT; }
+    return DQZ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *dqz_status_str(dqz_status s) {
+    switch (s) {
+        case DQZ_OK: return "ok";
+        case DQZ_EINVAL: return "invalid argument";
+        case DQZ_ETOOSMALL: return "buffer too small";
+        case DQZ_ENOMEM: return "out of memory";
+        case DQZ_ECORRUPT: return "corrupt archive";
+        case DQZ_EUNSUPPORTED: return "unsupported";
+        case DQZ_EHIP: return "HIP runtime error";
+        default: return "unknown status";
+    }
+}
+
+const char *dqz_ctx_last_error(const dqz_ctx *ctx) { return ctx ? ctx->last_error.c_str() : ""; }
+
+dqz_status dqz_ctx_create(int device, dqz_ctx **out) {
+    if (!out) return DQZ_EINVAL;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) {
+        (void)hipGetLastError();
+        return DQZ_EHIP;
+    }
+    if (device < 0 || device >= count) return DQZ_EINVAL;
+    dqz_ctx *ctx = new (std::nothrow) dqz_ctx;
+    if (!ctx) return DQZ_ENOMEM;
+    ctx->device = device;
+    if (hipSetDevice(device) != hipSuccess) { delete ctx; return DQZ_EHIP; }
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
+        ctx->ncu = ncu;
+    if (hipHostMalloc((void **)&ctx->h_ctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        delete ctx;
+        return DQZ_ENOMEM;
+    }
+    *out = ctx;
+    return DQZ_OK;
+}
+
+void dqz_ctx_destroy(dqz_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->ws) (void)hipFree(ctx->ws);
+    if (ctx->h_ctl) (void)hipHostFree(ctx->h_ctl);
+    for (int k = 0; k < 2; k++)
+        for (int i = 0; i <= DQZ_MAX_STAGES; i++)
+            if (ctx->ev[k][i]) (void)hipEventDestroy(ctx->ev[k][i]);
+    delete ctx;
+}
+
+dqz_status dqz_compress_bound(const dqz_shape *shape, const dqz_params *params, uint64_t *archive_max,
+                              uint64_t *workspace_bytes) {
+    if (!params) return DQZ_EINVAL;
+    Plan P;
+    std::string why;
+    dqz_status st = make_geom(shape, P.g, why);
+    if (st != DQZ_OK) return st;
+    uint32_t radius, sub, csubs;
+    fill_params(params, radius, sub, csubs);
+    if ((st = make_layout(P.g, radius, sub, csubs, P.L, why)) != DQZ_OK) return st;
+    P.tiles_q = quantize_tiles(P.g);
+    P.tiles_e = encode_tiles(P.g);
+    // every element an outlier and a patch (16 bytes) and a 64-bit code
+    if (archive_max) *archive_max = P.L.off_exc + 16ull * P.g.nelem + 8ull * P.g.nelem + 8;
+    if (workspace_bytes) *workspace_bytes = ws_layout(P, true).total;
+    return DQZ_OK;
+}
+
+dqz_status dqz_compress(dqz_ctx *ctx, const float *d_field, const dqz_shape *shape, const dqz_params *params,
+                        void *d_archive, uint64_t archive_cap, uint64_t *archive_bytes, void *h_header,
+                        void *stream) {
+    if (!ctx) return DQZ_EINVAL;
+    ctx->last_error.clear();
+    if (archive_bytes) *archive_bytes = 0;
+    if (!params || !d_archive || !archive_bytes) return fail(ctx, DQZ_EINVAL, "null argument");
+    if (!(params->eb > 0.0) || !std::isfinite(params->eb)) return fail(ctx, DQZ_EINVAL, "eb must be finite and > 0");
+    if (params->eb_mode != DQZ_EB_ABS && params->eb_mode != DQZ_EB_VALREL) return fail(ctx, DQZ_EINVAL, "bad eb_mode");
+    Plan P;
+    std::string why;
+    dqz_status st = make_geom(shape, P.g, why);
+    if (st != DQZ_OK) return fail(ctx, st, why);
+    if (P.g.nelem && !d_field) return fail(ctx, DQZ_EINVAL, "null field");
+    uint32_t radius, sub, csubs;
+    fill_params(params, radius, sub, csubs);
+    if ((st = make_layout(P.g, radius, sub, csubs, P.L, why)) != DQZ_OK) return fail(ctx, st, why);
+    if (params->eb_mode == DQZ_EB_ABS) {
+        const double e = params->eb;
+        const float h = (float)(2.0 * e), r = (float)(1.0 / (2.0 * e));
+        if (e < (double)FLT_MIN || !std::isfinite(h) || !(r >= FLT_MIN) || !std::isfinite(r))
+            return fail(ctx, DQZ_EINVAL, "eb out of the fp32 range");
+    }
+    P.L.cap = archive_cap;
+    if (archive_cap < P.L.off_exc) {
+        *archive_bytes = 0;
+        return fail(ctx, DQZ_ETOOSMALL, "archive capacity below the fixed sections");
+    }
+    P.tiles_q = quantize_tiles(P.g);
+    P.tiles_e = encode_tiles(P.g);
+    const WsLayout W = ws_layout(P, true);
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    if ((st = ensure_ws(ctx, W.total)) != DQZ_OK) return st;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    uint8_t *ws = reinterpret_cast<uint8_t *>(ctx->ws);
+    Ctl *ctl = reinterpret_cast<Ctl *>(ws + W.ctl);
+    uint32_t *hist = reinterpret_cast<uint32_t *>(ws + W.hist);
+    uint64_t *lbq = reinterpret_cast<uint64_t *>(ws + W.lbq);
+    uint64_t *lbe = reinterpret_cast<uint64_t *>(ws + W.lbe);
+    uint64_t *book = reinterpret_cast<uint64_t *>(ws + W.book);
+    uint16_t *codes = reinterpret_cast<uint16_t *>(ws + W.codes);
+    uint8_t *arc = reinterpret_cast<uint8_t *>(d_archive);
+
+    ctx->ev_ready[0] = false;
+    mark(ctx, 0, 0, s);
+    launch_init(s, ctl, ws + W.hist, W.zero_end - W.hist, params->eb_mode, params->eb);
+    mark(ctx, 0, 1, s);
+    if (params->eb_mode == DQZ_EB_VALREL) launch_minmax(s, d_field, P.g.nelem, ctl, params->eb, ctx->ncu);
+    mark(ctx, 0, 2, s);
+    launch_quantize(s, d_field, P.g, P.L, ctl, codes, hist, lbq, arc);
+    mark(ctx, 0, 3, s);
+    launch_codebook(s, P.g, P.L, ctl, hist, book, arc, params->eb_mode, params->eb);
+    mark(ctx, 0, 4, s);
+    launch_zero_stream(s, P.g, ctl, arc);
+    mark(ctx, 0, 5, s);
+    launch_encode(s, P.g, P.L, ctl, codes, book, lbe, arc);
+    mark(ctx, 0, 6, s);
+    HIP_TRY(ctx, hipGetLastError());
+    HIP_TRY(ctx, hipMemcpyAsync(ctx->h_ctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    ctx->ev_ready[0] = ctx->timing;
+    ctx->last_codes = codes;
+    ctx->last_hist = hist;
+    ctx->last_book = book;
+    ctx->last_padded = P.g.padded;
+    ctx->last_nsym = P.L.nsym;
+    const Ctl &c = *ctx->h_ctl;
+    if (c.status & ST_ETOOSMALL) *archive_bytes = c.archive_bytes;
+    st = status_from_device(ctx, c.status);
+    if (st != DQZ_OK) return st;
+    *archive_bytes = c.archive_bytes;
+    if (h_header) memcpy(h_header, c.header, kHeaderBytes);
+    return DQZ_OK;
+}
+
+dqz_status dqz_archive_info(const void *h_header, uint64_t header_bytes, dqz_shape *shape, dqz_params *params,
+                            uint64_t *field_elems, uint64_t *archive_bytes) {
+    HeaderInfo hi;
+    std::string why;
+    dqz_status st = parse_header(reinterpret_cast<const uint8_t *>(h_header), header_bytes, hi, nullptr, why);
+    if (st != DQZ_OK) return st;
+    if (shape) *shape = hi.shape;
+    if (params) *params = hi.params;
+    if (field_elems) *field_elems = hi.nelem;
+    if (archive_bytes) *archive_bytes = hi.archive_bytes;
+    return DQZ_OK;
+}
+
+dqz_status dqz_decompress(dqz_ctx *ctx, const void *d_archive, uint64_t archive_bytes, const void *h_header,
+                          float *d_field, uint64_t field_cap_elems, void *stream) {
+    if (!ctx) return DQZ_EINVAL;
+    ctx->last_error.clear();
+    if (!d_archive) return fail(ctx, DQZ_EINVAL, "null archive");
+    if (archive_bytes < kHeaderBytes) return fail(ctx, DQZ_ECORRUPT, "archive shorter than its header");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    uint8_t hb[kHeaderBytes];
+    if (h_header) {
+        memcpy(hb, h_header, kHeaderBytes);
+    } else {
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->h_ctl->header, d_archive, kHeaderBytes, hipMemcpyDeviceToHost, s));
+        HIP_TRY(ctx, hipStreamSynchronize(s));
+        memcpy(hb, ctx->h_ctl->header, kHeaderBytes);
+    }
+    HeaderInfo hi;
+    Plan P;
+    std::string why;
+    dqz_status st = parse_header(hb, kHeaderBytes, hi, &P, why);
+    if (st != DQZ_OK) return fail(ctx, st, why);
+    if (hi.archive_bytes != archive_bytes) return fail(ctx, DQZ_ECORRUPT, "archive length differs from its header");
+    if (field_cap_elems < hi.nelem) return fail(ctx, DQZ_ETOOSMALL, "field capacity too small");
+    if (hi.nelem && !d_field) return fail(ctx, DQZ_EINVAL, "null field");
+    if (hi.nelem == 0) return DQZ_OK;
+    const WsLayout W = ws_layout(P, false);
+    if ((st = ensure_ws(ctx, W.total)) != DQZ_OK) return st;
+    uint8_t *ws = reinterpret_cast<uint8_t *>(ctx->ws);
+    DecodeTables *tab = reinterpret_cast<DecodeTables *>(ws + W.tab);
+    const uint8_t *arc = reinterpret_cast<const uint8_t *>(d_archive);
+    ctx->ev_ready[1] = false;
+    mark(ctx, 1, 0, s);
+    launch_decode_tables(s, P.L, arc, hi.max_len, tab);
+    mark(ctx, 1, 1, s);
+    launch_decode(s, P.g, P.L, arc, hi.off_str, hi.n_words, (uint32_t)hi.n_exc, hi.h, tab, d_field);
+    mark(ctx, 1, 2, s);
+    HIP_TRY(ctx, hipGetLastError());
+    HIP_TRY(ctx, hipMemcpyAsync(&ctx->h_ctl->status, &tab->status, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, hipStreamSynchronize(s));
+    ctx->ev_ready[1] = ctx->timing;
+    return status_from_device(ctx, ctx->h_ctl->status);
+}
+
+dqz_status dqz_ctx_set_timing(dqz_ctx *ctx, int enable) {
+    if (!ctx) return DQZ_EINVAL;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    if (enable && !ctx->ev[0][0]) {
+        for (int k = 0; k < 2; k++)
+            for (int i = 0; i <= DQZ_MAX_STAGES; i++) HIP_TRY(ctx, hipEventCreate(&ctx->ev[k][i]));
+    }
+    ctx->timing = enable != 0;
+    ctx->ev_ready[0] = ctx->ev_ready[1] = false;
+    return DQZ_OK;
+}
+
+dqz_status dqz_stage_times(dqz_ctx *ctx, int which, double *us, int *n_stages) {
+    if (!ctx || !us || !n_stages || which < 0 || which > 1) return DQZ_EINVAL;
+    *n_stages = 0;
+    if (!ctx->ev_ready[which]) return fail(ctx, DQZ_EINVAL, "no timed call of this kind on this context");
+    const int n = ctx->n_ev[which] - 1;
+    for (int i = 0; i < n; i++) {
+        float ms = 0.0f;
+        HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev[which][i], ctx->ev[which][i + 1]));
+        us[i] = 1000.0 * ms;
+    }
+    *n_stages = n;
+    return DQZ_OK;
+}
+
+dqz_status dqz_debug_copy(dqz_ctx *ctx, int what, void *h_dst, uint64_t bytes) {
+    if (!ctx || !h_dst) return DQZ_EINVAL;
+    const void *src = nullptr;
+    uint64_t need = 0;
+    switch (what) {
+        case DQZ_DBG_CODES: src = ctx->last_codes; need = 2 * ctx->last_padded; break;
+        case DQZ_DBG_HISTOGRAM: src = ctx->last_hist; need = 4ull * ctx->last_nsym; break;
+        case DQZ_DBG_CODEBOOK: src = ctx->last_book; need = 8ull * ctx->last_nsym; break;
+        default: return fail(ctx, DQZ_EINVAL, "unknown stage");
+    }
+    if (!src) return fail(ctx, DQZ_EINVAL, "no compression has run on this context");
+    if (bytes != need) return fail(ctx, DQZ_EINVAL, "size mismatch");
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    HIP_TRY(ctx, hipMemcpy(h_dst, src, bytes, hipMemcpyDeviceToHost));
+    return DQZ_OK;
+}
+
+}  // extern "C"

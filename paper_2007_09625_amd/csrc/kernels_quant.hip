@@ -1,0 +1,550 @@
+// kernels_quant.hip -- error bound, range reduction and dual-quantization.
+//
+//   k_init      clears the control block and device counters; absolute-eb
+//               mode derives h = fl32(2 eb), r = fl32(1 / (2 eb)) here.
+//   k_minmax    finite min / max in IEEE total order for the
+//               value-range-relative bound (footnote in Sec. 3.2.2); the
+//               last workgroup derives eb_abs, h and r on the device.
+//   k_quant{1,2,3}d
+//               prequantization d° = round(x / 2eb) (Sec. 3.1.2), the
+//               1-layer Lorenzo delta inside zero-padded blocks (Sec. 3.1.1),
+//               postquantization with the +-R cap and outliers (Algorithm 2),
+//               the rehearsal check that turns a missed bound into a patch
+//               (Algorithm 1's watchdog), an LDS-privatized histogram of the
+//               codes (Sec. 3.2.1), and ordered compaction of the exceptions
+//               via decoupled look-back.
+//
+// Each quantize workgroup takes one tile of kTile padded positions by a
+// dynamic ticket, so tiles finish roughly in stream order and the look-back
+// never waits on a tile that has not started.  The tile is staged in LDS
+// with fully coalesced row loads; the Lorenzo delta is the mixed backward
+// difference, computed per axis with registers (slow axis) and cross-lane
+// shuffles (fast axes).
+#include "dqz_internal.h"
+
+#include <float.h>
+
+namespace dqz {
+
+// ---------------------------------------------------------------------------
+// init / error bound
+// ---------------------------------------------------------------------------
+__device__ void derive_eb(Ctl *ctl, double e) {
+    bool ok = isfinite(e) && e >= (double)FLT_MIN;
+    const double two_e = 2.0 * e;
+    const float h = (float)two_e;
+    const float r = (float)(1.0 / two_e);
+    ok = ok && isfinite(h) && isfinite(r) && r >= FLT_MIN;
+    if (!ok) atomicOr(&ctl->status, ST_EINVAL);
+    ctl->eb_abs = e;
+    ctl->h = h;
+    ctl->r = r;
+}
+
+__global__ void k_init(Ctl *ctl, uint32_t *zero_base, uint64_t zero_words, int eb_mode, double eb) {
+    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = tid; i < zero_words; i += stride) zero_base[i] = 0u;
+    if (tid == 0) {
+        uint32_t *c = reinterpret_cast<uint32_t *>(ctl);
+        for (uint32_t i = 0; i < sizeof(Ctl) / 4; i++) c[i] = 0u;
+        ctl->vmin_key = 0xFFFFFFFFu;
+        ctl->vmax_key = 0u;
+        if (eb_mode == 0) derive_eb(ctl, eb);
+    }
+}
+
+void launch_init(hipStream_t s, Ctl *ctl, void *zero_base, uint64_t zero_bytes, int eb_mode, double eb) {
+    const uint64_t words = zero_bytes / 4;
+    uint32_t blocks = (uint32_t)((words + 255) / 256);
+    if (blocks < 1) blocks = 1;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(k_init, dim3(blocks), dim3(256), 0, s, ctl, (uint32_t *)zero_base, words, eb_mode, eb);
+}
+
+__device__ __forceinline__ void key_acc(uint32_t u, uint32_t &lo, uint32_t &hi) {
+    if ((u & 0x7F800000u) != 0x7F800000u) {   // finite
+        const uint32_t k = f2key(u);
+        lo = k < lo ? k : lo;
+        hi = k > hi ? k : hi;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_minmax(const float *__restrict__ x, uint64_t n, Ctl *ctl, double valrel) {
+    uint32_t lo = 0xFFFFFFFFu, hi = 0u;
+    const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint32_t *u = reinterpret_cast<const uint32_t *>(x);
+    if ((reinterpret_cast<uintptr_t>(x) & 15u) == 0) {
+        const uint64_t n4 = n / 4;
+        typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+        const u32x4 *v = reinterpret_cast<const u32x4 *>(x);
+        for (uint64_t i = tid; i < n4; i += stride) {
+            const u32x4 w = __builtin_nontemporal_load(v + i);
+            key_acc(w.x, lo, hi);
+            key_acc(w.y, lo, hi);
+            key_acc(w.z, lo, hi);
+            key_acc(w.w, lo, hi);
+        }
+        for (uint64_t i = n4 * 4 + tid; i < n; i += stride) key_acc(u[i], lo, hi);
+    } else {
+        for (uint64_t i = tid; i < n; i += stride) key_acc(u[i], lo, hi);
+    }
+    // workgroup reduction
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const uint32_t a = __shfl_xor(lo, off, 64), b = __shfl_xor(hi, off, 64);
+        lo = a < lo ? a : lo;
+        hi = b > hi ? b : hi;
+    }
+    __shared__ uint32_t s_lo[4], s_hi[4];
+    __shared__ bool s_last;
+    const uint32_t w = threadIdx.x / 64;
+    if (lane_id() == 0) { s_lo[w] = lo; s_hi[w] = hi; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (uint32_t i = 1; i < blockDim.x / 64; i++) {
+            lo = s_lo[i] < lo ? s_lo[i] : lo;
+            hi = s_hi[i] > hi ? s_hi[i] : hi;
+        }
+        atomicMin(&ctl->vmin_key, lo);
+        atomicMax(&ctl->vmax_key, hi);
+        __threadfence();
+        const uint32_t t = atomicAdd(&ctl->minmax_done, 1u);
+        s_last = (t == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (s_last && threadIdx.x == 0) {
+        __threadfence();
+        const uint32_t klo = __hip_atomic_load(&ctl->vmin_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t khi = __hip_atomic_load(&ctl->vmax_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        double range = 1.0;
+        if (klo != 0xFFFFFFFFu) {   // at least one finite value
+            const float fmin = __uint_as_float(key2f(klo));
+            const float fmax = __uint_as_float(key2f(khi));
+            const double d = (double)fmax - (double)fmin;
+            if (d > 0.0) range = d;
+        }
+        derive_eb(ctl, valrel * range);
+    }
+}
+
+void launch_minmax(hipStream_t s, const float *x, uint64_t n, Ctl *ctl, double valrel, int ncu) {
+    uint64_t want = (n / 4 + 255) / 256;
+    uint32_t blocks = (uint32_t)(want < (uint64_t)ncu * 8 ? want : (uint64_t)ncu * 8);
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_minmax, dim3(blocks), dim3(256), 0, s, x, n, ctl, valrel);
+}
+
+// ---------------------------------------------------------------------------
+// shared pieces of the quantize kernels
+// ---------------------------------------------------------------------------
+struct QuantArgs {
+    const float *x;
+    Geom g;
+    Layout L;
+    Ctl *ctl;
+    uint16_t *codes;
+    uint32_t *hist;      // global histogram (2R)
+    uint64_t *lb;        // look-back words, one per tile
+    uint8_t *archive;
+    uint32_t n_tiles;
+    uint32_t tiles_per_row;
+};
+
+// LDS histogram privatization: one replica per workgroup, flushed once.
+__device__ __forceinline__ void hist_flush(uint32_t *sh_hist, uint32_t nsym, uint32_t *ghist) {
+    for (uint32_t b = threadIdx.x; b < nsym; b += blockDim.x) {
+        const uint32_t c = sh_hist[b];
+        if (c) atomicAdd(ghist + b, c);
+    }
+}
+
+// Workgroup-level ordered allocation of exception records: every wave
+// reports its record count; returns this wave's first global record index.
+// Also publishes / resolves the tile's look-back word.
+__device__ __forceinline__ uint64_t exceptions_base(const QuantArgs &a, uint32_t tile, uint32_t wave_count,
+                                                    uint32_t wave_out, uint32_t wave_patch, uint32_t *sh) {
+    // sh: [0..3] wave counts, [4] tile base low, [5] tile base high, [6..7] out/patch
+    const uint32_t w = threadIdx.x / 64, nw = blockDim.x / 64;
+    if (lane_id() == 0) { sh[w] = wave_count; sh[8 + w] = wave_out; sh[12 + w] = wave_patch; }
+    __syncthreads();
+    if (w == 0) {
+        uint32_t tot = 0, tout = 0, tpat = 0;
+        for (uint32_t i = 0; i < nw; i++) { tot += sh[i]; tout += sh[8 + i]; tpat += sh[12 + i]; }
+        uint64_t base = 0;
+        if (tile == 0) {
+            if (lane_id() == 0) lb_publish(a.lb, tile, tot, 2);
+        } else {
+            if (lane_id() == 0) lb_publish(a.lb, tile, tot, 1);
+            base = lb_exclusive(a.lb, tile);
+            if (lane_id() == 0) lb_publish(a.lb, tile, base + tot, 2);
+        }
+        if (lane_id() == 0) {
+            sh[4] = (uint32_t)base;
+            sh[5] = (uint32_t)(base >> 32);
+            if (tout) atomicAdd(&a.ctl->n_out, tout);
+            if (tpat) atomicAdd(&a.ctl->n_patch, tpat);
+            if (tile == a.n_tiles - 1) a.ctl->n_exc = (uint32_t)(base + tot);
+        }
+    }
+    __syncthreads();
+    uint64_t base = (uint64_t)sh[4] | ((uint64_t)sh[5] << 32);
+    for (uint32_t i = 0; i < w; i++) base += sh[i];
+    return base;
+}
+
+__device__ __forceinline__ void put_exc(const QuantArgs &a, uint64_t idx, uint32_t key, uint32_t payload) {
+    const uint64_t off = a.L.off_exc + 8ull * idx;
+    if (off + 8 <= a.L.cap) {
+        uint2 rec;
+        rec.x = key;
+        rec.y = payload;
+        *reinterpret_cast<uint2 *>(a.archive + off) = rec;
+    } else {
+        atomicOr(&a.ctl->status, ST_ETOOSMALL);
+    }
+}
+
+__device__ __forceinline__ uint32_t take_ticket(Ctl *ctl, uint32_t *sh_ticket) {
+    if (threadIdx.x == 0) *sh_ticket = atomicAdd(&ctl->ticket_q, 1u);
+    __syncthreads();
+    return *sh_ticket;
+}
+
+// ---------------------------------------------------------------------------
+// 3D: tile = 8 consecutive 8x8x8 blocks along x in one block row.
+// Wave w handles blocks 2w, 2w+1; lane (y, x) = (lane / 8, lane % 8) holds
+// the 8 points of its z column in registers.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kT3 = 8;           // blocks per 3D tile
+constexpr uint32_t kRow3 = 8 * kT3 + 8;   // LDS row pitch (floats), padded against bank conflicts
+
+__global__ __launch_bounds__(256) void k_quant3d(QuantArgs a) {
+    extern __shared__ uint32_t sh_hist[];
+    __shared__ float s_tile[8][8][kRow3];
+    __shared__ uint32_t s_misc[16];
+    __shared__ uint32_t s_ticket;
+
+    Ctl *ctl = a.ctl;
+    if (ctl->status & ST_EINVAL) return;
+    const float r = ctl->r, h = ctl->h;
+    const double eb = ctl->eb_abs;
+    const int32_t R = (int32_t)a.L.radius;
+    for (uint32_t b = threadIdx.x; b < a.L.nsym; b += blockDim.x) sh_hist[b] = 0;
+
+    const uint32_t tile = take_ticket(ctl, &s_ticket);
+    const uint32_t tx = tile % a.tiles_per_row;
+    const uint32_t rowid = tile / a.tiles_per_row;
+    const uint32_t By = rowid % a.g.nb[1], Bz = rowid / a.g.nb[1];
+    const uint32_t z0 = Bz * 8, y0 = By * 8, x0 = tx * kT3 * 8;
+    const uint32_t nz = a.g.n[0], ny = a.g.n[1], nx = a.g.n[2];
+
+    // stage the tile: 64 rows (z, y) of 64 floats, one wave per row
+    for (uint32_t rr = threadIdx.x / 64; rr < 64; rr += blockDim.x / 64) {
+        const uint32_t z = rr / 8, y = rr % 8, xx = lane_id();
+        float v = 0.0f;
+        if (z0 + z < nz && y0 + y < ny && x0 + xx < nx)
+            v = __builtin_nontemporal_load(a.x + ((uint64_t)(z0 + z) * ny + (y0 + y)) * nx + (x0 + xx));
+        s_tile[z][y][xx] = v;
+    }
+    __syncthreads();
+
+    const uint32_t lane = lane_id(), w = threadIdx.x / 64;
+    const uint32_t ly = lane / 8, lx = lane % 8;
+    int32_t delta[2][8];
+    uint32_t flags_o = 0, flags_p = 0;   // bit (j*8 + z)
+    uint32_t wave_count = 0, wave_out = 0, wave_patch = 0;
+#pragma unroll
+    for (uint32_t j = 0; j < 2; j++) {
+        const uint32_t bxl = 2 * w + j;              // block within tile
+        const uint32_t Bx = tx * kT3 + bxl;
+        const bool blk_ok = Bx < a.g.nb[2];
+        const uint32_t gx = x0 + bxl * 8 + lx, gy = y0 + ly;
+        const uint64_t blk = ((uint64_t)Bz * a.g.nb[1] + By) * a.g.nb[2] + Bx;
+        int32_t prev = 0;   // d° of (z-1) in this column; padding layer is 0
+#pragma unroll
+        for (uint32_t z = 0; z < 8; z++) {
+            const bool real = blk_ok && gx < nx && gy < ny && (z0 + z) < nz;
+            const float v = s_tile[z][ly][bxl * 8 + lx];
+            const int32_t d = prequant(v, r);
+            // mixed backward difference: z (registers), then y, x (lanes)
+            const uint32_t dz = (uint32_t)d - (uint32_t)prev;
+            prev = d;
+            const uint32_t up_y = __shfl_up(dz, 8, 64);
+            const uint32_t dyz = dz - (ly > 0 ? up_y : 0u);
+            const uint32_t up_x = __shfl_up(dyz, 1, 64);
+            const int32_t del = (int32_t)(dyz - (lx > 0 ? up_x : 0u));
+            delta[j][z] = del;
+            const bool incap = del > -R && del < R;
+            const bool o = real && !incap;
+            const bool p = real && needs_patch(v, d, h, eb);
+            uint16_t q = kNoSymbol;
+            if (real) {
+                q = incap ? (uint16_t)(del + R) : (uint16_t)0;
+                atomicAdd(&sh_hist[q], 1u);
+            }
+            if (blk_ok) a.codes[blk * 512 + z * 64 + lane] = q;
+            flags_o |= (o ? 1u : 0u) << (j * 8 + z);
+            flags_p |= (p ? 1u : 0u) << (j * 8 + z);
+            const uint64_t mo = __ballot(o), mp = __ballot(p);
+            wave_count += __popcll(mo) + __popcll(mp);
+            wave_out += __popcll(mo);
+            wave_patch += __popcll(mp);
+        }
+    }
+
+    const uint64_t base0 = exceptions_base(a, tile, wave_count, wave_out, wave_patch, s_misc);
+    if (wave_count) {
+        uint64_t base = base0;
+        const uint64_t below = lanes_below(lane);
+#pragma unroll
+        for (uint32_t j = 0; j < 2; j++) {
+            const uint32_t bxl = 2 * w + j;
+            const uint64_t blk = ((uint64_t)Bz * a.g.nb[1] + By) * a.g.nb[2] + (tx * kT3 + bxl);
+#pragma unroll
+            for (uint32_t z = 0; z < 8; z++) {
+                const bool o = (flags_o >> (j * 8 + z)) & 1u, p = (flags_p >> (j * 8 + z)) & 1u;
+                const uint64_t mo = __ballot(o), mp = __ballot(p);
+                if ((mo | mp) == 0) continue;
+                const uint64_t idx = base + __popcll(mo & below) + __popcll(mp & below);
+                const uint32_t pos = (uint32_t)(blk * 512 + z * 64 + lane);
+                if (o) put_exc(a, idx, 2u * pos, (uint32_t)delta[j][z]);
+                if (p) put_exc(a, idx + (o ? 1 : 0), 2u * pos + 1u, __float_as_uint(s_tile[z][ly][bxl * 8 + lx]));
+                base += __popcll(mo) + __popcll(mp);
+            }
+        }
+    }
+    __syncthreads();
+    hist_flush(sh_hist, a.L.nsym, a.hist);
+}
+
+// ---------------------------------------------------------------------------
+// 2D: tile = 16 consecutive 16x16 blocks along x in one block row.  Wave w
+// handles blocks 4w..4w+3; lane -> (block 4w + lane/16, column lane%16)
+// walking the 16 rows, so the y difference stays in registers and the x
+// difference is a shuffle inside each 16-lane row.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kT2 = 16;
+
+__global__ __launch_bounds__(256) void k_quant2d(QuantArgs a) {
+    extern __shared__ uint32_t sh_hist[];
+    __shared__ float s_tile[16][16 * kT2];
+    __shared__ uint32_t s_misc[16];
+    __shared__ uint32_t s_ticket;
+
+    Ctl *ctl = a.ctl;
+    if (ctl->status & ST_EINVAL) return;
+    const float r = ctl->r, h = ctl->h;
+    const double eb = ctl->eb_abs;
+    const int32_t R = (int32_t)a.L.radius;
+    for (uint32_t b = threadIdx.x; b < a.L.nsym; b += blockDim.x) sh_hist[b] = 0;
+
+    const uint32_t tile = take_ticket(ctl, &s_ticket);
+    const uint32_t tx = tile % a.tiles_per_row, By = tile / a.tiles_per_row;
+    const uint32_t y0 = By * 16, x0 = tx * kT2 * 16;
+    const uint32_t ny = a.g.n[1], nx = a.g.n[2];
+    for (uint32_t rr = 0; rr < 16; rr++) {
+        const uint32_t xx = threadIdx.x;
+        float v = 0.0f;
+        if (y0 + rr < ny && x0 + xx < nx) v = __builtin_nontemporal_load(a.x + (uint64_t)(y0 + rr) * nx + x0 + xx);
+        s_tile[rr][xx] = v;
+    }
+    __syncthreads();
+
+    const uint32_t lane = lane_id(), w = threadIdx.x / 64;
+    const uint32_t grp = lane / 16, lx = lane % 16;
+    const uint32_t bxl = 4 * w + grp;
+    const uint32_t Bx = tx * kT2 + bxl;
+    const bool blk_ok = Bx < a.g.nb[2];
+    const uint32_t gx = x0 + bxl * 16 + lx;
+    const uint64_t blk = (uint64_t)By * a.g.nb[2] + Bx;
+    int32_t delta[16];
+    uint32_t flags_o = 0, flags_p = 0;
+    uint32_t my_count = 0, wave_out = 0, wave_patch = 0;
+    int32_t prev = 0;
+#pragma unroll
+    for (uint32_t y = 0; y < 16; y++) {
+        const bool real = blk_ok && gx < nx && (y0 + y) < ny;
+        const float v = s_tile[y][bxl * 16 + lx];
+        const int32_t d = prequant(v, r);
+        const uint32_t dy = (uint32_t)d - (uint32_t)prev;
+        prev = d;
+        const uint32_t up = __shfl_up(dy, 1, 64);
+        const int32_t del = (int32_t)(dy - (lx > 0 ? up : 0u));
+        delta[y] = del;
+        const bool incap = del > -R && del < R;
+        const bool o = real && !incap;
+        const bool p = real && needs_patch(v, d, h, eb);
+        uint16_t q = kNoSymbol;
+        if (real) {
+            q = incap ? (uint16_t)(del + R) : (uint16_t)0;
+            atomicAdd(&sh_hist[q], 1u);
+        }
+        if (blk_ok) a.codes[blk * 256 + y * 16 + lx] = q;
+        flags_o |= (o ? 1u : 0u) << y;
+        flags_p |= (p ? 1u : 0u) << y;
+        my_count += (o ? 1u : 0u) + (p ? 1u : 0u);
+        wave_out += __popcll(__ballot(o));
+        wave_patch += __popcll(__ballot(p));
+    }
+    // records are ordered block by block: group totals, then exclusive over groups
+    uint32_t grp_total = my_count;
+#pragma unroll
+    for (int off = 8; off >= 1; off >>= 1) grp_total += __shfl_xor(grp_total, off, 16);
+    const uint32_t g0 = __shfl(grp_total, 0, 64), g1 = __shfl(grp_total, 16, 64), g2 = __shfl(grp_total, 32, 64),
+                   g3 = __shfl(grp_total, 48, 64);
+    const uint32_t wave_count = g0 + g1 + g2 + g3;
+    const uint32_t grp_off = (grp > 0 ? g0 : 0u) + (grp > 1 ? g1 : 0u) + (grp > 2 ? g2 : 0u);
+    const uint64_t base0 = exceptions_base(a, tile, wave_count, wave_out, wave_patch, s_misc);
+    if (wave_count) {
+        uint64_t base = base0 + grp_off;
+        const uint64_t gmask = 0xFFFFull << (16 * grp);
+        const uint64_t below = lanes_below(lane) & gmask;
+#pragma unroll
+        for (uint32_t y = 0; y < 16; y++) {
+            const bool o = (flags_o >> y) & 1u, p = (flags_p >> y) & 1u;
+            const uint64_t mo = __ballot(o), mp = __ballot(p);
+            if ((mo | mp) == 0) continue;
+            const uint64_t idx = base + __popcll(mo & below) + __popcll(mp & below);
+            const uint32_t pos = (uint32_t)(blk * 256 + y * 16 + lx);
+            if (o) put_exc(a, idx, 2u * pos, (uint32_t)delta[y]);
+            if (p) put_exc(a, idx + (o ? 1 : 0), 2u * pos + 1u, __float_as_uint(s_tile[y][bxl * 16 + lx]));
+            base += __popcll(mo & gmask) + __popcll(mp & gmask);
+        }
+    }
+    __syncthreads();
+    hist_flush(sh_hist, a.L.nsym, a.hist);
+}
+
+// ---------------------------------------------------------------------------
+// 1D: tile = 4096 consecutive points (128 blocks of 32).  Thread t owns the
+// 16 consecutive points [16t, 16t + 16), half a block; the first point of an
+// odd thread takes its neighbour from the previous lane.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_quant1d(QuantArgs a) {
+    extern __shared__ uint32_t sh_hist[];
+    __shared__ float s_tile[kTile];
+    __shared__ uint32_t s_misc[16];
+    __shared__ uint32_t s_ticket;
+
+    Ctl *ctl = a.ctl;
+    if (ctl->status & ST_EINVAL) return;
+    const float r = ctl->r, h = ctl->h;
+    const double eb = ctl->eb_abs;
+    const int32_t R = (int32_t)a.L.radius;
+    for (uint32_t b = threadIdx.x; b < a.L.nsym; b += blockDim.x) sh_hist[b] = 0;
+
+    const uint32_t tile = take_ticket(ctl, &s_ticket);
+    const uint64_t p0 = (uint64_t)tile * kTile;
+    const uint64_t n = a.g.nelem;
+    for (uint32_t k = threadIdx.x; k < kTile; k += blockDim.x) {
+        float v = 0.0f;
+        if (p0 + k < n) v = __builtin_nontemporal_load(a.x + p0 + k);
+        s_tile[k] = v;
+    }
+    __syncthreads();
+
+    const uint32_t t = threadIdx.x, lane = lane_id();
+    int32_t d[16];
+#pragma unroll
+    for (uint32_t i = 0; i < 16; i++) d[i] = prequant(s_tile[16 * t + i], r);
+    const uint32_t nb_prev = __shfl_up((uint32_t)d[15], 1, 64);
+    int32_t delta[16];
+    uint32_t flags_o = 0, flags_p = 0, my_count = 0;
+    uint16_t q[16];
+#pragma unroll
+    for (uint32_t i = 0; i < 16; i++) {
+        uint32_t pred = 0;
+        if (i > 0) pred = (uint32_t)d[i - 1];
+        else if (t & 1u) pred = nb_prev;      // lane t-1 is in the same wave (t odd)
+        const int32_t del = (int32_t)((uint32_t)d[i] - pred);
+        delta[i] = del;
+        const uint64_t pos = p0 + 16 * t + i;
+        const bool exists = pos < a.g.padded;
+        const bool real = pos < n;
+        const bool incap = del > -R && del < R;
+        const bool o = real && !incap;
+        const bool p = real && needs_patch(s_tile[16 * t + i], d[i], h, eb);
+        uint16_t qq = kNoSymbol;
+        if (real) {
+            qq = incap ? (uint16_t)(del + R) : (uint16_t)0;
+            atomicAdd(&sh_hist[qq], 1u);
+        }
+        q[i] = qq;
+        (void)exists;
+        flags_o |= (o ? 1u : 0u) << i;
+        flags_p |= (p ? 1u : 0u) << i;
+        my_count += (o ? 1u : 0u) + (p ? 1u : 0u);
+    }
+    // codes: 16 consecutive u16 per thread (two 16-byte stores)
+    {
+        const uint64_t pos0 = p0 + 16 * t;
+        if (pos0 + 16 <= a.g.padded) {
+            uint4 v0, v1;
+            v0.x = q[0] | ((uint32_t)q[1] << 16); v0.y = q[2] | ((uint32_t)q[3] << 16);
+            v0.z = q[4] | ((uint32_t)q[5] << 16); v0.w = q[6] | ((uint32_t)q[7] << 16);
+            v1.x = q[8] | ((uint32_t)q[9] << 16); v1.y = q[10] | ((uint32_t)q[11] << 16);
+            v1.z = q[12] | ((uint32_t)q[13] << 16); v1.w = q[14] | ((uint32_t)q[15] << 16);
+            uint4 *dst = reinterpret_cast<uint4 *>(a.codes + pos0);
+            dst[0] = v0;
+            dst[1] = v1;
+        } else {
+#pragma unroll
+            for (uint32_t i = 0; i < 16; i++)
+                if (pos0 + i < a.g.padded) a.codes[pos0 + i] = q[i];
+        }
+    }
+    const uint32_t incl = wave_incl_scan<uint32_t>(my_count);
+    const uint32_t wave_count = __shfl(incl, 63, 64);
+    const uint32_t wave_out = wave_sum<uint32_t>(__popc(flags_o));
+    const uint32_t wave_patch = wave_sum<uint32_t>(__popc(flags_p));
+    const uint64_t base0 = exceptions_base(a, tile, wave_count, wave_out, wave_patch, s_misc);
+    if (my_count) {
+        uint64_t idx = base0 + incl - my_count;
+#pragma unroll
+        for (uint32_t i = 0; i < 16; i++) {
+            const uint32_t pos = (uint32_t)(p0 + 16 * t + i);
+            if ((flags_o >> i) & 1u) put_exc(a, idx++, 2u * pos, (uint32_t)delta[i]);
+            if ((flags_p >> i) & 1u) put_exc(a, idx++, 2u * pos + 1u, __float_as_uint(s_tile[16 * t + i]));
+        }
+    }
+    (void)lane;
+    __syncthreads();
+    hist_flush(sh_hist, a.L.nsym, a.hist);
+}
+
+uint32_t quantize_tiles(const Geom &g) {
+    if (g.nelem == 0) return 0;
+    if (g.ndim == 3) return g.nb[0] * g.nb[1] * ((g.nb[2] + kT3 - 1) / kT3);
+    if (g.ndim == 2) return g.nb[1] * ((g.nb[2] + kT2 - 1) / kT2);
+    return (uint32_t)((g.padded + kTile - 1) / kTile);
+}
+
+void launch_quantize(hipStream_t s, const float *x, const Geom &g, const Layout &L, Ctl *ctl, uint16_t *codes,
+                     uint32_t *hist, uint64_t *lb, uint8_t *archive) {
+    QuantArgs a;
+    a.x = x;
+    a.g = g;
+    a.L = L;
+    a.ctl = ctl;
+    a.codes = codes;
+    a.hist = hist;
+    a.lb = lb;
+    a.archive = archive;
+    a.n_tiles = quantize_tiles(g);
+    if (a.n_tiles == 0) return;
+    const size_t lds = sizeof(uint32_t) * L.nsym;
+    if (g.ndim == 3) {
+        a.tiles_per_row = (g.nb[2] + kT3 - 1) / kT3;
+        hipLaunchKernelGGL(k_quant3d, dim3(a.n_tiles), dim3(256), lds, s, a);
+    } else if (g.ndim == 2) {
+        a.tiles_per_row = (g.nb[2] + kT2 - 1) / kT2;
+        hipLaunchKernelGGL(k_quant2d, dim3(a.n_tiles), dim3(256), lds, s, a);
+    } else {
+        a.tiles_per_row = 1;
+        hipLaunchKernelGGL(k_quant1d, dim3(a.n_tiles), dim3(256), lds, s, a);
+    }
+}
+
+}  // namespace dqz

@@ -1,0 +1,260 @@
+"""Python binding of libdqz (argument marshalling only).
+
+Every function here forwards to the C ABI declared in ``include/dqz.h``; the
+compression itself runs in the HIP kernels of ``libdqz.so``.  PyTorch is used
+only to own device memory and to name the current HIP stream.  There is no
+fallback path: if the library is missing, importing raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdqz.so")
+
+DQZ_OK, DQZ_EINVAL, DQZ_ETOOSMALL, DQZ_ENOMEM, DQZ_ECORRUPT, DQZ_EUNSUPPORTED, DQZ_EHIP = 0, -1, -2, -3, -4, -5, -6
+DQZ_EB_ABS, DQZ_EB_VALREL = 0, 1
+DQZ_HEADER_BYTES = 128
+DQZ_DBG_CODES, DQZ_DBG_HISTOGRAM, DQZ_DBG_CODEBOOK = 1, 2, 3
+
+EXPORTED = ("dqz_ctx_create", "dqz_ctx_destroy", "dqz_compress_bound", "dqz_compress", "dqz_archive_info",
+            "dqz_decompress", "dqz_status_str", "dqz_ctx_last_error", "dqz_debug_copy", "dqz_ctx_set_timing",
+            "dqz_stage_times")
+DQZ_MAX_STAGES = 8
+COMPRESS_STAGES = ("init", "range_eb", "quantize", "codebook", "stream_clear", "encode")
+DECOMPRESS_STAGES = ("decode_tables", "decode")
+
+
+class DqzError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(msg)
+        self.status = status
+
+
+class dqz_shape(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("dims", ctypes.c_uint64 * 3)]
+
+
+class dqz_params(ctypes.Structure):
+    _fields_ = [("eb", ctypes.c_double), ("eb_mode", ctypes.c_int32), ("radius", ctypes.c_uint32),
+                ("sub_size", ctypes.c_uint32), ("chunk_subs", ctypes.c_uint32)]
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libdqz.so is not built ({LIB_PATH}); run __graft_entry__.build()")
+    # torch ships its own HIP runtime under the same soname; load it first so
+    # that libdqz binds to the runtime that owns the process's device memory
+    # and streams (two runtimes in one process cannot share the GPU).
+    import torch  # noqa: F401
+    lib = ctypes.CDLL(LIB_PATH)
+    P, u64, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32
+    lib.dqz_ctx_create.argtypes = [ctypes.c_int, ctypes.POINTER(P)]
+    lib.dqz_ctx_create.restype = i32
+    lib.dqz_ctx_destroy.argtypes = [P]
+    lib.dqz_ctx_destroy.restype = None
+    lib.dqz_compress_bound.argtypes = [ctypes.POINTER(dqz_shape), ctypes.POINTER(dqz_params),
+                                       ctypes.POINTER(u64), ctypes.POINTER(u64)]
+    lib.dqz_compress_bound.restype = i32
+    lib.dqz_compress.argtypes = [P, P, ctypes.POINTER(dqz_shape), ctypes.POINTER(dqz_params), P, u64,
+                                 ctypes.POINTER(u64), P, P]
+    lib.dqz_compress.restype = i32
+    lib.dqz_archive_info.argtypes = [P, u64, ctypes.POINTER(dqz_shape), ctypes.POINTER(dqz_params),
+                                     ctypes.POINTER(u64), ctypes.POINTER(u64)]
+    lib.dqz_archive_info.restype = i32
+    lib.dqz_decompress.argtypes = [P, P, u64, P, P, u64, P]
+    lib.dqz_decompress.restype = i32
+    lib.dqz_status_str.argtypes = [i32]
+    lib.dqz_status_str.restype = ctypes.c_char_p
+    lib.dqz_ctx_last_error.argtypes = [P]
+    lib.dqz_ctx_last_error.restype = ctypes.c_char_p
+    lib.dqz_debug_copy.argtypes = [P, ctypes.c_int, P, u64]
+    lib.dqz_debug_copy.restype = i32
+    lib.dqz_ctx_set_timing.argtypes = [P, ctypes.c_int]
+    lib.dqz_ctx_set_timing.restype = i32
+    lib.dqz_stage_times.argtypes = [P, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)]
+    lib.dqz_stage_times.restype = i32
+    return lib
+
+
+lib = _load()
+
+
+def make_shape(shape) -> dqz_shape:
+    s = dqz_shape()
+    s.ndim = len(shape)           # the library rejects ndim outside 1..3
+    for i, d in enumerate(list(shape)[:3]):
+        s.dims[i] = int(d)
+    return s
+
+
+def make_params(eb: float, mode: int = DQZ_EB_VALREL, radius: int = 0, sub_size: int = 0,
+                chunk_subs: int = 0) -> dqz_params:
+    p = dqz_params()
+    p.eb = float(eb)
+    p.eb_mode = int(mode)
+    p.radius = int(radius)
+    p.sub_size = int(sub_size)
+    p.chunk_subs = int(chunk_subs)
+    return p
+
+
+def _mode(mode) -> int:
+    if isinstance(mode, str):
+        return {"abs": DQZ_EB_ABS, "valrel": DQZ_EB_VALREL}[mode]
+    return int(mode)
+
+
+def dqz_compress_bound(shape, params: dqz_params):
+    amax, ws = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    s = make_shape(shape)
+    st = lib.dqz_compress_bound(ctypes.byref(s), ctypes.byref(params), ctypes.byref(amax), ctypes.byref(ws))
+    if st != DQZ_OK:
+        raise DqzError(st, f"dqz_compress_bound: {lib.dqz_status_str(st).decode()}")
+    return int(amax.value), int(ws.value)
+
+
+def dqz_archive_info(header: bytes):
+    s, p = dqz_shape(), dqz_params()
+    n, ab = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    buf = ctypes.create_string_buffer(bytes(header), len(header))
+    st = lib.dqz_archive_info(buf, len(header), ctypes.byref(s), ctypes.byref(p), ctypes.byref(n), ctypes.byref(ab))
+    if st != DQZ_OK:
+        raise DqzError(st, f"dqz_archive_info: {lib.dqz_status_str(st).decode()}")
+    shape = tuple(int(s.dims[i]) for i in range(s.ndim))
+    return shape, p, int(n.value), int(ab.value)
+
+
+@dataclass
+class Compressed:
+    """An archive in device memory plus a host copy of its header."""
+    archive: "object"        # torch.uint8 CUDA tensor, exactly the archive bytes
+    header: bytes            # the 128-byte header
+
+    @property
+    def nbytes(self) -> int:
+        return int(self.archive.numel())
+
+
+class Context:
+    """Owns one dqz_ctx (device scratch kept across calls)."""
+
+    def __init__(self, device: int = 0):
+        import torch  # device memory and streams only
+        self._torch = torch
+        self.device = device
+        h = ctypes.c_void_p()
+        st = lib.dqz_ctx_create(device, ctypes.byref(h))
+        if st != DQZ_OK:
+            raise DqzError(st, f"dqz_ctx_create: {lib.dqz_status_str(st).decode()}")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.dqz_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int, what: str):
+        if st != DQZ_OK:
+            msg = lib.dqz_ctx_last_error(self.handle).decode()
+            raise DqzError(st, f"{what}: {lib.dqz_status_str(st).decode()} ({msg})")
+
+    def _stream(self, stream):
+        torch = self._torch
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        return ctypes.c_void_p(stream.cuda_stream)
+
+    # -- raw C-ABI forwarding (caller-provided buffers) -------------------------------
+    def dqz_compress(self, field_ptr: int, shape, params: dqz_params, archive_ptr: int, archive_cap: int,
+                     stream=None):
+        """Returns (status, archive_bytes, header bytes)."""
+        s = make_shape(shape)
+        nbytes = ctypes.c_uint64(0)
+        hdr = ctypes.create_string_buffer(DQZ_HEADER_BYTES)
+        st = lib.dqz_compress(self.handle, ctypes.c_void_p(field_ptr), ctypes.byref(s), ctypes.byref(params),
+                              ctypes.c_void_p(archive_ptr), int(archive_cap), ctypes.byref(nbytes), hdr,
+                              self._stream(stream))
+        return st, int(nbytes.value), hdr.raw
+
+    def dqz_decompress(self, archive_ptr: int, archive_bytes: int, header: bytes | None, field_ptr: int,
+                       field_cap_elems: int, stream=None) -> int:
+        hb = ctypes.create_string_buffer(bytes(header), DQZ_HEADER_BYTES) if header is not None else None
+        return lib.dqz_decompress(self.handle, ctypes.c_void_p(archive_ptr), int(archive_bytes), hb,
+                                  ctypes.c_void_p(field_ptr), int(field_cap_elems), self._stream(stream))
+
+    def dqz_ctx_set_timing(self, enable: bool):
+        self._check(lib.dqz_ctx_set_timing(self.handle, 1 if enable else 0), "dqz_ctx_set_timing")
+
+    def dqz_stage_times(self, which: int) -> dict:
+        """Microseconds per stage of the last timed compress (0) / decompress (1)."""
+        us = (ctypes.c_double * DQZ_MAX_STAGES)()
+        n = ctypes.c_int(0)
+        self._check(lib.dqz_stage_times(self.handle, which, us, ctypes.byref(n)), "dqz_stage_times")
+        names = COMPRESS_STAGES if which == 0 else DECOMPRESS_STAGES
+        return {names[i]: float(us[i]) for i in range(n.value)}
+
+    def dqz_debug_copy(self, what: int, nbytes: int):
+        import numpy as np
+        out = np.empty(nbytes, np.uint8)
+        st = lib.dqz_debug_copy(self.handle, what, ctypes.c_void_p(out.ctypes.data), nbytes)
+        self._check(st, "dqz_debug_copy")
+        return out
+
+    # -- tensor-level helpers ---------------------------------------------------------
+    def compress(self, field, eb: float, mode="valrel", radius: int = 0, sub_size: int = 0, chunk_subs: int = 0,
+                 out=None, stream=None) -> Compressed:
+        """Compress a float32 CUDA tensor (1-3 dims, contiguous)."""
+        torch = self._torch
+        if field.dtype != torch.float32 or not field.is_cuda or not field.is_contiguous():
+            raise DqzError(DQZ_EINVAL, "field must be a contiguous float32 CUDA tensor")
+        params = make_params(eb, _mode(mode), radius, sub_size, chunk_subs)
+        shape = tuple(field.shape)
+        bound, _ = dqz_compress_bound(shape, params)
+        if out is None or out.numel() < bound:
+            out = torch.empty(bound, dtype=torch.uint8, device=field.device)
+        st, nbytes, hdr = self.dqz_compress(field.data_ptr(), shape, params, out.data_ptr(), out.numel(), stream)
+        self._check(st, "dqz_compress")
+        return Compressed(out[:nbytes], hdr)
+
+    def decompress(self, comp, out=None, stream=None):
+        """Decompress a Compressed (or a uint8 CUDA tensor holding an archive)."""
+        torch = self._torch
+        if isinstance(comp, Compressed):
+            arc, hdr = comp.archive, comp.header
+        else:
+            arc, hdr = comp, None
+        if hdr is None:
+            hdr = bytes(arc[:DQZ_HEADER_BYTES].cpu().numpy().tobytes())
+        shape, _, n, _ = dqz_archive_info(hdr)
+        if out is None:
+            out = torch.empty(shape, dtype=torch.float32, device=arc.device)
+        st = self.dqz_decompress(arc.data_ptr(), arc.numel(), hdr, out.data_ptr(), out.numel(), stream)
+        self._check(st, "dqz_decompress")
+        return out
+
+
+_default = {}
+
+
+def default_context(device: int = 0) -> Context:
+    if device not in _default:
+        _default[device] = Context(device)
+    return _default[device]
+
+
+def compress(field, eb: float, mode="valrel", **kw) -> Compressed:
+    return default_context(field.device.index or 0).compress(field, eb, mode, **kw)
+
+
+def decompress(comp, **kw):
+    arc = comp.archive if isinstance(comp, Compressed) else comp
+    return default_context(arc.device.index or 0).decompress(comp, **kw)

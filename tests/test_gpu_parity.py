@@ -1,0 +1,223 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bar: archive bytes bit-exact (codes, histogram-derived lengths, exception
+lists, tables and bitstream are all inside the archive), decompressed floats
+bit-exact, and |x - x'| <= eb_abs on every element.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import archive_util as au
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2007_09625_amd import dqz
+    return dqz.Context(0)
+
+
+def _gpu_round_trip(ctx, x, eb, mode, **kw):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0")
+    comp = ctx.compress(t, eb, mode, **kw)
+    y = ctx.decompress(comp)
+    torch.cuda.synchronize()
+    return comp.archive.cpu().numpy(), comp.header, y.cpu().numpy()
+
+
+def _explain_mismatch(ctx, x, eb, mode, gpu_arc, ref_arc):
+    """Locate the first differing stage for the failure message."""
+    from paper_2007_09625_amd import dqz
+    lines = []
+    if gpu_arc.size != ref_arc.size:
+        lines.append(f"archive sizes differ: gpu {gpu_arc.size} oracle {ref_arc.size}")
+    else:
+        d = np.nonzero(gpu_arc != ref_arc)[0]
+        lines.append(f"{d.size} bytes differ, first at {d[:8].tolist()}")
+    try:
+        gs, rs = au.sections(gpu_arc), au.sections(ref_arc)
+        lines.append(f"section offsets {rs['offsets']}")
+        for k in ("lengths", "chunks", "subs", "exc_key", "exc_payload", "stream"):
+            a, b = gs[k], rs[k]
+            if a.shape != b.shape or not np.array_equal(a, b):
+                idx = int(np.argmax(a[:min(a.size, b.size)] != b[:min(a.size, b.size)])) if min(a.size, b.size) else 0
+                lines.append(f"section {k} differs: sizes {a.size} vs {b.size}, first diff at {idx}")
+        gh, rh = gs["header"], rs["header"]
+        for k in gh:
+            if gh[k] != rh[k]:
+                lines.append(f"header {k}: gpu {gh[k]} oracle {rh[k]}")
+        import oracle
+        _, codes, freq, _ = oracle.stages(x, eb, mode, gh["radius"])
+        hist = ctx.dqz_debug_copy(dqz.DQZ_DBG_HISTOGRAM, 4 * 2 * gh["radius"]).view(np.uint32)
+        if not np.array_equal(hist.astype(np.uint64), freq):
+            lines.append(f"histogram differs at bins {np.nonzero(hist != freq)[0][:10]}")
+        padded = gs["padded"]
+        gcodes = ctx.dqz_debug_copy(dqz.DQZ_DBG_CODES, 2 * padded).view(np.uint16)
+        real = gcodes[gcodes != 0xFFFF]
+        if real.size != codes.size or not np.array_equal(real, codes):
+            d = np.nonzero(real[:codes.size] != codes[:real.size])[0]
+            lines.append(f"codes differ: {real.size} vs {codes.size} real codes, first diffs {d[:10]}")
+    except Exception as e:  # pragma: no cover - diagnostics only
+        lines.append(f"(diagnostics failed: {e!r})")
+    return "\n".join(lines)
+
+
+def _check(ctx, x, eb=1e-4, mode=1, **kw):
+    import oracle
+    gpu_arc, hdr, y = _gpu_round_trip(ctx, x, eb, mode, **kw)
+    okw = {k: v for k, v in kw.items()}
+    ref_arc = oracle.compress(x, eb, mode, **{"radius": okw.get("radius", 512),
+                                               "sub_size": okw.get("sub_size", 128),
+                                               "chunk_subs": okw.get("chunk_subs", 64)})
+    if not np.array_equal(gpu_arc, ref_arc):
+        pytest.fail("archive differs from the oracle\n" + _explain_mismatch(ctx, x, eb, mode, gpu_arc, ref_arc))
+    assert hdr == ref_arc[:128].tobytes()
+    ref_y = oracle.decompress(ref_arc)
+    assert y.shape == x.shape
+    assert np.array_equal(y.view(np.uint32), ref_y.view(np.uint32)), "decompressed floats differ from the oracle"
+    eb_abs = au.header(ref_arc)["eb_abs"]
+    xf, yf = x.astype(np.float64).ravel(), y.astype(np.float64).ravel()
+    fin = np.isfinite(xf)
+    assert np.all(np.abs(xf[fin] - yf[fin]) <= eb_abs)
+    return ref_arc
+
+
+SHAPES_3D = [(8, 8, 8), (9, 17, 70), (24, 40, 52), (1, 1, 77), (3, 70, 5), (16, 16, 520), (33, 65, 130)]
+SHAPES_2D = [(1, 3), (16, 16), (45, 70), (17, 300), (200, 600), (3, 4100)]
+SHAPES_1D = [(1,), (33,), (4096,), (4097,), (100003,), ((1 << 20) + 3,)]
+
+
+@pytest.mark.parametrize("shape", SHAPES_3D + SHAPES_2D + SHAPES_1D, ids=str)
+def test_parity_shapes(ctx, shape):
+    from synth import fields
+    if len(shape) == 3:
+        x = fields.hurricane3d(shape, seed=sum(shape))
+    elif len(shape) == 2:
+        x = fields.fourier2d(shape, seed=sum(shape))
+    else:
+        x = fields.particles1d(shape[0], seed=shape[0] % 97, shuffle_block=512)
+    _check(ctx, x)
+
+
+@pytest.mark.parametrize("eb,mode", [(1e-2, 1), (1e-3, 1), (1e-5, 1), (1e-3, 0), (0.25, 0)])
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+def test_parity_error_bounds(ctx, eb, mode, ndim):
+    from synth import fields
+    x = {1: lambda: fields.particles1d(50000, seed=5, shuffle_block=256),
+         2: lambda: fields.fourier2d((70, 90), seed=6),
+         3: lambda: fields.hurricane3d((20, 30, 40), seed=7)}[ndim]()
+    _check(ctx, x, eb, mode)
+
+
+@pytest.mark.parametrize("sub_size,chunk_subs", [(32, 1), (64, 4), (128, 64), (256, 128), (512, 2), (1024, 65536)])
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+def test_parity_table_geometry(ctx, sub_size, chunk_subs, ndim):
+    from synth import fields
+    x = {1: lambda: fields.particles1d(70001, seed=8, shuffle_block=128),
+         2: lambda: fields.fourier2d((100, 130), seed=9),
+         3: lambda: fields.hurricane3d((17, 45, 70), seed=10)}[ndim]()
+    _check(ctx, x, 1e-4, 1, sub_size=sub_size, chunk_subs=chunk_subs)
+
+
+@pytest.mark.parametrize("radius", [1, 2, 8, 64, 1024])
+def test_parity_radius(ctx, radius):
+    from synth import fields
+    x = fields.hurricane3d((16, 24, 40), seed=radius)
+    _check(ctx, x, 1e-4, 1, radius=radius)
+
+
+@pytest.mark.parametrize("case", ["constant", "specials", "all_outliers", "large_magnitude", "zeros", "tiny_eb"])
+def test_parity_degenerate(ctx, case):
+    rng = np.random.default_rng(3)
+    mode, eb = 1, 1e-4
+    if case == "constant":
+        x = np.full((10, 20, 30), -7.5, np.float32)
+    elif case == "specials":
+        x = rng.standard_normal((40, 50)).astype(np.float32)
+        x.ravel()[[0, 7, 100, 999, 1500]] = [np.nan, np.inf, -np.inf, -0.0, 1e-42]
+    elif case == "all_outliers":
+        x = (rng.standard_normal(20000) * 1e4).astype(np.float32)
+        mode, eb = 0, 1e-3
+    elif case == "large_magnitude":
+        base = np.float32(3000.0)
+        x = (base.view(np.uint32) + np.arange(1 << 16, dtype=np.uint32)).view(np.float32).reshape(64, 1024)
+        mode, eb = 0, 3.3e-4
+    elif case == "zeros":
+        x = np.zeros((5, 6, 7), np.float32)
+    elif case == "tiny_eb":
+        x = rng.standard_normal((30, 30, 30)).astype(np.float32)
+        eb = 1e-7
+    _check(ctx, x, eb, mode)
+
+
+def test_parity_empty_field(ctx):
+    import torch
+    import oracle
+    x = np.zeros((0,), np.float32)
+    t = torch.zeros((0,), dtype=torch.float32, device="cuda:0")
+    comp = ctx.compress(t, 1e-4)
+    assert np.array_equal(comp.archive.cpu().numpy(), oracle.compress(x, 1e-4))
+    y = ctx.decompress(comp)
+    assert y.numel() == 0
+
+
+def test_archive_deterministic_and_reusable_context(ctx):
+    import torch
+    from synth import fields
+    x = torch.from_numpy(fields.hurricane3d((30, 64, 64), seed=1)).cuda()
+    a = ctx.compress(x, 1e-4).archive.cpu().numpy()
+    small = torch.from_numpy(fields.fourier2d((20, 20), seed=2)).cuda()
+    ctx.compress(small, 1e-3)
+    b = ctx.compress(x, 1e-4).archive.cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+def test_gpu_decodes_oracle_archive_and_rejects_damage(ctx):
+    """The decoder accepts the oracle's archive and reports damaged tables."""
+    import torch
+    import oracle
+    from paper_2007_09625_amd import dqz
+    from synth import fields
+    x = fields.hurricane3d((20, 30, 40), seed=4)
+    arc = oracle.compress(x, 1e-4)
+    y = ctx.decompress(torch.from_numpy(arc).cuda())
+    assert np.array_equal(y.cpu().numpy().view(np.uint32), oracle.decompress(arc).view(np.uint32))
+    bad = arc.copy()
+    bad[au.sections(arc)["offsets"]["sub"]] ^= 1      # subchunk table disagrees with the stream
+    with pytest.raises(dqz.DqzError) as e:
+        ctx.decompress(torch.from_numpy(bad).cuda())
+    assert e.value.status == dqz.DQZ_ECORRUPT
+    bad = arc.copy()
+    bad[au.sections(arc)["offsets"]["len"] + 512] ^= 3   # lengths no longer a complete prefix code
+    with pytest.raises(dqz.DqzError) as e:
+        ctx.decompress(torch.from_numpy(bad).cuda())
+    assert e.value.status == dqz.DQZ_ECORRUPT
+
+
+def test_capacity_too_small(ctx):
+    import torch
+    from paper_2007_09625_amd import dqz
+    from synth import fields
+    x = torch.from_numpy(fields.hurricane3d((16, 32, 32), seed=5)).cuda()
+    good = ctx.compress(x, 1e-4)
+    out = torch.empty(good.nbytes - 1, dtype=torch.uint8, device="cuda:0")
+    st, need, _ = ctx.dqz_compress(x.data_ptr(), tuple(x.shape), dqz.make_params(1e-4), out.data_ptr(), out.numel())
+    assert st == dqz.DQZ_ETOOSMALL and need == good.nbytes
+    st, need, _ = ctx.dqz_compress(x.data_ptr(), tuple(x.shape), dqz.make_params(1e-4), out.data_ptr(), 100)
+    assert st == dqz.DQZ_ETOOSMALL
+
+
+@pytest.mark.parametrize("name,eb", [("c1", 1e-4), ("c2", 1e-4), ("c2", 1e-3)])
+def test_parity_full_size_workloads(ctx, name, eb):
+    """The 2D 1800x3600 and 3D 100x500x500 workloads at full size, in the
+    launch configuration the benchmark times."""
+    from synth import fields
+    x = fields.workload(name)
+    arc = _check(ctx, x, eb, 1)
+    h = au.header(arc)
+    print(f"{name} eb={eb}: {x.nbytes / arc.size:.2f}x, {8 * arc.size / x.size:.3f} bits/elem, "
+          f"outliers {h['n_out']}, patches {h['n_patch']}, max_len {h['max_len']}")
