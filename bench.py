@@ -55,6 +55,9 @@ def main() -> int:
     ap.add_argument("--eb", type=float, default=1e-4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stage-timing", action="store_true", help="time without per-stage HIP events")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="K",
+                    help="after the timed steps, run K plain device copies of the field (4N bytes read, 4N "
+                         "written) so hardware byte counters can be scaled against a copy of known size")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -117,6 +120,10 @@ def main() -> int:
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ctx.dqz_ctx_set_timing(False)
+
+    for _ in range(args.copy_calibration):
+        y.copy_(x)
+    torch.cuda.synchronize()
 
     sec_per_step = (t1 - t0) / args.steps
     orig = 4.0 * n

@@ -68,6 +68,7 @@ typedef int32_t dqz_status;
 #define DQZ_ECORRUPT (-4)     /* archive fails validation */
 #define DQZ_EUNSUPPORTED (-5) /* valid request outside this build's limits */
 #define DQZ_EHIP (-6)         /* a HIP runtime call failed (message in dqz_ctx_last_error) */
+#define DQZ_EINTERNAL (-7)    /* a device-side ordering wait timed out (kernels exited; retry) */
 
 #define DQZ_EB_ABS 0     /* eb is the absolute bound */
 #define DQZ_EB_VALREL 1  /* eb is relative to (max - min) of the finite values */
@@ -151,10 +152,13 @@ dqz_status dqz_stage_times(dqz_ctx *ctx, int which, double *us, int *n_stages);
  *   DQZ_DBG_CODES      u16 per padded position (0xFFFF outside the field)
  *   DQZ_DBG_HISTOGRAM  u32[2R]
  *   DQZ_DBG_CODEBOOK   u64[2R], (length << 56) | canonical code
+ *   DQZ_DBG_PHASES     u64[24], phase timestamps of the one-workgroup kernels
  * `bytes` must equal the buffer's size. */
 #define DQZ_DBG_CODES 1
 #define DQZ_DBG_HISTOGRAM 2
 #define DQZ_DBG_CODEBOOK 3
+#define DQZ_DBG_PHASES 4     /* u64[24]: wall-clock (100 MHz) marks inside the codebook
+                                kernel [0..15] and the decoding-table kernel [16..23] */
 dqz_status dqz_debug_copy(dqz_ctx *ctx, int what, void *h_dst, uint64_t bytes);
 
 #ifdef __cplusplus

@@ -32,6 +32,8 @@ struct dqz_ctx {
     uint64_t *last_book = nullptr;
     uint64_t last_padded = 0;
     uint32_t last_nsym = 0;
+    Ctl *last_ctl = nullptr;
+    DecodeTables *last_tab = nullptr;
     // per-stage timing
     bool timing = false;
     hipEvent_t ev[2][DQZ_MAX_STAGES + 1] = {};
@@ -130,7 +132,7 @@ void fill_params(const dqz_params *p, uint32_t &radius, uint32_t &sub, uint32_t 
 
 // device scratch layout
 struct WsLayout {
-    uint64_t ctl, hist, lbq, lbe, zero_end, book, codes, tab, total;
+    uint64_t ctl, hist, lbq, lbe, zero_end, book, book32, parts, codes, tab, total;
 };
 
 // control block and decoding tables at fixed offsets, then the compression
@@ -141,11 +143,13 @@ WsLayout ws_layout(const Plan &P, bool compress) {
     w.ctl = 0;
     w.tab = align_up(sizeof(Ctl), 256);
     w.hist = align_up(w.tab + sizeof(DecodeTables), 256);
-    w.lbq = align_up(w.hist + 4ull * P.L.nsym, 256);
+    w.lbq = align_up(w.hist + 4ull * kHistReplicas * P.L.nsym, 256);
     w.lbe = align_up(w.lbq + 8ull * P.tiles_q, 256);
     w.zero_end = align_up(w.lbe + 8ull * P.tiles_e, 256);
     w.book = w.zero_end;
-    w.codes = align_up(w.book + 8ull * P.L.nsym, 256);
+    w.book32 = align_up(w.book + 8ull * P.L.nsym, 256);
+    w.parts = align_up(w.book32 + 4ull * P.L.nsym, 256);
+    w.codes = align_up(w.parts + 8ull * kMinmaxMaxBlocks, 256);
     w.total = compress ? align_up(w.codes + 2ull * P.g.padded, 256) : w.hist;
     return w;
 }
@@ -176,6 +180,7 @@ void mark(dqz_ctx *ctx, int which, int i, hipStream_t s) {
 }
 
 dqz_status status_from_device(dqz_ctx *ctx, uint32_t st) {
+    if (st & ST_EINTERNAL) return fail(ctx, DQZ_EINTERNAL, "a device-side ordering wait timed out");
     if (st & ST_EINVAL) return fail(ctx, DQZ_EINVAL, "error bound out of range for this field");
     if (st & ST_EUNSUPPORTED) return fail(ctx, DQZ_EUNSUPPORTED, "code length above 64 bits");
     if (st & ST_ECORRUPT) return fail(ctx, DQZ_ECORRUPT, "archive failed validation");
@@ -264,6 +269,7 @@ const char *dqz_status_str(dqz_status s) {
         case DQZ_ECORRUPT: return "corrupt archive";
         case DQZ_EUNSUPPORTED: return "unsupported";
         case DQZ_EHIP: return "HIP runtime error";
+        case DQZ_EINTERNAL: return "internal device error";
         default: return "unknown status";
     }
 }
@@ -364,6 +370,8 @@ dqz_status dqz_compress(dqz_ctx *ctx, const float *d_field, const dqz_shape *sha
     uint64_t *lbq = reinterpret_cast<uint64_t *>(ws + W.lbq);
     uint64_t *lbe = reinterpret_cast<uint64_t *>(ws + W.lbe);
     uint64_t *book = reinterpret_cast<uint64_t *>(ws + W.book);
+    uint32_t *book32 = reinterpret_cast<uint32_t *>(ws + W.book32);
+    uint32_t *parts = reinterpret_cast<uint32_t *>(ws + W.parts);
     uint16_t *codes = reinterpret_cast<uint16_t *>(ws + W.codes);
     uint8_t *arc = reinterpret_cast<uint8_t *>(d_archive);
 
@@ -371,15 +379,15 @@ dqz_status dqz_compress(dqz_ctx *ctx, const float *d_field, const dqz_shape *sha
     mark(ctx, 0, 0, s);
     launch_init(s, ctl, ws + W.hist, W.zero_end - W.hist, params->eb_mode, params->eb);
     mark(ctx, 0, 1, s);
-    if (params->eb_mode == DQZ_EB_VALREL) launch_minmax(s, d_field, P.g.nelem, ctl, params->eb, ctx->ncu);
+    if (params->eb_mode == DQZ_EB_VALREL) launch_minmax(s, d_field, P.g.nelem, ctl, parts, params->eb, ctx->ncu);
     mark(ctx, 0, 2, s);
     launch_quantize(s, d_field, P.g, P.L, ctl, codes, hist, lbq, arc);
     mark(ctx, 0, 3, s);
-    launch_codebook(s, P.g, P.L, ctl, hist, book, arc, params->eb_mode, params->eb);
+    launch_codebook(s, P.g, P.L, ctl, hist, book, book32, arc, params->eb_mode, params->eb);
     mark(ctx, 0, 4, s);
     launch_zero_stream(s, P.g, ctl, arc);
     mark(ctx, 0, 5, s);
-    launch_encode(s, P.g, P.L, ctl, codes, book, lbe, arc);
+    launch_encode(s, P.g, P.L, ctl, codes, book, book32, lbe, arc);
     mark(ctx, 0, 6, s);
     HIP_TRY(ctx, hipGetLastError());
     HIP_TRY(ctx, hipMemcpyAsync(ctx->h_ctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
@@ -388,6 +396,8 @@ dqz_status dqz_compress(dqz_ctx *ctx, const float *d_field, const dqz_shape *sha
     ctx->last_codes = codes;
     ctx->last_hist = hist;
     ctx->last_book = book;
+    ctx->last_ctl = ctl;
+    ctx->last_tab = reinterpret_cast<DecodeTables *>(ws + W.tab);
     ctx->last_padded = P.g.padded;
     ctx->last_nsym = P.L.nsym;
     const Ctl &c = *ctx->h_ctl;
@@ -487,8 +497,33 @@ dqz_status dqz_debug_copy(dqz_ctx *ctx, int what, void *h_dst, uint64_t bytes) {
     uint64_t need = 0;
     switch (what) {
         case DQZ_DBG_CODES: src = ctx->last_codes; need = 2 * ctx->last_padded; break;
-        case DQZ_DBG_HISTOGRAM: src = ctx->last_hist; need = 4ull * ctx->last_nsym; break;
+        case DQZ_DBG_HISTOGRAM: {
+            // the kernels keep kHistReplicas partial copies; return their sum
+            if (!ctx->last_hist) return fail(ctx, DQZ_EINVAL, "no compression has run on this context");
+            need = 4ull * ctx->last_nsym;
+            if (bytes != need) return fail(ctx, DQZ_EINVAL, "size mismatch");
+            std::string buf(4ull * kHistReplicas * ctx->last_nsym, '\0');
+            HIP_TRY(ctx, hipSetDevice(ctx->device));
+            HIP_TRY(ctx, hipMemcpy(&buf[0], ctx->last_hist, buf.size(), hipMemcpyDeviceToHost));
+            const uint32_t *parts = reinterpret_cast<const uint32_t *>(buf.data());
+            uint32_t *dst = reinterpret_cast<uint32_t *>(h_dst);
+            for (uint32_t i = 0; i < ctx->last_nsym; i++) {
+                uint32_t v = 0;
+                for (uint32_t r = 0; r < kHistReplicas; r++) v += parts[r * ctx->last_nsym + i];
+                dst[i] = v;
+            }
+            return DQZ_OK;
+        }
         case DQZ_DBG_CODEBOOK: src = ctx->last_book; need = 8ull * ctx->last_nsym; break;
+        case DQZ_DBG_PHASES: {
+            if (!ctx->last_ctl) return fail(ctx, DQZ_EINVAL, "no compression has run on this context");
+            if (bytes != 8 * 24) return fail(ctx, DQZ_EINVAL, "size mismatch");
+            HIP_TRY(ctx, hipSetDevice(ctx->device));
+            uint64_t *dst = reinterpret_cast<uint64_t *>(h_dst);
+            HIP_TRY(ctx, hipMemcpy(dst, ctx->last_ctl->phase, 8 * 16, hipMemcpyDeviceToHost));
+            HIP_TRY(ctx, hipMemcpy(dst + 16, ctx->last_tab->phase, 8 * 8, hipMemcpyDeviceToHost));
+            return DQZ_OK;
+        }
         default: return fail(ctx, DQZ_EINVAL, "unknown stage");
     }
     if (!src) return fail(ctx, DQZ_EINVAL, "no compression has run on this context");

@@ -11,7 +11,9 @@ constexpr uint32_t kHeaderBytes = 128;
 constexpr uint32_t kMagic = 0x315A5144u;   // bytes 'D' 'Q' 'Z' '1'
 constexpr uint32_t kVersion = 1;
 constexpr uint32_t kTile = 4096;           // padded positions per quantize / encode tile
-constexpr uint32_t kLutBits = 12;          // first-level decode table width
+constexpr uint32_t kLutBits = 13;          // decode table width (u16 entries: len << 11 | sym)
+constexpr uint32_t kHistReplicas = 16;     // global histogram copies (spreads the flush atomics)
+constexpr uint32_t kSpinLimit = 1u << 20;  // look-back polls before a wait is declared stuck
 constexpr uint32_t kMaxRadius = 1024;      // codebook kernel keeps 2R <= 2048 symbols in LDS
 constexpr uint32_t kMaxSyms = 2 * kMaxRadius;
 constexpr uint16_t kNoSymbol = 0xFFFF;     // code slot of a padded position outside the field
@@ -23,6 +25,7 @@ enum : uint32_t {
     ST_ETOOSMALL = 2u,     // archive capacity exceeded
     ST_EUNSUPPORTED = 4u,  // code longer than 64 bits
     ST_ECORRUPT = 8u,      // archive fails validation during decode
+    ST_EINTERNAL = 16u,    // a look-back wait exceeded its poll limit (kernel exits anyway)
 };
 
 // Geometry: every field is viewed as (nz, ny, nx) with block extents
@@ -64,17 +67,22 @@ struct Ctl {
     uint64_t n_words;
     // copy of the header as written (for the host readback)
     uint8_t header[kHeaderBytes];
+    // phase timestamps (wall clock, 100 MHz) of the one-workgroup kernels
+    uint64_t phase[16];
 };
 
 // Decoder tables built from the archive's code lengths.
 struct DecodeTables {
-    uint32_t lut[1u << kLutBits];   // (len << 16) | sym; len == 0: longer code
+    uint16_t lut[1u << kLutBits];   // (len << 11) | sym for codes of <= kLutBits bits;
+                                    // (min_len << 11) | 0x8000 for a prefix of longer codes
+    uint64_t limit[65];             // left-aligned end of the codes of length <= l
     uint64_t first_code[65];        // canonical first code of each length
     uint32_t count[65];             // codes of each length
     uint32_t first_index[65];       // index of the first such code in `sorted`
     uint16_t sorted[kMaxSyms];      // symbols in canonical order
     uint32_t max_len;
     uint32_t status;
+    uint64_t phase[8];
 };
 
 // ---------------------------------------------------------------------------
@@ -133,11 +141,19 @@ __device__ __forceinline__ void lb_publish(uint64_t *st, uint32_t tile, uint64_t
 
 // Called by all 64 lanes of one wave; returns the sum of the values of all
 // tiles before `tile`.
-__device__ inline uint64_t lb_exclusive(const uint64_t *st, uint32_t tile) {
+// Tiles are numbered by workgroup index; workgroups are dispatched in
+// index order, so every tile a wait depends on has started.  The poll count
+// is bounded anyway: a stuck wait sets ST_EINTERNAL in *err and returns.
+__device__ inline uint64_t lb_exclusive(const uint64_t *st, uint32_t tile, uint32_t *err) {
     const uint32_t lane = lane_id();
     uint64_t excl = 0;
     int64_t base = (int64_t)tile - 1;
+    uint32_t polls = 0;
     while (base >= 0) {
+        if (++polls > kSpinLimit) {
+            if (lane == 0) atomicOr(err, ST_EINTERNAL);
+            return excl;
+        }
         const int64_t j = base - (int64_t)lane;
         uint64_t s = 2;   // virtual predecessor before tile 0: inclusive, value 0
         if (j >= 0) s = __hip_atomic_load(st + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -175,15 +191,16 @@ __device__ __forceinline__ bool needs_patch(float v, int32_t d, float h, double 
 // Launchers (defined in the kernel translation units).
 // ---------------------------------------------------------------------------
 void launch_init(hipStream_t s, Ctl *ctl, void *zero_base, uint64_t zero_bytes, int eb_mode, double eb);
-void launch_minmax(hipStream_t s, const float *x, uint64_t n, Ctl *ctl, double valrel, int ncu);
+void launch_minmax(hipStream_t s, const float *x, uint64_t n, Ctl *ctl, uint32_t *partials, double valrel, int ncu);
+constexpr uint32_t kMinmaxMaxBlocks = 2048;
 void launch_quantize(hipStream_t s, const float *x, const Geom &g, const Layout &L, Ctl *ctl, uint16_t *codes,
                      uint32_t *hist, uint64_t *lb, uint8_t *archive);
 uint32_t quantize_tiles(const Geom &g);
 void launch_codebook(hipStream_t s, const Geom &g, const Layout &L, Ctl *ctl, const uint32_t *hist,
-                     uint64_t *book, uint8_t *archive, int eb_mode, double eb_param);
+                     uint64_t *book, uint32_t *book32, uint8_t *archive, int eb_mode, double eb_param);
 void launch_zero_stream(hipStream_t s, const Geom &g, Ctl *ctl, uint8_t *archive);
 void launch_encode(hipStream_t s, const Geom &g, const Layout &L, Ctl *ctl, const uint16_t *codes,
-                   const uint64_t *book, uint64_t *lb, uint8_t *archive);
+                   const uint64_t *book, const uint32_t *book32, uint64_t *lb, uint8_t *archive);
 uint32_t encode_tiles(const Geom &g);
 void launch_decode_tables(hipStream_t s, const Layout &L, const uint8_t *archive, uint32_t max_len_hdr,
                           DecodeTables *tab);

@@ -33,59 +33,105 @@ struct DecArgs {
     uint32_t qstride;   // LDS code-buffer stride per subchunk (sub_size + 2: spreads lanes over banks)
 };
 
+// Per-lane bit reader: `cur` holds the next 64 stream bits MSB-first
+// (`avail` of them valid).  Stream words arrive through a queue of three
+// prefetched 8-byte word pairs (q0 is being consumed, `qpos` = next word of
+// q0), so each load is issued about 24 symbols before its bits are needed.
 struct BitReader {
     uint64_t cur;
+    uint64_t bp;       // stream position of the top bit of `cur`
+    uint64_t q0, q1, q2;
+    uint64_t pidx;     // next pair to load
+    uint32_t qpos;
     int32_t avail;
-    uint64_t widx;
-    uint64_t bp;
 };
 
 __device__ __forceinline__ uint32_t ld_word(const DecArgs &a, uint64_t i) {
     return i < a.n_words ? a.words[i] : 0u;
 }
 
+__device__ __forceinline__ uint64_t ld_pair(const DecArgs &a, uint64_t p) {
+    const uint64_t w = 2 * p;
+    if (w + 1 < a.n_words) return reinterpret_cast<const uint64_t *>(a.words)[p];
+    return (uint64_t)ld_word(a, w) | ((uint64_t)ld_word(a, w + 1) << 32);
+}
+
 __device__ __forceinline__ void br_init(const DecArgs &a, BitReader &br, uint64_t start) {
     const uint64_t w = start >> 5;
     const uint32_t o = (uint32_t)(start & 31u);
-    br.cur = (((uint64_t)ld_word(a, w) << 32) | ld_word(a, w + 1)) << o;
+    const uint64_t p = w >> 1;
+    const uint64_t P0 = ld_pair(a, p), P1 = ld_pair(a, p + 1), P2 = ld_pair(a, p + 2), P3 = ld_pair(a, p + 3);
+    uint32_t w0, w1;
+    if (w & 1u) { w0 = (uint32_t)(P0 >> 32); w1 = (uint32_t)P1; br.qpos = 1; }
+    else { w0 = (uint32_t)P0; w1 = (uint32_t)(P0 >> 32); br.qpos = 0; }
+    br.cur = (((uint64_t)w0 << 32) | w1) << o;
     br.avail = 64 - (int32_t)o;
-    br.widx = w + 2;
+    br.q0 = P1;
+    br.q1 = P2;
+    br.q2 = P3;
+    br.pidx = p + 4;
     br.bp = start;
 }
 
-__device__ __forceinline__ uint32_t decode_one(const DecArgs &a, BitReader &br, const uint32_t *lut, uint32_t max_len,
-                                               bool &bad) {
+__device__ __forceinline__ void br_refill(const DecArgs &a, BitReader &br) {
     if (br.avail <= 32) {
-        br.cur |= (uint64_t)ld_word(a, br.widx++) << (32 - br.avail);
+        const uint32_t w = br.qpos ? (uint32_t)(br.q0 >> 32) : (uint32_t)br.q0;
+        br.cur |= (uint64_t)w << (32 - br.avail);
         br.avail += 32;
+        if (br.qpos) {
+            br.q0 = br.q1;
+            br.q1 = br.q2;
+            br.q2 = ld_pair(a, br.pidx++);
+            br.qpos = 0;
+        } else {
+            br.qpos = 1;
+        }
     }
+}
+
+// LDS copy of the decoding tables
+struct DecLds {
+    uint64_t limit[65];
+    uint64_t first_code[65];
+    uint32_t first_index[65];
+};
+
+__device__ __forceinline__ uint32_t decode_one(const DecArgs &a, BitReader &br, const uint16_t *lut,
+                                               const DecLds &t, const uint16_t *sorted, uint32_t max_len,
+                                               bool &bad) {
+    br_refill(a, br);
     const uint32_t e = lut[(uint32_t)(br.cur >> (64 - kLutBits))];
-    if (e) {
-        const uint32_t len = e >> 16;
-        br.cur <<= len;
-        br.avail -= (int32_t)len;
-        br.bp += len;
-        return e & 0xFFFFu;
-    }
-    // longer code: canonical first-code rule on a fresh 64-bit window
-    const uint64_t w = br.bp >> 5;
-    const uint32_t o = (uint32_t)(br.bp & 31u);
-    const uint64_t hi = ((uint64_t)ld_word(a, w) << 32) | ld_word(a, w + 1);
-    const uint64_t win = o ? ((hi << o) | (ld_word(a, w + 2) >> (32 - o))) : hi;
-    for (uint32_t l = kLutBits + 1; l <= max_len; l++) {
+    uint32_t len, sym;
+    if (!(e & 0x8000u)) {
+        len = e >> 11;
+        sym = e & 0x7FFu;
+        if (len == 0) { bad = true; len = 1; }
+    } else {
+        // a longer code: canonical limits from the shortest possible length
+        // (codes over 32 bits need a full 64-bit window from memory)
+        uint32_t l = e & 63u;
+        uint64_t win = br.cur;
+        if (max_len > 32) {
+            const uint64_t w = br.bp >> 5;
+            const uint32_t o = (uint32_t)(br.bp & 31u);
+            const uint64_t hi = ((uint64_t)ld_word(a, w) << 32) | ld_word(a, w + 1);
+            win = o ? ((hi << o) | (ld_word(a, w + 2) >> (32 - o))) : hi;
+        }
+        while (l < max_len && win >= t.limit[l]) l++;
         const uint64_t c = win >> (64 - l);
-        const uint64_t d = c - a.tab->first_code[l];
-        if (c >= a.tab->first_code[l] && d < a.tab->count[l]) {
-            const uint32_t idx = a.tab->first_index[l] + (uint32_t)d;
-            if (idx >= kMaxSyms) break;
-            const uint32_t sym = a.tab->sorted[idx];
+        const uint64_t idx = t.first_index[l] + (c - t.first_code[l]);
+        if (idx >= a.L.nsym) { bad = true; sym = a.L.radius; }
+        else sym = sorted[idx];
+        if ((int32_t)l > br.avail) {   // only possible for codes over 32 bits
             br_init(a, br, br.bp + l);
             return sym;
         }
+        len = l;
     }
-    bad = true;
-    br_init(a, br, br.bp + 1);
-    return a.L.radius;
+    br.cur <<= len;
+    br.avail -= (int32_t)len;
+    br.bp += len;
+    return sym;
 }
 
 // Is padded position p inside the field?
@@ -128,10 +174,22 @@ __device__ __forceinline__ uint32_t lower_bound_key(const uint2 *exc, uint32_t n
 
 __global__ __launch_bounds__(64 * kDecMaxWaves) void k_decode(DecArgs a) {
     extern __shared__ uint32_t s_dyn[];
-    uint32_t *s_lut = s_dyn;                                            // 1 << kLutBits
-    uint16_t *s_q = reinterpret_cast<uint16_t *>(s_dyn + (1u << kLutBits));
+    __shared__ DecLds s_t;
+    uint16_t *s_lut = reinterpret_cast<uint16_t *>(s_dyn);                       // 1 << kLutBits
+    uint16_t *s_sorted = s_lut + (1u << kLutBits);                               // nsym
+    uint16_t *s_q = s_sorted + a.L.nsym;                                         // waves * 64 * qstride
     if (a.tab->status) return;   // the code lengths failed validation: tables are not usable
-    for (uint32_t i = threadIdx.x; i < (1u << kLutBits); i += blockDim.x) s_lut[i] = a.tab->lut[i];
+    {
+        const uint32_t *src = reinterpret_cast<const uint32_t *>(a.tab->lut);
+        uint32_t *dst = reinterpret_cast<uint32_t *>(s_lut);
+        for (uint32_t i = threadIdx.x; i < (1u << kLutBits) / 2; i += blockDim.x) dst[i] = src[i];
+        for (uint32_t i = threadIdx.x; i < a.L.nsym; i += blockDim.x) s_sorted[i] = a.tab->sorted[i];
+        for (uint32_t i = threadIdx.x; i < 65; i += blockDim.x) {
+            s_t.limit[i] = a.tab->limit[i];
+            s_t.first_code[i] = a.tab->first_code[i];
+            s_t.first_index[i] = a.tab->first_index[i];
+        }
+    }
     __syncthreads();
 
     const uint32_t lane = lane_id(), w = threadIdx.x / 64;
@@ -186,10 +244,12 @@ __global__ __launch_bounds__(64 * kDecMaxWaves) void k_decode(DecArgs a) {
             const uint32_t max_len = a.tab->max_len < 63u ? a.tab->max_len : 63u;
             const uint32_t cnt = (uint32_t)(pb - pa);
             if (full) {
-                for (uint32_t i = 0; i < cnt; i++) myq[i] = (uint16_t)decode_one(a, br, s_lut, max_len, bad);
+                for (uint32_t i = 0; i < cnt; i++)
+                    myq[i] = (uint16_t)decode_one(a, br, s_lut, s_t, s_sorted, max_len, bad);
             } else {
                 for (uint32_t i = 0; i < cnt; i++)
-                    myq[i] = pos_real(a.g, pa + i) ? (uint16_t)decode_one(a, br, s_lut, max_len, bad) : (uint16_t)a.L.radius;
+                    myq[i] = pos_real(a.g, pa + i) ? (uint16_t)decode_one(a, br, s_lut, s_t, s_sorted, max_len, bad)
+                                                   : (uint16_t)a.L.radius;
             }
             if (br.bp - start != bits_s) bad = true;
         }
@@ -301,7 +361,7 @@ __global__ __launch_bounds__(64 * kDecMaxWaves) void k_decode(DecArgs a) {
 static uint32_t decode_waves(const Layout &L) { return L.sub_size <= 256 ? kDecMaxWaves : 1u; }
 
 size_t decode_lds_bytes(const Layout &L) {
-    return sizeof(uint32_t) * (1u << kLutBits) + sizeof(uint16_t) * decode_waves(L) * 64 * (L.sub_size + 2);
+    return sizeof(uint16_t) * ((1u << kLutBits) + L.nsym + (size_t)decode_waves(L) * 64 * (L.sub_size + 2));
 }
 
 void launch_decode(hipStream_t s, const Geom &g, const Layout &L, const uint8_t *archive, uint64_t off_str,

@@ -2,9 +2,11 @@
 //
 // The paper encodes each symbol to a fixed-length (code, width) word in one
 // fine-grained pass and then concatenates the words chunk by chunk with one
-// thread per chunk.  Here both steps are one pass: each workgroup takes a
-// tile of kTile padded positions (by dynamic ticket), looks the codes up in
-// an LDS copy of the codebook, scans the code widths across the workgroup,
+// thread per chunk.  Here both steps are one pass: each workgroup handles a
+// tile of kTile padded positions (tile index = workgroup index), looks the
+// codes up in an LDS copy of the codebook (32-bit codewords when every code
+// fits in 24 bits, the paper's adaptive representation, else 64-bit), scans
+// the code widths across the workgroup,
 // obtains the tile's global bit offset by decoupled look-back, and packs the
 // codewords into an LDS word buffer that is then written out as one
 // contiguous run of stream words.  Words shared with the neighbouring tiles
@@ -30,9 +32,22 @@ struct EncArgs {
     Ctl *ctl;
     const uint16_t *codes;
     const uint64_t *book;
+    const uint32_t *book32;
     uint64_t *lb;
     uint8_t *archive;
     uint32_t n_tiles;
+};
+
+template <bool WIDE> struct Codeword;
+template <> struct Codeword<false> {
+    typedef uint32_t T;
+    static __device__ __forceinline__ uint32_t len(uint32_t e) { return e >> 24; }
+    static __device__ __forceinline__ uint64_t code(uint32_t e) { return e & 0xFFFFFFu; }
+};
+template <> struct Codeword<true> {
+    typedef uint64_t T;
+    static __device__ __forceinline__ uint32_t len(uint64_t e) { return (uint32_t)(e >> 56); }
+    static __device__ __forceinline__ uint64_t code(uint64_t e) { return e & 0x00FFFFFFFFFFFFFFull; }
 };
 
 constexpr uint32_t kEncPer = kTile / 256;              // positions per thread
@@ -50,23 +65,41 @@ __device__ __forceinline__ void or_bits(uint32_t *buf, uint32_t bit, uint64_t co
     }
 }
 
-__global__ __launch_bounds__(256) void k_encode(EncArgs a) {
-    extern __shared__ uint64_t s_dyn[];
-    uint64_t *s_book = s_dyn;                                           // nsym
-    uint32_t *s_words = reinterpret_cast<uint32_t *>(s_dyn + a.L.nsym);  // kEncWords
-    __shared__ uint32_t s_sub[kTile / 32];
-    __shared__ uint32_t s_wave[4];
-    __shared__ uint32_t s_ticket;
-    __shared__ unsigned long long s_G;
+struct EncLds {
+    uint32_t sub[kTile / 32];
+    uint32_t wave[4];
+    unsigned long long G;
+};
 
+template <bool WIDE>
+__device__ __forceinline__ void encode_tile(const EncArgs &a, uint64_t *s_dyn, EncLds &sh) {
+    typedef Codeword<WIDE> CW;
+    typedef typename CW::T Entry;
+    uint32_t *s_words = reinterpret_cast<uint32_t *>(s_dyn);                // kEncWords
+    Entry *s_book = reinterpret_cast<Entry *>(s_dyn + (kEncWords + 1) / 2);
+    uint32_t *s_sub = sh.sub;
+    uint32_t *s_wave = sh.wave;
+    unsigned long long &s_G = sh.G;
     Ctl *ctl = a.ctl;
-    if (ctl->status & (ST_EINVAL | ST_ETOOSMALL | ST_EUNSUPPORTED)) return;
     const uint32_t tid = threadIdx.x, lane = lane_id(), w = tid / 64;
-    for (uint32_t i = tid; i < a.L.nsym; i += 256) s_book[i] = a.book[i];
+    const Entry *gbook = WIDE ? reinterpret_cast<const Entry *>(a.book) : reinterpret_cast<const Entry *>(a.book32);
+    {
+        // codebook into LDS: up to kMaxSyms / 256 loads per thread, all in flight
+        Entry e[kMaxSyms / 256];
+#pragma unroll
+        for (uint32_t k = 0; k < kMaxSyms / 256; k++) {
+            const uint32_t i = tid + 256 * k;
+            if (i < a.L.nsym) e[k] = gbook[i];
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < kMaxSyms / 256; k++) {
+            const uint32_t i = tid + 256 * k;
+            if (i < a.L.nsym) s_book[i] = e[k];
+        }
+    }
     for (uint32_t i = tid; i < kTile / 32; i += 256) s_sub[i] = 0;
-    if (tid == 0) s_ticket = atomicAdd(&ctl->ticket_e, 1u);
     __syncthreads();
-    const uint32_t tile = s_ticket;
+    const uint32_t tile = blockIdx.x;
     const uint64_t p0 = (uint64_t)tile * kTile;
     const uint64_t my0 = p0 + (uint64_t)kEncPer * tid;
     const uint32_t padded = a.g.padded;
@@ -88,7 +121,7 @@ __global__ __launch_bounds__(256) void k_encode(EncArgs a) {
     uint32_t my_bits = 0;
 #pragma unroll
     for (uint32_t i = 0; i < kEncPer; i++)
-        if (q[i] != kNoSymbol) my_bits += (uint32_t)(s_book[q[i]] >> 56);
+        if (q[i] != kNoSymbol) my_bits += CW::len(s_book[q[i]]);
 
     // workgroup exclusive scan of bit counts
     const uint32_t incl = wave_incl_scan<uint32_t>(my_bits);
@@ -108,7 +141,7 @@ __global__ __launch_bounds__(256) void k_encode(EncArgs a) {
             if (lane == 0) lb_publish(a.lb, 0, tile_bits, 2);
         } else {
             if (lane == 0) lb_publish(a.lb, tile, tile_bits, 1);
-            G = lb_exclusive(a.lb, tile);
+            G = lb_exclusive(a.lb, tile, &ctl->status);
             if (lane == 0) lb_publish(a.lb, tile, G + tile_bits, 2);
         }
         if (lane == 0) s_G = G;
@@ -142,9 +175,9 @@ __global__ __launch_bounds__(256) void k_encode(EncArgs a) {
 #pragma unroll
     for (uint32_t i = 0; i < kEncPer; i++) {
         if (q[i] == kNoSymbol) continue;
-        const uint64_t e = s_book[q[i]];
-        const uint32_t len = (uint32_t)(e >> 56);
-        or_bits(s_words, bit, e & 0x00FFFFFFFFFFFFFFull, len);
+        const Entry e = s_book[q[i]];
+        const uint32_t len = CW::len(e);
+        or_bits(s_words, bit, CW::code(e), len);
         bit += len;
     }
     __syncthreads();
@@ -164,6 +197,14 @@ __global__ __launch_bounds__(256) void k_encode(EncArgs a) {
     }
 }
 
+__global__ __launch_bounds__(256) void k_encode(EncArgs a) {
+    extern __shared__ uint64_t s_dyn[];
+    __shared__ EncLds sh;
+    if (a.ctl->status & (ST_EINVAL | ST_ETOOSMALL | ST_EUNSUPPORTED | ST_EINTERNAL)) return;
+    if (a.ctl->max_len <= 24) encode_tile<false>(a, s_dyn, sh);
+    else encode_tile<true>(a, s_dyn, sh);
+}
+
 void launch_zero_stream(hipStream_t s, const Geom &g, Ctl *ctl, uint8_t *archive) {
     if (g.nelem == 0) return;
     hipLaunchKernelGGL(k_zero_stream, dim3(512), dim3(256), 0, s, ctl, archive);
@@ -172,18 +213,19 @@ void launch_zero_stream(hipStream_t s, const Geom &g, Ctl *ctl, uint8_t *archive
 uint32_t encode_tiles(const Geom &g) { return (uint32_t)((g.padded + kTile - 1) / kTile); }
 
 void launch_encode(hipStream_t s, const Geom &g, const Layout &L, Ctl *ctl, const uint16_t *codes,
-                   const uint64_t *book, uint64_t *lb, uint8_t *archive) {
+                   const uint64_t *book, const uint32_t *book32, uint64_t *lb, uint8_t *archive) {
     EncArgs a;
     a.g = g;
     a.L = L;
     a.ctl = ctl;
     a.codes = codes;
     a.book = book;
+    a.book32 = book32;
     a.lb = lb;
     a.archive = archive;
     a.n_tiles = encode_tiles(g);
     if (a.n_tiles == 0) return;
-    const size_t lds = sizeof(uint64_t) * L.nsym + sizeof(uint32_t) * kEncWords;
+    const size_t lds = sizeof(uint64_t) * ((kEncWords + 1) / 2 + L.nsym);
     hipLaunchKernelGGL(k_encode, dim3(a.n_tiles), dim3(256), lds, s, a);
 }
 

@@ -24,24 +24,87 @@ namespace dqz {
 
 constexpr uint32_t kBookThreads = 256;
 
-template <typename K>
-__device__ void bitonic_sort(K *key, uint32_t ns) {
-    for (uint32_t k = 2; k <= ns; k <<= 1) {
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            for (uint32_t i = threadIdx.x; i < ns; i += blockDim.x) {
-                const uint32_t ixj = i ^ j;
-                if (ixj > i) {
-                    const K a = key[i], b = key[ixj];
-                    const bool asc = (i & k) == 0;
-                    if ((a > b) == asc) {
-                        key[i] = b;
-                        key[ixj] = a;
-                    }
+// Bitonic sort of 256 * E 64-bit keys held E per thread (thread t holds
+// elements t*E .. t*E + E - 1).  Partners within a thread are compared in
+// registers, partners within a wave through cross-lane shuffles, and only
+// the strides spanning waves go through LDS (`xch`, 256 * E entries).  Every
+// loop has a compile-time trip count, so register indices stay static.
+template <int E>
+__device__ __forceinline__ void sort_keys(uint64_t (&k)[E], uint64_t *xch) {
+    constexpr uint32_t NS = 256u * E;
+    const uint32_t t = threadIdx.x;
+#pragma unroll
+    for (uint32_t kk = 2; kk <= NS; kk <<= 1) {
+#pragma unroll
+        for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
+            if (j < (uint32_t)E) {
+#pragma unroll
+                for (uint32_t r = 0; r < (uint32_t)E; r++) {
+                    if (r & j) continue;
+                    const uint32_t e = t * E + r;
+                    const bool asc = (e & kk) == 0;
+                    const uint64_t a = k[r], b = k[r | j];
+                    if ((a > b) == asc) { k[r] = b; k[r | j] = a; }
                 }
+            } else if (j < 64u * E) {
+#pragma unroll
+                for (uint32_t r = 0; r < (uint32_t)E; r++) {
+                    const uint32_t e = t * E + r;
+                    const uint64_t o = __shfl_xor(k[r], (int)(j / E), 64);
+                    const bool lower = (e & j) == 0, asc = (e & kk) == 0;
+                    const uint64_t mn = o < k[r] ? o : k[r], mx = o < k[r] ? k[r] : o;
+                    k[r] = (lower == asc) ? mn : mx;
+                }
+            } else {
+#pragma unroll
+                for (uint32_t r = 0; r < (uint32_t)E; r++) xch[t * E + r] = k[r];
+                __syncthreads();
+#pragma unroll
+                for (uint32_t r = 0; r < (uint32_t)E; r++) {
+                    const uint32_t e = t * E + r;
+                    const uint64_t o = xch[e ^ j];
+                    const bool lower = (e & j) == 0, asc = (e & kk) == 0;
+                    const uint64_t mn = o < k[r] ? o : k[r], mx = o < k[r] ? k[r] : o;
+                    k[r] = (lower == asc) ? mn : mx;
+                }
+                __syncthreads();
             }
-            __syncthreads();
         }
     }
+}
+
+// Sort `ns` keys produced by make(i) (i < ns; padding slots get ~0) into
+// out[0 .. max(ns, 256)).  ns is a power of two <= kMaxSyms.
+template <typename F>
+__device__ __forceinline__ void sort_into(uint32_t ns, uint64_t *out, uint64_t *xch, F make) {
+    const uint32_t t = threadIdx.x;
+    if (ns <= 256) {
+        uint64_t k[1] = {t < ns ? make(t) : ~0ull};
+        sort_keys<1>(k, xch);
+        out[t] = k[0];
+    } else if (ns == 512) {
+        uint64_t k[2];
+#pragma unroll
+        for (int r = 0; r < 2; r++) k[r] = make(t * 2 + r);
+        sort_keys<2>(k, xch);
+#pragma unroll
+        for (int r = 0; r < 2; r++) out[t * 2 + r] = k[r];
+    } else if (ns == 1024) {
+        uint64_t k[4];
+#pragma unroll
+        for (int r = 0; r < 4; r++) k[r] = make(t * 4 + r);
+        sort_keys<4>(k, xch);
+#pragma unroll
+        for (int r = 0; r < 4; r++) out[t * 4 + r] = k[r];
+    } else {
+        uint64_t k[8];
+#pragma unroll
+        for (int r = 0; r < 8; r++) k[r] = make(t * 8 + r);
+        sort_keys<8>(k, xch);
+#pragma unroll
+        for (int r = 0; r < 8; r++) out[t * 8 + r] = k[r];
+    }
+    __syncthreads();
 }
 
 struct HeaderArgs {
@@ -55,38 +118,40 @@ __device__ void put_le(uint8_t *p, uint32_t off, uint64_t v, uint32_t bytes) {
 }
 
 // Canonical numbering shared by the codebook and the decoding tables: sorts
-// symbols by (length, symbol) into `order`, fills count / first_index /
-// first_code, returns max length.  `len` has ns entries (0 = unused).
+// symbols by (length, symbol) into `key` (entries (len << 16) | sym, unused
+// symbols last as ~0), fills count / first_index / first_code per length.
 struct CanonScratch {
     uint64_t key[kMaxSyms];
+    uint64_t xch[kMaxSyms];
+    uint64_t first_code[66];
     uint32_t count[66];
     uint32_t first_index[66];
-    uint64_t first_code[66];
     uint32_t n_used;
     uint32_t max_len;
 };
 
 __device__ void canonical_order(const uint8_t *len, uint32_t ns, CanonScratch &c) {
-    for (uint32_t s = threadIdx.x; s < ns; s += blockDim.x)
-        c.key[s] = len[s] ? (((uint64_t)len[s] << 16) | s) : ~0ull;
     for (uint32_t l = threadIdx.x; l < 66; l += blockDim.x) {
         c.count[l] = 0;
         c.first_index[l] = 0;
         c.first_code[l] = 0;
     }
     if (threadIdx.x == 0) { c.n_used = 0; c.max_len = 0; }
-    __syncthreads();
-    bitonic_sort<uint64_t>(c.key, ns);
-    for (uint32_t i = threadIdx.x; i < ns; i += blockDim.x) {
+    sort_into(ns, c.key, c.xch, [&](uint32_t s) -> uint64_t {
+        return (s < ns && len[s]) ? (((uint64_t)len[s] << 16) | s) : ~0ull;
+    });
+    const uint32_t nk = ns < 256 ? 256 : ns;
+    for (uint32_t i = threadIdx.x; i < nk; i += blockDim.x) {
         const uint64_t k = c.key[i];
         if (k == ~0ull) continue;
         const uint32_t l = (uint32_t)(k >> 16);
         const bool first = (i == 0) || ((uint32_t)(c.key[i - 1] >> 16) != l);
         if (first) c.first_index[l] = i;
-        const bool last = (i + 1 == ns) || c.key[i + 1] == ~0ull || ((uint32_t)(c.key[i + 1] >> 16) != l);
+        const bool end = (i + 1 == nk) || c.key[i + 1] == ~0ull;
+        const bool last = end || ((uint32_t)(c.key[i + 1] >> 16) != l);
         if (last) {
-            c.count[l] = i + 1;   // fixed up to a count below
-            if ((i + 1 == ns) || c.key[i + 1] == ~0ull) { c.n_used = i + 1; c.max_len = l; }
+            c.count[l] = i + 1;   // turned into a count below
+            if (end) { c.n_used = i + 1; c.max_len = l; }
         }
     }
     __syncthreads();
@@ -103,13 +168,10 @@ __device__ void canonical_order(const uint8_t *len, uint32_t ns, CanonScratch &c
 }
 
 // ---------------------------------------------------------------------------
-// K2: histogram -> lengths -> canonical codebook -> header + lengths section
+// K2: histogram replicas -> lengths -> canonical codebook -> header + lengths
 // ---------------------------------------------------------------------------
 struct BookLds {
-    union {
-        uint64_t key[kMaxSyms];
-        CanonScratch canon;
-    };
+    CanonScratch canon;                  // key / xch double as the leaf sort buffers
     uint32_t leaf_w[kMaxSyms];
     uint16_t leaf_sym[kMaxSyms];
     uint32_t int_w[kMaxSyms];
@@ -119,80 +181,91 @@ struct BookLds {
     uint16_t round_start[kMaxSyms + 1];
     uint8_t depth_int[kMaxSyms];
     uint8_t len[kMaxSyms];
-    uint32_t n, la, ib, ic, nl, ni, T, rounds, done;
+    uint32_t hist[kMaxSyms];
+    uint8_t hdr[kHeaderBytes];
+    uint32_t n;
+    uint32_t nl[2], ni[2];
     unsigned long long total_bits;
-    uint32_t max_len;
 };
 
 __global__ __launch_bounds__(kBookThreads) void k_codebook(const uint32_t *__restrict__ hist, Ctl *ctl,
-                                                           uint64_t *__restrict__ book, uint8_t *archive,
-                                                           Layout L, Geom g, HeaderArgs hdr) {
+                                                           uint64_t *__restrict__ book, uint32_t *__restrict__ book32,
+                                                           uint8_t *archive, Layout L, Geom g, HeaderArgs hdr) {
     __shared__ BookLds s;
     const uint32_t tid = threadIdx.x, T = blockDim.x;
     const uint32_t ns = L.nsym;
-    if (ctl->status & ST_EINVAL) return;
+    if (ctl->status & (ST_EINVAL | ST_EINTERNAL)) return;
+    if (tid == 0) ctl->phase[0] = wall_clock64();
 
-    for (uint32_t i = tid; i < ns; i += T) {
-        const uint32_t f = hist[i];
-        s.key[i] = f ? (((uint64_t)f << 16) | i) : ~0ull;
-        s.len[i] = 0;
+    // sum the global histogram replicas (all loads of a thread in flight)
+    {
+        constexpr uint32_t kPer = kMaxSyms / kBookThreads;
+        uint32_t f[kPer];
+#pragma unroll
+        for (uint32_t k = 0; k < kPer; k++) f[k] = 0;
+#pragma unroll
+        for (uint32_t r = 0; r < kHistReplicas; r++) {
+#pragma unroll
+            for (uint32_t k = 0; k < kPer; k++) {
+                const uint32_t i = tid + kBookThreads * k;
+                if (i < ns) f[k] += hist[r * ns + i];
+            }
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < kPer; k++) {
+            const uint32_t i = tid + kBookThreads * k;
+            if (i < ns) { s.hist[i] = f[k]; s.len[i] = 0; }
+        }
     }
-    if (tid == 0) { s.n = 0; s.total_bits = 0; s.max_len = 0; }
+    if (tid == 0) { s.n = 0; s.total_bits = 0; s.nl[0] = s.nl[1] = s.ni[0] = s.ni[1] = 0; }
     __syncthreads();
-    bitonic_sort<uint64_t>(s.key, ns);
-    for (uint32_t i = tid; i < ns; i += T) {
-        const uint64_t k = s.key[i];
+    if (tid == 0) ctl->phase[1] = wall_clock64();
+    // leaves with nonzero frequency sorted by (frequency, symbol)
+    sort_into(ns, s.canon.key, s.canon.xch, [&](uint32_t i) -> uint64_t {
+        return (i < ns && s.hist[i]) ? (((uint64_t)s.hist[i] << 16) | i) : ~0ull;
+    });
+    const uint32_t nk = ns < 256 ? 256 : ns;
+    for (uint32_t i = tid; i < nk; i += T) {
+        const uint64_t k = s.canon.key[i];
         if (k != ~0ull) {
             s.leaf_w[i] = (uint32_t)(k >> 16);
             s.leaf_sym[i] = (uint16_t)(k & 0xFFFF);
-            if (i + 1 == ns || s.key[i + 1] == ~0ull) s.n = i + 1;
+            if (i + 1 == nk || s.canon.key[i + 1] == ~0ull) s.n = i + 1;
         }
     }
     __syncthreads();
     const uint32_t n = s.n;
+    if (tid == 0) ctl->phase[2] = wall_clock64();
     if (n == 1) {
         if (tid == 0) s.len[s.leaf_sym[0]] = 1;
     } else if (n > 1) {
-        if (tid == 0) { s.la = 0; s.ib = 0; s.ic = 0; s.rounds = 0; s.done = 0; }
-        __syncthreads();
+        // rounds of the two-queue construction; every thread tracks the queue
+        // state (la: next leaf, ib: next unmerged internal, ic: internals made)
+        uint32_t la = 0, ib = 0, ic = 0, rounds = 0;
         for (;;) {
-            if (tid == 0) {
-                const uint32_t la = s.la, ib = s.ib, ic = s.ic;
-                if ((n - la) + (ic - ib) <= 1) {
-                    s.done = 1;
-                } else {
-                    uint32_t a = la, b = ib, tsum = 0;
-                    for (int k = 0; k < 2; k++) {
-                        const bool leaf = a < n && (b >= ic || s.leaf_w[a] <= s.int_w[b]);
-                        tsum += leaf ? s.leaf_w[a++] : s.int_w[b++];
-                    }
-                    s.T = tsum;
-                    s.nl = 0;
-                    s.ni = 0;
-                }
+            if ((n - la) + (ic - ib) <= 1) break;
+            // T = the two lightest available items (leaf first on ties)
+            uint32_t a = la, b = ib, Tw = 0;
+#pragma unroll
+            for (int q = 0; q < 2; q++) {
+                const bool leaf = a < n && (b >= ic || s.leaf_w[a] <= s.int_w[b]);
+                Tw += leaf ? s.leaf_w[a++] : s.int_w[b++];
             }
-            __syncthreads();
-            if (s.done) break;
-            const uint32_t la = s.la, ib = s.ib, ic = s.ic, Tw = s.T;
-            // the items of weight <= T form a prefix of each sorted queue
+            const uint32_t par = rounds & 1u;
+            // items of weight <= T form a prefix of each sorted queue
             for (uint32_t i = la + tid; i < n; i += T)
-                if (s.leaf_w[i] <= Tw && (i + 1 == n || s.leaf_w[i + 1] > Tw)) s.nl = i + 1 - la;
+                if (s.leaf_w[i] <= Tw && (i + 1 == n || s.leaf_w[i + 1] > Tw)) s.nl[par] = i + 1 - la;
             for (uint32_t i = ib + tid; i < ic; i += T)
-                if (s.int_w[i] <= Tw && (i + 1 == ic || s.int_w[i + 1] > Tw)) s.ni = i + 1 - ib;
+                if (s.int_w[i] <= Tw && (i + 1 == ic || s.int_w[i + 1] > Tw)) s.ni[par] = i + 1 - ib;
             __syncthreads();
-            if (tid == 0) {
-                uint32_t nl = s.nl, ni = s.ni;
-                if ((nl + ni) & 1u) {   // odd: the last item of the merged order waits
-                    const bool int_last = ni > 0 && (nl == 0 || s.int_w[ib + ni - 1] >= s.leaf_w[la + nl - 1]);
-                    if (int_last) ni--; else nl--;
-                }
-                s.nl = nl;
-                s.ni = ni;
+            uint32_t nl = s.nl[par], ni = s.ni[par];
+            if ((nl + ni) & 1u) {   // odd: the last item of the merged order waits
+                const bool int_last = ni > 0 && (nl == 0 || s.int_w[ib + ni - 1] >= s.leaf_w[la + nl - 1]);
+                if (int_last) ni--; else nl--;
             }
-            __syncthreads();
-            const uint32_t nl = s.nl, ni = s.ni;
-            // merge ranks: a leaf goes after internals strictly lighter; an
-            // internal goes after leaves of equal or lower weight
+            if (tid == 0) { s.nl[par ^ 1u] = 0; s.ni[par ^ 1u] = 0; }
+            // merge ranks: a leaf goes after the internals strictly lighter;
+            // an internal after the leaves of equal or lower weight
             for (uint32_t k = tid; k < nl; k += T) {
                 const uint32_t w = s.leaf_w[la + k];
                 uint32_t lo = 0, hi = ni;
@@ -218,24 +291,21 @@ __global__ __launch_bounds__(kBookThreads) void k_codebook(const uint32_t *__res
             __syncthreads();
             const uint32_t p = (nl + ni) / 2;
             for (uint32_t k = tid; k < p; k += T) s.int_w[ic + k] = s.merged_w[2 * k] + s.merged_w[2 * k + 1];
+            if (tid == 0) s.round_start[rounds] = (uint16_t)ic;
             __syncthreads();
-            if (tid == 0) {
-                s.round_start[s.rounds++] = (uint16_t)ic;
-                s.la = la + nl;
-                s.ib = ib + ni;
-                s.ic = ic + p;
-            }
-            __syncthreads();
+            la += nl;
+            ib += ni;
+            ic += p;
+            rounds++;
         }
-        // depths: the root is the last internal node; every node's parent
-        // was created in a later round, so walk the rounds backwards
-        const uint32_t nint = s.ic, rounds = s.rounds;
-        if (tid == 0) s.round_start[rounds] = (uint16_t)nint;
+        // depths: the root is the last internal node; every node's parent was
+        // created in a later round, so walk the rounds backwards
+        if (tid == 0) { s.round_start[rounds] = (uint16_t)ic; ctl->phase[3] = wall_clock64(); ctl->phase[8] = rounds; }
         __syncthreads();
         for (int32_t rd = (int32_t)rounds - 1; rd >= 0; rd--) {
             const uint32_t b0 = s.round_start[rd], b1 = s.round_start[rd + 1];
             for (uint32_t k = b0 + tid; k < b1; k += T)
-                s.depth_int[k] = (k == nint - 1) ? 0 : (uint8_t)(s.depth_int[s.parent_int[k]] + 1);
+                s.depth_int[k] = (k == ic - 1) ? 0 : (uint8_t)(s.depth_int[s.parent_int[k]] + 1);
             __syncthreads();
         }
         for (uint32_t i = tid; i < n; i += T) {
@@ -245,24 +315,32 @@ __global__ __launch_bounds__(kBookThreads) void k_codebook(const uint32_t *__res
     }
     __syncthreads();
 
-    // canonical codes
+    // canonical codes; the fixed-width codeword form (Sec. 3.2.2) is 32-bit
+    // (len << 24 | code) when every code fits in 24 bits, else 64-bit
+    if (tid == 0) ctl->phase[4] = wall_clock64();
     canonical_order(s.len, ns, s.canon);
-    for (uint32_t i = tid; i < ns; i += T) {
+    if (tid == 0) ctl->phase[5] = wall_clock64();
+    const uint32_t max_len = s.canon.max_len;
+    for (uint32_t i = tid; i < nk; i += T) {
         const uint64_t k = s.canon.key[i];
         if (k == ~0ull) continue;
         const uint32_t l = (uint32_t)(k >> 16), sym = (uint32_t)(k & 0xFFFF);
         const uint64_t code = s.canon.first_code[l] + (i - s.canon.first_index[l]);
         book[sym] = ((uint64_t)l << 56) | code;
+        if (max_len <= 24) book32[sym] = (l << 24) | (uint32_t)code;
     }
     for (uint32_t sym = tid; sym < ns; sym += T) {
-        if (s.len[sym] == 0) book[sym] = 0;
-        const uint64_t c = (uint64_t)hist[sym] * s.len[sym];
+        if (s.len[sym] == 0) {
+            book[sym] = 0;
+            book32[sym] = 0;
+        }
+        const uint64_t c = (uint64_t)s.hist[sym] * s.len[sym];
         if (c) atomicAdd(&s.total_bits, (unsigned long long)c);
     }
     __syncthreads();
 
     if (tid == 0) {
-        const uint32_t max_len = s.canon.max_len;
+        ctl->phase[6] = wall_clock64();
         if (max_len > 64) atomicOr(&ctl->status, ST_EUNSUPPORTED);
         const uint64_t total_bits = s.total_bits;
         const uint64_t n_words = (total_bits + 31) / 32;
@@ -275,8 +353,8 @@ __global__ __launch_bounds__(kBookThreads) void k_codebook(const uint32_t *__res
         ctl->off_str = off_str;
         ctl->archive_bytes = end;
         if (end > L.cap) atomicOr(&ctl->status, ST_ETOOSMALL);
-        // header
-        uint8_t *hb = ctl->header;
+        // header (assembled in LDS, then copied out by all threads)
+        uint8_t *hb = s.hdr;
         for (uint32_t i = 0; i < kHeaderBytes; i++) hb[i] = 0;
         put_le(hb, 0, kMagic, 4);
         put_le(hb, 4, kVersion, 2);
@@ -305,15 +383,19 @@ __global__ __launch_bounds__(kBookThreads) void k_codebook(const uint32_t *__res
     }
     __syncthreads();
     // header + lengths into the archive (the host checked that the fixed
-    // sections fit the capacity)
-    for (uint32_t i = tid; i < kHeaderBytes; i += T) archive[i] = ctl->header[i];
+    // sections fit the capacity); zero the alignment pads
+    for (uint32_t i = tid; i < kHeaderBytes; i += T) {
+        archive[i] = s.hdr[i];
+        ctl->header[i] = s.hdr[i];
+    }
     for (uint32_t i = tid; i < ns; i += T) archive[L.off_len + i] = s.len[i];
-    for (uint64_t i = L.off_len + ns + tid; i < L.off_chunk; i += T) archive[i] = 0;   // alignment pads
+    for (uint64_t i = L.off_len + ns + tid; i < L.off_chunk; i += T) archive[i] = 0;
     for (uint64_t i = L.off_sub + 2ull * L.n_sub + tid; i < L.off_exc; i += T) archive[i] = 0;
+    if (tid == 0) ctl->phase[7] = wall_clock64();
 }
 
 void launch_codebook(hipStream_t st, const Geom &g, const Layout &L, Ctl *ctl, const uint32_t *hist, uint64_t *book,
-                     uint8_t *archive, int eb_mode, double eb_param) {
+                     uint32_t *book32, uint8_t *archive, int eb_mode, double eb_param) {
     HeaderArgs h;
     h.dims[0] = g.n[0];
     h.dims[1] = g.n[1];
@@ -321,7 +403,7 @@ void launch_codebook(hipStream_t st, const Geom &g, const Layout &L, Ctl *ctl, c
     h.eb_param = eb_param;
     h.ndim = g.ndim;
     h.eb_mode = (uint32_t)eb_mode;
-    hipLaunchKernelGGL(k_codebook, dim3(1), dim3(kBookThreads), 0, st, hist, ctl, book, archive, L, g, h);
+    hipLaunchKernelGGL(k_codebook, dim3(1), dim3(kBookThreads), 0, st, hist, ctl, book, book32, archive, L, g, h);
 }
 
 // ---------------------------------------------------------------------------
@@ -332,21 +414,22 @@ __global__ __launch_bounds__(kBookThreads) void k_decode_tables(const uint8_t *_
                                                                 uint32_t max_len_hdr, DecodeTables *tab) {
     __shared__ CanonScratch c;
     __shared__ uint8_t len[kMaxSyms];
-    __shared__ uint64_t s_short[kMaxSyms];   // left-aligned (to kLutBits) codes of length <= kLutBits
-    __shared__ uint32_t s_nshort, s_bad;
+    __shared__ uint32_t s_bad;
     const uint32_t tid = threadIdx.x, T = blockDim.x, ns = L.nsym;
-    for (uint32_t i = tid; i < ns; i += T) len[i] = archive[L.off_len + i];
-    if (tid == 0) { s_bad = 0; s_nshort = 0; }
+    if (tid == 0) { s_bad = 0; tab->phase[0] = wall_clock64(); }
     __syncthreads();
-    for (uint32_t i = tid; i < ns; i += T)
+    for (uint32_t i = tid; i < ns; i += T) {
+        len[i] = archive[L.off_len + i];
         if (len[i] > 63) s_bad = 1;
+    }
     __syncthreads();
     if (s_bad) {
-        if (tid == 0) tab->status = ST_ECORRUPT;
+        if (tid == 0) { tab->status = ST_ECORRUPT; tab->max_len = 0; }
         return;
     }
     canonical_order(len, ns, c);
     if (tid == 0) {
+        tab->phase[1] = wall_clock64();
         // Kraft: the code space must be exactly filled (or a lone symbol of length 1)
         int64_t left = 1;
         bool over = false;
@@ -357,46 +440,51 @@ __global__ __launch_bounds__(kBookThreads) void k_decode_tables(const uint8_t *_
         }
         const bool lone = c.n_used == 1 && c.count[1] == 1;
         uint32_t st = 0;
-        if (over || (!lone && c.n_used > 0 && left != 0) || c.max_len != max_len_hdr) st = ST_ECORRUPT;
+        if (over || (!lone && c.n_used > 0 && left != 0) || c.max_len != max_len_hdr || c.max_len > 63) st = ST_ECORRUPT;
         tab->status = st;
         tab->max_len = c.max_len;
-        uint32_t nshort = 0;
-        for (uint32_t l = 1; l <= kLutBits; l++) nshort += c.count[l];
-        s_nshort = nshort;
     }
     for (uint32_t l = tid; l < 65; l += T) {
         tab->first_code[l] = c.first_code[l];
         tab->count[l] = c.count[l];
         tab->first_index[l] = c.first_index[l];
+        // codes of length <= l occupy [0, limit) of the left-aligned code space
+        tab->limit[l] = (l == 0) ? 0ull : (l == 64 ? ~0ull : ((c.first_code[l] + c.count[l]) << (64 - l)));
     }
-    __syncthreads();
-    const uint32_t nshort = s_nshort;
     for (uint32_t i = tid; i < ns; i += T) {
         const uint64_t k = c.key[i];
         tab->sorted[i] = (k == ~0ull) ? 0 : (uint16_t)(k & 0xFFFF);
-        if (i < nshort) {
-            const uint32_t l = (uint32_t)(k >> 16);
-            const uint64_t code = c.first_code[l] + (i - c.first_index[l]);
-            s_short[i] = code << (kLutBits - l);
+    }
+    // each table slot v (the next kLutBits stream bits): its code length is
+    // 1 + the number of lengths l <= kLutBits whose codes all lie below v
+    // (canonical codes of length <= l fill [0, limit_l)); longer codes get the
+    // shortest length that can follow the prefix
+    uint32_t lim[kLutBits + 1];
+#pragma unroll
+    for (uint32_t l = 1; l <= kLutBits; l++)
+        lim[l] = (uint32_t)((c.first_code[l] + c.count[l]) << (kLutBits - l));
+    for (uint32_t v = tid; v < (1u << kLutBits); v += T) {
+        uint32_t l = 1;
+#pragma unroll
+        for (uint32_t k = 1; k <= kLutBits; k++) l += (lim[k] <= v) ? 1u : 0u;
+        uint32_t e = 0;
+        if (l <= kLutBits) {
+            const uint64_t code = (uint64_t)(v >> (kLutBits - l));
+            const uint64_t d = code - c.first_code[l];
+            if (code >= c.first_code[l] && d < c.count[l]) {
+                const uint64_t k = c.key[c.first_index[l] + (uint32_t)d];
+                e = (l << 11) | (uint32_t)(k & 0x7FF);
+            }
+        } else if (c.max_len > kLutBits) {
+            const uint64_t w = (uint64_t)v << (64 - kLutBits);
+            uint32_t ll = kLutBits + 1;
+            while (ll < c.max_len && w >= ((c.first_code[ll] + c.count[ll]) << (64 - ll))) ll++;
+            e = 0x8000u | ll;
         }
+        tab->lut[v] = (uint16_t)e;
     }
     __syncthreads();
-    // each table slot: the short code whose left-aligned range covers it
-    for (uint32_t v = tid; v < (1u << kLutBits); v += T) {
-        uint32_t lo = 0, hi = nshort;   // last entry with start <= v
-        while (lo < hi) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (s_short[mid] <= v) lo = mid + 1; else hi = mid;
-        }
-        uint32_t e = 0;
-        if (lo > 0) {
-            const uint32_t i = lo - 1;
-            const uint64_t k = c.key[i];
-            const uint32_t l = (uint32_t)(k >> 16);
-            if (v < s_short[i] + (1ull << (kLutBits - l))) e = (l << 16) | (uint32_t)(k & 0xFFFF);
-        }
-        tab->lut[v] = e;
-    }
+    if (tid == 0) tab->phase[2] = wall_clock64();
 }
 
 void launch_decode_tables(hipStream_t st, const Layout &L, const uint8_t *archive, uint32_t max_len_hdr,

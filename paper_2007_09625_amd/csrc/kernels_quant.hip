@@ -14,9 +14,9 @@
 //               codes (Sec. 3.2.1), and ordered compaction of the exceptions
 //               via decoupled look-back.
 //
-// Each quantize workgroup takes one tile of kTile padded positions by a
-// dynamic ticket, so tiles finish roughly in stream order and the look-back
-// never waits on a tile that has not started.  The tile is staged in LDS
+// Each quantize workgroup handles one tile of kTile padded positions, tile
+// index = workgroup index (workgroups start in index order, so the
+// look-back only waits on tiles already running).  The tile is staged in LDS
 // with fully coalesced row loads; the Lorenzo delta is the mixed backward
 // difference, computed per axis with registers (slow axis) and cross-lane
 // shuffles (fast axes).
@@ -70,7 +70,10 @@ __device__ __forceinline__ void key_acc(uint32_t u, uint32_t &lo, uint32_t &hi) 
     }
 }
 
-__global__ __launch_bounds__(256) void k_minmax(const float *__restrict__ x, uint64_t n, Ctl *ctl, double valrel) {
+// Pass 1: each workgroup reduces its grid-stride share and writes one
+// (min key, max key) pair; no atomics (same-address device atomics
+// serialize across the whole chip).
+__global__ __launch_bounds__(256) void k_minmax(const float *__restrict__ x, uint64_t n, uint32_t *partials) {
     uint32_t lo = 0xFFFFFFFFu, hi = 0u;
     const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -79,18 +82,31 @@ __global__ __launch_bounds__(256) void k_minmax(const float *__restrict__ x, uin
         const uint64_t n4 = n / 4;
         typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
         const u32x4 *v = reinterpret_cast<const u32x4 *>(x);
-        for (uint64_t i = tid; i < n4; i += stride) {
+        // four independent 16-byte loads in flight per thread per iteration
+        uint64_t i = tid;
+        for (; i + 3 * stride < n4; i += 4 * stride) {
+            u32x4 w[4];
+#pragma unroll
+            for (int k = 0; k < 4; k++) w[k] = __builtin_nontemporal_load(v + i + k * stride);
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                key_acc(w[k].x, lo, hi);
+                key_acc(w[k].y, lo, hi);
+                key_acc(w[k].z, lo, hi);
+                key_acc(w[k].w, lo, hi);
+            }
+        }
+        for (; i < n4; i += stride) {
             const u32x4 w = __builtin_nontemporal_load(v + i);
             key_acc(w.x, lo, hi);
             key_acc(w.y, lo, hi);
             key_acc(w.z, lo, hi);
             key_acc(w.w, lo, hi);
         }
-        for (uint64_t i = n4 * 4 + tid; i < n; i += stride) key_acc(u[i], lo, hi);
+        for (uint64_t j = n4 * 4 + tid; j < n; j += stride) key_acc(u[j], lo, hi);
     } else {
-        for (uint64_t i = tid; i < n; i += stride) key_acc(u[i], lo, hi);
+        for (uint64_t j = tid; j < n; j += stride) key_acc(u[j], lo, hi);
     }
-    // workgroup reduction
 #pragma unroll
     for (int off = 32; off >= 1; off >>= 1) {
         const uint32_t a = __shfl_xor(lo, off, 64), b = __shfl_xor(hi, off, 64);
@@ -98,7 +114,35 @@ __global__ __launch_bounds__(256) void k_minmax(const float *__restrict__ x, uin
         hi = b > hi ? b : hi;
     }
     __shared__ uint32_t s_lo[4], s_hi[4];
-    __shared__ bool s_last;
+    const uint32_t w = threadIdx.x / 64;
+    if (lane_id() == 0) { s_lo[w] = lo; s_hi[w] = hi; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (uint32_t k = 1; k < blockDim.x / 64; k++) {
+            lo = s_lo[k] < lo ? s_lo[k] : lo;
+            hi = s_hi[k] > hi ? s_hi[k] : hi;
+        }
+        partials[2 * blockIdx.x] = lo;
+        partials[2 * blockIdx.x + 1] = hi;
+    }
+}
+
+// Pass 2 (one workgroup): combine the partials, derive eb_abs, h, r.
+__global__ __launch_bounds__(256) void k_minmax_final(const uint32_t *partials, uint32_t nparts, Ctl *ctl,
+                                                      double valrel) {
+    uint32_t lo = 0xFFFFFFFFu, hi = 0u;
+    for (uint32_t i = threadIdx.x; i < nparts; i += blockDim.x) {
+        const uint32_t a = partials[2 * i], b = partials[2 * i + 1];
+        lo = a < lo ? a : lo;
+        hi = b > hi ? b : hi;
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        const uint32_t a = __shfl_xor(lo, off, 64), b = __shfl_xor(hi, off, 64);
+        lo = a < lo ? a : lo;
+        hi = b > hi ? b : hi;
+    }
+    __shared__ uint32_t s_lo[4], s_hi[4];
     const uint32_t w = threadIdx.x / 64;
     if (lane_id() == 0) { s_lo[w] = lo; s_hi[w] = hi; }
     __syncthreads();
@@ -107,21 +151,12 @@ __global__ __launch_bounds__(256) void k_minmax(const float *__restrict__ x, uin
             lo = s_lo[i] < lo ? s_lo[i] : lo;
             hi = s_hi[i] > hi ? s_hi[i] : hi;
         }
-        atomicMin(&ctl->vmin_key, lo);
-        atomicMax(&ctl->vmax_key, hi);
-        __threadfence();
-        const uint32_t t = atomicAdd(&ctl->minmax_done, 1u);
-        s_last = (t == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (s_last && threadIdx.x == 0) {
-        __threadfence();
-        const uint32_t klo = __hip_atomic_load(&ctl->vmin_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t khi = __hip_atomic_load(&ctl->vmax_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ctl->vmin_key = lo;
+        ctl->vmax_key = hi;
         double range = 1.0;
-        if (klo != 0xFFFFFFFFu) {   // at least one finite value
-            const float fmin = __uint_as_float(key2f(klo));
-            const float fmax = __uint_as_float(key2f(khi));
+        if (lo != 0xFFFFFFFFu) {   // at least one finite value
+            const float fmin = __uint_as_float(key2f(lo));
+            const float fmax = __uint_as_float(key2f(hi));
             const double d = (double)fmax - (double)fmin;
             if (d > 0.0) range = d;
         }
@@ -129,11 +164,14 @@ __global__ __launch_bounds__(256) void k_minmax(const float *__restrict__ x, uin
     }
 }
 
-void launch_minmax(hipStream_t s, const float *x, uint64_t n, Ctl *ctl, double valrel, int ncu) {
+void launch_minmax(hipStream_t s, const float *x, uint64_t n, Ctl *ctl, uint32_t *partials, double valrel, int ncu) {
     uint64_t want = (n / 4 + 255) / 256;
-    uint32_t blocks = (uint32_t)(want < (uint64_t)ncu * 8 ? want : (uint64_t)ncu * 8);
+    uint64_t cap = (uint64_t)ncu * 4;
+    if (cap > kMinmaxMaxBlocks) cap = kMinmaxMaxBlocks;
+    uint32_t blocks = (uint32_t)(want < cap ? want : cap);
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_minmax, dim3(blocks), dim3(256), 0, s, x, n, ctl, valrel);
+    hipLaunchKernelGGL(k_minmax, dim3(blocks), dim3(256), 0, s, x, n, partials);
+    hipLaunchKernelGGL(k_minmax_final, dim3(1), dim3(256), 0, s, partials, blocks, ctl, valrel);
 }
 
 // ---------------------------------------------------------------------------
@@ -152,11 +190,13 @@ struct QuantArgs {
     uint32_t tiles_per_row;
 };
 
-// LDS histogram privatization: one replica per workgroup, flushed once.
+// LDS histogram privatization: one replica per workgroup, flushed once into
+// one of kHistReplicas global copies (summed by the codebook kernel).
 __device__ __forceinline__ void hist_flush(uint32_t *sh_hist, uint32_t nsym, uint32_t *ghist) {
+    uint32_t *dst = ghist + (blockIdx.x % kHistReplicas) * nsym;
     for (uint32_t b = threadIdx.x; b < nsym; b += blockDim.x) {
         const uint32_t c = sh_hist[b];
-        if (c) atomicAdd(ghist + b, c);
+        if (c) atomicAdd(dst + b, c);
     }
 }
 
@@ -177,7 +217,7 @@ __device__ __forceinline__ uint64_t exceptions_base(const QuantArgs &a, uint32_t
             if (lane_id() == 0) lb_publish(a.lb, tile, tot, 2);
         } else {
             if (lane_id() == 0) lb_publish(a.lb, tile, tot, 1);
-            base = lb_exclusive(a.lb, tile);
+            base = lb_exclusive(a.lb, tile, &a.ctl->status);
             if (lane_id() == 0) lb_publish(a.lb, tile, base + tot, 2);
         }
         if (lane_id() == 0) {
@@ -206,11 +246,7 @@ __device__ __forceinline__ void put_exc(const QuantArgs &a, uint64_t idx, uint32
     }
 }
 
-__device__ __forceinline__ uint32_t take_ticket(Ctl *ctl, uint32_t *sh_ticket) {
-    if (threadIdx.x == 0) *sh_ticket = atomicAdd(&ctl->ticket_q, 1u);
-    __syncthreads();
-    return *sh_ticket;
-}
+
 
 // ---------------------------------------------------------------------------
 // 3D: tile = 8 consecutive 8x8x8 blocks along x in one block row.
@@ -224,7 +260,6 @@ __global__ __launch_bounds__(256) void k_quant3d(QuantArgs a) {
     extern __shared__ uint32_t sh_hist[];
     __shared__ float s_tile[8][8][kRow3];
     __shared__ uint32_t s_misc[16];
-    __shared__ uint32_t s_ticket;
 
     Ctl *ctl = a.ctl;
     if (ctl->status & ST_EINVAL) return;
@@ -233,20 +268,31 @@ __global__ __launch_bounds__(256) void k_quant3d(QuantArgs a) {
     const int32_t R = (int32_t)a.L.radius;
     for (uint32_t b = threadIdx.x; b < a.L.nsym; b += blockDim.x) sh_hist[b] = 0;
 
-    const uint32_t tile = take_ticket(ctl, &s_ticket);
+    __syncthreads();
+    const uint32_t tile = blockIdx.x;
     const uint32_t tx = tile % a.tiles_per_row;
     const uint32_t rowid = tile / a.tiles_per_row;
     const uint32_t By = rowid % a.g.nb[1], Bz = rowid / a.g.nb[1];
     const uint32_t z0 = Bz * 8, y0 = By * 8, x0 = tx * kT3 * 8;
     const uint32_t nz = a.g.n[0], ny = a.g.n[1], nx = a.g.n[2];
 
-    // stage the tile: 64 rows (z, y) of 64 floats, one wave per row
-    for (uint32_t rr = threadIdx.x / 64; rr < 64; rr += blockDim.x / 64) {
-        const uint32_t z = rr / 8, y = rr % 8, xx = lane_id();
-        float v = 0.0f;
-        if (z0 + z < nz && y0 + y < ny && x0 + xx < nx)
-            v = __builtin_nontemporal_load(a.x + ((uint64_t)(z0 + z) * ny + (y0 + y)) * nx + (x0 + xx));
-        s_tile[z][y][xx] = v;
+    // stage the tile: 64 rows (z, y) of 64 floats, one wave per row; all 16
+    // loads of a thread are issued before any is used
+    {
+        float v[16];
+        const uint32_t xx = lane_id(), w0 = threadIdx.x / 64;
+#pragma unroll
+        for (uint32_t k = 0; k < 16; k++) {
+            const uint32_t rr = w0 + 4 * k, z = rr / 8, y = rr % 8;
+            v[k] = 0.0f;
+            if (z0 + z < nz && y0 + y < ny && x0 + xx < nx)
+                v[k] = __builtin_nontemporal_load(a.x + ((uint64_t)(z0 + z) * ny + (y0 + y)) * nx + (x0 + xx));
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < 16; k++) {
+            const uint32_t rr = w0 + 4 * k;
+            s_tile[rr / 8][rr % 8][xx] = v[k];
+        }
     }
     __syncthreads();
 
@@ -331,7 +377,6 @@ __global__ __launch_bounds__(256) void k_quant2d(QuantArgs a) {
     extern __shared__ uint32_t sh_hist[];
     __shared__ float s_tile[16][16 * kT2];
     __shared__ uint32_t s_misc[16];
-    __shared__ uint32_t s_ticket;
 
     Ctl *ctl = a.ctl;
     if (ctl->status & ST_EINVAL) return;
@@ -340,15 +385,21 @@ __global__ __launch_bounds__(256) void k_quant2d(QuantArgs a) {
     const int32_t R = (int32_t)a.L.radius;
     for (uint32_t b = threadIdx.x; b < a.L.nsym; b += blockDim.x) sh_hist[b] = 0;
 
-    const uint32_t tile = take_ticket(ctl, &s_ticket);
+    __syncthreads();
+    const uint32_t tile = blockIdx.x;
     const uint32_t tx = tile % a.tiles_per_row, By = tile / a.tiles_per_row;
     const uint32_t y0 = By * 16, x0 = tx * kT2 * 16;
     const uint32_t ny = a.g.n[1], nx = a.g.n[2];
-    for (uint32_t rr = 0; rr < 16; rr++) {
+    {
+        float v[16];
         const uint32_t xx = threadIdx.x;
-        float v = 0.0f;
-        if (y0 + rr < ny && x0 + xx < nx) v = __builtin_nontemporal_load(a.x + (uint64_t)(y0 + rr) * nx + x0 + xx);
-        s_tile[rr][xx] = v;
+#pragma unroll
+        for (uint32_t rr = 0; rr < 16; rr++) {
+            v[rr] = 0.0f;
+            if (y0 + rr < ny && x0 + xx < nx) v[rr] = __builtin_nontemporal_load(a.x + (uint64_t)(y0 + rr) * nx + x0 + xx);
+        }
+#pragma unroll
+        for (uint32_t rr = 0; rr < 16; rr++) s_tile[rr][xx] = v[rr];
     }
     __syncthreads();
 
@@ -426,7 +477,6 @@ __global__ __launch_bounds__(256) void k_quant1d(QuantArgs a) {
     extern __shared__ uint32_t sh_hist[];
     __shared__ float s_tile[kTile];
     __shared__ uint32_t s_misc[16];
-    __shared__ uint32_t s_ticket;
 
     Ctl *ctl = a.ctl;
     if (ctl->status & ST_EINVAL) return;
@@ -435,17 +485,23 @@ __global__ __launch_bounds__(256) void k_quant1d(QuantArgs a) {
     const int32_t R = (int32_t)a.L.radius;
     for (uint32_t b = threadIdx.x; b < a.L.nsym; b += blockDim.x) sh_hist[b] = 0;
 
-    const uint32_t tile = take_ticket(ctl, &s_ticket);
+    __syncthreads();
+    const uint32_t tile = blockIdx.x;
     const uint64_t p0 = (uint64_t)tile * kTile;
     const uint64_t n = a.g.nelem;
-    for (uint32_t k = threadIdx.x; k < kTile; k += blockDim.x) {
-        float v = 0.0f;
-        if (p0 + k < n) v = __builtin_nontemporal_load(a.x + p0 + k);
-        s_tile[k] = v;
+    {
+        float v[kTile / 256];
+#pragma unroll
+        for (uint32_t k = 0; k < kTile / 256; k++) {
+            const uint64_t e = p0 + threadIdx.x + 256 * k;
+            v[k] = (e < n) ? __builtin_nontemporal_load(a.x + e) : 0.0f;
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < kTile / 256; k++) s_tile[threadIdx.x + 256 * k] = v[k];
     }
     __syncthreads();
 
-    const uint32_t t = threadIdx.x, lane = lane_id();
+    const uint32_t t = threadIdx.x;
     int32_t d[16];
 #pragma unroll
     for (uint32_t i = 0; i < 16; i++) d[i] = prequant(s_tile[16 * t + i], r);
@@ -461,7 +517,6 @@ __global__ __launch_bounds__(256) void k_quant1d(QuantArgs a) {
         const int32_t del = (int32_t)((uint32_t)d[i] - pred);
         delta[i] = del;
         const uint64_t pos = p0 + 16 * t + i;
-        const bool exists = pos < a.g.padded;
         const bool real = pos < n;
         const bool incap = del > -R && del < R;
         const bool o = real && !incap;
@@ -472,7 +527,6 @@ __global__ __launch_bounds__(256) void k_quant1d(QuantArgs a) {
             atomicAdd(&sh_hist[qq], 1u);
         }
         q[i] = qq;
-        (void)exists;
         flags_o |= (o ? 1u : 0u) << i;
         flags_p |= (p ? 1u : 0u) << i;
         my_count += (o ? 1u : 0u) + (p ? 1u : 0u);
@@ -509,7 +563,6 @@ __global__ __launch_bounds__(256) void k_quant1d(QuantArgs a) {
             if ((flags_p >> i) & 1u) put_exc(a, idx++, 2u * pos + 1u, __float_as_uint(s_tile[16 * t + i]));
         }
     }
-    (void)lane;
     __syncthreads();
     hist_flush(sh_hist, a.L.nsym, a.hist);
 }

@@ -15,9 +15,10 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdqz.so")
 
 DQZ_OK, DQZ_EINVAL, DQZ_ETOOSMALL, DQZ_ENOMEM, DQZ_ECORRUPT, DQZ_EUNSUPPORTED, DQZ_EHIP = 0, -1, -2, -3, -4, -5, -6
+DQZ_EINTERNAL = -7
 DQZ_EB_ABS, DQZ_EB_VALREL = 0, 1
 DQZ_HEADER_BYTES = 128
-DQZ_DBG_CODES, DQZ_DBG_HISTOGRAM, DQZ_DBG_CODEBOOK = 1, 2, 3
+DQZ_DBG_CODES, DQZ_DBG_HISTOGRAM, DQZ_DBG_CODEBOOK, DQZ_DBG_PHASES = 1, 2, 3, 4
 
 EXPORTED = ("dqz_ctx_create", "dqz_ctx_destroy", "dqz_compress_bound", "dqz_compress", "dqz_archive_info",
             "dqz_decompress", "dqz_status_str", "dqz_ctx_last_error", "dqz_debug_copy", "dqz_ctx_set_timing",

@@ -48,7 +48,7 @@ def test_library_links_no_oracle(dqz):
 
 
 def test_status_strings(dqz):
-    for st in range(0, -7, -1):
+    for st in range(0, -8, -1):
         assert dqz.lib.dqz_status_str(st)
 
 
