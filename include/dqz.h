@@ -139,8 +139,9 @@ const char *dqz_ctx_last_error(const dqz_ctx *ctx);
  * per-call cost); dqz_stage_times then returns the elapsed microseconds of
  * each stage of the most recent call of that kind:
  *   compress   (which = 0): [0] init, [1] value range + eb (0 in absolute
- *              mode), [2] dual-quantization + histogram + exceptions,
- *              [3] codebook + header, [4] stream clear, [5] encode + deflate
+ *              mode), [2] dual-quantization + histogram + exceptions (with
+ *              their tile scan), [3] codebook + header, [4] encode + deflate
+ *              (width count + tile scan + packing)
  *   decompress (which = 1): [0] decoding tables, [1] inflate + reconstruct
  * `us` must hold DQZ_MAX_STAGES doubles; *n_stages receives the count. */
 #define DQZ_MAX_STAGES 8

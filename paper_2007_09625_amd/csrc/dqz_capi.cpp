@@ -130,27 +130,53 @@ void fill_params(const dqz_params *p, uint32_t &radius, uint32_t &sub, uint32_t 
     csubs = p->chunk_subs ? p->chunk_subs : kDefaultChunkSubs;
 }
 
-// device scratch layout
+// device scratch layout: control block and decoding tables at fixed
+// offsets, then the zeroed region (histogram replicas, scan counters), then
+// the compression buffers (so a decompression never overwrites the last
+// compression's stage buffers kept for dqz_debug_copy)
 struct WsLayout {
-    uint64_t ctl, hist, lbq, lbe, zero_end, book, book32, parts, codes, tab, total;
+    uint64_t ctl, tab, hist, zero_end;
+    uint64_t hist_sum, book, book32, parts;
+    uint64_t qval[2], qexcl[2], qseg_total[2];
+    uint64_t eval, eexcl, eseg_total;
+    uint64_t stage, codes, total;
+    uint32_t n_segs_q, n_segs_e, cap;
 };
 
-// control block and decoding tables at fixed offsets, then the compression
-// buffers (so a decompression never overwrites the last compression's stage
-// buffers kept for dqz_debug_copy)
-WsLayout ws_layout(const Plan &P, bool compress) {
+WsLayout ws_layout(const Plan &P, bool compress, uint32_t cap) {
     WsLayout w;
-    w.ctl = 0;
-    w.tab = align_up(sizeof(Ctl), 256);
-    w.hist = align_up(w.tab + sizeof(DecodeTables), 256);
-    w.lbq = align_up(w.hist + 4ull * kHistReplicas * P.L.nsym, 256);
-    w.lbe = align_up(w.lbq + 8ull * P.tiles_q, 256);
-    w.zero_end = align_up(w.lbe + 8ull * P.tiles_e, 256);
-    w.book = w.zero_end;
-    w.book32 = align_up(w.book + 8ull * P.L.nsym, 256);
-    w.parts = align_up(w.book32 + 4ull * P.L.nsym, 256);
-    w.codes = align_up(w.parts + 8ull * kMinmaxMaxBlocks, 256);
-    w.total = compress ? align_up(w.codes + 2ull * P.g.padded, 256) : w.hist;
+    auto take = [](uint64_t &cur, uint64_t bytes) {
+        const uint64_t at = align_up(cur, 256);
+        cur = at + bytes;
+        return at;
+    };
+    w.n_segs_q = (P.tiles_q + kSegTiles - 1) / kSegTiles;
+    w.n_segs_e = (P.tiles_e + kSegTiles - 1) / kSegTiles;
+    w.cap = cap;
+    uint64_t cur = 0;
+    w.ctl = take(cur, sizeof(Ctl));
+    w.tab = take(cur, sizeof(DecodeTables));
+    if (!compress) {
+        w.total = align_up(cur, 256);
+        return w;
+    }
+    w.hist = take(cur, 4ull * kHistReplicas * P.L.nsym);
+    w.hist_sum = take(cur, 4ull * P.L.nsym);   // zeroed too: an empty field never writes it
+    w.zero_end = align_up(cur, 256);
+    w.book = take(cur, 8ull * P.L.nsym);
+    w.book32 = take(cur, 4ull * P.L.nsym);
+    w.parts = take(cur, 8ull * kMinmaxMaxBlocks);
+    for (int k = 0; k < 2; k++) {
+        w.qval[k] = take(cur, 4ull * P.tiles_q);
+        w.qexcl[k] = take(cur, 4ull * P.tiles_q);
+        w.qseg_total[k] = take(cur, 8ull * w.n_segs_q);
+    }
+    w.eval = take(cur, 4ull * P.tiles_e);
+    w.eexcl = take(cur, 4ull * P.tiles_e);
+    w.eseg_total = take(cur, 8ull * w.n_segs_e);
+    w.stage = take(cur, 8ull * cap * P.tiles_q);
+    w.codes = take(cur, 2ull * P.g.padded);
+    w.total = align_up(cur, 256);
     return w;
 }
 
@@ -180,7 +206,7 @@ void mark(dqz_ctx *ctx, int which, int i, hipStream_t s) {
 }
 
 dqz_status status_from_device(dqz_ctx *ctx, uint32_t st) {
-    if (st & ST_EINTERNAL) return fail(ctx, DQZ_EINTERNAL, "a device-side ordering wait timed out");
+    if (st & ST_EINTERNAL) return fail(ctx, DQZ_EINTERNAL, "internal consistency check failed");
     if (st & ST_EINVAL) return fail(ctx, DQZ_EINVAL, "error bound out of range for this field");
     if (st & ST_EUNSUPPORTED) return fail(ctx, DQZ_EUNSUPPORTED, "code length above 64 bits");
     if (st & ST_ECORRUPT) return fail(ctx, DQZ_ECORRUPT, "archive failed validation");
@@ -326,7 +352,7 @@ dqz_status dqz_compress_bound(const dqz_shape *shape, const dqz_params *params, 
     P.tiles_e = encode_tiles(P.g);
     // every element an outlier and a patch (16 bytes) and a 64-bit code
     if (archive_max) *archive_max = P.L.off_exc + 16ull * P.g.nelem + 8ull * P.g.nelem + 8;
-    if (workspace_bytes) *workspace_bytes = ws_layout(P, true).total;
+    if (workspace_bytes) *workspace_bytes = ws_layout(P, true, kExcCap).total;
     return DQZ_OK;
 }
 
@@ -360,53 +386,87 @@ dqz_status dqz_compress(dqz_ctx *ctx, const float *d_field, const dqz_shape *sha
     }
     P.tiles_q = quantize_tiles(P.g);
     P.tiles_e = encode_tiles(P.g);
-    const WsLayout W = ws_layout(P, true);
     HIP_TRY(ctx, hipSetDevice(ctx->device));
-    if ((st = ensure_ws(ctx, W.total)) != DQZ_OK) return st;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    uint8_t *ws = reinterpret_cast<uint8_t *>(ctx->ws);
-    Ctl *ctl = reinterpret_cast<Ctl *>(ws + W.ctl);
-    uint32_t *hist = reinterpret_cast<uint32_t *>(ws + W.hist);
-    uint64_t *lbq = reinterpret_cast<uint64_t *>(ws + W.lbq);
-    uint64_t *lbe = reinterpret_cast<uint64_t *>(ws + W.lbe);
-    uint64_t *book = reinterpret_cast<uint64_t *>(ws + W.book);
-    uint32_t *book32 = reinterpret_cast<uint32_t *>(ws + W.book32);
-    uint32_t *parts = reinterpret_cast<uint32_t *>(ws + W.parts);
-    uint16_t *codes = reinterpret_cast<uint16_t *>(ws + W.codes);
     uint8_t *arc = reinterpret_cast<uint8_t *>(d_archive);
+    // first attempt with kExcCap staged exception records per quantize tile;
+    // a tile with more sends the call round again with room for every element
+    for (uint32_t cap : {kExcCap, 2 * kTile}) {
+        const WsLayout W = ws_layout(P, true, cap);
+        if ((st = ensure_ws(ctx, W.total)) != DQZ_OK) return st;
+        uint8_t *ws = reinterpret_cast<uint8_t *>(ctx->ws);
+        Ctl *ctl = reinterpret_cast<Ctl *>(ws + W.ctl);
+        uint32_t *hist = reinterpret_cast<uint32_t *>(ws + W.hist);
+        uint64_t *book = reinterpret_cast<uint64_t *>(ws + W.book);
+        uint32_t *book32 = reinterpret_cast<uint32_t *>(ws + W.book32);
+        uint32_t *parts = reinterpret_cast<uint32_t *>(ws + W.parts);
+        uint16_t *codes = reinterpret_cast<uint16_t *>(ws + W.codes);
+        QuantBufs qb;
+        qb.codes = codes;
+        qb.hist = hist;
+        qb.hist_sum = reinterpret_cast<uint32_t *>(ws + W.hist_sum);
+        qb.stage = reinterpret_cast<uint2 *>(ws + W.stage);
+        qb.cap = cap;
+        TileScan &qs = qb.scan;
+        for (int k = 0; k < 2; k++) {
+            qs.val[k] = reinterpret_cast<uint32_t *>(ws + W.qval[k]);
+            qs.excl[k] = reinterpret_cast<uint32_t *>(ws + W.qexcl[k]);
+            qs.seg_total[k] = reinterpret_cast<uint64_t *>(ws + W.qseg_total[k]);
+        }
+        qs.n_tiles = P.tiles_q;
+        qs.n_segs = W.n_segs_q;
+        qs.nvals = 2;
+        EncodeBufs eb;
+        eb.codes = codes;
+        eb.book = book;
+        eb.book32 = book32;
+        eb.stage = qb.stage;
+        eb.cap = cap;
+        eb.qscan = qs;
+        eb.n_tiles_q = P.tiles_q;
+        TileScan &es = eb.escan;
+        es.val[0] = reinterpret_cast<uint32_t *>(ws + W.eval);
+        es.excl[0] = reinterpret_cast<uint32_t *>(ws + W.eexcl);
+        es.seg_total[0] = reinterpret_cast<uint64_t *>(ws + W.eseg_total);
+        es.val[1] = es.excl[1] = nullptr;
+        es.seg_total[1] = nullptr;
+        es.n_tiles = P.tiles_e;
+        es.n_segs = W.n_segs_e;
+        es.nvals = 1;
 
-    ctx->ev_ready[0] = false;
-    mark(ctx, 0, 0, s);
-    launch_init(s, ctl, ws + W.hist, W.zero_end - W.hist, params->eb_mode, params->eb);
-    mark(ctx, 0, 1, s);
-    if (params->eb_mode == DQZ_EB_VALREL) launch_minmax(s, d_field, P.g.nelem, ctl, parts, params->eb, ctx->ncu);
-    mark(ctx, 0, 2, s);
-    launch_quantize(s, d_field, P.g, P.L, ctl, codes, hist, lbq, arc);
-    mark(ctx, 0, 3, s);
-    launch_codebook(s, P.g, P.L, ctl, hist, book, book32, arc, params->eb_mode, params->eb);
-    mark(ctx, 0, 4, s);
-    launch_zero_stream(s, P.g, ctl, arc);
-    mark(ctx, 0, 5, s);
-    launch_encode(s, P.g, P.L, ctl, codes, book, book32, lbe, arc);
-    mark(ctx, 0, 6, s);
-    HIP_TRY(ctx, hipGetLastError());
-    HIP_TRY(ctx, hipMemcpyAsync(ctx->h_ctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
-    HIP_TRY(ctx, hipStreamSynchronize(s));
-    ctx->ev_ready[0] = ctx->timing;
-    ctx->last_codes = codes;
-    ctx->last_hist = hist;
-    ctx->last_book = book;
-    ctx->last_ctl = ctl;
-    ctx->last_tab = reinterpret_cast<DecodeTables *>(ws + W.tab);
-    ctx->last_padded = P.g.padded;
-    ctx->last_nsym = P.L.nsym;
-    const Ctl &c = *ctx->h_ctl;
-    if (c.status & ST_ETOOSMALL) *archive_bytes = c.archive_bytes;
-    st = status_from_device(ctx, c.status);
-    if (st != DQZ_OK) return st;
-    *archive_bytes = c.archive_bytes;
-    if (h_header) memcpy(h_header, c.header, kHeaderBytes);
-    return DQZ_OK;
+        ctx->ev_ready[0] = false;
+        mark(ctx, 0, 0, s);
+        launch_init(s, ctl, ws + W.hist, W.zero_end - W.hist, params->eb_mode, params->eb);
+        mark(ctx, 0, 1, s);
+        if (params->eb_mode == DQZ_EB_VALREL) launch_minmax(s, d_field, P.g.nelem, ctl, parts, params->eb, ctx->ncu);
+        mark(ctx, 0, 2, s);
+        launch_quantize(s, d_field, P.g, P.L, ctl, qb);
+        mark(ctx, 0, 3, s);
+        launch_codebook(s, P.g, P.L, ctl, qb.hist_sum, book, book32, arc, params->eb_mode, params->eb, qs);
+        mark(ctx, 0, 4, s);
+        launch_encode(s, P.g, P.L, ctl, eb, arc);
+        mark(ctx, 0, 5, s);
+        HIP_TRY(ctx, hipGetLastError());
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->h_ctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        HIP_TRY(ctx, hipStreamSynchronize(s));
+        ctx->ev_ready[0] = ctx->timing;
+        ctx->last_codes = codes;
+        ctx->last_hist = hist;
+        ctx->last_book = book;
+        ctx->last_ctl = ctl;
+        ctx->last_tab = reinterpret_cast<DecodeTables *>(ws + W.tab);
+        ctx->last_padded = P.g.padded;
+        ctx->last_nsym = P.L.nsym;
+        const Ctl &c = *ctx->h_ctl;
+        if ((c.status & ST_RETRY) && cap < 2 * kTile) continue;
+        if (c.status & ST_ETOOSMALL) *archive_bytes = c.archive_bytes;
+        st = status_from_device(ctx, c.status);
+        if (st != DQZ_OK) return st;
+        *archive_bytes = c.archive_bytes;
+        if (h_header) memcpy(h_header, c.header, kHeaderBytes);
+        return DQZ_OK;
+    }
+    return fail(ctx, DQZ_EINTERNAL, "exception staging overflowed twice");
 }
 
 dqz_status dqz_archive_info(const void *h_header, uint64_t header_bytes, dqz_shape *shape, dqz_params *params,
@@ -447,7 +507,7 @@ dqz_status dqz_decompress(dqz_ctx *ctx, const void *d_archive, uint64_t archive_
     if (field_cap_elems < hi.nelem) return fail(ctx, DQZ_ETOOSMALL, "field capacity too small");
     if (hi.nelem && !d_field) return fail(ctx, DQZ_EINVAL, "null field");
     if (hi.nelem == 0) return DQZ_OK;
-    const WsLayout W = ws_layout(P, false);
+    const WsLayout W = ws_layout(P, false, 0);
     if ((st = ensure_ws(ctx, W.total)) != DQZ_OK) return st;
     uint8_t *ws = reinterpret_cast<uint8_t *>(ctx->ws);
     DecodeTables *tab = reinterpret_cast<DecodeTables *>(ws + W.tab);

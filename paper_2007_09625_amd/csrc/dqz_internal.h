@@ -13,7 +13,7 @@ constexpr uint32_t kVersion = 1;
 constexpr uint32_t kTile = 4096;           // padded positions per quantize / encode tile
 constexpr uint32_t kLutBits = 13;          // decode table width (u16 entries: len << 11 | sym)
 constexpr uint32_t kHistReplicas = 16;     // global histogram copies (spreads the flush atomics)
-constexpr uint32_t kSpinLimit = 1u << 20;  // look-back polls before a wait is declared stuck
+constexpr uint32_t kExcCap = 512;          // staged exception records per quantize tile (first attempt)
 constexpr uint32_t kMaxRadius = 1024;      // codebook kernel keeps 2R <= 2048 symbols in LDS
 constexpr uint32_t kMaxSyms = 2 * kMaxRadius;
 constexpr uint16_t kNoSymbol = 0xFFFF;     // code slot of a padded position outside the field
@@ -25,7 +25,8 @@ enum : uint32_t {
     ST_ETOOSMALL = 2u,     // archive capacity exceeded
     ST_EUNSUPPORTED = 4u,  // code longer than 64 bits
     ST_ECORRUPT = 8u,      // archive fails validation during decode
-    ST_EINTERNAL = 16u,    // a look-back wait exceeded its poll limit (kernel exits anyway)
+    ST_EINTERNAL = 16u,    // internal consistency check failed
+    ST_RETRY = 32u,        // exception staging overflowed: compress again with full staging
 };
 
 // Geometry: every field is viewed as (nz, ny, nx) with block extents
@@ -57,10 +58,12 @@ struct Ctl {
     float h, r;
     uint32_t vmin_key, vmax_key;   // totally ordered keys of the finite range
     uint32_t status;
-    uint32_t ticket_q, ticket_e;   // dynamic tile tickets (quantize, encode)
-    uint32_t minmax_done;
     uint32_t n_out, n_patch, n_exc;
     uint32_t max_len;
+    uint32_t exc_overflow;          // a quantize tile had more exceptions than its staging slots
+    uint32_t pad1;
+    uint64_t exc_total, out_total;  // written by the last quantize segment
+    uint64_t bits_total;            // written by the last encode-count segment
     uint64_t total_bits;
     uint64_t off_str;
     uint64_t archive_bytes;
@@ -130,49 +133,79 @@ __device__ __forceinline__ T wave_incl_scan(T v) {
 }
 
 // ---------------------------------------------------------------------------
-// Decoupled look-back (single-pass ordered prefix over tiles taken in ticket
-// order).  One 64-bit word per tile: value << 2 | flag, flag 0 = not yet
-// published, 1 = tile aggregate, 2 = inclusive prefix.  Value and flag share
-// one word, so relaxed agent-scope atomics suffice.
+// Ordered prefix over tiles, through kernel boundaries only (no spin-waits,
+// no device-scope fences: on a multi-XCD part an agent-scope release writes
+// back the L2).  The producer kernel stores one value per tile; k_seg_scan
+// (one workgroup per segment of kSegTiles tiles) writes the exclusive prefix
+// inside each segment and the segment totals; a consumer workgroup adds the
+// totals of the segments before its own with one block reduction.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void lb_publish(uint64_t *st, uint32_t tile, uint64_t value, uint32_t flag) {
-    __hip_atomic_store(st + tile, (value << 2) | flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+constexpr uint32_t kSegTiles = 256;
+constexpr uint32_t kMaxSegs = 2048;   // 2^31 positions / kTile / kSegTiles
+
+struct TileScan {
+    uint32_t *val[2];        // per tile
+    uint32_t *excl[2];       // per tile, exclusive inside the segment
+    uint64_t *seg_total[2];  // per segment
+    uint32_t n_tiles, n_segs, nvals;
+};
+
+// Exclusive scan over the 256 threads of a workgroup (u64), returns the total
+// in *total.  sh: 4 u64 of LDS scratch.
+__device__ __forceinline__ uint64_t block_excl_scan256(uint64_t v, uint64_t *sh, uint64_t *total) {
+    const uint32_t lane = lane_id(), w = threadIdx.x / 64;
+    const uint64_t incl = wave_incl_scan<uint64_t>(v);
+    __syncthreads();
+    if (lane == 63) sh[w] = incl;
+    __syncthreads();
+    uint64_t off = 0, tot = 0;
+    for (uint32_t i = 0; i < 4; i++) {
+        if (i < w) off += sh[i];
+        tot += sh[i];
+    }
+    *total = tot;
+    return off + incl - v;
 }
 
-// Called by all 64 lanes of one wave; returns the sum of the values of all
-// tiles before `tile`.
-// Tiles are numbered by workgroup index; workgroups are dispatched in
-// index order, so every tile a wait depends on has started.  The poll count
-// is bounded anyway: a stuck wait sets ST_EINTERNAL in *err and returns.
-__device__ inline uint64_t lb_exclusive(const uint64_t *st, uint32_t tile, uint32_t *err) {
-    const uint32_t lane = lane_id();
-    uint64_t excl = 0;
-    int64_t base = (int64_t)tile - 1;
-    uint32_t polls = 0;
-    while (base >= 0) {
-        if (++polls > kSpinLimit) {
-            if (lane == 0) atomicOr(err, ST_EINTERNAL);
-            return excl;
-        }
-        const int64_t j = base - (int64_t)lane;
-        uint64_t s = 2;   // virtual predecessor before tile 0: inclusive, value 0
-        if (j >= 0) s = __hip_atomic_load(st + j, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t flag = (uint32_t)(s & 3u);
-        const uint64_t empty = __ballot(flag == 0);
-        const uint64_t incl = __ballot(flag == 2);
-        if (incl) {
-            const uint32_t first = (uint32_t)__ffsll((unsigned long long)incl) - 1u;
-            const uint64_t need = (first == 63) ? ~0ull : ((2ull << first) - 1ull);
-            if (empty & need) { __builtin_amdgcn_s_sleep(1); continue; }
-            excl += wave_sum<uint64_t>(lane <= first ? (s >> 2) : 0ull);
-            break;
-        }
-        if (empty) { __builtin_amdgcn_s_sleep(1); continue; }
-        excl += wave_sum<uint64_t>(s >> 2);
-        base -= 64;
-    }
-    return excl;
+// Sum over the 256 threads of a workgroup (u64).  sh: 4 u64 of LDS scratch.
+__device__ __forceinline__ uint64_t block_sum256(uint64_t v, uint64_t *sh) {
+    uint64_t tot;
+    (void)block_excl_scan256(v, sh, &tot);
+    return tot;
 }
+
+// Producer side: one thread records the tile's value(s).
+__device__ __forceinline__ void tile_publish(const TileScan &S, uint32_t tile, uint32_t v0, uint32_t v1) {
+    if (threadIdx.x == 0) {
+        S.val[0][tile] = v0;
+        if (S.nvals > 1) S.val[1][tile] = v1;
+    }
+}
+
+// Consumer side (all 256 threads): global exclusive prefix of value k at
+// `tile`.  Reads the totals of the segments before the tile's own.
+__device__ __forceinline__ uint64_t tile_offset(const TileScan &S, uint32_t k, uint32_t tile, uint64_t *sh) {
+    const uint32_t seg = tile / kSegTiles;
+    uint64_t part = 0;
+    for (uint32_t i = threadIdx.x; i < seg; i += 256) part += S.seg_total[k][i];
+    return block_sum256(part, sh) + S.excl[k][tile];
+}
+
+// Grand total of value k (all 256 threads).
+__device__ __forceinline__ uint64_t scan_total(const TileScan &S, uint32_t k, uint64_t *sh) {
+    uint64_t part = 0;
+    for (uint32_t i = threadIdx.x; i < S.n_segs; i += 256) part += S.seg_total[k][i];
+    return block_sum256(part, sh);
+}
+
+// Optional side job of the quantize segment scan: sum the histogram
+// replicas into the final histogram (hist_out[b] = sum of the replicas).
+struct HistJob {
+    const uint32_t *replicas;
+    uint32_t *hist_out;
+    uint32_t nsym;
+};
+void launch_seg_scan(hipStream_t s, const TileScan &S, const HistJob *hj = nullptr);
 
 // ---------------------------------------------------------------------------
 // Dual-quantization arithmetic (single IEEE operations, no contraction).
@@ -193,14 +226,30 @@ __device__ __forceinline__ bool needs_patch(float v, int32_t d, float h, double 
 void launch_init(hipStream_t s, Ctl *ctl, void *zero_base, uint64_t zero_bytes, int eb_mode, double eb);
 void launch_minmax(hipStream_t s, const float *x, uint64_t n, Ctl *ctl, uint32_t *partials, double valrel, int ncu);
 constexpr uint32_t kMinmaxMaxBlocks = 2048;
-void launch_quantize(hipStream_t s, const float *x, const Geom &g, const Layout &L, Ctl *ctl, uint16_t *codes,
-                     uint32_t *hist, uint64_t *lb, uint8_t *archive);
+struct QuantBufs {
+    uint16_t *codes;
+    uint32_t *hist;        // kHistReplicas * 2R
+    uint32_t *hist_sum;    // 2R, the replicas summed
+    uint2 *stage;          // tiles * cap exception records
+    uint32_t cap;
+    TileScan scan;         // exception count (0) and outlier count (1) per tile
+};
+void launch_quantize(hipStream_t s, const float *x, const Geom &g, const Layout &L, Ctl *ctl, const QuantBufs &b);
 uint32_t quantize_tiles(const Geom &g);
 void launch_codebook(hipStream_t s, const Geom &g, const Layout &L, Ctl *ctl, const uint32_t *hist,
-                     uint64_t *book, uint32_t *book32, uint8_t *archive, int eb_mode, double eb_param);
-void launch_zero_stream(hipStream_t s, const Geom &g, Ctl *ctl, uint8_t *archive);
-void launch_encode(hipStream_t s, const Geom &g, const Layout &L, Ctl *ctl, const uint16_t *codes,
-                   const uint64_t *book, const uint32_t *book32, uint64_t *lb, uint8_t *archive);
+                     uint64_t *book, uint32_t *book32, uint8_t *archive, int eb_mode, double eb_param,
+                     const TileScan &qscan);
+struct EncodeBufs {
+    const uint16_t *codes;
+    const uint64_t *book;
+    const uint32_t *book32;
+    const uint2 *stage;    // quantize staging
+    uint32_t cap;
+    TileScan qscan;        // offsets of the staged exceptions
+    TileScan escan;        // bits per encode tile
+    uint32_t n_tiles_q;
+};
+void launch_encode(hipStream_t s, const Geom &g, const Layout &L, Ctl *ctl, const EncodeBufs &b, uint8_t *archive);
 uint32_t encode_tiles(const Geom &g);
 void launch_decode_tables(hipStream_t s, const Layout &L, const uint8_t *archive, uint32_t max_len_hdr,
                           DecodeTables *tab);

@@ -131,37 +131,88 @@ struct CanonScratch {
 };
 
 __device__ void canonical_order(const uint8_t *len, uint32_t ns, CanonScratch &c) {
-    for (uint32_t l = threadIdx.x; l < 66; l += blockDim.x) {
+    // counting sort of the symbols by code length, stable in the symbol:
+    // within a wave, ballots give each symbol its rank among the wave's
+    // symbols of equal length; per-(chunk, length) counts give the rest
+    const uint32_t tid = threadIdx.x, lane = lane_id(), w = tid / 64;
+    const uint32_t nk = ns < 256 ? 256 : ns;
+    const uint32_t chunks = nk / 256;              // symbols per thread: tid + 256 * r
+    uint32_t *cnt = reinterpret_cast<uint32_t *>(c.xch);   // [chunks * 4 waves][65]
+    for (uint32_t l = tid; l < 66; l += blockDim.x) {
         c.count[l] = 0;
         c.first_index[l] = 0;
         c.first_code[l] = 0;
     }
-    if (threadIdx.x == 0) { c.n_used = 0; c.max_len = 0; }
-    sort_into(ns, c.key, c.xch, [&](uint32_t s) -> uint64_t {
-        return (s < ns && len[s]) ? (((uint64_t)len[s] << 16) | s) : ~0ull;
-    });
-    const uint32_t nk = ns < 256 ? 256 : ns;
-    for (uint32_t i = threadIdx.x; i < nk; i += blockDim.x) {
-        const uint64_t k = c.key[i];
-        if (k == ~0ull) continue;
-        const uint32_t l = (uint32_t)(k >> 16);
-        const bool first = (i == 0) || ((uint32_t)(c.key[i - 1] >> 16) != l);
-        if (first) c.first_index[l] = i;
-        const bool end = (i + 1 == nk) || c.key[i + 1] == ~0ull;
-        const bool last = end || ((uint32_t)(c.key[i + 1] >> 16) != l);
-        if (last) {
-            c.count[l] = i + 1;   // turned into a count below
-            if (end) { c.n_used = i + 1; c.max_len = l; }
+    uint32_t ml = 0;
+    for (uint32_t r = 0; r < chunks; r++) {
+        const uint32_t sym = tid + 256 * r;
+        const uint32_t l = sym < ns ? len[sym] : 0u;
+        ml = l > ml ? l : ml;
+    }
+    ml = wave_max<uint32_t>(ml);
+    if (lane == 0) cnt[w] = ml;
+    __syncthreads();
+    const uint32_t m01 = cnt[0] > cnt[1] ? cnt[0] : cnt[1], m23 = cnt[2] > cnt[3] ? cnt[2] : cnt[3];
+    const uint32_t max_len = m01 > m23 ? m01 : m23;
+    __syncthreads();
+    // lengths above 64 (only reachable from damaged input) are reported through
+    // max_len and otherwise left out of the order
+    const uint32_t lmax = max_len > 64 ? 64 : max_len;
+    constexpr uint32_t kChunks = kMaxSyms / 256;
+    uint32_t myrank[kChunks];
+#pragma unroll
+    for (uint32_t r = 0; r < kChunks; r++) {
+        myrank[r] = 0;
+        if (r >= chunks) continue;
+        const uint32_t sym = tid + 256 * r;
+        const uint32_t l = sym < ns ? len[sym] : 0u;
+        const uint64_t below = lanes_below(lane);
+        uint32_t rk = 0;
+        for (uint32_t L = 1; L <= lmax; L++) {
+            const uint64_t m = __ballot(l == L);
+            if (l == L) rk = __popcll(m & below);
+            if (lane == 0) cnt[(r * 4 + w) * 65 + L] = __popcll(m);
         }
+        myrank[r] = rk;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-        for (uint32_t l = 1; l <= 64; l++)
-            if (c.count[l]) c.count[l] -= c.first_index[l];
+    // per length: exclusive prefix over the (chunk, wave) groups, in symbol order
+    const uint32_t groups = chunks * 4;
+    for (uint32_t L = 1 + tid; L <= lmax; L += blockDim.x) {
+        uint32_t run = 0;
+        for (uint32_t gi = 0; gi < groups; gi++) {
+            const uint32_t v = cnt[gi * 65 + L];
+            cnt[gi * 65 + L] = run;
+            run += v;
+        }
+        c.count[L] = run;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t acc = 0;
+        for (uint32_t L = 1; L <= 64; L++) {
+            c.first_index[L] = acc;
+            acc += c.count[L];
+        }
+        c.n_used = acc;
+        c.max_len = max_len;
         uint64_t code = 0;
         for (uint32_t bits = 1; bits <= 64; bits++) {
             code = (code + c.count[bits - 1]) << 1;
             c.first_code[bits] = code;
+        }
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < nk; i += blockDim.x) c.key[i] = ~0ull;
+    __syncthreads();
+#pragma unroll
+    for (uint32_t r = 0; r < kChunks; r++) {
+        if (r >= chunks) continue;
+        const uint32_t sym = tid + 256 * r;
+        const uint32_t l = sym < ns ? len[sym] : 0u;
+        if (l && l <= lmax) {
+            const uint32_t pos = c.first_index[l] + cnt[(r * 4 + w) * 65 + l] + myrank[r];
+            c.key[pos] = ((uint64_t)l << 16) | sym;
         }
     }
     __syncthreads();
@@ -190,26 +241,23 @@ struct BookLds {
 
 __global__ __launch_bounds__(kBookThreads) void k_codebook(const uint32_t *__restrict__ hist, Ctl *ctl,
                                                            uint64_t *__restrict__ book, uint32_t *__restrict__ book32,
-                                                           uint8_t *archive, Layout L, Geom g, HeaderArgs hdr) {
+                                                           uint8_t *archive, Layout L, Geom g, HeaderArgs hdr,
+                                                           TileScan qscan) {
     __shared__ BookLds s;
+    __shared__ uint64_t s_red[4];
     const uint32_t tid = threadIdx.x, T = blockDim.x;
     const uint32_t ns = L.nsym;
     if (ctl->status & (ST_EINVAL | ST_EINTERNAL)) return;
     if (tid == 0) ctl->phase[0] = wall_clock64();
 
-    // sum the global histogram replicas (all loads of a thread in flight)
+    // the histogram (replicas already summed by the segment scan)
     {
         constexpr uint32_t kPer = kMaxSyms / kBookThreads;
         uint32_t f[kPer];
 #pragma unroll
-        for (uint32_t k = 0; k < kPer; k++) f[k] = 0;
-#pragma unroll
-        for (uint32_t r = 0; r < kHistReplicas; r++) {
-#pragma unroll
-            for (uint32_t k = 0; k < kPer; k++) {
-                const uint32_t i = tid + kBookThreads * k;
-                if (i < ns) f[k] += hist[r * ns + i];
-            }
+        for (uint32_t k = 0; k < kPer; k++) {
+            const uint32_t i = tid + kBookThreads * k;
+            f[k] = (i < ns) ? hist[i] : 0u;
         }
 #pragma unroll
         for (uint32_t k = 0; k < kPer; k++) {
@@ -219,6 +267,12 @@ __global__ __launch_bounds__(kBookThreads) void k_codebook(const uint32_t *__res
     }
     if (tid == 0) { s.n = 0; s.total_bits = 0; s.nl[0] = s.nl[1] = s.ni[0] = s.ni[1] = 0; }
     __syncthreads();
+    // exception totals from the quantize tiles' segment totals
+    {
+        const uint64_t exc = scan_total(qscan, 0, s_red);
+        const uint64_t out = scan_total(qscan, 1, s_red);
+        if (tid == 0) { ctl->exc_total = exc; ctl->out_total = out; }
+    }
     if (tid == 0) ctl->phase[1] = wall_clock64();
     // leaves with nonzero frequency sorted by (frequency, symbol)
     sort_into(ns, s.canon.key, s.canon.xch, [&](uint32_t i) -> uint64_t {
@@ -342,9 +396,13 @@ __global__ __launch_bounds__(kBookThreads) void k_codebook(const uint32_t *__res
     if (tid == 0) {
         ctl->phase[6] = wall_clock64();
         if (max_len > 64) atomicOr(&ctl->status, ST_EUNSUPPORTED);
+        if (ctl->exc_overflow) atomicOr(&ctl->status, ST_RETRY);
         const uint64_t total_bits = s.total_bits;
         const uint64_t n_words = (total_bits + 31) / 32;
-        const uint32_t n_exc = ctl->n_exc;
+        const uint32_t n_exc = (uint32_t)ctl->exc_total;
+        ctl->n_exc = n_exc;
+        ctl->n_out = (uint32_t)ctl->out_total;
+        ctl->n_patch = (uint32_t)(ctl->exc_total - ctl->out_total);
         const uint64_t off_str = L.off_exc + 8ull * n_exc;
         const uint64_t end = off_str + 4ull * n_words;
         ctl->max_len = max_len;
@@ -395,7 +453,7 @@ __global__ __launch_bounds__(kBookThreads) void k_codebook(const uint32_t *__res
 }
 
 void launch_codebook(hipStream_t st, const Geom &g, const Layout &L, Ctl *ctl, const uint32_t *hist, uint64_t *book,
-                     uint32_t *book32, uint8_t *archive, int eb_mode, double eb_param) {
+                     uint32_t *book32, uint8_t *archive, int eb_mode, double eb_param, const TileScan &qscan) {
     HeaderArgs h;
     h.dims[0] = g.n[0];
     h.dims[1] = g.n[1];
@@ -403,7 +461,7 @@ void launch_codebook(hipStream_t st, const Geom &g, const Layout &L, Ctl *ctl, c
     h.eb_param = eb_param;
     h.ndim = g.ndim;
     h.eb_mode = (uint32_t)eb_mode;
-    hipLaunchKernelGGL(k_codebook, dim3(1), dim3(kBookThreads), 0, st, hist, ctl, book, book32, archive, L, g, h);
+    hipLaunchKernelGGL(k_codebook, dim3(1), dim3(kBookThreads), 0, st, hist, ctl, book, book32, archive, L, g, h, qscan);
 }
 
 // ---------------------------------------------------------------------------

@@ -11,12 +11,12 @@
 //               postquantization with the +-R cap and outliers (Algorithm 2),
 //               the rehearsal check that turns a missed bound into a patch
 //               (Algorithm 1's watchdog), an LDS-privatized histogram of the
-//               codes (Sec. 3.2.1), and ordered compaction of the exceptions
-//               via decoupled look-back.
+//               codes (Sec. 3.2.1), and the per-tile exception records.
 //
-// Each quantize workgroup handles one tile of kTile padded positions, tile
-// index = workgroup index (workgroups start in index order, so the
-// look-back only waits on tiles already running).  The tile is staged in LDS
+// Each quantize workgroup handles one tile of kTile padded positions.  Its
+// exception records (in stream order) go to the tile's staging slots and
+// its record count is scanned across tiles by k_seg_scan; the encoder later
+// copies the records to their final place.  The tile is staged in LDS
 // with fully coalesced row loads; the Lorenzo delta is the mixed backward
 // difference, computed per axis with registers (slow axis) and cross-lane
 // shuffles (fast axes).
@@ -182,10 +182,7 @@ struct QuantArgs {
     Geom g;
     Layout L;
     Ctl *ctl;
-    uint16_t *codes;
-    uint32_t *hist;      // global histogram (2R)
-    uint64_t *lb;        // look-back words, one per tile
-    uint8_t *archive;
+    QuantBufs b;
     uint32_t n_tiles;
     uint32_t tiles_per_row;
 };
@@ -200,53 +197,43 @@ __device__ __forceinline__ void hist_flush(uint32_t *sh_hist, uint32_t nsym, uin
     }
 }
 
-// Workgroup-level ordered allocation of exception records: every wave
-// reports its record count; returns this wave's first global record index.
-// Also publishes / resolves the tile's look-back word.
-__device__ __forceinline__ uint64_t exceptions_base(const QuantArgs &a, uint32_t tile, uint32_t wave_count,
-                                                    uint32_t wave_out, uint32_t wave_patch, uint32_t *sh) {
-    // sh: [0..3] wave counts, [4] tile base low, [5] tile base high, [6..7] out/patch
+// Each wave reports its record count; returns the wave's first record index
+// inside the tile and the tile totals.
+__device__ __forceinline__ uint32_t wave_base_in_tile(uint32_t wave_count, uint32_t wave_out, uint32_t *sh,
+                                                      uint32_t &tile_count, uint32_t &tile_out) {
     const uint32_t w = threadIdx.x / 64, nw = blockDim.x / 64;
-    if (lane_id() == 0) { sh[w] = wave_count; sh[8 + w] = wave_out; sh[12 + w] = wave_patch; }
+    if (lane_id() == 0) { sh[w] = wave_count; sh[8 + w] = wave_out; }
     __syncthreads();
-    if (w == 0) {
-        uint32_t tot = 0, tout = 0, tpat = 0;
-        for (uint32_t i = 0; i < nw; i++) { tot += sh[i]; tout += sh[8 + i]; tpat += sh[12 + i]; }
-        uint64_t base = 0;
-        if (tile == 0) {
-            if (lane_id() == 0) lb_publish(a.lb, tile, tot, 2);
-        } else {
-            if (lane_id() == 0) lb_publish(a.lb, tile, tot, 1);
-            base = lb_exclusive(a.lb, tile, &a.ctl->status);
-            if (lane_id() == 0) lb_publish(a.lb, tile, base + tot, 2);
-        }
-        if (lane_id() == 0) {
-            sh[4] = (uint32_t)base;
-            sh[5] = (uint32_t)(base >> 32);
-            if (tout) atomicAdd(&a.ctl->n_out, tout);
-            if (tpat) atomicAdd(&a.ctl->n_patch, tpat);
-            if (tile == a.n_tiles - 1) a.ctl->n_exc = (uint32_t)(base + tot);
-        }
+    uint32_t base = 0, tot = 0, tout = 0;
+    for (uint32_t i = 0; i < nw; i++) {
+        if (i < w) base += sh[i];
+        tot += sh[i];
+        tout += sh[8 + i];
     }
-    __syncthreads();
-    uint64_t base = (uint64_t)sh[4] | ((uint64_t)sh[5] << 32);
-    for (uint32_t i = 0; i < w; i++) base += sh[i];
+    tile_count = tot;
+    tile_out = tout;
     return base;
 }
 
-__device__ __forceinline__ void put_exc(const QuantArgs &a, uint64_t idx, uint32_t key, uint32_t payload) {
-    const uint64_t off = a.L.off_exc + 8ull * idx;
-    if (off + 8 <= a.L.cap) {
+__device__ __forceinline__ void put_exc(const QuantArgs &a, uint32_t tile, uint32_t idx, uint32_t key, uint32_t payload) {
+    if (idx < a.b.cap) {
         uint2 rec;
         rec.x = key;
         rec.y = payload;
-        *reinterpret_cast<uint2 *>(a.archive + off) = rec;
-    } else {
-        atomicOr(&a.ctl->status, ST_ETOOSMALL);
+        a.b.stage[(uint64_t)tile * a.b.cap + idx] = rec;
     }
 }
 
-
+// Tile epilogue shared by all dimensionalities: overflow flag, histogram
+// flush, and the wait-free scan of the record counts.
+__device__ __forceinline__ void tile_epilogue(const QuantArgs &a, uint32_t tile, uint32_t tile_count, uint32_t tile_out,
+                                              uint32_t *sh_hist, uint64_t *sh64) {
+    if (threadIdx.x == 0 && tile_count > a.b.cap) a.ctl->exc_overflow = 1u;
+    __syncthreads();
+    hist_flush(sh_hist, a.L.nsym, a.b.hist);
+    tile_publish(a.b.scan, tile, tile_count, tile_out);
+    (void)sh64;
+}
 
 // ---------------------------------------------------------------------------
 // 3D: tile = 8 consecutive 8x8x8 blocks along x in one block row.
@@ -260,6 +247,7 @@ __global__ __launch_bounds__(256) void k_quant3d(QuantArgs a) {
     extern __shared__ uint32_t sh_hist[];
     __shared__ float s_tile[8][8][kRow3];
     __shared__ uint32_t s_misc[16];
+    __shared__ uint64_t s_scan[10];
 
     Ctl *ctl = a.ctl;
     if (ctl->status & ST_EINVAL) return;
@@ -330,7 +318,7 @@ __global__ __launch_bounds__(256) void k_quant3d(QuantArgs a) {
                 q = incap ? (uint16_t)(del + R) : (uint16_t)0;
                 atomicAdd(&sh_hist[q], 1u);
             }
-            if (blk_ok) a.codes[blk * 512 + z * 64 + lane] = q;
+            if (blk_ok) a.b.codes[blk * 512 + z * 64 + lane] = q;
             flags_o |= (o ? 1u : 0u) << (j * 8 + z);
             flags_p |= (p ? 1u : 0u) << (j * 8 + z);
             const uint64_t mo = __ballot(o), mp = __ballot(p);
@@ -340,9 +328,11 @@ __global__ __launch_bounds__(256) void k_quant3d(QuantArgs a) {
         }
     }
 
-    const uint64_t base0 = exceptions_base(a, tile, wave_count, wave_out, wave_patch, s_misc);
+    uint32_t tile_count, tile_out;
+    const uint32_t base0 = wave_base_in_tile(wave_count, wave_out, s_misc, tile_count, tile_out);
+    (void)wave_patch;
     if (wave_count) {
-        uint64_t base = base0;
+        uint32_t base = base0;
         const uint64_t below = lanes_below(lane);
 #pragma unroll
         for (uint32_t j = 0; j < 2; j++) {
@@ -353,16 +343,15 @@ __global__ __launch_bounds__(256) void k_quant3d(QuantArgs a) {
                 const bool o = (flags_o >> (j * 8 + z)) & 1u, p = (flags_p >> (j * 8 + z)) & 1u;
                 const uint64_t mo = __ballot(o), mp = __ballot(p);
                 if ((mo | mp) == 0) continue;
-                const uint64_t idx = base + __popcll(mo & below) + __popcll(mp & below);
+                const uint32_t idx = base + __popcll(mo & below) + __popcll(mp & below);
                 const uint32_t pos = (uint32_t)(blk * 512 + z * 64 + lane);
-                if (o) put_exc(a, idx, 2u * pos, (uint32_t)delta[j][z]);
-                if (p) put_exc(a, idx + (o ? 1 : 0), 2u * pos + 1u, __float_as_uint(s_tile[z][ly][bxl * 8 + lx]));
+                if (o) put_exc(a, tile, idx, 2u * pos, (uint32_t)delta[j][z]);
+                if (p) put_exc(a, tile, idx + (o ? 1 : 0), 2u * pos + 1u, __float_as_uint(s_tile[z][ly][bxl * 8 + lx]));
                 base += __popcll(mo) + __popcll(mp);
             }
         }
     }
-    __syncthreads();
-    hist_flush(sh_hist, a.L.nsym, a.hist);
+    tile_epilogue(a, tile, tile_count, tile_out, sh_hist, s_scan);
 }
 
 // ---------------------------------------------------------------------------
@@ -377,6 +366,7 @@ __global__ __launch_bounds__(256) void k_quant2d(QuantArgs a) {
     extern __shared__ uint32_t sh_hist[];
     __shared__ float s_tile[16][16 * kT2];
     __shared__ uint32_t s_misc[16];
+    __shared__ uint64_t s_scan[10];
 
     Ctl *ctl = a.ctl;
     if (ctl->status & ST_EINVAL) return;
@@ -432,7 +422,7 @@ __global__ __launch_bounds__(256) void k_quant2d(QuantArgs a) {
             q = incap ? (uint16_t)(del + R) : (uint16_t)0;
             atomicAdd(&sh_hist[q], 1u);
         }
-        if (blk_ok) a.codes[blk * 256 + y * 16 + lx] = q;
+        if (blk_ok) a.b.codes[blk * 256 + y * 16 + lx] = q;
         flags_o |= (o ? 1u : 0u) << y;
         flags_p |= (p ? 1u : 0u) << y;
         my_count += (o ? 1u : 0u) + (p ? 1u : 0u);
@@ -447,9 +437,11 @@ __global__ __launch_bounds__(256) void k_quant2d(QuantArgs a) {
                    g3 = __shfl(grp_total, 48, 64);
     const uint32_t wave_count = g0 + g1 + g2 + g3;
     const uint32_t grp_off = (grp > 0 ? g0 : 0u) + (grp > 1 ? g1 : 0u) + (grp > 2 ? g2 : 0u);
-    const uint64_t base0 = exceptions_base(a, tile, wave_count, wave_out, wave_patch, s_misc);
+    uint32_t tile_count, tile_out;
+    const uint32_t base0 = wave_base_in_tile(wave_count, wave_out, s_misc, tile_count, tile_out);
+    (void)wave_patch;
     if (wave_count) {
-        uint64_t base = base0 + grp_off;
+        uint32_t base = base0 + grp_off;
         const uint64_t gmask = 0xFFFFull << (16 * grp);
         const uint64_t below = lanes_below(lane) & gmask;
 #pragma unroll
@@ -457,15 +449,14 @@ __global__ __launch_bounds__(256) void k_quant2d(QuantArgs a) {
             const bool o = (flags_o >> y) & 1u, p = (flags_p >> y) & 1u;
             const uint64_t mo = __ballot(o), mp = __ballot(p);
             if ((mo | mp) == 0) continue;
-            const uint64_t idx = base + __popcll(mo & below) + __popcll(mp & below);
+            const uint32_t idx = base + __popcll(mo & below) + __popcll(mp & below);
             const uint32_t pos = (uint32_t)(blk * 256 + y * 16 + lx);
-            if (o) put_exc(a, idx, 2u * pos, (uint32_t)delta[y]);
-            if (p) put_exc(a, idx + (o ? 1 : 0), 2u * pos + 1u, __float_as_uint(s_tile[y][bxl * 16 + lx]));
+            if (o) put_exc(a, tile, idx, 2u * pos, (uint32_t)delta[y]);
+            if (p) put_exc(a, tile, idx + (o ? 1 : 0), 2u * pos + 1u, __float_as_uint(s_tile[y][bxl * 16 + lx]));
             base += __popcll(mo & gmask) + __popcll(mp & gmask);
         }
     }
-    __syncthreads();
-    hist_flush(sh_hist, a.L.nsym, a.hist);
+    tile_epilogue(a, tile, tile_count, tile_out, sh_hist, s_scan);
 }
 
 // ---------------------------------------------------------------------------
@@ -477,6 +468,7 @@ __global__ __launch_bounds__(256) void k_quant1d(QuantArgs a) {
     extern __shared__ uint32_t sh_hist[];
     __shared__ float s_tile[kTile];
     __shared__ uint32_t s_misc[16];
+    __shared__ uint64_t s_scan[10];
 
     Ctl *ctl = a.ctl;
     if (ctl->status & ST_EINVAL) return;
@@ -540,31 +532,32 @@ __global__ __launch_bounds__(256) void k_quant1d(QuantArgs a) {
             v0.z = q[4] | ((uint32_t)q[5] << 16); v0.w = q[6] | ((uint32_t)q[7] << 16);
             v1.x = q[8] | ((uint32_t)q[9] << 16); v1.y = q[10] | ((uint32_t)q[11] << 16);
             v1.z = q[12] | ((uint32_t)q[13] << 16); v1.w = q[14] | ((uint32_t)q[15] << 16);
-            uint4 *dst = reinterpret_cast<uint4 *>(a.codes + pos0);
+            uint4 *dst = reinterpret_cast<uint4 *>(a.b.codes + pos0);
             dst[0] = v0;
             dst[1] = v1;
         } else {
 #pragma unroll
             for (uint32_t i = 0; i < 16; i++)
-                if (pos0 + i < a.g.padded) a.codes[pos0 + i] = q[i];
+                if (pos0 + i < a.g.padded) a.b.codes[pos0 + i] = q[i];
         }
     }
     const uint32_t incl = wave_incl_scan<uint32_t>(my_count);
     const uint32_t wave_count = __shfl(incl, 63, 64);
     const uint32_t wave_out = wave_sum<uint32_t>(__popc(flags_o));
     const uint32_t wave_patch = wave_sum<uint32_t>(__popc(flags_p));
-    const uint64_t base0 = exceptions_base(a, tile, wave_count, wave_out, wave_patch, s_misc);
+    uint32_t tile_count, tile_out;
+    const uint32_t base0 = wave_base_in_tile(wave_count, wave_out, s_misc, tile_count, tile_out);
+    (void)wave_patch;
     if (my_count) {
-        uint64_t idx = base0 + incl - my_count;
+        uint32_t idx = base0 + incl - my_count;
 #pragma unroll
         for (uint32_t i = 0; i < 16; i++) {
             const uint32_t pos = (uint32_t)(p0 + 16 * t + i);
-            if ((flags_o >> i) & 1u) put_exc(a, idx++, 2u * pos, (uint32_t)delta[i]);
-            if ((flags_p >> i) & 1u) put_exc(a, idx++, 2u * pos + 1u, __float_as_uint(s_tile[16 * t + i]));
+            if ((flags_o >> i) & 1u) put_exc(a, tile, idx++, 2u * pos, (uint32_t)delta[i]);
+            if ((flags_p >> i) & 1u) put_exc(a, tile, idx++, 2u * pos + 1u, __float_as_uint(s_tile[16 * t + i]));
         }
     }
-    __syncthreads();
-    hist_flush(sh_hist, a.L.nsym, a.hist);
+    tile_epilogue(a, tile, tile_count, tile_out, sh_hist, s_scan);
 }
 
 uint32_t quantize_tiles(const Geom &g) {
@@ -574,17 +567,13 @@ uint32_t quantize_tiles(const Geom &g) {
     return (uint32_t)((g.padded + kTile - 1) / kTile);
 }
 
-void launch_quantize(hipStream_t s, const float *x, const Geom &g, const Layout &L, Ctl *ctl, uint16_t *codes,
-                     uint32_t *hist, uint64_t *lb, uint8_t *archive) {
+void launch_quantize(hipStream_t s, const float *x, const Geom &g, const Layout &L, Ctl *ctl, const QuantBufs &b) {
     QuantArgs a;
     a.x = x;
     a.g = g;
     a.L = L;
     a.ctl = ctl;
-    a.codes = codes;
-    a.hist = hist;
-    a.lb = lb;
-    a.archive = archive;
+    a.b = b;
     a.n_tiles = quantize_tiles(g);
     if (a.n_tiles == 0) return;
     const size_t lds = sizeof(uint32_t) * L.nsym;
@@ -598,6 +587,11 @@ void launch_quantize(hipStream_t s, const float *x, const Geom &g, const Layout 
         a.tiles_per_row = 1;
         hipLaunchKernelGGL(k_quant1d, dim3(a.n_tiles), dim3(256), lds, s, a);
     }
+    HistJob hj;
+    hj.replicas = b.hist;
+    hj.hist_out = b.hist_sum;
+    hj.nsym = L.nsym;
+    launch_seg_scan(s, b.scan, &hj);
 }
 
 }  // namespace dqz
