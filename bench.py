@@ -37,6 +37,35 @@ WORKLOADS = {
 }
 
 
+KERNEL_OF_STAGE = {"range_eb": ("k_minmax", "kernels_quant.hip"), "quantize": ("k_quant", "kernels_quant.hip"),
+                   "encode": ("k_enc_pack", "kernels_encode.hip"), "decode": ("k_decode", "kernels_decode.hip")}
+
+
+def counted_traffic(stage, workload):
+    """HBM bytes per launch of the stage's main kernel from the committed
+    FETCH_SIZE / WRITE_SIZE counter summary (profiles/traffic_<workload>.json),
+    each counter scaled by what it reads for a plain device copy of known size.
+    None when there is no summary for that kernel or when the kernel's source
+    file has changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if stage not in KERNEL_OF_STAGE or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    kernel, src = KERNEL_OF_STAGE[stage]
+    k = rec.get("kernels", {}).get(kernel)
+    if not k:
+        return None
+    with open(os.path.join(ROOT, "paper_2007_09625_amd", "csrc", src), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != k["source_sha256"]:
+            return None
+    cal = rec["copy_calibration"]
+    fetch_scale = cal["bytes"] / (cal["fetch_kib"] * 1024.0)
+    write_scale = cal["bytes"] / (cal["write_kib"] * 1024.0)
+    return k["fetch_kib"] * 1024.0 * fetch_scale + k["write_kib"] * 1024.0 * write_scale
+
+
 def pct(v, q):
     s = sorted(v)
     if not s:
@@ -161,8 +190,10 @@ def main() -> int:
     roofline = None
     if dom:
         ach = algo[dom] / (stages_us[dom] * 1e-6) / 1e9
+        traffic = counted_traffic(dom, args.workload)
         roofline = {"bound": "hbm", "kernel": dom, "achieved": round(ach, 1), "peak": HBM_PEAK_GBPS,
-                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBPS, 4), "traffic": None,
+                    "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBPS, 4),
+                    "traffic": round(traffic) if traffic is not None else None,
                     "algorithmic_bytes": algo[dom], "avg_us": round(stages_us[dom], 2)}
 
     comp_p50, dec_p50 = pct(lat_c, 0.5), pct(lat_d, 0.5)

@@ -221,3 +221,31 @@ def test_parity_full_size_workloads(ctx, name, eb):
     h = au.header(arc)
     print(f"{name} eb={eb}: {x.nbytes / arc.size:.2f}x, {8 * arc.size / x.size:.3f} bits/elem, "
           f"outliers {h['n_out']}, patches {h['n_patch']}, max_len {h['max_len']}")
+
+
+def _fibonacci_field(k, seed):
+    """1D field (absolute eb 0.5, so prequant is the identity on integers) whose
+    Lorenzo deltas take k values with Fibonacci frequencies: the Huffman tree is
+    a chain and the longest code has k - 1 bits.  Values are rebuilt from the
+    chosen deltas block by block (1D blocks of 32), so every delta is exact."""
+    fib = [1, 1]
+    while len(fib) < k:
+        fib.append(fib[-1] + fib[-2])
+    deltas = np.repeat(np.arange(-(k // 2), k - k // 2, dtype=np.int64), fib[:k])
+    rng = np.random.default_rng(seed)
+    rng.shuffle(deltas)
+    n = deltas.size
+    pad = (-n) % 32
+    blocks = np.concatenate([deltas, np.zeros(pad, np.int64)]).reshape(-1, 32)
+    x = np.cumsum(blocks, axis=1).ravel()[:n]
+    assert np.abs(x).max() < (1 << 24)
+    return x.astype(np.float32)
+
+
+@pytest.mark.parametrize("k", [28, 35], ids=["max_len27", "max_len34"])
+def test_parity_long_codes(ctx, k):
+    """Codes longer than 24 bits take the 64-bit codeword path of the encoder;
+    codes longer than 32 bits take the decoder's window restart."""
+    x = _fibonacci_field(k, seed=k)
+    arc = _check(ctx, x, 0.5, 0, radius=64)
+    assert au.header(arc)["max_len"] == k - 1
