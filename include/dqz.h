@@ -153,13 +153,18 @@ dqz_status dqz_stage_times(dqz_ctx *ctx, int which, double *us, int *n_stages);
  *   DQZ_DBG_CODES      u16 per padded position (0xFFFF outside the field)
  *   DQZ_DBG_HISTOGRAM  u32[2R]
  *   DQZ_DBG_CODEBOOK   u64[2R], (length << 56) | canonical code
- *   DQZ_DBG_PHASES     u64[24], phase timestamps of the one-workgroup kernels
+ *   DQZ_DBG_PHASES     u64[32], phase timestamps of the one-workgroup kernels and
+ *                      decode-phase durations (recorded while stage timing is on)
  * `bytes` must equal the buffer's size. */
 #define DQZ_DBG_CODES 1
 #define DQZ_DBG_HISTOGRAM 2
 #define DQZ_DBG_CODEBOOK 3
-#define DQZ_DBG_PHASES 4     /* u64[24]: wall-clock (100 MHz) marks inside the codebook
-                                kernel [0..15] and the decoding-table kernel [16..23] */
+#define DQZ_DBG_PHASES 4     /* u64[32], wall clock at 100 MHz: marks inside the codebook
+                                kernel [0..15] and the decoding-table kernel [16..18];
+                                first decode-wave start [24], last decode-wave end [25],
+                                decode-phase durations summed over the decode waves
+                                [26..31]: tables, stream window + exception search,
+                                inflate, outlier marks, reconstruct, patches */
 dqz_status dqz_debug_copy(dqz_ctx *ctx, int what, void *h_dst, uint64_t bytes);
 
 #ifdef __cplusplus

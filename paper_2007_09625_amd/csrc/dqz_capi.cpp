@@ -516,7 +516,7 @@ dqz_status dqz_decompress(dqz_ctx *ctx, const void *d_archive, uint64_t archive_
     mark(ctx, 1, 0, s);
     launch_decode_tables(s, P.L, arc, hi.max_len, tab);
     mark(ctx, 1, 1, s);
-    launch_decode(s, P.g, P.L, arc, hi.off_str, hi.n_words, (uint32_t)hi.n_exc, hi.h, tab, d_field);
+    launch_decode(s, P.g, P.L, arc, hi.off_str, hi.n_words, (uint32_t)hi.n_exc, hi.h, tab, d_field, ctx->timing);
     mark(ctx, 1, 2, s);
     HIP_TRY(ctx, hipGetLastError());
     HIP_TRY(ctx, hipMemcpyAsync(&ctx->h_ctl->status, &tab->status, 4, hipMemcpyDeviceToHost, s));
@@ -577,11 +577,11 @@ dqz_status dqz_debug_copy(dqz_ctx *ctx, int what, void *h_dst, uint64_t bytes) {
         case DQZ_DBG_CODEBOOK: src = ctx->last_book; need = 8ull * ctx->last_nsym; break;
         case DQZ_DBG_PHASES: {
             if (!ctx->last_ctl) return fail(ctx, DQZ_EINVAL, "no compression has run on this context");
-            if (bytes != 8 * 24) return fail(ctx, DQZ_EINVAL, "size mismatch");
+            if (bytes != 8 * 32) return fail(ctx, DQZ_EINVAL, "size mismatch");
             HIP_TRY(ctx, hipSetDevice(ctx->device));
             uint64_t *dst = reinterpret_cast<uint64_t *>(h_dst);
             HIP_TRY(ctx, hipMemcpy(dst, ctx->last_ctl->phase, 8 * 16, hipMemcpyDeviceToHost));
-            HIP_TRY(ctx, hipMemcpy(dst + 16, ctx->last_tab->phase, 8 * 8, hipMemcpyDeviceToHost));
+            HIP_TRY(ctx, hipMemcpy(dst + 16, ctx->last_tab->phase, 8 * 16, hipMemcpyDeviceToHost));
             return DQZ_OK;
         }
         default: return fail(ctx, DQZ_EINVAL, "unknown stage");

@@ -85,7 +85,10 @@ struct DecodeTables {
     uint16_t sorted[kMaxSyms];      // symbols in canonical order
     uint32_t max_len;
     uint32_t status;
-    uint64_t phase[8];
+    // [0..2] this kernel's marks; [8] first decode-wave start, [9] last
+    // decode-wave end, [10..15] decode-phase durations summed over the waves
+    // (tables, window + search, inflate, outlier marks, reconstruct, patches)
+    uint64_t phase[16];
 };
 
 // ---------------------------------------------------------------------------
@@ -118,6 +121,15 @@ __device__ __forceinline__ T wave_max(T v) {
         v = o > v ? o : v;
     }
     return v;
+}
+
+// Workgroups of one launch are dispatched round-robin over the 8 XCDs, each
+// with its own L2.  This bijection of [0, n) gives every XCD a contiguous run
+// of tiles, so cache lines shared by neighbouring tiles stay in one L2.
+constexpr uint32_t kXcds = 8;
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t wg, uint32_t n) {
+    const uint32_t x = wg % kXcds, k = wg / kXcds, q = n / kXcds, r = n % kXcds;
+    return x * q + (x < r ? x : r) + k;
 }
 
 // Inclusive prefix sum over the 64 lanes.
@@ -255,6 +267,6 @@ void launch_decode_tables(hipStream_t s, const Layout &L, const uint8_t *archive
                           DecodeTables *tab);
 size_t decode_lds_bytes(const Layout &L);
 void launch_decode(hipStream_t s, const Geom &g, const Layout &L, const uint8_t *archive, uint64_t off_str,
-                   uint64_t n_words, uint32_t n_exc, float h, DecodeTables *tab, float *out);
+                   uint64_t n_words, uint32_t n_exc, float h, DecodeTables *tab, float *out, bool trace);
 
 }  // namespace dqz

@@ -125,18 +125,6 @@ __global__ __launch_bounds__(256) void k_enc_count(EncArgs a) {
 // ---------------------------------------------------------------------------
 // pass 2
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void or_bits(uint32_t *buf, uint32_t bit, uint64_t code, uint32_t len) {
-    // write `len` bits of `code` (MSB first) starting at buffer bit `bit`
-    while (len) {
-        const uint32_t w = bit >> 5, o = bit & 31u;
-        const uint32_t take = (32u - o) < len ? (32u - o) : len;
-        const uint32_t chunk = (uint32_t)((code >> (len - take)) & ((take == 32u) ? 0xFFFFFFFFull : ((1ull << take) - 1ull)));
-        atomicOr(buf + w, chunk << (32u - o - take));
-        bit += take;
-        len -= take;
-    }
-}
-
 template <bool WIDE>
 __device__ __forceinline__ void pack_tile(const EncArgs &a, uint64_t *s_dyn, uint64_t *s_scan) {
     typedef Codeword<WIDE> CW;
@@ -182,14 +170,45 @@ __device__ __forceinline__ void pack_tile(const EncArgs &a, uint64_t *s_dyn, uin
             *reinterpret_cast<uint64_t *>(a.archive + a.L.off_chunk + 8ull * (s / a.L.chunk_subs)) = G + excl;
     }
     __syncthreads();
-    uint32_t bit = lead + excl;
+    {
+        // the thread's codes are built MSB-first in a 64-bit register (current
+        // word in bits 63..32); words wholly inside the thread's bit range are
+        // stored plainly, the first and last words (shared with the
+        // neighbouring threads when the range starts or ends mid-word) are ORed
+        const uint32_t bit = lead + excl;
+        uint32_t w = bit >> 5, fill = bit & 31u;
+        bool head = fill != 0;
+        uint64_t acc = 0;
 #pragma unroll
-    for (uint32_t i = 0; i < kEncPer; i++) {
-        if (q[i] == kNoSymbol) continue;
-        const Entry e = s_book[q[i]];
-        const uint32_t len = CW::len(e);
-        or_bits(s_words, bit, CW::code(e), len);
-        bit += len;
+        for (uint32_t i = 0; i < kEncPer; i++) {
+            if (q[i] == kNoSymbol) continue;
+            const Entry e = s_book[q[i]];
+            const uint32_t len = CW::len(e);
+            const uint64_t code = CW::code(e);
+#pragma unroll
+            for (uint32_t part = 0; part < (WIDE ? 2u : 1u); part++) {
+                // WIDE codes over 32 bits go in two parts, high part first
+                uint32_t l = len;
+                uint64_t c = code;
+                if (WIDE) {
+                    if (part == 0) { l = len > 32u ? len - 32u : 0u; c = code >> 32; }
+                    else { l = len > 32u ? 32u : len; c = code & 0xFFFFFFFFull; }
+                }
+                if (l == 0) continue;
+                acc |= (c << (64u - l)) >> fill;
+                fill += l;
+                if (fill >= 32u) {
+                    const uint32_t v = (uint32_t)(acc >> 32);
+                    if (head) atomicOr(&s_words[w], v);
+                    else s_words[w] = v;
+                    head = false;
+                    acc <<= 32;
+                    fill -= 32u;
+                    w++;
+                }
+            }
+        }
+        if (fill) atomicOr(&s_words[w], (uint32_t)(acc >> 32));
     }
     __syncthreads();
     uint32_t *stream = reinterpret_cast<uint32_t *>(a.archive + ctl->off_str);

@@ -23,6 +23,7 @@
 namespace dqz {
 
 constexpr uint32_t kBookThreads = 256;
+constexpr uint32_t kTableThreads = 1024;   // decoding tables: one workgroup fills the 8192-entry table
 
 // Bitonic sort of 256 * E 64-bit keys held E per thread (thread t holds
 // elements t*E .. t*E + E - 1).  Partners within a thread are compared in
@@ -134,10 +135,11 @@ __device__ void canonical_order(const uint8_t *len, uint32_t ns, CanonScratch &c
     // counting sort of the symbols by code length, stable in the symbol:
     // within a wave, ballots give each symbol its rank among the wave's
     // symbols of equal length; per-(chunk, length) counts give the rest
-    const uint32_t tid = threadIdx.x, lane = lane_id(), w = tid / 64;
-    const uint32_t nk = ns < 256 ? 256 : ns;
-    const uint32_t chunks = nk / 256;              // symbols per thread: tid + 256 * r
-    uint32_t *cnt = reinterpret_cast<uint32_t *>(c.xch);   // [chunks * 4 waves][65]
+    // any block of 256..1024 threads (a multiple of 64); symbol tid + B * r
+    const uint32_t tid = threadIdx.x, lane = lane_id(), w = tid / 64, B = blockDim.x, W = B / 64;
+    const uint32_t nk = ns < B ? B : ns;
+    const uint32_t chunks = nk / B;
+    uint32_t *cnt = reinterpret_cast<uint32_t *>(c.xch);   // [chunks * W waves][65]
     for (uint32_t l = tid; l < 66; l += blockDim.x) {
         c.count[l] = 0;
         c.first_index[l] = 0;
@@ -145,15 +147,15 @@ __device__ void canonical_order(const uint8_t *len, uint32_t ns, CanonScratch &c
     }
     uint32_t ml = 0;
     for (uint32_t r = 0; r < chunks; r++) {
-        const uint32_t sym = tid + 256 * r;
+        const uint32_t sym = tid + B * r;
         const uint32_t l = sym < ns ? len[sym] : 0u;
         ml = l > ml ? l : ml;
     }
     ml = wave_max<uint32_t>(ml);
     if (lane == 0) cnt[w] = ml;
     __syncthreads();
-    const uint32_t m01 = cnt[0] > cnt[1] ? cnt[0] : cnt[1], m23 = cnt[2] > cnt[3] ? cnt[2] : cnt[3];
-    const uint32_t max_len = m01 > m23 ? m01 : m23;
+    uint32_t max_len = 0;
+    for (uint32_t k = 0; k < W; k++) max_len = cnt[k] > max_len ? cnt[k] : max_len;
     __syncthreads();
     // lengths above 64 (only reachable from damaged input) are reported through
     // max_len and otherwise left out of the order
@@ -164,20 +166,20 @@ __device__ void canonical_order(const uint8_t *len, uint32_t ns, CanonScratch &c
     for (uint32_t r = 0; r < kChunks; r++) {
         myrank[r] = 0;
         if (r >= chunks) continue;
-        const uint32_t sym = tid + 256 * r;
+        const uint32_t sym = tid + B * r;
         const uint32_t l = sym < ns ? len[sym] : 0u;
         const uint64_t below = lanes_below(lane);
         uint32_t rk = 0;
         for (uint32_t L = 1; L <= lmax; L++) {
             const uint64_t m = __ballot(l == L);
             if (l == L) rk = __popcll(m & below);
-            if (lane == 0) cnt[(r * 4 + w) * 65 + L] = __popcll(m);
+            if (lane == 0) cnt[(r * W + w) * 65 + L] = __popcll(m);
         }
         myrank[r] = rk;
     }
     __syncthreads();
     // per length: exclusive prefix over the (chunk, wave) groups, in symbol order
-    const uint32_t groups = chunks * 4;
+    const uint32_t groups = chunks * W;
     for (uint32_t L = 1 + tid; L <= lmax; L += blockDim.x) {
         uint32_t run = 0;
         for (uint32_t gi = 0; gi < groups; gi++) {
@@ -188,19 +190,25 @@ __device__ void canonical_order(const uint8_t *len, uint32_t ns, CanonScratch &c
         c.count[L] = run;
     }
     __syncthreads();
-    if (tid == 0) {
-        uint32_t acc = 0;
-        for (uint32_t L = 1; L <= 64; L++) {
-            c.first_index[L] = acc;
-            acc += c.count[L];
+    if (tid < 64) {
+        // lane l stands for length l + 1: first_index is the exclusive prefix
+        // of the counts; first_code[b] = sum_{j<b} count[j] << (b - j) (the
+        // RFC 1951 recurrence code_b = (code_{b-1} + count_{b-1}) << 1, unrolled)
+        // comes from a shift-weighted scan S_l = count_l + (S_{l-1} << 1),
+        // first_code[l + 1] = S_l << 1; no partial sum exceeds 2^63 for l <= 62
+        const uint32_t l = tid + 1;
+        const uint32_t cl = c.count[l];
+        const uint32_t incl = wave_incl_scan<uint32_t>(cl);
+        c.first_index[l] = incl - cl;
+        uint64_t S = cl;
+#pragma unroll
+        for (uint32_t k = 1; k < 64; k <<= 1) {
+            const uint64_t o = __shfl_up(S, k, 64);
+            if (tid >= k) S += o << k;
         }
-        c.n_used = acc;
-        c.max_len = max_len;
-        uint64_t code = 0;
-        for (uint32_t bits = 1; bits <= 64; bits++) {
-            code = (code + c.count[bits - 1]) << 1;
-            c.first_code[bits] = code;
-        }
+        if (l + 1 <= 64) c.first_code[l + 1] = S << 1;
+        if (tid == 0) c.first_code[1] = 0;
+        if (tid == 63) { c.n_used = incl; c.max_len = max_len; }
     }
     __syncthreads();
     for (uint32_t i = tid; i < nk; i += blockDim.x) c.key[i] = ~0ull;
@@ -208,10 +216,10 @@ __device__ void canonical_order(const uint8_t *len, uint32_t ns, CanonScratch &c
 #pragma unroll
     for (uint32_t r = 0; r < kChunks; r++) {
         if (r >= chunks) continue;
-        const uint32_t sym = tid + 256 * r;
+        const uint32_t sym = tid + B * r;
         const uint32_t l = sym < ns ? len[sym] : 0u;
         if (l && l <= lmax) {
-            const uint32_t pos = c.first_index[l] + cnt[(r * 4 + w) * 65 + l] + myrank[r];
+            const uint32_t pos = c.first_index[l] + cnt[(r * W + w) * 65 + l] + myrank[r];
             c.key[pos] = ((uint64_t)l << 16) | sym;
         }
     }
@@ -383,13 +391,17 @@ __global__ __launch_bounds__(kBookThreads) void k_codebook(const uint32_t *__res
         book[sym] = ((uint64_t)l << 56) | code;
         if (max_len <= 24) book32[sym] = (l << 24) | (uint32_t)code;
     }
+    uint64_t my_bits = 0;
     for (uint32_t sym = tid; sym < ns; sym += T) {
         if (s.len[sym] == 0) {
             book[sym] = 0;
             book32[sym] = 0;
         }
-        const uint64_t c = (uint64_t)s.hist[sym] * s.len[sym];
-        if (c) atomicAdd(&s.total_bits, (unsigned long long)c);
+        my_bits += (uint64_t)s.hist[sym] * s.len[sym];
+    }
+    {
+        const uint64_t tb = block_sum256(my_bits, s_red);
+        if (tid == 0) s.total_bits = tb;
     }
     __syncthreads();
 
@@ -468,13 +480,18 @@ void launch_codebook(hipStream_t st, const Geom &g, const Layout &L, Ctl *ctl, c
 // D0: archive code lengths -> canonical decoding tables.  Validates that the
 // lengths describe a complete prefix code (or one symbol of length 1).
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBookThreads) void k_decode_tables(const uint8_t *__restrict__ archive, Layout L,
+__global__ __launch_bounds__(kTableThreads) void k_decode_tables(const uint8_t *__restrict__ archive, Layout L,
                                                                 uint32_t max_len_hdr, DecodeTables *tab) {
     __shared__ CanonScratch c;
     __shared__ uint8_t len[kMaxSyms];
     __shared__ uint32_t s_bad;
     const uint32_t tid = threadIdx.x, T = blockDim.x, ns = L.nsym;
-    if (tid == 0) { s_bad = 0; tab->phase[0] = wall_clock64(); }
+    if (tid == 0) {
+        s_bad = 0;
+        tab->phase[0] = wall_clock64();
+        tab->phase[8] = ~0ull;
+        for (uint32_t k = 9; k < 16; k++) tab->phase[k] = 0;
+    }
     __syncthreads();
     for (uint32_t i = tid; i < ns; i += T) {
         len[i] = archive[L.off_len + i];
@@ -547,7 +564,7 @@ __global__ __launch_bounds__(kBookThreads) void k_decode_tables(const uint8_t *_
 
 void launch_decode_tables(hipStream_t st, const Layout &L, const uint8_t *archive, uint32_t max_len_hdr,
                           DecodeTables *tab) {
-    hipLaunchKernelGGL(k_decode_tables, dim3(1), dim3(kBookThreads), 0, st, archive, L, max_len_hdr, tab);
+    hipLaunchKernelGGL(k_decode_tables, dim3(1), dim3(kTableThreads), 0, st, archive, L, max_len_hdr, tab);
 }
 
 }  // namespace dqz

@@ -257,7 +257,7 @@ __global__ __launch_bounds__(256) void k_quant3d(QuantArgs a) {
     for (uint32_t b = threadIdx.x; b < a.L.nsym; b += blockDim.x) sh_hist[b] = 0;
 
     __syncthreads();
-    const uint32_t tile = blockIdx.x;
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const uint32_t tx = tile % a.tiles_per_row;
     const uint32_t rowid = tile / a.tiles_per_row;
     const uint32_t By = rowid % a.g.nb[1], Bz = rowid / a.g.nb[1];
@@ -376,7 +376,7 @@ __global__ __launch_bounds__(256) void k_quant2d(QuantArgs a) {
     for (uint32_t b = threadIdx.x; b < a.L.nsym; b += blockDim.x) sh_hist[b] = 0;
 
     __syncthreads();
-    const uint32_t tile = blockIdx.x;
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const uint32_t tx = tile % a.tiles_per_row, By = tile / a.tiles_per_row;
     const uint32_t y0 = By * 16, x0 = tx * kT2 * 16;
     const uint32_t ny = a.g.n[1], nx = a.g.n[2];
@@ -478,7 +478,7 @@ __global__ __launch_bounds__(256) void k_quant1d(QuantArgs a) {
     for (uint32_t b = threadIdx.x; b < a.L.nsym; b += blockDim.x) sh_hist[b] = 0;
 
     __syncthreads();
-    const uint32_t tile = blockIdx.x;
+    const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
     const uint64_t p0 = (uint64_t)tile * kTile;
     const uint64_t n = a.g.nelem;
     {
