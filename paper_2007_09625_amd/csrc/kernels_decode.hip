@@ -15,6 +15,11 @@
 
 namespace dqz {
 
+// LDS-typed pointers: every access through them is a ds_* instruction (a
+// generic pointer could be merged with a global one into a flat access)
+typedef __attribute__((address_space(3))) uint16_t lds_u16;
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+
 constexpr uint32_t kDecMaxWaves = 2;   // waves per workgroup (they share the lookup table)
 
 struct DecArgs {
@@ -54,12 +59,13 @@ struct DecLds {
 };
 
 // Decode one symbol from the top of `cur` (more than 32 valid bits, so every
-// code of up to 32 bits is present).  Codes longer than 32 bits (possible
-// only when max_len > 32) are read from a fresh 64-bit window in memory and
-// set `reinit`: the caller then restarts its reader at the new position.
-__device__ __forceinline__ uint32_t decode_sym(const DecArgs &a, uint64_t &cur, int32_t &avail, uint64_t &bp,
-                                               const uint16_t *lut, const DecLds &t, const uint16_t *sorted,
-                                               uint32_t max_len, bool &bad, bool &reinit) {
+// code of up to 32 bits is present); `used` counts the lane's consumed bits.
+// Codes longer than 32 bits (possible only when max_len > 32) are read from
+// a fresh 64-bit window in memory and set `reinit`: the caller then restarts
+// its reader at the new position.
+__device__ __forceinline__ uint32_t decode_sym(const DecArgs &a, uint64_t &cur, int32_t &avail, uint32_t &used,
+                                               uint64_t start, const lds_u16 *lut, const DecLds &t,
+                                               const lds_u16 *sorted, uint32_t max_len, bool &bad, bool &reinit) {
     const uint32_t e = lut[(uint32_t)(cur >> (64 - kLutBits))];
     uint32_t len, sym;
     if (!(e & 0x8000u)) {
@@ -71,6 +77,7 @@ __device__ __forceinline__ uint32_t decode_sym(const DecArgs &a, uint64_t &cur, 
         uint32_t l = e & 63u;
         uint64_t win = cur;
         if (max_len > 32) {
+            const uint64_t bp = start + used;
             const uint64_t w = bp >> 5;
             const uint32_t o = (uint32_t)(bp & 31u);
             const uint64_t hi = ((uint64_t)ld_word(a, w) << 32) | ld_word(a, w + 1);
@@ -83,14 +90,14 @@ __device__ __forceinline__ uint32_t decode_sym(const DecArgs &a, uint64_t &cur, 
         else sym = sorted[idx];
         len = l;
         if ((int32_t)l > avail) {   // only possible for codes over 32 bits
-            bp += l;
+            used += l;
             reinit = true;
             return sym;
         }
     }
     cur <<= len;
     avail -= (int32_t)len;
-    bp += len;
+    used += len;
     return sym;
 }
 
@@ -116,81 +123,125 @@ __device__ __forceinline__ uint64_t pos_to_index(const Geom &g, uint64_t p) {
     return ((uint64_t)(Bz * g.b[0] + iz) * g.n[1] + (By * g.b[1] + iy)) * g.n[2] + (Bx * g.b[2] + ix);
 }
 
-// Stream word i from the wave's LDS window [wlo, wlo + nwin), else from
-// memory (only for stream ranges the window cannot hold).  Window word k
-// sits at k + k/16: lanes read words about one subchunk apart, and the pad
-// spreads those reads over the LDS banks.
+// Window word k sits at k + k/16: lanes read words about one subchunk apart,
+// and the pad spreads those reads over the LDS banks.
 __device__ __forceinline__ uint32_t win_slot(uint32_t k) { return k + (k >> 4); }
 
-__device__ __forceinline__ uint32_t win_word(const DecArgs &a, const uint32_t *win, uint64_t wlo, uint32_t nwin,
-                                             uint64_t i) {
-    const uint64_t k = i - wlo;   // wraps for i < wlo
-    if (__builtin_expect(k < nwin, 1)) return win[win_slot((uint32_t)k)];
-    return ld_word(a, i);
+// n copies of an 8-bit row mask in consecutive bytes (n clamped to 0..4)
+__device__ __forceinline__ uint32_t rows8(uint32_t rowmask, int32_t n) {
+    n = n < 0 ? 0 : (n > 4 ? 4 : n);
+    return n ? rowmask * (0x01010101u >> (8 * (4 - n))) : 0u;
 }
 
-// Inflate `cnt` padded positions starting at stream bit `start` into q[];
-// returns the stream position after the last code.  `cur` holds the next
-// stream bits MSB-first (more than 32 of them before each decode); `nxt` is
-// the following stream word, read one refill ahead.
-// Which positions of a partly filled block lie inside the field.  Block
-// edges are powers of two (8^3, 16^2), so a position's in-block
-// coordinates are bit fields; the block's valid extents are recomputed only
-// when the position enters a new block.
-struct RealTest {
-    uint32_t xs, ys, bshift;        // log2 of the block's x and y edges and of its volume
-    uint32_t cur_blk = ~0u, vx = 0, vy = 0, vz = 0;
-    __device__ __forceinline__ bool operator()(const Geom &g, uint32_t p) {
-        if (g.ndim == 1) return p < g.nelem;
-        const uint32_t blk = p >> bshift;
-        if (blk != cur_blk) {
-            cur_blk = blk;
-            const uint32_t Bx = blk % g.nb[2], By = (blk / g.nb[2]) % g.nb[1], Bz = blk / (g.nb[2] * g.nb[1]);
-            vx = g.n[2] - Bx * g.b[2];
-            vy = g.n[1] - By * g.b[1];
-            vz = g.n[0] - Bz * g.b[0];
-        }
-        const uint32_t in = p & ((1u << bshift) - 1u);
-        return (in & (g.b[2] - 1u)) < vx && ((in >> xs) & (g.b[1] - 1u)) < vy && (in >> (xs + ys)) < vz;
+// In-field mask of the 32 padded positions [p, p + 32), p a multiple of 32:
+// bit k is set when position p + k lies inside the field.  Such a run lies in
+// one block (8^3, 16^2 or 32 positions) and covers whole rows of it: four
+// rows of 8 in 3D, two rows of 16 in 2D.
+__device__ __forceinline__ uint32_t real_mask32(const Geom &g, uint32_t p) {
+    if (p >= g.padded) return 0u;
+    if (g.ndim == 1) {
+        const uint64_t c = g.nelem > p ? g.nelem - p : 0;
+        return c >= 32 ? ~0u : ((1u << c) - 1u);
     }
-};
+    if (g.ndim == 2) {
+        const uint32_t blk = p >> 8, y0 = (p & 255u) >> 4;
+        const uint32_t Bx = blk % g.nb[2], By = blk / g.nb[2];
+        const uint32_t vx = min(16u, g.n[2] - 16 * Bx), vy = min(16u, g.n[1] - 16 * By);
+        const uint32_t row = (1u << vx) - 1u;
+        return (y0 < vy ? row : 0u) | (y0 + 1 < vy ? row << 16 : 0u);
+    }
+    const uint32_t blk = p >> 9, in = p & 511u;
+    const uint32_t Bx = blk % g.nb[2], By = (blk / g.nb[2]) % g.nb[1], Bz = blk / (g.nb[2] * g.nb[1]);
+    const uint32_t vx = min(8u, g.n[2] - 8 * Bx), vy = min(8u, g.n[1] - 8 * By), vz = min(8u, g.n[0] - 8 * Bz);
+    if ((in >> 6) >= vz) return 0u;
+    return rows8((1u << vx) - 1u, (int32_t)vy - (int32_t)((in >> 3) & 7u));
+}
 
-template <bool FULL>
-__device__ __forceinline__ uint64_t inflate_run(const DecArgs &a, const uint32_t *win, uint64_t wlo, uint32_t nwin,
-                                                uint64_t start, uint32_t pa, uint32_t cnt, uint16_t *q,
-                                                const uint16_t *lut, const DecLds &t, const uint16_t *sorted,
-                                                uint32_t max_len, bool &bad) {
-    RealTest real;
-    real.xs = __builtin_ctz(a.g.b[2]);
-    real.ys = __builtin_ctz(a.g.b[1]);
-    real.bshift = __builtin_ctz(a.g.bvol);
-    uint64_t bp = start;
-    uint64_t wi = (bp >> 5) + 2;
-    uint64_t cur = (((uint64_t)win_word(a, win, wlo, nwin, bp >> 5) << 32) | win_word(a, win, wlo, nwin, (bp >> 5) + 1))
-                   << (bp & 31u);
-    int32_t avail = 64 - (int32_t)(bp & 31u);
-    uint32_t nxt = win_word(a, win, wlo, nwin, wi);
-    for (uint32_t i = 0; i < cnt; i++) {
-        if (avail <= 32) {
-            cur |= (uint64_t)nxt << (32 - avail);
-            avail += 32;
-            nxt = win_word(a, win, wlo, nwin, ++wi);
-        }
-        uint32_t sym = a.L.radius;
-        if (FULL || real(a.g, pa + i)) {
-            bool reinit = false;
-            sym = decode_sym(a, cur, avail, bp, lut, t, sorted, max_len, bad, reinit);
-            if (reinit) {   // after a code over 32 bits: restart the reader at bp
-                wi = (bp >> 5) + 2;
-                cur = (((uint64_t)win_word(a, win, wlo, nwin, bp >> 5) << 32) |
-                       win_word(a, win, wlo, nwin, (bp >> 5) + 1)) << (bp & 31u);
-                avail = 64 - (int32_t)(bp & 31u);
-                nxt = win_word(a, win, wlo, nwin, wi);
+// Inflate the S padded positions of the subchunk starting at stream bit
+// `start` (positions pa ..) into q[]; returns the number of stream bits
+// consumed.  The common step has no divergent branch: the refill is a
+// select, the next stream word is read from the LDS window every step, and
+// the in-field test is a bit of a 32-position mask.  Codes the lookup table
+// does not resolve (longer than kLutBits), invalid table entries and stream
+// words outside the window take one uniform branch that is rarely entered.
+__device__ __forceinline__ uint32_t inflate(const DecArgs &a, const lds_u32 *win, uint32_t nwin, uint64_t wlo,
+                                            uint64_t start, uint32_t pa, uint32_t S, lds_u16 *q, const lds_u16 *lut,
+                                            const DecLds &t, const lds_u16 *sorted, uint32_t max_len, bool &bad) {
+    const uint64_t sw = start >> 5;   // the lane's first stream word
+    // window index of word sw + kr is relw + kr; a lane outside the window
+    // (only with damaged chunk offsets) misses on every read
+    const uint32_t relw = (sw >= wlo && sw - wlo < nwin) ? (uint32_t)(sw - wlo) : nwin;
+    const uint32_t wlast = nwin ? nwin - 1 : 0;
+    auto word = [&](uint32_t kr) -> uint32_t {
+        const uint32_t k = relw + kr;
+        return (k < nwin) ? win[win_slot(k)] : ld_word(a, sw + kr);
+    };
+    const uint32_t R = a.L.radius;
+    uint32_t used = 0, kr = 2;
+    uint32_t o = (uint32_t)(start & 31u);
+    uint64_t cur = (((uint64_t)word(0) << 32) | word(1)) << o;
+    int32_t avail = 64 - (int32_t)o;
+    uint32_t nxt = word(kr);
+    uint32_t rmask = 0;
+    for (uint32_t i = 0; i < S; i++) {
+        if ((i & 31u) == 0) rmask = real_mask32(a.g, pa + i);
+        // refill: the next word enters right below the valid bits
+        const bool need = avail <= 32;
+        const uint32_t shl = need ? (uint32_t)(32 - avail) : 0u;
+        cur |= need ? ((uint64_t)nxt << shl) : 0ull;
+        avail += need ? 32 : 0;
+        kr += need ? 1u : 0u;
+        const uint32_t k = relw + kr;
+        nxt = win[win_slot(k < nwin ? k : wlast)];
+        // decode
+        const bool real = (rmask >> (i & 31u)) & 1u;
+        const uint32_t e = lut[(uint32_t)(cur >> (64 - kLutBits))];
+        uint32_t len = (e >> 11) & 15u, sym = e & 0x7FFu;
+        const bool slow = real && ((e & 0x8000u) || len == 0);
+        bool moved = false;
+        if (__any((int)(slow || k >= nwin))) {
+            if (k >= nwin) nxt = ld_word(a, sw + kr);
+            if (slow && !(e & 0x8000u)) {   // no code starts with these bits
+                bad = true;
+                len = 1;
+                sym = R;
+            } else if (slow) {
+                // a longer code: canonical limits from the shortest possible length
+                uint32_t l = e & 63u;
+                uint64_t wv = cur;
+                if (max_len > 32) {
+                    const uint64_t bp = start + used;
+                    const uint64_t ww = bp >> 5;
+                    const uint32_t ob = (uint32_t)(bp & 31u);
+                    const uint64_t h2 = ((uint64_t)ld_word(a, ww) << 32) | ld_word(a, ww + 1);
+                    wv = ob ? ((h2 << ob) | (ld_word(a, ww + 2) >> (32 - ob))) : h2;
+                }
+                while (l < max_len && wv >= t.limit[l]) l++;
+                const uint64_t c = wv >> (64 - l);
+                const uint64_t idx = t.first_index[l] + (c - t.first_code[l]);
+                if (idx >= a.L.nsym) { bad = true; sym = R; }
+                else sym = sorted[idx];
+                len = l;
+                if ((int32_t)l > avail) {   // a code over 32 bits: restart the reader after it
+                    used += l;
+                    const uint64_t bp = start + used;
+                    o = (uint32_t)(bp & 31u);
+                    kr = (uint32_t)((bp >> 5) - sw);
+                    cur = (((uint64_t)word(kr) << 32) | word(kr + 1)) << o;
+                    avail = 64 - (int32_t)o;
+                    kr += 2;
+                    nxt = word(kr);
+                    moved = true;
+                }
             }
         }
-        q[i] = (uint16_t)sym;
+        if (!real || moved) len = 0;
+        cur <<= len;
+        avail -= (int32_t)len;
+        used += len;
+        q[i] = (uint16_t)(real ? sym : R);
     }
-    return bp;
+    return used;
 }
 
 // Wave-cooperative lower bound over the exception keys: the first index e
@@ -289,54 +340,275 @@ __device__ __forceinline__ uint32_t stride8_scan(uint32_t t, uint32_t lane) {
     return s + ((row & 1u) ? ofe : 0u) + (row >= 2 ? low : 0u);
 }
 
-// code buffer slot -> wrapping delta
-__device__ __forceinline__ uint32_t slot_delta(const DecArgs &a, uint16_t q, uint32_t e0, bool &bad) {
-    if (q & 0x8000u) return a.exc[e0 + (q & 0x7FFFu)].y;
+// code buffer slot -> wrapping delta; outlier deltas come from the wave's
+// LDS copy of its first kDecXp exception payloads, later ones from memory
+constexpr uint32_t kDecXp = 256;
+__device__ __forceinline__ uint32_t slot_delta(const DecArgs &a, uint16_t q, uint32_t e0, const lds_u32 *xp,
+                                               bool &bad) {
+    if (q & 0x8000u) {
+        const uint32_t k = q & 0x7FFFu;
+        return k < kDecXp ? xp[k] : a.exc[e0 + k].y;
+    }
     if (q == 0) bad = true;
     return (uint32_t)q - a.L.radius;
+}
+
+// ---- prologue shared by both decode kernels ------------------------------
+
+// The decoding tables into LDS: 16-byte loads, eight of a thread's in flight
+// at once (the lookup table is 16 KB at offset 0 of the 256-byte aligned
+// tables; the sorted symbols are 8-byte aligned, nsym a multiple of 2).
+__device__ __forceinline__ void tables_to_lds(const DecArgs &a, lds_u16 *s_lut, lds_u16 *s_sorted, DecLds &t) {
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    const u32x4 *src = reinterpret_cast<const u32x4 *>(a.tab->lut);
+    __attribute__((address_space(3))) u32x4 *dst = (__attribute__((address_space(3))) u32x4 *)s_lut;
+    constexpr uint32_t kVec = (1u << kLutBits) * 2 / 16;
+    for (uint32_t i0 = threadIdx.x; i0 < kVec; i0 += 8 * blockDim.x) {
+        u32x4 v[8];
+#pragma unroll
+        for (uint32_t j = 0; j < 8; j++) {
+            const uint32_t i = i0 + j * blockDim.x;
+            v[j] = src[i < kVec ? i : 0];
+        }
+#pragma unroll
+        for (uint32_t j = 0; j < 8; j++) {
+            const uint32_t i = i0 + j * blockDim.x;
+            if (i < kVec) dst[i] = v[j];
+        }
+    }
+    const uint32_t *ssrc = reinterpret_cast<const uint32_t *>(a.tab->sorted);
+    lds_u32 *sdst = (lds_u32 *)s_sorted;
+    for (uint32_t i = threadIdx.x; i < a.L.nsym / 2; i += blockDim.x) sdst[i] = ssrc[i];
+    for (uint32_t i = threadIdx.x; i < 65; i += blockDim.x) {
+        const uint64_t l = a.tab->limit[i], f = a.tab->first_code[i];
+        const uint32_t x = a.tab->first_index[i];
+        t.limit[i] = l;
+        t.first_code[i] = f;
+        t.first_index[i] = x;
+    }
+}
+
+// Start bit of the lane's subchunk s = sub0 + lane (chunk offset + prefix of
+// the subchunk bit counts), its bit count, and the wave's stream range copied
+// into the LDS window (coalesced, unconditional loads).  Called by whole
+// active waves.
+struct WaveStream {
+    uint64_t start, wlo;
+    uint32_t bits, nwin;
+};
+__device__ __forceinline__ WaveStream wave_stream(const DecArgs &a, uint64_t sub0, uint32_t lane, bool has,
+                                                  lds_u32 *win) {
+    WaveStream r;
+    const uint64_t s = sub0 + lane;
+    const uint8_t *subp = a.archive + a.L.off_sub;
+    r.bits = has ? ((uint32_t)subp[2 * s] | ((uint32_t)subp[2 * s + 1] << 8)) : 0u;
+    const uint32_t incl = wave_incl_scan<uint32_t>(r.bits);
+    const uint32_t excl = incl - r.bits;
+    const uint32_t C = a.L.chunk_subs;
+    const uint64_t *chunks = reinterpret_cast<const uint64_t *>(a.archive + a.L.off_chunk);
+    if (C >= 64) {
+        const uint64_t cs = (sub0 / C) * C;
+        uint64_t pre = 0;
+        for (uint64_t j = cs + lane; j < sub0; j += 64) pre += (uint32_t)subp[2 * j] | ((uint32_t)subp[2 * j + 1] << 8);
+        pre = wave_sum<uint64_t>(pre);
+        r.start = chunks[sub0 / C] + pre + excl;
+    } else {
+        const uint64_t c = (has ? s : sub0) / C;
+        const uint32_t k = (uint32_t)(c * C - sub0);
+        const uint32_t at = __shfl(excl, (int)k, 64);
+        r.start = chunks[c] + excl - at;
+    }
+    // the window starts at the first subchunk's word and covers the last
+    // subchunk's end plus the two words a reader may look past it
+    r.wlo = __shfl(r.start, 0, 64) >> 5;
+    const uint64_t whi = wave_max<uint64_t>(has ? ((r.start + r.bits) >> 5) + 3 : 0);
+    const uint32_t cap = a.win_words / 17 * 16;   // logical words whose padded slots fit
+    r.nwin = whi > r.wlo ? (uint32_t)(whi - r.wlo < cap ? whi - r.wlo : cap) : 0u;
+    for (uint32_t b = 0; b < r.nwin; b += 64 * 8) {
+        uint32_t v[8];
+#pragma unroll
+        for (uint32_t j = 0; j < 8; j++) v[j] = ld_word(a, r.wlo + b + j * 64 + lane);
+#pragma unroll
+        for (uint32_t j = 0; j < 8; j++) {
+            const uint32_t k = b + j * 64 + lane;
+            if (k < r.nwin) win[win_slot(k)] = v[j];
+        }
+    }
+    return r;
+}
+
+// ---- reconstruction for subchunks of 128 positions, in registers ----------
+//
+// The lane reads back its own 128 codes.  In 3D they are two z-planes of one
+// 8^3 block, and the block's four subchunks sit in one DPP quad: the 2D
+// prefix sums of each plane are in-lane, the z prefix crosses the quad by two
+// lane shifts.  In 2D they are 8 rows of a 16^2 block (a lane pair per block);
+// in 1D four whole 32-blocks, all in-lane.
+
+// lane j - 1 (j - 2) of the lane's quad; quad_perm [0,0,1,2] and [0,0,0,1]
+__device__ __forceinline__ uint32_t quad_shr1(uint32_t v) {
+    return pinned((uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x90, 0xF, 0xF, false));
+}
+__device__ __forceinline__ uint32_t quad_shr2(uint32_t v) {
+    return pinned((uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x40, 0xF, 0xF, false));
+}
+// lanes 1 and 3 of the quad receive lanes 0 and 2: quad_perm [0,0,2,2]
+__device__ __forceinline__ uint32_t quad_pair_lo(uint32_t v) {
+    return pinned((uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xA0, 0xF, 0xF, false));
+}
+
+// Called by whole active waves (the cross-lane steps need every lane).
+__device__ __forceinline__ void recon128(const DecArgs &a, const lds_u16 *wq, uint32_t lane, uint32_t P0,
+                                         uint32_t e0, const lds_u32 *xp, bool has, bool &bad) {
+    const Geom &g = a.g;
+    const float h = a.h;
+    const uint32_t R = a.L.radius;
+    int32_t v[128];
+    {
+        // the lane's codes: 64 aligned pairs (the code-buffer stride is even)
+        const lds_u32 *src = (const lds_u32 *)(wq + lane * a.qstride);
+        uint32_t special = 0;
+#pragma unroll
+        for (uint32_t k = 0; k < 64; k++) {
+            const uint32_t two = has ? src[k] : (R | (R << 16));
+            const uint32_t q0 = two & 0xFFFFu, q1 = two >> 16;
+            v[2 * k] = (int32_t)q0 - (int32_t)R;
+            v[2 * k + 1] = (int32_t)q1 - (int32_t)R;
+            // code 0 (an unmarked outlier) or a marked outlier slot
+            special |= ((q0 - 1u) >= 0x7FFFu ? 1u : 0u) | ((q1 - 1u) >= 0x7FFFu ? 1u : 0u);
+        }
+        if (special) {
+#pragma unroll
+            for (uint32_t i = 0; i < 128; i++) {
+                const uint32_t q = (uint32_t)(v[i] + (int32_t)R);
+                if (q & 0x8000u) v[i] = (int32_t)slot_delta(a, (uint16_t)q, e0, xp, bad);
+                else if (q == 0) bad = true;
+            }
+        }
+    }
+    const uint32_t pa = P0 + lane * 128u;
+    const uint32_t n1 = g.n[1], n2 = g.n[2];
+    const bool vec = (n2 % 4u == 0) && ((reinterpret_cast<uintptr_t>(a.out) & 15u) == 0);
+    if (g.ndim == 3) {
+        const uint32_t blk = pa >> 9;
+        const uint32_t Bx = blk % g.nb[2], By = (blk / g.nb[2]) % g.nb[1], Bz = blk / (g.nb[2] * g.nb[1]);
+        const uint32_t vx = min(8u, n2 - 8 * Bx), vy = min(8u, n1 - 8 * By), vz = min(8u, g.n[0] - 8 * Bz);
+#pragma unroll
+        for (uint32_t zi = 0; zi < 2; zi++) {
+#pragma unroll
+            for (uint32_t y = 0; y < 8; y++)
+#pragma unroll
+                for (uint32_t x = 1; x < 8; x++) v[zi * 64 + y * 8 + x] += v[zi * 64 + y * 8 + x - 1];
+#pragma unroll
+            for (uint32_t y = 1; y < 8; y++)
+#pragma unroll
+                for (uint32_t x = 0; x < 8; x++) v[zi * 64 + y * 8 + x] += v[zi * 64 + (y - 1) * 8 + x];
+        }
+        const uint32_t jq = lane & 3u;
+#pragma unroll
+        for (uint32_t k = 0; k < 64; k++) {
+            const uint32_t b = (uint32_t)(v[64 + k] + v[k]);   // planes 2j and 2j + 1
+            const uint32_t s1 = quad_shr1(b);
+            const uint32_t t1 = b + (jq >= 1 ? s1 : 0u);
+            const uint32_t s2 = quad_shr2(t1);
+            const uint32_t t = t1 + (jq >= 2 ? s2 : 0u);       // inclusive over the quad
+            v[k] += (int32_t)(t - b);
+            v[64 + k] = (int32_t)t;
+        }
+        if (!has) return;
+        const uint32_t z0 = 2 * jq;
+#pragma unroll
+        for (uint32_t zi = 0; zi < 2; zi++) {
+            if (z0 + zi >= vz) continue;
+            const uint64_t zz = 8ull * Bz + z0 + zi;
+#pragma unroll
+            for (uint32_t y = 0; y < 8; y++) {
+                if (y >= vy) continue;
+                float *o = a.out + (zz * n1 + 8 * By + y) * n2 + 8 * Bx;
+                const uint32_t r = zi * 64 + y * 8;
+                if (vx == 8 && vec) {
+                    reinterpret_cast<float4 *>(o)[0] = make_float4(dequant(v[r], h), dequant(v[r + 1], h),
+                                                                   dequant(v[r + 2], h), dequant(v[r + 3], h));
+                    reinterpret_cast<float4 *>(o)[1] = make_float4(dequant(v[r + 4], h), dequant(v[r + 5], h),
+                                                                   dequant(v[r + 6], h), dequant(v[r + 7], h));
+                } else {
+#pragma unroll
+                    for (uint32_t x = 0; x < 8; x++)
+                        if (x < vx) o[x] = dequant(v[r + x], h);
+                }
+            }
+        }
+    } else if (g.ndim == 2) {
+        const uint32_t blk = pa >> 8;
+        const uint32_t Bx = blk % g.nb[2], By = blk / g.nb[2];
+        const uint32_t vx = min(16u, n2 - 16 * Bx), vy = min(16u, n1 - 16 * By);
+#pragma unroll
+        for (uint32_t y = 0; y < 8; y++)
+#pragma unroll
+            for (uint32_t x = 1; x < 16; x++) v[y * 16 + x] += v[y * 16 + x - 1];
+#pragma unroll
+        for (uint32_t y = 1; y < 8; y++)
+#pragma unroll
+            for (uint32_t x = 0; x < 16; x++) v[y * 16 + x] += v[(y - 1) * 16 + x];
+        const uint32_t j2 = lane & 1u;
+#pragma unroll
+        for (uint32_t x = 0; x < 16; x++) {
+            const uint32_t lower = quad_pair_lo((uint32_t)v[7 * 16 + x]);   // the lower half-block's column sums
+            const int32_t add = j2 ? (int32_t)lower : 0;
+#pragma unroll
+            for (uint32_t y = 0; y < 8; y++) v[y * 16 + x] += add;
+        }
+        if (!has) return;
+        const uint32_t y0 = 8 * j2;
+#pragma unroll
+        for (uint32_t y = 0; y < 8; y++) {
+            if (y0 + y >= vy) continue;
+            float *o = a.out + (uint64_t)(16 * By + y0 + y) * n2 + 16 * Bx;
+            const uint32_t r = y * 16;
+            if (vx == 16 && vec) {
+#pragma unroll
+                for (uint32_t qd = 0; qd < 4; qd++)
+                    reinterpret_cast<float4 *>(o)[qd] =
+                        make_float4(dequant(v[r + 4 * qd], h), dequant(v[r + 4 * qd + 1], h),
+                                    dequant(v[r + 4 * qd + 2], h), dequant(v[r + 4 * qd + 3], h));
+            } else {
+#pragma unroll
+                for (uint32_t x = 0; x < 16; x++)
+                    if (x < vx) o[x] = dequant(v[r + x], h);
+            }
+        }
+    } else {
+#pragma unroll
+        for (uint32_t i = 1; i < 128; i++)
+            if (i & 31u) v[i] += v[i - 1];
+        if (!has) return;
+        float *o = a.out + pa;
+        const uint64_t c64 = g.nelem > pa ? g.nelem - pa : 0;
+        if (c64 >= 128 && ((reinterpret_cast<uintptr_t>(a.out) & 15u) == 0)) {
+#pragma unroll
+            for (uint32_t qd = 0; qd < 32; qd++)
+                reinterpret_cast<float4 *>(o)[qd] = make_float4(dequant(v[4 * qd], h), dequant(v[4 * qd + 1], h),
+                                                                dequant(v[4 * qd + 2], h), dequant(v[4 * qd + 3], h));
+        } else {
+            const uint32_t c = (uint32_t)c64;
+#pragma unroll
+            for (uint32_t i = 0; i < 128; i++)
+                if (i < c) o[i] = dequant(v[i], h);
+        }
+    }
 }
 
 __global__ __launch_bounds__(64 * kDecMaxWaves) void k_decode(DecArgs a) {
     extern __shared__ uint32_t s_dyn[];
     __shared__ DecLds s_t;
-    uint16_t *s_lut = reinterpret_cast<uint16_t *>(s_dyn);                       // 1 << kLutBits
-    uint16_t *s_sorted = s_lut + (1u << kLutBits);                               // nsym
-    uint16_t *s_q = s_sorted + a.L.nsym;                                         // waves * 64 * qstride
-    uint32_t *s_win = reinterpret_cast<uint32_t *>(s_q + (uint64_t)(blockDim.x / 64) * 64 * a.qstride);  // waves * win_words
+    lds_u16 *s_lut = (lds_u16 *)s_dyn;                                              // 1 << kLutBits
+    lds_u16 *s_sorted = s_lut + (1u << kLutBits);                                  // nsym
+    lds_u16 *s_q = s_sorted + a.L.nsym;                                            // waves * 64 * qstride
+    lds_u32 *s_win = (lds_u32 *)(s_q + (blockDim.x / 64) * 64 * a.qstride);        // waves * win_words
     if (a.tab->status) return;   // the code lengths failed validation: tables are not usable
     uint64_t tm[7];
     tm[0] = a.trace ? wall_clock64() : 0;
-    {
-        // tables into LDS: 16-byte loads, eight of a thread's in flight at once
-        // (the lookup table is 16 KB at offset 0 of the 256-byte aligned tables;
-        // the sorted symbols are 8-byte aligned, nsym a multiple of 2)
-        const uint4 *src = reinterpret_cast<const uint4 *>(a.tab->lut);
-        uint4 *dst = reinterpret_cast<uint4 *>(s_lut);
-        constexpr uint32_t kVec = (1u << kLutBits) * 2 / 16;
-        for (uint32_t i0 = threadIdx.x; i0 < kVec; i0 += 8 * blockDim.x) {
-            uint4 v[8];
-#pragma unroll
-            for (uint32_t j = 0; j < 8; j++) {
-                const uint32_t i = i0 + j * blockDim.x;
-                v[j] = src[i < kVec ? i : 0];
-            }
-#pragma unroll
-            for (uint32_t j = 0; j < 8; j++) {
-                const uint32_t i = i0 + j * blockDim.x;
-                if (i < kVec) dst[i] = v[j];
-            }
-        }
-        const uint32_t *ssrc = reinterpret_cast<const uint32_t *>(a.tab->sorted);
-        uint32_t *sdst = reinterpret_cast<uint32_t *>(s_sorted);
-        for (uint32_t i = threadIdx.x; i < a.L.nsym / 2; i += blockDim.x) sdst[i] = ssrc[i];
-        for (uint32_t i = threadIdx.x; i < 65; i += blockDim.x) {
-            const uint64_t l = a.tab->limit[i], f = a.tab->first_code[i];
-            const uint32_t x = a.tab->first_index[i];
-            s_t.limit[i] = l;
-            s_t.first_code[i] = f;
-            s_t.first_index[i] = x;
-        }
-    }
+    tables_to_lds(a, s_lut, s_sorted, s_t);
     __syncthreads();
     if (a.trace) tm[1] = wall_clock64();
 
@@ -344,7 +616,7 @@ __global__ __launch_bounds__(64 * kDecMaxWaves) void k_decode(DecArgs a) {
     const uint32_t gw = blockIdx.x * (blockDim.x / 64) + w;
     const bool active = gw < a.wave_tasks;
     const uint32_t S = a.L.sub_size, sh = a.L.sub_shift;
-    uint16_t *wq = s_q + (uint64_t)w * 64 * a.qstride;
+    lds_u16 *wq = s_q + w * 64 * a.qstride;
     const uint64_t sub0 = (uint64_t)gw * 64;
     const uint64_t P0 = sub0 << sh;
     const uint64_t P1 = active ? ((P0 + (64ull << sh)) < a.g.padded ? (P0 + (64ull << sh)) : a.g.padded) : P0;
@@ -357,42 +629,14 @@ __global__ __launch_bounds__(64 * kDecMaxWaves) void k_decode(DecArgs a) {
     uint32_t bits_s = 0;
     uint64_t start = 0, wlo = 0;
     uint32_t nwin = 0;
-    uint32_t *win = s_win + (uint64_t)w * a.win_words;
+    lds_u32 *win = s_win + w * a.win_words;
+    lds_u32 *xp = s_win + (blockDim.x / 64) * a.win_words + w * kDecXp;   // exception payloads
     if (active) {
-        const uint8_t *subp = a.archive + a.L.off_sub;
-        bits_s = has ? ((uint32_t)subp[2 * s] | ((uint32_t)subp[2 * s + 1] << 8)) : 0u;
-        const uint32_t incl = wave_incl_scan<uint32_t>(bits_s);
-        const uint32_t excl = incl - bits_s;
-        const uint32_t C = a.L.chunk_subs;
-        const uint64_t *chunks = reinterpret_cast<const uint64_t *>(a.archive + a.L.off_chunk);
-        if (C >= 64) {
-            const uint64_t cs = (sub0 / C) * C;
-            uint64_t pre = 0;
-            for (uint64_t j = cs + lane; j < sub0; j += 64) pre += (uint32_t)subp[2 * j] | ((uint32_t)subp[2 * j + 1] << 8);
-            pre = wave_sum<uint64_t>(pre);
-            start = chunks[sub0 / C] + pre + excl;
-        } else {
-            const uint64_t c = (has ? s : sub0) / C;
-            const uint32_t k = (uint32_t)(c * C - sub0);
-            const uint32_t at = __shfl(excl, (int)k, 64);
-            start = chunks[c] + excl - at;
-        }
-        // the window starts at the first subchunk's word and covers the last
-        // subchunk's end plus the two words a reader may look past it
-        wlo = __shfl(start, 0, 64) >> 5;
-        const uint64_t whi = wave_max<uint64_t>(has ? ((start + bits_s) >> 5) + 3 : 0);
-        const uint32_t cap = a.win_words / 17 * 16;   // logical words whose padded slots fit
-        nwin = whi > wlo ? (uint32_t)(whi - wlo < cap ? whi - wlo : cap) : 0u;
-        for (uint32_t b = 0; b < nwin; b += 64 * 8) {
-            uint32_t v[8];
-#pragma unroll
-            for (uint32_t j = 0; j < 8; j++) v[j] = ld_word(a, wlo + b + j * 64 + lane);
-#pragma unroll
-            for (uint32_t j = 0; j < 8; j++) {
-                const uint32_t k = b + j * 64 + lane;
-                if (k < nwin) win[win_slot(k)] = v[j];
-            }
-        }
+        const WaveStream ws = wave_stream(a, sub0, lane, has, win);
+        bits_s = ws.bits;
+        start = ws.start;
+        wlo = ws.wlo;
+        nwin = ws.nwin;
         // ---- exception range of this wave
         e0 = wave_lower_bound(a.exc, a.n_exc, 2ull * P0, lane);
         e1 = wave_lower_bound(a.exc, a.n_exc, 2ull * P1, lane);
@@ -402,40 +646,31 @@ __global__ __launch_bounds__(64 * kDecMaxWaves) void k_decode(DecArgs a) {
     // ---- inflate the subchunk into the LDS code buffer
     if (has) {
         const uint32_t pa = (uint32_t)(s << sh);
-        const uint32_t pb = (pa + S) < a.g.padded ? (pa + S) : a.g.padded;
-        uint16_t *myq = wq + lane * a.qstride;
-        bool full;
-        if (a.g.ndim == 1) {
-            full = pb <= a.g.nelem;
-        } else {
-            full = true;
-            for (uint32_t blk = (uint32_t)(pa / a.g.bvol); blk <= (uint32_t)((pb - 1) / a.g.bvol); blk++)
-                full = full && block_full(a.g, blk);
-        }
         const uint32_t max_len = a.tab->max_len < 63u ? a.tab->max_len : 63u;
-        const uint32_t cnt = (uint32_t)(pb - pa);
-        const uint64_t end =
-            full ? inflate_run<true>(a, win, wlo, nwin, start, pa, cnt, myq, s_lut, s_t, s_sorted, max_len, bad)
-                 : inflate_run<false>(a, win, wlo, nwin, start, pa, cnt, myq, s_lut, s_t, s_sorted, max_len, bad);
-        if (end - start != bits_s) bad = true;
+        const uint32_t used = inflate(a, win, nwin, wlo, start, pa, S, wq + lane * a.qstride, s_lut, s_t, s_sorted,
+                                      max_len, bad);
+        if (used != bits_s) bad = true;
     }
     if (a.trace) tm[3] = wall_clock64();
     __syncthreads();
     if (active) {
         // ---- outliers: mark their slots with an index into the exception list
         for (uint32_t e = e0 + lane; e < e1; e += 64) {
-            const uint32_t key = a.exc[e].x;
-            if (key & 1u) continue;
-            const uint64_t loc = (uint64_t)(key >> 1) - P0;
+            const uint2 r = a.exc[e];
+            if (e - e0 < kDecXp) xp[e - e0] = r.y;
+            if (r.x & 1u) continue;
+            const uint64_t loc = (uint64_t)(r.x >> 1) - P0;
             if (loc >= P1 - P0) { bad = true; continue; }   // only in an unsorted (damaged) list
-            uint16_t *slot = wq + (loc >> sh) * a.qstride + (loc & (S - 1));
+            lds_u16 *slot = wq + (loc >> sh) * a.qstride + (loc & (S - 1));
             if (*slot != 0 || e - e0 > 0x7FFFu) bad = true;
             else *slot = (uint16_t)(0x8000u | (e - e0));
         }
     }
     __syncthreads();
     if (a.trace) tm[4] = wall_clock64();
-    if (active) {
+    if (active && S == 128) {
+        recon128(a, wq, lane, (uint32_t)P0, e0, xp, has, bad);
+    } else if (active) {
         const Geom &g = a.g;
         const float h = a.h;
         auto qat = [&](uint64_t loc) -> uint16_t { return wq[(loc >> sh) * a.qstride + (loc & (S - 1))]; };
@@ -448,7 +683,7 @@ __global__ __launch_bounds__(64 * kDecMaxWaves) void k_decode(DecArgs a) {
                 uint32_t run = 0;
 #pragma unroll
                 for (uint32_t z = 0; z < 8; z++) {
-                    run += slot_delta(a, qat(base + z * 64 + lane), e0, bad);
+                    run += slot_delta(a, qat(base + z * 64 + lane), e0, xp, bad);
                     v[z] = run;
                 }
 #pragma unroll
@@ -473,7 +708,7 @@ __global__ __launch_bounds__(64 * kDecMaxWaves) void k_decode(DecArgs a) {
                 const uint32_t x = Bx * 16 + lx;
                 uint32_t col = 0;
                 for (uint32_t y = 0; y < 16; y++) {
-                    if (ok) col += slot_delta(a, qat(base + y * 16 + lx), e0, bad);
+                    if (ok) col += slot_delta(a, qat(base + y * 16 + lx), e0, xp, bad);
                     const uint32_t t = seg_scan<16>(col, lane);
                     const uint32_t yy = By * 16 + y;
                     if (ok && x < g.n[2] && yy < g.n[1]) a.out[(uint64_t)yy * g.n[2] + x] = dequant((int32_t)t, h);
@@ -483,7 +718,7 @@ __global__ __launch_bounds__(64 * kDecMaxWaves) void k_decode(DecArgs a) {
             for (uint64_t off = 0; P0 + off < P1; off += 64) {
                 const uint64_t loc = off + lane;
                 const uint64_t p = P0 + loc;
-                const uint32_t t = seg_scan<32>((p < P1) ? slot_delta(a, qat(loc), e0, bad) : 0u, lane);
+                const uint32_t t = seg_scan<32>((p < P1) ? slot_delta(a, qat(loc), e0, xp, bad) : 0u, lane);
                 if (p < g.nelem) a.out[p] = dequant((int32_t)t, h);
             }
         }
@@ -516,7 +751,7 @@ constexpr uint32_t kDecWinWordsMax = 2688;        // 10.5 KiB stream window per 
 
 static size_t decode_lds_fixed(const Layout &L) {
     return sizeof(uint16_t) * ((1u << kLutBits) + L.nsym + (size_t)decode_waves(L) * 64 * (L.sub_size + 2)) +
-           sizeof(DecLds);
+           sizeof(uint32_t) * decode_waves(L) * kDecXp + sizeof(DecLds);
 }
 
 // stream-window words per wave: the cap, or what the LDS left over allows
@@ -551,6 +786,7 @@ void launch_decode(hipStream_t s, const Geom &g, const Layout &L, const uint8_t 
     a.win_words = decode_win_words(L);
     a.trace = trace ? 1u : 0u;
     if (a.wave_tasks == 0) return;
+
     const uint32_t waves = decode_waves(L);
     const uint32_t blocks = (a.wave_tasks + waves - 1) / waves;
     const size_t lds = decode_lds_bytes(L);
