@@ -134,9 +134,12 @@ const char *dqz_status_str(dqz_status status);
 /* Text of the last error on this context ("" if none). */
 const char *dqz_ctx_last_error(const dqz_ctx *ctx);
 
-/* Per-stage timing.  While enabled, every dqz_compress / dqz_decompress on
- * this context records HIP events on its stream between its kernels (a small
- * per-call cost); dqz_stage_times then returns the elapsed microseconds of
+/* Per-stage timing.  `level` 0 turns it off.  At level 1 every dqz_compress /
+ * dqz_decompress on this context records HIP events on its stream between its
+ * kernels (a small per-call cost); level 2 also sums per-wave phase durations
+ * inside the decoding kernel (DQZ_DBG_PHASES), which costs a few
+ * same-address atomics per wave and slows that kernel noticeably.
+ * dqz_stage_times returns the elapsed microseconds of
  * each stage of the most recent call of that kind:
  *   compress   (which = 0): [0] init, [1] value range + eb (0 in absolute
  *              mode), [2] dual-quantization + histogram + exceptions (with
@@ -145,7 +148,7 @@ const char *dqz_ctx_last_error(const dqz_ctx *ctx);
  *   decompress (which = 1): [0] decoding tables, [1] inflate + reconstruct
  * `us` must hold DQZ_MAX_STAGES doubles; *n_stages receives the count. */
 #define DQZ_MAX_STAGES 8
-dqz_status dqz_ctx_set_timing(dqz_ctx *ctx, int enable);
+dqz_status dqz_ctx_set_timing(dqz_ctx *ctx, int level);
 dqz_status dqz_stage_times(dqz_ctx *ctx, int which, double *us, int *n_stages);
 
 /* Stage dumps for parity testing: copy an intermediate buffer of the most
@@ -154,7 +157,7 @@ dqz_status dqz_stage_times(dqz_ctx *ctx, int which, double *us, int *n_stages);
  *   DQZ_DBG_HISTOGRAM  u32[2R]
  *   DQZ_DBG_CODEBOOK   u64[2R], (length << 56) | canonical code
  *   DQZ_DBG_PHASES     u64[32], phase timestamps of the one-workgroup kernels and
- *                      decode-phase durations (recorded while stage timing is on)
+ *                      decode-phase durations (recorded at timing level 2)
  * `bytes` must equal the buffer's size. */
 #define DQZ_DBG_CODES 1
 #define DQZ_DBG_HISTOGRAM 2

@@ -34,8 +34,10 @@ struct dqz_ctx {
     uint32_t last_nsym = 0;
     Ctl *last_ctl = nullptr;
     DecodeTables *last_tab = nullptr;
-    // per-stage timing
+    // per-stage timing (events between kernels) and, at level 2, the decoding
+    // kernel's per-wave phase sums
     bool timing = false;
+    bool trace = false;
     hipEvent_t ev[2][DQZ_MAX_STAGES + 1] = {};
     int n_ev[2] = {0, 0};
     bool ev_ready[2] = {false, false};
@@ -516,7 +518,7 @@ dqz_status dqz_decompress(dqz_ctx *ctx, const void *d_archive, uint64_t archive_
     mark(ctx, 1, 0, s);
     launch_decode_tables(s, P.L, arc, hi.max_len, tab);
     mark(ctx, 1, 1, s);
-    launch_decode(s, P.g, P.L, arc, hi.off_str, hi.n_words, (uint32_t)hi.n_exc, hi.h, tab, d_field, ctx->timing);
+    launch_decode(s, P.g, P.L, arc, hi.off_str, hi.n_words, (uint32_t)hi.n_exc, hi.h, tab, d_field, ctx->trace);
     mark(ctx, 1, 2, s);
     HIP_TRY(ctx, hipGetLastError());
     HIP_TRY(ctx, hipMemcpyAsync(&ctx->h_ctl->status, &tab->status, 4, hipMemcpyDeviceToHost, s));
@@ -525,14 +527,17 @@ dqz_status dqz_decompress(dqz_ctx *ctx, const void *d_archive, uint64_t archive_
     return status_from_device(ctx, ctx->h_ctl->status);
 }
 
-dqz_status dqz_ctx_set_timing(dqz_ctx *ctx, int enable) {
+dqz_status dqz_ctx_set_timing(dqz_ctx *ctx, int level) {
     if (!ctx) return DQZ_EINVAL;
+    if (level < 0 || level > 2) return fail(ctx, DQZ_EINVAL, "timing level must be 0, 1 or 2");
+    const bool enable = level > 0;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     if (enable && !ctx->ev[0][0]) {
         for (int k = 0; k < 2; k++)
             for (int i = 0; i <= DQZ_MAX_STAGES; i++) HIP_TRY(ctx, hipEventCreate(&ctx->ev[k][i]));
     }
-    ctx->timing = enable != 0;
+    ctx->timing = enable;
+    ctx->trace = level == 2;
     ctx->ev_ready[0] = ctx->ev_ready[1] = false;
     return DQZ_OK;
 }

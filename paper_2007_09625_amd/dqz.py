@@ -192,8 +192,9 @@ class Context:
         return lib.dqz_decompress(self.handle, ctypes.c_void_p(archive_ptr), int(archive_bytes), hb,
                                   ctypes.c_void_p(field_ptr), int(field_cap_elems), self._stream(stream))
 
-    def dqz_ctx_set_timing(self, enable: bool):
-        self._check(lib.dqz_ctx_set_timing(self.handle, 1 if enable else 0), "dqz_ctx_set_timing")
+    def dqz_ctx_set_timing(self, level):
+        """0 off, 1 (or True) stage events, 2 also the decoding kernel's per-wave phase sums."""
+        self._check(lib.dqz_ctx_set_timing(self.handle, int(level)), "dqz_ctx_set_timing")
 
     def dqz_stage_times(self, which: int) -> dict:
         """Microseconds per stage of the last timed compress (0) / decompress (1)."""
