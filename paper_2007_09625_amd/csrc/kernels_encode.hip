@@ -32,7 +32,6 @@ struct EncArgs {
 };
 
 constexpr uint32_t kEncPer = kTile / 256;              // positions per thread
-constexpr uint32_t kEncWords = kTile * 64 / 32 + 2;    // worst case tile span in words
 constexpr uint32_t kBadStatus = ST_EINVAL | ST_ETOOSMALL | ST_EUNSUPPORTED | ST_EINTERNAL | ST_RETRY;
 
 template <bool WIDE> struct Codeword;
@@ -125,62 +124,63 @@ __global__ __launch_bounds__(256) void k_enc_count(EncArgs a) {
 // ---------------------------------------------------------------------------
 // pass 2
 // ---------------------------------------------------------------------------
-template <bool WIDE>
-__device__ __forceinline__ void pack_tile(const EncArgs &a, uint64_t *s_dyn, uint64_t *s_scan) {
+// One packing pass over PER consecutive positions per thread starting at
+// padded position p0 + PER * tid, the pass's first bit at stream bit `base`.
+// The thread's codewords are built MSB-first in a 64-bit register (current
+// word in bits 63..32); words wholly inside the thread's bit range are stored
+// plainly into the LDS word buffer, the first and last ones (shared with the
+// neighbouring threads when the range starts or ends mid-word) are ORed.
+// The buffer then leaves as one contiguous run; its first and last words are
+// shared with the neighbouring passes and merged into the stream by atomic OR.
+// Returns the pass's bit count.
+template <bool WIDE, uint32_t PER>
+__device__ __forceinline__ uint32_t pack_pass(const EncArgs &a, uint64_t p0, uint64_t base,
+                                              const typename Codeword<WIDE>::T *s_book, uint32_t *s_words,
+                                              uint64_t *s_scan) {
     typedef Codeword<WIDE> CW;
     typedef typename CW::T Entry;
-    uint32_t *s_words = reinterpret_cast<uint32_t *>(s_dyn);                // kEncWords
-    Entry *s_book = reinterpret_cast<Entry *>(s_dyn + (kEncWords + 1) / 2);
-    Ctl *ctl = a.ctl;
-    const uint32_t tid = threadIdx.x, t = blockIdx.x;
-    const Entry *gbook = WIDE ? reinterpret_cast<const Entry *>(a.b.book) : reinterpret_cast<const Entry *>(a.b.book32);
-    {
-        // codebook into LDS: all loads of a thread in flight
-        Entry e[kMaxSyms / 256];
+    const uint32_t tid = threadIdx.x;
+    const uint64_t my0 = p0 + (uint64_t)PER * tid;
+    uint16_t q[PER];
+    if (my0 + PER <= a.g.padded) {
+        const uint4 *src = reinterpret_cast<const uint4 *>(a.b.codes + my0);
 #pragma unroll
-        for (uint32_t k = 0; k < kMaxSyms / 256; k++) {
-            const uint32_t i = tid + 256 * k;
-            if (i < a.L.nsym) e[k] = gbook[i];
-        }
+        for (uint32_t v = 0; v < PER / 8; v++) {
+            const uint4 u4 = src[v];
+            const uint32_t u[4] = {u4.x, u4.y, u4.z, u4.w};
 #pragma unroll
-        for (uint32_t k = 0; k < kMaxSyms / 256; k++) {
-            const uint32_t i = tid + 256 * k;
-            if (i < a.L.nsym) s_book[i] = e[k];
+            for (uint32_t i = 0; i < 4; i++) {
+                q[8 * v + 2 * i] = (uint16_t)(u[i] & 0xFFFF);
+                q[8 * v + 2 * i + 1] = (uint16_t)(u[i] >> 16);
+            }
         }
+    } else {
+#pragma unroll
+        for (uint32_t i = 0; i < PER; i++) q[i] = (my0 + i < a.g.padded) ? a.b.codes[my0 + i] : kNoSymbol;
     }
-    const uint64_t G = tile_offset(a.b.escan, 0, t, s_scan);
-    const uint64_t p0 = (uint64_t)t * kTile;
-    const uint64_t my0 = p0 + (uint64_t)kEncPer * tid;
-    uint16_t q[kEncPer];
-    load_codes(a, my0, q);
-    __syncthreads();
     uint32_t my_bits = 0;
 #pragma unroll
-    for (uint32_t i = 0; i < kEncPer; i++)
+    for (uint32_t i = 0; i < PER; i++)
         if (q[i] != kNoSymbol) my_bits += CW::len(s_book[q[i]]);
-    uint64_t tile_bits;
-    const uint32_t excl = (uint32_t)block_excl_scan256(my_bits, s_scan, &tile_bits);
-    const uint32_t lead = (uint32_t)(G & 31u);
-    const uint32_t nwords = (lead + (uint32_t)tile_bits + 31u) >> 5;
+    uint64_t pass_bits;
+    const uint32_t excl = (uint32_t)block_excl_scan256(my_bits, s_scan, &pass_bits);
+    const uint32_t lead = (uint32_t)(base & 31u);
+    const uint32_t nwords = (lead + (uint32_t)pass_bits + 31u) >> 5;
     for (uint32_t i = tid; i < nwords; i += 256) s_words[i] = 0u;
-    // chunk offsets that start inside this tile
+    // chunk offsets that start inside this pass
     if ((my0 & (a.L.sub_size - 1)) == 0 && my0 < a.g.padded) {
-        const uint64_t s = my0 >> a.L.sub_shift;
-        if ((s & (a.L.chunk_subs - 1)) == 0)
-            *reinterpret_cast<uint64_t *>(a.archive + a.L.off_chunk + 8ull * (s / a.L.chunk_subs)) = G + excl;
+        const uint64_t sub = my0 >> a.L.sub_shift;
+        if ((sub & (a.L.chunk_subs - 1)) == 0)
+            *reinterpret_cast<uint64_t *>(a.archive + a.L.off_chunk + 8ull * (sub / a.L.chunk_subs)) = base + excl;
     }
     __syncthreads();
     {
-        // the thread's codes are built MSB-first in a 64-bit register (current
-        // word in bits 63..32); words wholly inside the thread's bit range are
-        // stored plainly, the first and last words (shared with the
-        // neighbouring threads when the range starts or ends mid-word) are ORed
         const uint32_t bit = lead + excl;
         uint32_t w = bit >> 5, fill = bit & 31u;
         bool head = fill != 0;
         uint64_t acc = 0;
 #pragma unroll
-        for (uint32_t i = 0; i < kEncPer; i++) {
+        for (uint32_t i = 0; i < PER; i++) {
             if (q[i] == kNoSymbol) continue;
             const Entry e = s_book[q[i]];
             const uint32_t len = CW::len(e);
@@ -211,10 +211,10 @@ __device__ __forceinline__ void pack_tile(const EncArgs &a, uint64_t *s_dyn, uin
         if (fill) atomicOr(&s_words[w], (uint32_t)(acc >> 32));
     }
     __syncthreads();
-    uint32_t *stream = reinterpret_cast<uint32_t *>(a.archive + ctl->off_str);
-    const uint64_t W0 = G >> 5;
+    uint32_t *stream = reinterpret_cast<uint32_t *>(a.archive + a.ctl->off_str);
+    const uint64_t W0 = base >> 5;
     const bool shared_first = lead != 0;
-    const bool shared_last = ((lead + (uint32_t)tile_bits) & 31u) != 0;
+    const bool shared_last = ((lead + (uint32_t)pass_bits) & 31u) != 0;
     for (uint32_t i = tid; i < nwords; i += 256) {
         const uint32_t v = s_words[i];
         const bool edge = (i == 0 && shared_first) || (i == nwords - 1 && shared_last);
@@ -224,14 +224,66 @@ __device__ __forceinline__ void pack_tile(const EncArgs &a, uint64_t *s_dyn, uin
             stream[W0 + i] = v;
         }
     }
+    return (uint32_t)pass_bits;
+}
+
+// A pass spans at most kPackWords words: a whole tile of codes up to 32 bits,
+// or half a tile of codes up to 63 bits (the 64-bit codeword path packs a
+// tile in two halves).
+constexpr uint32_t kPackWords = kTile + 2;
+
+template <bool WIDE>
+__device__ __forceinline__ void pack_tile(const EncArgs &a, uint32_t *s_words, uint64_t *s_book_raw,
+                                          uint64_t *s_scan, uint64_t *s_G) {
+    typedef typename Codeword<WIDE>::T Entry;
+    Entry *s_book = reinterpret_cast<Entry *>(s_book_raw);
+    const uint32_t tid = threadIdx.x, t = blockIdx.x;
+    const Entry *gbook = WIDE ? reinterpret_cast<const Entry *>(a.b.book) : reinterpret_cast<const Entry *>(a.b.book32);
+    {
+        // codebook into LDS: all loads of a thread in flight
+        Entry e[kMaxSyms / 256];
+#pragma unroll
+        for (uint32_t k = 0; k < kMaxSyms / 256; k++) {
+            const uint32_t i = tid + 256 * k;
+            if (i < a.L.nsym) e[k] = gbook[i];
+        }
+        // the tile's global bit offset: wave 0 sums the totals of the earlier segments
+        if (tid < 64) {
+            const uint32_t seg = t / kSegTiles;
+            uint64_t part = 0;
+            for (uint32_t i = tid; i < seg; i += 64) part += a.b.escan.seg_total[0][i];
+            part = wave_sum<uint64_t>(part);
+            if (tid == 0) *s_G = part + a.b.escan.excl[0][t];
+        }
+#pragma unroll
+        for (uint32_t k = 0; k < kMaxSyms / 256; k++) {
+            const uint32_t i = tid + 256 * k;
+            if (i < a.L.nsym) s_book[i] = e[k];
+        }
+    }
+    __syncthreads();
+    const uint64_t G = *s_G;
+    const uint64_t p0 = (uint64_t)t * kTile;
+    if (!WIDE) {
+        (void)pack_pass<false, kEncPer>(a, p0, G, reinterpret_cast<const uint32_t *>(s_book), s_words, s_scan);
+    } else {
+        const uint32_t b0 = pack_pass<true, kEncPer / 2>(a, p0, G, reinterpret_cast<const uint64_t *>(s_book),
+                                                         s_words, s_scan);
+        __syncthreads();   // the word buffer is reused
+        (void)pack_pass<true, kEncPer / 2>(a, p0 + kTile / 2, G + b0, reinterpret_cast<const uint64_t *>(s_book),
+                                           s_words, s_scan);
+    }
 }
 
 __global__ __launch_bounds__(256) void k_enc_pack(EncArgs a) {
     extern __shared__ uint64_t s_dyn[];
     __shared__ uint64_t s_scan[10];
+    __shared__ uint64_t s_G;
     if (a.ctl->status & kBadStatus) return;
-    if (a.ctl->max_len <= 24) pack_tile<false>(a, s_dyn, s_scan);
-    else pack_tile<true>(a, s_dyn, s_scan);
+    uint32_t *s_words = reinterpret_cast<uint32_t *>(s_dyn);               // kPackWords
+    uint64_t *s_book = s_dyn + (kPackWords + 1) / 2;                       // nsym entries
+    if (a.ctl->max_len <= 24) pack_tile<false>(a, s_words, s_book, s_scan, &s_G);
+    else pack_tile<true>(a, s_words, s_book, s_scan, &s_G);
 }
 
 // One workgroup per segment: exclusive prefix of the tile values inside
@@ -281,7 +333,7 @@ void launch_encode(hipStream_t s, const Geom &g, const Layout &L, Ctl *ctl, cons
     const uint32_t grid1 = a.n_tiles_e > b.n_tiles_q ? a.n_tiles_e : b.n_tiles_q;
     hipLaunchKernelGGL(k_enc_count, dim3(grid1), dim3(256), 0, s, a);
     launch_seg_scan(s, b.escan);
-    const size_t lds = sizeof(uint64_t) * ((kEncWords + 1) / 2 + L.nsym);
+    const size_t lds = sizeof(uint64_t) * ((kPackWords + 1) / 2 + L.nsym);
     hipLaunchKernelGGL(k_enc_pack, dim3(a.n_tiles_e), dim3(256), lds, s, a);
 }
 
