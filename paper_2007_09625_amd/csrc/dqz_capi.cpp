@@ -141,7 +141,7 @@ struct WsLayout {
     uint64_t hist_sum, book, book32, parts;
     uint64_t qval[2], qexcl[2], qseg_total[2];
     uint64_t eval, eexcl, eseg_total;
-    uint64_t stage, codes, total;
+    uint64_t stage, codes, qws, total;
     uint32_t n_segs_q, n_segs_e, cap;
 };
 
@@ -159,6 +159,8 @@ WsLayout ws_layout(const Plan &P, bool compress, uint32_t cap) {
     w.ctl = take(cur, sizeof(Ctl));
     w.tab = take(cur, sizeof(DecodeTables));
     if (!compress) {
+        // decoded codes of 128-position subchunks, 256 bytes per subchunk
+        w.qws = P.L.sub_size == 128 ? take(cur, 256ull * P.L.n_sub) : 0;
         w.total = align_up(cur, 256);
         return w;
     }
@@ -518,7 +520,8 @@ dqz_status dqz_decompress(dqz_ctx *ctx, const void *d_archive, uint64_t archive_
     mark(ctx, 1, 0, s);
     launch_decode_tables(s, P.L, arc, hi.max_len, tab);
     mark(ctx, 1, 1, s);
-    launch_decode(s, P.g, P.L, arc, hi.off_str, hi.n_words, (uint32_t)hi.n_exc, hi.h, tab, d_field, ctx->trace);
+    uint4 *qws = P.L.sub_size == 128 ? reinterpret_cast<uint4 *>(ws + W.qws) : nullptr;
+    launch_decode(s, P.g, P.L, arc, hi.off_str, hi.n_words, (uint32_t)hi.n_exc, hi.h, tab, d_field, ctx->trace, qws);
     mark(ctx, 1, 2, s);
     HIP_TRY(ctx, hipGetLastError());
     HIP_TRY(ctx, hipMemcpyAsync(&ctx->h_ctl->status, &tab->status, 4, hipMemcpyDeviceToHost, s));

@@ -267,6 +267,7 @@ void launch_decode_tables(hipStream_t s, const Layout &L, const uint8_t *archive
                           DecodeTables *tab);
 size_t decode_lds_bytes(const Layout &L);
 void launch_decode(hipStream_t s, const Geom &g, const Layout &L, const uint8_t *archive, uint64_t off_str,
-                   uint64_t n_words, uint32_t n_exc, float h, DecodeTables *tab, float *out, bool trace);
+                   uint64_t n_words, uint32_t n_exc, float h, DecodeTables *tab, float *out, bool trace,
+                   uint4 *qws);
 
 }  // namespace dqz

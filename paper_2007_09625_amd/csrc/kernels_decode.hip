@@ -39,6 +39,7 @@ struct DecArgs {
     uint32_t qstride;   // LDS code-buffer stride per subchunk (sub_size + 2: spreads lanes over banks)
     uint32_t win_words; // LDS stream-window words per wave
     uint32_t trace;     // record phase durations into tab->phase
+    uint4 *qws;         // 128-position subchunks: 16 x 16 bytes of codes per subchunk
 };
 
 // Stream word i.  Indices past the end are clamped to the last word rather
@@ -457,39 +458,44 @@ __device__ __forceinline__ uint32_t quad_pair_lo(uint32_t v) {
     return pinned((uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xA0, 0xF, 0xF, false));
 }
 
-// Called by whole active waves (the cross-lane steps need every lane).
-__device__ __forceinline__ void recon128(const DecArgs &a, const lds_u16 *wq, uint32_t lane, uint32_t P0,
-                                         uint32_t e0, const lds_u32 *xp, bool has, bool &bad) {
-    const Geom &g = a.g;
-    const float h = a.h;
+// The lane's 128 deltas from its codes in the LDS code buffer (outlier slots
+// marked with their index in the exception list).
+__device__ __forceinline__ void deltas_from_lds(const DecArgs &a, const lds_u16 *wq, uint32_t lane, uint32_t e0,
+                                                const lds_u32 *xp, bool has, bool &bad, int32_t (&v)[128]) {
     const uint32_t R = a.L.radius;
-    int32_t v[128];
-    {
-        // the lane's codes: 64 aligned pairs (the code-buffer stride is even)
-        const lds_u32 *src = (const lds_u32 *)(wq + lane * a.qstride);
-        uint32_t special = 0;
+    // the lane's codes: 64 aligned pairs (the code-buffer stride is even)
+    const lds_u32 *src = (const lds_u32 *)(wq + lane * a.qstride);
+    uint32_t special = 0;
 #pragma unroll
-        for (uint32_t k = 0; k < 64; k++) {
-            const uint32_t two = has ? src[k] : (R | (R << 16));
-            const uint32_t q0 = two & 0xFFFFu, q1 = two >> 16;
-            v[2 * k] = (int32_t)q0 - (int32_t)R;
-            v[2 * k + 1] = (int32_t)q1 - (int32_t)R;
-            // code 0 (an unmarked outlier) or a marked outlier slot
-            special |= ((q0 - 1u) >= 0x7FFFu ? 1u : 0u) | ((q1 - 1u) >= 0x7FFFu ? 1u : 0u);
-        }
-        if (special) {
+    for (uint32_t k = 0; k < 64; k++) {
+        const uint32_t two = has ? src[k] : (R | (R << 16));
+        const uint32_t q0 = two & 0xFFFFu, q1 = two >> 16;
+        v[2 * k] = (int32_t)q0 - (int32_t)R;
+        v[2 * k + 1] = (int32_t)q1 - (int32_t)R;
+        // code 0 (an unmarked outlier) or a marked outlier slot
+        special |= ((q0 - 1u) >= 0x7FFFu ? 1u : 0u) | ((q1 - 1u) >= 0x7FFFu ? 1u : 0u);
+    }
+    if (special) {
 #pragma unroll
-            for (uint32_t i = 0; i < 128; i++) {
-                const uint32_t q = (uint32_t)(v[i] + (int32_t)R);
-                if (q & 0x8000u) v[i] = (int32_t)slot_delta(a, (uint16_t)q, e0, xp, bad);
-                else if (q == 0) bad = true;
-            }
+        for (uint32_t i = 0; i < 128; i++) {
+            const uint32_t q = (uint32_t)(v[i] + (int32_t)R);
+            if (q & 0x8000u) v[i] = (int32_t)slot_delta(a, (uint16_t)q, e0, xp, bad);
+            else if (q == 0) bad = true;
         }
     }
+}
+
+// Reconstruction of the lane's 128 deltas in place, dequantization and the
+// stores of its in-field values.  Called by whole active waves (the
+// cross-lane steps need every lane).
+template <uint32_t NDIM>
+__device__ __forceinline__ void recon128(const DecArgs &a, int32_t (&v)[128], uint32_t lane, uint32_t P0, bool has) {
+    const Geom &g = a.g;
+    const float h = a.h;
     const uint32_t pa = P0 + lane * 128u;
     const uint32_t n1 = g.n[1], n2 = g.n[2];
     const bool vec = (n2 % 4u == 0) && ((reinterpret_cast<uintptr_t>(a.out) & 15u) == 0);
-    if (g.ndim == 3) {
+    if (NDIM == 3) {
         const uint32_t blk = pa >> 9;
         const uint32_t Bx = blk % g.nb[2], By = (blk / g.nb[2]) % g.nb[1], Bz = blk / (g.nb[2] * g.nb[1]);
         const uint32_t vx = min(8u, n2 - 8 * Bx), vy = min(8u, n1 - 8 * By), vz = min(8u, g.n[0] - 8 * Bz);
@@ -504,41 +510,45 @@ __device__ __forceinline__ void recon128(const DecArgs &a, const lds_u16 *wq, ui
 #pragma unroll
                 for (uint32_t x = 0; x < 8; x++) v[zi * 64 + y * 8 + x] += v[zi * 64 + (y - 1) * 8 + x];
         }
-        const uint32_t jq = lane & 3u;
+        // z prefix across the quad, one row of the two planes at a time; each
+        // row is stored as soon as it is final (keeps few rows live)
+        const uint32_t jq = lane & 3u, z0 = 2 * jq;
+        const bool okA = has && z0 < vz, okB = has && z0 + 1 < vz;
+        float *oA = a.out + ((8ull * Bz + z0) * n1 + 8 * By) * n2 + 8 * Bx;
+        float *oB = oA + (uint64_t)n1 * n2;
 #pragma unroll
-        for (uint32_t k = 0; k < 64; k++) {
-            const uint32_t b = (uint32_t)(v[64 + k] + v[k]);   // planes 2j and 2j + 1
-            const uint32_t s1 = quad_shr1(b);
-            const uint32_t t1 = b + (jq >= 1 ? s1 : 0u);
-            const uint32_t s2 = quad_shr2(t1);
-            const uint32_t t = t1 + (jq >= 2 ? s2 : 0u);       // inclusive over the quad
-            v[k] += (int32_t)(t - b);
-            v[64 + k] = (int32_t)t;
-        }
-        if (!has) return;
-        const uint32_t z0 = 2 * jq;
+        for (uint32_t y = 0; y < 8; y++) {
 #pragma unroll
-        for (uint32_t zi = 0; zi < 2; zi++) {
-            if (z0 + zi >= vz) continue;
-            const uint64_t zz = 8ull * Bz + z0 + zi;
+            for (uint32_t x = 0; x < 8; x++) {
+                const uint32_t k = y * 8 + x;
+                const uint32_t b = (uint32_t)(v[64 + k] + v[k]);   // planes 2j and 2j + 1
+                const uint32_t s1 = quad_shr1(b);
+                const uint32_t t1 = b + (jq >= 1 ? s1 : 0u);
+                const uint32_t s2 = quad_shr2(t1);
+                const uint32_t t = t1 + (jq >= 2 ? s2 : 0u);       // inclusive over the quad
+                v[k] += (int32_t)(t - b);
+                v[64 + k] = (int32_t)t;
+            }
+            if (y < vy) {
 #pragma unroll
-            for (uint32_t y = 0; y < 8; y++) {
-                if (y >= vy) continue;
-                float *o = a.out + (zz * n1 + 8 * By + y) * n2 + 8 * Bx;
-                const uint32_t r = zi * 64 + y * 8;
-                if (vx == 8 && vec) {
-                    reinterpret_cast<float4 *>(o)[0] = make_float4(dequant(v[r], h), dequant(v[r + 1], h),
-                                                                   dequant(v[r + 2], h), dequant(v[r + 3], h));
-                    reinterpret_cast<float4 *>(o)[1] = make_float4(dequant(v[r + 4], h), dequant(v[r + 5], h),
-                                                                   dequant(v[r + 6], h), dequant(v[r + 7], h));
-                } else {
+                for (uint32_t zi = 0; zi < 2; zi++) {
+                    if (!(zi ? okB : okA)) continue;
+                    float *o = (zi ? oB : oA) + (uint64_t)y * n2;
+                    const uint32_t r = zi * 64 + y * 8;
+                    if (vx == 8 && vec) {
+                        reinterpret_cast<float4 *>(o)[0] = make_float4(dequant(v[r], h), dequant(v[r + 1], h),
+                                                                       dequant(v[r + 2], h), dequant(v[r + 3], h));
+                        reinterpret_cast<float4 *>(o)[1] = make_float4(dequant(v[r + 4], h), dequant(v[r + 5], h),
+                                                                       dequant(v[r + 6], h), dequant(v[r + 7], h));
+                    } else {
 #pragma unroll
-                    for (uint32_t x = 0; x < 8; x++)
-                        if (x < vx) o[x] = dequant(v[r + x], h);
+                        for (uint32_t x = 0; x < 8; x++)
+                            if (x < vx) o[x] = dequant(v[r + x], h);
+                    }
                 }
             }
         }
-    } else if (g.ndim == 2) {
+    } else if (NDIM == 2) {
         const uint32_t blk = pa >> 8;
         const uint32_t Bx = blk % g.nb[2], By = blk / g.nb[2];
         const uint32_t vx = min(16u, n2 - 16 * Bx), vy = min(16u, n1 - 16 * By);
@@ -669,7 +679,11 @@ __global__ __launch_bounds__(64 * kDecMaxWaves) void k_decode(DecArgs a) {
     __syncthreads();
     if (a.trace) tm[4] = wall_clock64();
     if (active && S == 128) {
-        recon128(a, wq, lane, (uint32_t)P0, e0, xp, has, bad);
+        int32_t v[128];
+        deltas_from_lds(a, wq, lane, e0, xp, has, bad, v);
+        if (a.g.ndim == 3) recon128<3>(a, v, lane, (uint32_t)P0, has);
+        else if (a.g.ndim == 2) recon128<2>(a, v, lane, (uint32_t)P0, has);
+        else recon128<1>(a, v, lane, (uint32_t)P0, has);
     } else if (active) {
         const Geom &g = a.g;
         const float h = a.h;
@@ -744,6 +758,260 @@ __global__ __launch_bounds__(64 * kDecMaxWaves) void k_decode(DecArgs a) {
     }
 }
 
+constexpr uint32_t kG128Waves = 4;       // waves per workgroup (they share the lookup table)
+constexpr uint32_t kG128Win = 2432;      // LDS stream-window slots per wave (9.5 KiB)
+constexpr uint32_t kG128Out = 512;       // outlier records staged per wave (position u16 + delta u32)
+
+// The lane's 128 deltas from its codes in the workspace slot; outliers (code
+// 0) take their deltas from the wave's staged outlier list, or from the
+// archive's exception list when the wave had more outliers than were staged.
+// Every outlier record must be used exactly once.
+__device__ __forceinline__ void deltas_from_slot(const DecArgs &a, const uint4 *qslot, uint32_t lane, uint32_t P0,
+                                                 uint32_t e0, uint32_t e1, uint32_t n_out, const lds_u16 *opos,
+                                                 const lds_u32 *oval, uint32_t cap, bool has, bool &bad,
+                                                 int32_t (&v)[128]) {
+    const uint32_t R = a.L.radius;
+    uint32_t zero = 0;
+    if (has) {
+#pragma unroll
+        for (uint32_t g = 0; g < 16; g++) {
+            const uint4 q4 = qslot[g];
+            const uint32_t u[4] = {q4.x, q4.y, q4.z, q4.w};
+#pragma unroll
+            for (uint32_t k = 0; k < 4; k++) {
+                const uint32_t q0 = u[k] & 0xFFFFu, q1 = u[k] >> 16;
+                v[8 * g + 2 * k] = (int32_t)q0 - (int32_t)R;
+                v[8 * g + 2 * k + 1] = (int32_t)q1 - (int32_t)R;
+                zero |= (q0 == 0 ? 1u : 0u) | (q1 == 0 ? 1u : 0u);
+            }
+        }
+    } else {
+#pragma unroll
+        for (uint32_t i = 0; i < 128; i++) v[i] = 0;
+    }
+    uint32_t hits = 0;
+    if (zero) {
+        const uint32_t rel0 = lane * 128u;
+        const bool ovf = n_out > cap;
+        uint32_t oc;
+        {
+            uint32_t lo = ovf ? e0 : 0u, hi = ovf ? e1 : n_out;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                const bool below = ovf ? ((uint64_t)a.exc[mid].x < 2ull * (P0 + rel0)) : (opos[mid] < rel0);
+                if (below) lo = mid + 1; else hi = mid;
+            }
+            oc = lo;
+        }
+#pragma unroll
+        for (uint32_t i = 0; i < 128; i++) {
+            if (v[i] != -(int32_t)R) continue;   // code 0 marks an outlier
+            int32_t d = 0;
+            if (!ovf) {
+                if (oc < n_out && opos[oc] == rel0 + i) d = (int32_t)oval[oc];
+                else bad = true;
+            } else {
+                while (oc < e1 && (a.exc[oc].x & 1u)) oc++;
+                if (oc < e1 && (a.exc[oc].x >> 1) == P0 + rel0 + i) d = (int32_t)a.exc[oc].y;
+                else bad = true;
+            }
+            v[i] = d;
+            oc++;
+            hits++;
+        }
+    }
+    if (wave_sum<uint32_t>(hits) != n_out) bad = true;
+}
+
+template <uint32_t NDIM>
+__device__ __forceinline__ void recon128g(const DecArgs &a, const uint4 *qslot, uint32_t lane, uint32_t P0, uint32_t e0,
+                                          uint32_t e1, uint32_t n_out, const lds_u16 *opos, const lds_u32 *oval,
+                                          bool has, bool &bad) {
+    int32_t v[128];
+    deltas_from_slot(a, qslot, lane, P0, e0, e1, n_out, opos, oval, kG128Out, has, bad, v);
+    recon128<NDIM>(a, v, lane, P0, has);
+}
+
+// ---------------------------------------------------------------------------
+// Decoder for subchunks of 128 positions (the default S) without an LDS code
+// buffer.  Each lane's codes go to a per-subchunk slot of a workspace array
+// (eight codes per 16-byte store) and come back to the same lane for the
+// register reconstruction, which also substitutes the lane's outliers from
+// the wave's staged outlier list.  Only the lookup tables, the stream window
+// and the staged outliers stay in LDS, so workgroups of four waves fit two
+// per CU (two waves per SIMD).
+// ---------------------------------------------------------------------------
+
+// Inflate the lane's 128 positions into 16 packed 16-byte groups of dst.
+// Same steps as inflate(); the inner loop over a group of eight positions is
+// unrolled so that the codes pack into registers.
+__device__ __forceinline__ uint32_t inflate128(const DecArgs &a, const lds_u32 *win, uint32_t nwin, uint64_t wlo,
+                                               uint64_t start, uint32_t pa, uint4 *dst, const lds_u16 *lut,
+                                               const DecLds &t, const lds_u16 *sorted, uint32_t max_len, bool &bad) {
+    const uint64_t sw = start >> 5;
+    const uint32_t relw = (sw >= wlo && sw - wlo < nwin) ? (uint32_t)(sw - wlo) : nwin;
+    const uint32_t wlast = nwin ? nwin - 1 : 0;
+    auto word = [&](uint32_t kr) -> uint32_t {
+        const uint32_t k = relw + kr;
+        return (k < nwin) ? win[win_slot(k)] : ld_word(a, sw + kr);
+    };
+    const uint32_t R = a.L.radius;
+    uint32_t used = 0, kr = 2;
+    uint32_t o = (uint32_t)(start & 31u);
+    uint64_t cur = (((uint64_t)word(0) << 32) | word(1)) << o;
+    int32_t avail = 64 - (int32_t)o;
+    uint32_t nxt = word(kr);
+    uint32_t rmask = 0;
+    for (uint32_t g = 0; g < 16; g++) {
+        if ((g & 3u) == 0) rmask = real_mask32(a.g, pa + g * 8);
+        uint32_t pk[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+        for (uint32_t j = 0; j < 8; j++) {
+            const bool need = avail <= 32;
+            const uint32_t shl = need ? (uint32_t)(32 - avail) : 0u;
+            cur |= need ? ((uint64_t)nxt << shl) : 0ull;
+            avail += need ? 32 : 0;
+            kr += need ? 1u : 0u;
+            const uint32_t k = relw + kr;
+            nxt = win[win_slot(k < nwin ? k : wlast)];
+            const bool real = (rmask >> ((g & 3u) * 8 + j)) & 1u;
+            const uint32_t e = lut[(uint32_t)(cur >> (64 - kLutBits))];
+            uint32_t len = (e >> 11) & 15u, sym = e & 0x7FFu;
+            const bool slow = real && ((e & 0x8000u) || len == 0);
+            bool moved = false;
+            if (__any((int)(slow || k >= nwin))) {
+                if (k >= nwin) nxt = ld_word(a, sw + kr);
+                if (slow && !(e & 0x8000u)) {   // no code starts with these bits
+                    bad = true;
+                    len = 1;
+                    sym = R;
+                } else if (slow) {
+                    uint32_t l = e & 63u;
+                    uint64_t wv = cur;
+                    if (max_len > 32) {
+                        const uint64_t bp = start + used;
+                        const uint64_t ww = bp >> 5;
+                        const uint32_t ob = (uint32_t)(bp & 31u);
+                        const uint64_t h2 = ((uint64_t)ld_word(a, ww) << 32) | ld_word(a, ww + 1);
+                        wv = ob ? ((h2 << ob) | (ld_word(a, ww + 2) >> (32 - ob))) : h2;
+                    }
+                    while (l < max_len && wv >= t.limit[l]) l++;
+                    const uint64_t c = wv >> (64 - l);
+                    const uint64_t idx = t.first_index[l] + (c - t.first_code[l]);
+                    if (idx >= a.L.nsym) { bad = true; sym = R; }
+                    else sym = sorted[idx];
+                    len = l;
+                    if ((int32_t)l > avail) {
+                        used += l;
+                        const uint64_t bp = start + used;
+                        o = (uint32_t)(bp & 31u);
+                        kr = (uint32_t)((bp >> 5) - sw);
+                        cur = (((uint64_t)word(kr) << 32) | word(kr + 1)) << o;
+                        avail = 64 - (int32_t)o;
+                        kr += 2;
+                        nxt = word(kr);
+                        moved = true;
+                    }
+                }
+            }
+            if (!real || moved) len = 0;
+            cur <<= len;
+            avail -= (int32_t)len;
+            used += len;
+            pk[j >> 1] |= (real ? sym : R) << (16 * (j & 1u));
+        }
+        dst[g] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
+    }
+    return used;
+}
+
+template <uint32_t NDIM>
+__global__ __launch_bounds__(64 * kG128Waves) __attribute__((amdgpu_waves_per_eu(2))) void k_decode_g128(DecArgs a) {
+    extern __shared__ uint32_t s_dyn[];
+    __shared__ DecLds s_t;
+    lds_u16 *s_lut = (lds_u16 *)s_dyn;                                 // 1 << kLutBits
+    lds_u16 *s_sorted = s_lut + (1u << kLutBits);                     // nsym
+    lds_u32 *s_win = (lds_u32 *)(s_sorted + a.L.nsym);                // waves * win_words
+    lds_u32 *s_oval = s_win + kG128Waves * a.win_words;               // waves * kG128Out
+    lds_u16 *s_opos = (lds_u16 *)(s_oval + kG128Waves * kG128Out);    // waves * kG128Out
+    if (a.tab->status) return;   // the code lengths failed validation: tables are not usable
+    uint64_t tm[7];
+    tm[0] = a.trace ? wall_clock64() : 0;
+    tables_to_lds(a, s_lut, s_sorted, s_t);
+    __syncthreads();
+    if (a.trace) tm[1] = wall_clock64();
+
+    const uint32_t lane = lane_id(), w = threadIdx.x / 64;
+    const uint32_t gw = blockIdx.x * kG128Waves + w;
+    const bool active = gw < a.wave_tasks;
+    const uint64_t sub0 = (uint64_t)gw * 64;
+    const uint32_t P0 = (uint32_t)(sub0 << 7);                        // padded positions are < 2^31
+    const uint32_t P1 = active ? (a.g.padded - P0 < 8192u ? a.g.padded : P0 + 8192u) : P0;
+    const bool has = active && sub0 + lane < a.L.n_sub;
+    lds_u32 *win = s_win + w * a.win_words;
+    lds_u32 *oval = s_oval + w * kG128Out;
+    lds_u16 *opos = s_opos + w * kG128Out;
+    bool bad = false;
+    WaveStream ws = {0, 0, 0, 0};
+    uint32_t e0 = 0, e1 = 0, n_out = 0;
+    if (active) {
+        ws = wave_stream(a, sub0, lane, has, win);
+        e0 = wave_lower_bound(a.exc, a.n_exc, 2ull * P0, lane);
+        e1 = wave_lower_bound(a.exc, a.n_exc, 2ull * P1, lane);
+        // the wave's outlier records, compacted in position order
+        for (uint32_t eb = e0; eb < e1; eb += 64) {
+            const uint32_t e = eb + lane;
+            uint2 r = make_uint2(1u, 0u);
+            if (e < e1) r = a.exc[e];
+            const bool is_out = !(r.x & 1u);
+            const uint64_t m = __ballot(is_out);
+            const uint32_t k = n_out + (uint32_t)__popcll(m & lanes_below(lane));
+            if (is_out) {
+                const uint32_t rp = (r.x >> 1) - P0;   // wraps for keys below the range (damaged list)
+                if (rp >= P1 - P0) bad = true;
+                else if (k < kG128Out) { opos[k] = (uint16_t)rp; oval[k] = r.y; }
+            }
+            n_out += (uint32_t)__popcll(m);
+        }
+    }
+    __syncthreads();
+    if (a.trace) tm[2] = wall_clock64();
+
+    uint4 *qslot = a.qws + (sub0 + lane) * 16;
+    if (has) {
+        const uint32_t max_len = a.tab->max_len < 63u ? a.tab->max_len : 63u;
+        const uint32_t used = inflate128(a, win, ws.nwin, ws.wlo, ws.start, P0 + lane * 128u, qslot, s_lut, s_t,
+                                         s_sorted, max_len, bad);
+        if (used != ws.bits) bad = true;
+    }
+    if (a.trace) tm[3] = wall_clock64();
+    if (a.trace) tm[4] = tm[3];
+    if (active) recon128g<NDIM>(a, qslot, lane, P0, e0, e1, n_out, opos, oval, has, bad);
+    __syncthreads();   // all regular values are stored before patches overwrite some
+    if (a.trace) tm[5] = wall_clock64();
+    if (active) {
+        for (uint32_t e = e0 + lane; e < e1; e += 64) {
+            const uint2 r = a.exc[e];
+            if (!(r.x & 1u)) continue;
+            const uint64_t p = r.x >> 1;
+            if (!pos_real(a.g, p)) { bad = true; continue; }
+            a.out[pos_to_index(a.g, p)] = __uint_as_float(r.y);
+        }
+    }
+    if (bad) atomicOr(a.status, ST_ECORRUPT);
+    if (a.trace && active && lane == 0) {
+        tm[6] = wall_clock64();
+        uint64_t *ph = const_cast<uint64_t *>(a.tab->phase);
+        atomicMin((unsigned long long *)&ph[8], (unsigned long long)tm[0]);
+        atomicMax((unsigned long long *)&ph[9], (unsigned long long)tm[6]);
+        for (int k = 0; k < 6; k++) atomicAdd((unsigned long long *)&ph[10 + k], (unsigned long long)(tm[k + 1] - tm[k]));
+    }
+}
+
+static size_t decode_g128_lds_bytes(const Layout &L) {
+    return sizeof(uint16_t) * ((1u << kLutBits) + L.nsym) + (size_t)kG128Waves * (4 * kG128Win + 6 * kG128Out);
+}
+
 static uint32_t decode_waves(const Layout &L) { return L.sub_size <= 256 ? kDecMaxWaves : 1u; }
 
 constexpr size_t kDecLdsLimit = 160 * 1024;       // LDS one workgroup may allocate on gfx950
@@ -767,7 +1035,8 @@ size_t decode_lds_bytes(const Layout &L) {
 }
 
 void launch_decode(hipStream_t s, const Geom &g, const Layout &L, const uint8_t *archive, uint64_t off_str,
-                   uint64_t n_words, uint32_t n_exc, float h, DecodeTables *tab, float *out, bool trace) {
+                   uint64_t n_words, uint32_t n_exc, float h, DecodeTables *tab, float *out, bool trace,
+                   uint4 *qws) {
     DecArgs a;
     a.g = g;
     a.L = L;
@@ -785,7 +1054,20 @@ void launch_decode(hipStream_t s, const Geom &g, const Layout &L, const uint8_t 
     a.qstride = L.sub_size + 2;
     a.win_words = decode_win_words(L);
     a.trace = trace ? 1u : 0u;
+    a.qws = qws;
     if (a.wave_tasks == 0) return;
+    if (L.sub_size == 128 && qws) {
+        a.win_words = kG128Win;
+        const uint32_t blocks = (a.wave_tasks + kG128Waves - 1) / kG128Waves;
+        const size_t lds = decode_g128_lds_bytes(L);
+        const void *fn = g.ndim == 3 ? (const void *)k_decode_g128<3>
+                                     : (g.ndim == 2 ? (const void *)k_decode_g128<2> : (const void *)k_decode_g128<1>);
+        if (lds > 65536) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (g.ndim == 3) hipLaunchKernelGGL(k_decode_g128<3>, dim3(blocks), dim3(64 * kG128Waves), lds, s, a);
+        else if (g.ndim == 2) hipLaunchKernelGGL(k_decode_g128<2>, dim3(blocks), dim3(64 * kG128Waves), lds, s, a);
+        else hipLaunchKernelGGL(k_decode_g128<1>, dim3(blocks), dim3(64 * kG128Waves), lds, s, a);
+        return;
+    }
 
     const uint32_t waves = decode_waves(L);
     const uint32_t blocks = (a.wave_tasks + waves - 1) / waves;
