@@ -24,7 +24,8 @@ struct dqz_ctx {
     int ncu = 256;
     void *ws = nullptr;        // device scratch
     size_t ws_bytes = 0;
-    Ctl *h_ctl = nullptr;      // pinned readback of the control block
+    Ctl *h_ctl = nullptr;      // readback block in pinned host memory, written by the kernels
+    Ctl *d_hctl = nullptr;     // the same block's device address
     std::string last_error;
     // most recent compression, for the stage dumps
     uint16_t *last_codes = nullptr;
@@ -136,6 +137,18 @@ void fill_params(const dqz_params *p, uint32_t &radius, uint32_t &sub, uint32_t 
 // offsets, then the zeroed region (histogram replicas, scan counters), then
 // the compression buffers (so a decompression never overwrites the last
 // compression's stage buffers kept for dqz_debug_copy)
+// Wait for the stream by polling: the end of each call is on the critical
+// path, and a polling wait returns sooner than a blocking one.
+hipError_t wait_stream(hipStream_t s) {
+    for (;;) {
+        const hipError_t e = hipStreamQuery(s);
+        if (e != hipErrorNotReady) return e;
+    }
+}
+
+// readback status before the codebook kernel has written the block
+constexpr uint32_t kNoReadback = 0xFFFFFFFFu;
+
 struct WsLayout {
     uint64_t ctl, tab, hist, zero_end;
     uint64_t hist_sum, book, book32, parts;
@@ -327,6 +340,12 @@ dqz_status dqz_ctx_create(int device, dqz_ctx **out) {
         delete ctx;
         return DQZ_ENOMEM;
     }
+    if (hipHostGetDevicePointer((void **)&ctx->d_hctl, ctx->h_ctl, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipHostFree(ctx->h_ctl);
+        delete ctx;
+        return DQZ_EHIP;
+    }
     *out = ctx;
     return DQZ_OK;
 }
@@ -440,19 +459,20 @@ dqz_status dqz_compress(dqz_ctx *ctx, const float *d_field, const dqz_shape *sha
 
         ctx->ev_ready[0] = false;
         mark(ctx, 0, 0, s);
+        ctx->h_ctl->status = kNoReadback;   // the codebook kernel overwrites it
         launch_init(s, ctl, ws + W.hist, W.zero_end - W.hist, params->eb_mode, params->eb);
         mark(ctx, 0, 1, s);
         if (params->eb_mode == DQZ_EB_VALREL) launch_minmax(s, d_field, P.g.nelem, ctl, parts, params->eb, ctx->ncu);
         mark(ctx, 0, 2, s);
         launch_quantize(s, d_field, P.g, P.L, ctl, qb);
         mark(ctx, 0, 3, s);
-        launch_codebook(s, P.g, P.L, ctl, qb.hist_sum, book, book32, arc, params->eb_mode, params->eb, qs);
+        launch_codebook(s, P.g, P.L, ctl, qb.hist_sum, book, book32, arc, params->eb_mode, params->eb, qs,
+                        ctx->d_hctl);
         mark(ctx, 0, 4, s);
         launch_encode(s, P.g, P.L, ctl, eb, arc);
         mark(ctx, 0, 5, s);
         HIP_TRY(ctx, hipGetLastError());
-        HIP_TRY(ctx, hipMemcpyAsync(ctx->h_ctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
-        HIP_TRY(ctx, hipStreamSynchronize(s));
+        HIP_TRY(ctx, wait_stream(s));
         ctx->ev_ready[0] = ctx->timing;
         ctx->last_codes = codes;
         ctx->last_hist = hist;
@@ -462,6 +482,7 @@ dqz_status dqz_compress(dqz_ctx *ctx, const float *d_field, const dqz_shape *sha
         ctx->last_padded = P.g.padded;
         ctx->last_nsym = P.L.nsym;
         const Ctl &c = *ctx->h_ctl;
+        if (c.status == kNoReadback) return fail(ctx, DQZ_EINTERNAL, "the codebook kernel did not report");
         if ((c.status & ST_RETRY) && cap < 2 * kTile) continue;
         if (c.status & ST_ETOOSMALL) *archive_bytes = c.archive_bytes;
         st = status_from_device(ctx, c.status);
@@ -518,14 +539,15 @@ dqz_status dqz_decompress(dqz_ctx *ctx, const void *d_archive, uint64_t archive_
     const uint8_t *arc = reinterpret_cast<const uint8_t *>(d_archive);
     ctx->ev_ready[1] = false;
     mark(ctx, 1, 0, s);
-    launch_decode_tables(s, P.L, arc, hi.max_len, tab);
+    ctx->h_ctl->status = 0;   // the decoding kernels set it on damage
+    launch_decode_tables(s, P.L, arc, hi.max_len, tab, &ctx->d_hctl->status);
     mark(ctx, 1, 1, s);
     uint4 *qws = P.L.sub_size == 128 ? reinterpret_cast<uint4 *>(ws + W.qws) : nullptr;
-    launch_decode(s, P.g, P.L, arc, hi.off_str, hi.n_words, (uint32_t)hi.n_exc, hi.h, tab, d_field, ctx->trace, qws);
+    launch_decode(s, P.g, P.L, arc, hi.off_str, hi.n_words, (uint32_t)hi.n_exc, hi.h, tab, d_field, ctx->trace, qws,
+                  &ctx->d_hctl->status);
     mark(ctx, 1, 2, s);
     HIP_TRY(ctx, hipGetLastError());
-    HIP_TRY(ctx, hipMemcpyAsync(&ctx->h_ctl->status, &tab->status, 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(ctx, hipStreamSynchronize(s));
+    HIP_TRY(ctx, wait_stream(s));
     ctx->ev_ready[1] = ctx->timing;
     return status_from_device(ctx, ctx->h_ctl->status);
 }

@@ -250,7 +250,8 @@ void launch_quantize(hipStream_t s, const float *x, const Geom &g, const Layout 
 uint32_t quantize_tiles(const Geom &g);
 void launch_codebook(hipStream_t s, const Geom &g, const Layout &L, Ctl *ctl, const uint32_t *hist,
                      uint64_t *book, uint32_t *book32, uint8_t *archive, int eb_mode, double eb_param,
-                     const TileScan &qscan);
+                     const TileScan &qscan,
+                     Ctl *hctl);
 struct EncodeBufs {
     const uint16_t *codes;
     const uint64_t *book;
@@ -264,10 +265,10 @@ struct EncodeBufs {
 void launch_encode(hipStream_t s, const Geom &g, const Layout &L, Ctl *ctl, const EncodeBufs &b, uint8_t *archive);
 uint32_t encode_tiles(const Geom &g);
 void launch_decode_tables(hipStream_t s, const Layout &L, const uint8_t *archive, uint32_t max_len_hdr,
-                          DecodeTables *tab);
+                          DecodeTables *tab, uint32_t *hstatus);
 size_t decode_lds_bytes(const Layout &L);
 void launch_decode(hipStream_t s, const Geom &g, const Layout &L, const uint8_t *archive, uint64_t off_str,
                    uint64_t n_words, uint32_t n_exc, float h, DecodeTables *tab, float *out, bool trace,
-                   uint4 *qws);
+                   uint4 *qws, uint32_t *hstatus);
 
 }  // namespace dqz

@@ -40,6 +40,7 @@ struct DecArgs {
     uint32_t win_words; // LDS stream-window words per wave
     uint32_t trace;     // record phase durations into tab->phase
     uint4 *qws;         // 128-position subchunks: 16 x 16 bytes of codes per subchunk
+    uint32_t *hstatus;  // status word in pinned host memory, read after the stream ends
 };
 
 // Stream word i.  Indices past the end are clamped to the last word rather
@@ -748,7 +749,10 @@ __global__ __launch_bounds__(64 * kDecMaxWaves) void k_decode(DecArgs a) {
             a.out[pos_to_index(a.g, p)] = __uint_as_float(r.y);
         }
     }
-    if (bad) atomicOr(a.status, ST_ECORRUPT);
+    if (bad) {
+        atomicOr(a.status, ST_ECORRUPT);
+        *a.hstatus = ST_ECORRUPT;
+    }
     if (a.trace && active && lane == 0) {
         tm[6] = wall_clock64();
         uint64_t *ph = const_cast<uint64_t *>(a.tab->phase);
@@ -998,7 +1002,10 @@ __global__ __launch_bounds__(64 * kG128Waves) __attribute__((amdgpu_waves_per_eu
             a.out[pos_to_index(a.g, p)] = __uint_as_float(r.y);
         }
     }
-    if (bad) atomicOr(a.status, ST_ECORRUPT);
+    if (bad) {
+        atomicOr(a.status, ST_ECORRUPT);
+        *a.hstatus = ST_ECORRUPT;
+    }
     if (a.trace && active && lane == 0) {
         tm[6] = wall_clock64();
         uint64_t *ph = const_cast<uint64_t *>(a.tab->phase);
@@ -1036,7 +1043,7 @@ size_t decode_lds_bytes(const Layout &L) {
 
 void launch_decode(hipStream_t s, const Geom &g, const Layout &L, const uint8_t *archive, uint64_t off_str,
                    uint64_t n_words, uint32_t n_exc, float h, DecodeTables *tab, float *out, bool trace,
-                   uint4 *qws) {
+                   uint4 *qws, uint32_t *hstatus) {
     DecArgs a;
     a.g = g;
     a.L = L;
@@ -1055,6 +1062,7 @@ void launch_decode(hipStream_t s, const Geom &g, const Layout &L, const uint8_t 
     a.win_words = decode_win_words(L);
     a.trace = trace ? 1u : 0u;
     a.qws = qws;
+    a.hstatus = hstatus;
     if (a.wave_tasks == 0) return;
     if (L.sub_size == 128 && qws) {
         a.win_words = kG128Win;

@@ -250,12 +250,16 @@ struct BookLds {
 __global__ __launch_bounds__(kBookThreads) void k_codebook(const uint32_t *__restrict__ hist, Ctl *ctl,
                                                            uint64_t *__restrict__ book, uint32_t *__restrict__ book32,
                                                            uint8_t *archive, Layout L, Geom g, HeaderArgs hdr,
-                                                           TileScan qscan) {
+                                                           TileScan qscan,
+                                                           Ctl *hctl) {
     __shared__ BookLds s;
     __shared__ uint64_t s_red[4];
     const uint32_t tid = threadIdx.x, T = blockDim.x;
     const uint32_t ns = L.nsym;
-    if (ctl->status & (ST_EINVAL | ST_EINTERNAL)) return;
+    if (ctl->status & (ST_EINVAL | ST_EINTERNAL)) {
+        if (tid == 0) hctl->status = ctl->status;   // the host reads this block after the stream ends
+        return;
+    }
     if (tid == 0) ctl->phase[0] = wall_clock64();
 
     // the histogram (replicas already summed by the segment scan)
@@ -457,6 +461,13 @@ __global__ __launch_bounds__(kBookThreads) void k_codebook(const uint32_t *__res
     for (uint32_t i = tid; i < kHeaderBytes; i += T) {
         archive[i] = s.hdr[i];
         ctl->header[i] = s.hdr[i];
+        hctl->header[i] = s.hdr[i];
+    }
+    if (tid == 0) {
+        // the host's readback block (pinned host memory): final once this
+        // kernel ends, since the encoding kernels add no status
+        hctl->archive_bytes = ctl->archive_bytes;
+        hctl->status = ctl->status;
     }
     for (uint32_t i = tid; i < ns; i += T) archive[L.off_len + i] = s.len[i];
     for (uint64_t i = L.off_len + ns + tid; i < L.off_chunk; i += T) archive[i] = 0;
@@ -465,7 +476,8 @@ __global__ __launch_bounds__(kBookThreads) void k_codebook(const uint32_t *__res
 }
 
 void launch_codebook(hipStream_t st, const Geom &g, const Layout &L, Ctl *ctl, const uint32_t *hist, uint64_t *book,
-                     uint32_t *book32, uint8_t *archive, int eb_mode, double eb_param, const TileScan &qscan) {
+                     uint32_t *book32, uint8_t *archive, int eb_mode, double eb_param, const TileScan &qscan,
+                     Ctl *hctl) {
     HeaderArgs h;
     h.dims[0] = g.n[0];
     h.dims[1] = g.n[1];
@@ -473,7 +485,7 @@ void launch_codebook(hipStream_t st, const Geom &g, const Layout &L, Ctl *ctl, c
     h.eb_param = eb_param;
     h.ndim = g.ndim;
     h.eb_mode = (uint32_t)eb_mode;
-    hipLaunchKernelGGL(k_codebook, dim3(1), dim3(kBookThreads), 0, st, hist, ctl, book, book32, archive, L, g, h, qscan);
+    hipLaunchKernelGGL(k_codebook, dim3(1), dim3(kBookThreads), 0, st, hist, ctl, book, book32, archive, L, g, h, qscan, hctl);
 }
 
 // ---------------------------------------------------------------------------
@@ -481,7 +493,7 @@ void launch_codebook(hipStream_t st, const Geom &g, const Layout &L, Ctl *ctl, c
 // lengths describe a complete prefix code (or one symbol of length 1).
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kTableThreads) void k_decode_tables(const uint8_t *__restrict__ archive, Layout L,
-                                                                uint32_t max_len_hdr, DecodeTables *tab) {
+                                                                uint32_t max_len_hdr, DecodeTables *tab, uint32_t *hstatus) {
     __shared__ CanonScratch c;
     __shared__ uint8_t len[kMaxSyms];
     __shared__ uint32_t s_bad;
@@ -499,7 +511,7 @@ __global__ __launch_bounds__(kTableThreads) void k_decode_tables(const uint8_t *
     }
     __syncthreads();
     if (s_bad) {
-        if (tid == 0) { tab->status = ST_ECORRUPT; tab->max_len = 0; }
+        if (tid == 0) { tab->status = ST_ECORRUPT; tab->max_len = 0; *hstatus = ST_ECORRUPT; }
         return;
     }
     canonical_order(len, ns, c);
@@ -517,6 +529,7 @@ __global__ __launch_bounds__(kTableThreads) void k_decode_tables(const uint8_t *
         uint32_t st = 0;
         if (over || (!lone && c.n_used > 0 && left != 0) || c.max_len != max_len_hdr || c.max_len > 63) st = ST_ECORRUPT;
         tab->status = st;
+        if (st) *hstatus = st;   // pinned host memory, read after the stream ends
         tab->max_len = c.max_len;
     }
     for (uint32_t l = tid; l < 65; l += T) {
@@ -563,8 +576,8 @@ __global__ __launch_bounds__(kTableThreads) void k_decode_tables(const uint8_t *
 }
 
 void launch_decode_tables(hipStream_t st, const Layout &L, const uint8_t *archive, uint32_t max_len_hdr,
-                          DecodeTables *tab) {
-    hipLaunchKernelGGL(k_decode_tables, dim3(1), dim3(kTableThreads), 0, st, archive, L, max_len_hdr, tab);
+                          DecodeTables *tab, uint32_t *hstatus) {
+    hipLaunchKernelGGL(k_decode_tables, dim3(1), dim3(kTableThreads), 0, st, archive, L, max_len_hdr, tab, hstatus);
 }
 
 }  // namespace dqz
