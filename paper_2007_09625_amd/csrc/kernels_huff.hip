@@ -247,6 +247,24 @@ struct BookLds {
     unsigned long long total_bits;
 };
 
+// Number of entries <= t in the ascending array A[0, m) (a prefix), found
+// by one wave with 64-way probes: about log64(m) dependent LDS reads.  The
+// probe positions are uniform arithmetic, so no lane exchange is needed.
+__device__ __forceinline__ uint32_t wave_count_le(const uint32_t *A, uint32_t m, uint32_t t, uint32_t lane) {
+    uint32_t lo = 0, hi = m;   // the count lies in [lo, hi]
+    while (hi - lo > 64) {
+        const uint64_t span = hi - lo;
+        const uint32_t idx = lo + (uint32_t)((span * (lane + 1)) / 65);   // strictly increasing in lane
+        const uint32_t c = (uint32_t)__popcll(__ballot(A[idx] <= t));
+        const uint32_t nlo = c ? lo + (uint32_t)((span * c) / 65) + 1 : lo;
+        const uint32_t nhi = c < 64 ? lo + (uint32_t)((span * (c + 1)) / 65) : hi;
+        lo = nlo;
+        hi = nhi;
+    }
+    const uint32_t idx = lo + lane;
+    return lo + (uint32_t)__popcll(__ballot(idx < hi && A[idx < hi ? idx : lo] <= t));
+}
+
 __global__ __launch_bounds__(kBookThreads) void k_codebook(const uint32_t *__restrict__ hist, Ctl *ctl,
                                                            uint64_t *__restrict__ book, uint32_t *__restrict__ book32,
                                                            uint8_t *archive, Layout L, Geom g, HeaderArgs hdr,
@@ -306,72 +324,104 @@ __global__ __launch_bounds__(kBookThreads) void k_codebook(const uint32_t *__res
         if (tid == 0) s.len[s.leaf_sym[0]] = 1;
     } else if (n > 1) {
         // rounds of the two-queue construction; every thread tracks the queue
-        // state (la: next leaf, ib: next unmerged internal, ic: internals made)
+        // state (la: next leaf, ib: next unmerged internal, ic: internals made).
+        // A round takes every item no heavier than T, the sum of the two
+        // lightest available items: nodes made later weigh at least T (and
+        // lose ties to leaves and to older nodes), so those items are exactly
+        // the next ones the sequential algorithm would merge, in the stable
+        // merge of the two queues (leaf first on equal weight), paired in order.
+        const uint32_t lane = lane_id();
         uint32_t la = 0, ib = 0, ic = 0, rounds = 0;
         for (;;) {
             if ((n - la) + (ic - ib) <= 1) break;
-            // T = the two lightest available items (leaf first on ties)
-            uint32_t a = la, b = ib, Tw = 0;
+            // T, from the first two items of each queue
+            const uint32_t l0 = la < n ? s.leaf_w[la] : 0u, l1 = la + 1 < n ? s.leaf_w[la + 1] : 0u;
+            const uint32_t i0 = ib < ic ? s.int_w[ib] : 0u, i1 = ib + 1 < ic ? s.int_w[ib + 1] : 0u;
+            uint32_t Tw;
+            {
+                uint32_t a = 0, b = 0, t = 0;
 #pragma unroll
-            for (int q = 0; q < 2; q++) {
-                const bool leaf = a < n && (b >= ic || s.leaf_w[a] <= s.int_w[b]);
-                Tw += leaf ? s.leaf_w[a++] : s.int_w[b++];
+                for (int q = 0; q < 2; q++) {
+                    const uint32_t lw = a == 0 ? l0 : l1, iw = b == 0 ? i0 : i1;
+                    const bool leaf = la + a < n && (ib + b >= ic || lw <= iw);
+                    t += leaf ? lw : iw;
+                    a += leaf ? 1u : 0u;
+                    b += leaf ? 0u : 1u;
+                }
+                Tw = t;
             }
-            const uint32_t par = rounds & 1u;
-            // items of weight <= T form a prefix of each sorted queue
-            for (uint32_t i = la + tid; i < n; i += T)
-                if (s.leaf_w[i] <= Tw && (i + 1 == n || s.leaf_w[i + 1] > Tw)) s.nl[par] = i + 1 - la;
-            for (uint32_t i = ib + tid; i < ic; i += T)
-                if (s.int_w[i] <= Tw && (i + 1 == ic || s.int_w[i + 1] > Tw)) s.ni[par] = i + 1 - ib;
-            __syncthreads();
-            uint32_t nl = s.nl[par], ni = s.ni[par];
+            // items of weight <= T: prefixes of both sorted queues (each wave
+            // finds them itself, so no barrier is needed)
+            uint32_t nl = wave_count_le(s.leaf_w + la, n - la, Tw, lane);
+            uint32_t ni = wave_count_le(s.int_w + ib, ic - ib, Tw, lane);
             if ((nl + ni) & 1u) {   // odd: the last item of the merged order waits
                 const bool int_last = ni > 0 && (nl == 0 || s.int_w[ib + ni - 1] >= s.leaf_w[la + nl - 1]);
                 if (int_last) ni--; else nl--;
             }
-            if (tid == 0) { s.nl[par ^ 1u] = 0; s.ni[par ^ 1u] = 0; }
-            // merge ranks: a leaf goes after the internals strictly lighter;
-            // an internal after the leaves of equal or lower weight
-            for (uint32_t k = tid; k < nl; k += T) {
-                const uint32_t w = s.leaf_w[la + k];
-                uint32_t lo = 0, hi = ni;
+            // the round's items in the stable merge of the two queues (leaf
+            // first on equal weight), paired in order: thread tid takes merged
+            // positions [d0, d0 + c), c even, found by a merge-path split
+            // (binary search over the shorter queue), then merges them in turn
+            const uint32_t m = nl + ni;
+            const uint32_t c = 2 * ((m + 2 * T - 1) / (2 * T));
+            const uint32_t d0 = tid * c;
+            if (d0 < m) {
+                // i leaves + j internals precede position d0: the largest i with
+                // leaf[i-1] <= int[d0-i] (or no such comparison)
+                uint32_t lo = d0 > ni ? d0 - ni : 0u, hi = d0 < nl ? d0 : nl;
                 while (lo < hi) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if (s.int_w[ib + mid] < w) lo = mid + 1; else hi = mid;
+                    const uint32_t mid = (lo + hi + 1) >> 1, j = d0 - mid;
+                    if (j >= ni || s.leaf_w[la + mid - 1] <= s.int_w[ib + j]) lo = mid; else hi = mid - 1;
                 }
-                const uint32_t rank = k + lo;
-                s.merged_w[rank] = w;
-                s.parent_leaf[la + k] = (uint16_t)(ic + rank / 2);
-            }
-            for (uint32_t k = tid; k < ni; k += T) {
-                const uint32_t w = s.int_w[ib + k];
-                uint32_t lo = 0, hi = nl;
-                while (lo < hi) {
-                    const uint32_t mid = (lo + hi) >> 1;
-                    if (s.leaf_w[la + mid] <= w) lo = mid + 1; else hi = mid;
+                uint32_t i = lo, j = d0 - lo, wa = 0;
+                const uint32_t d1 = d0 + c < m ? d0 + c : m;
+                for (uint32_t r = d0; r < d1; r++) {
+                    const bool leaf = i < nl && (j >= ni || s.leaf_w[la + i] <= s.int_w[ib + j]);
+                    uint32_t w;
+                    if (leaf) {
+                        w = s.leaf_w[la + i];
+                        s.parent_leaf[la + i] = (uint16_t)(ic + r / 2);
+                        i++;
+                    } else {
+                        w = s.int_w[ib + j];
+                        s.parent_int[ib + j] = (uint16_t)(ic + r / 2);
+                        j++;
+                    }
+                    if (r & 1u) s.int_w[ic + r / 2] = wa + w;
+                    else wa = w;
                 }
-                const uint32_t rank = k + lo;
-                s.merged_w[rank] = w;
-                s.parent_int[ib + k] = (uint16_t)(ic + rank / 2);
             }
-            __syncthreads();
-            const uint32_t p = (nl + ni) / 2;
-            for (uint32_t k = tid; k < p; k += T) s.int_w[ic + k] = s.merged_w[2 * k] + s.merged_w[2 * k + 1];
-            if (tid == 0) s.round_start[rounds] = (uint16_t)ic;
-            __syncthreads();
             la += nl;
             ib += ni;
-            ic += p;
+            ic += (nl + ni) / 2;
             rounds++;
+            __syncthreads();   // the new nodes' weights, for the next round
         }
-        // depths: the root is the last internal node; every node's parent was
-        // created in a later round, so walk the rounds backwards
-        if (tid == 0) { s.round_start[rounds] = (uint16_t)ic; ctl->phase[3] = wall_clock64(); ctl->phase[8] = rounds; }
-        __syncthreads();
-        for (int32_t rd = (int32_t)rounds - 1; rd >= 0; rd--) {
-            const uint32_t b0 = s.round_start[rd], b1 = s.round_start[rd + 1];
-            for (uint32_t k = b0 + tid; k < b1; k += T)
-                s.depth_int[k] = (k == ic - 1) ? 0 : (uint8_t)(s.depth_int[s.parent_int[k]] + 1);
+        if (tid == 0) { ctl->phase[3] = wall_clock64(); ctl->phase[8] = rounds; }
+        // depths of the internal nodes by pointer jumping: the root is the last
+        // node made; a node's depth is the length of its parent chain, doubled
+        // per step (ping-pong between two copies), about log2(rounds) steps
+        {
+            uint16_t *pa = s.parent_int, *pb = reinterpret_cast<uint16_t *>(s.merged_w);
+            uint8_t *da = s.depth_int, *db = reinterpret_cast<uint8_t *>(s.merged_w) + 2 * kMaxSyms;
+            const uint32_t root = ic - 1;
+            for (uint32_t k = tid; k < ic; k += T) {
+                da[k] = k == root ? 0 : 1;
+                if (k == root) pa[k] = (uint16_t)root;
+            }
+            __syncthreads();
+            for (uint32_t span = 1; span < rounds + 1; span <<= 1) {
+                for (uint32_t k = tid; k < ic; k += T) {
+                    const uint32_t q = pa[k];
+                    db[k] = (uint8_t)(da[k] + da[q]);
+                    pb[k] = pa[q];
+                }
+                __syncthreads();
+                uint16_t *tp = pa; pa = pb; pb = tp;
+                uint8_t *td = da; da = db; db = td;
+            }
+            if (da != s.depth_int)
+                for (uint32_t k = tid; k < ic; k += T) s.depth_int[k] = da[k];
             __syncthreads();
         }
         for (uint32_t i = tid; i < n; i += T) {
