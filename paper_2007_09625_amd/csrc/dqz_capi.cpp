@@ -172,8 +172,9 @@ WsLayout ws_layout(const Plan &P, bool compress, uint32_t cap) {
     w.ctl = take(cur, sizeof(Ctl));
     w.tab = take(cur, sizeof(DecodeTables));
     if (!compress) {
-        // decoded codes of 128-position subchunks, 256 bytes per subchunk
-        w.qws = P.L.sub_size == 128 ? take(cur, 256ull * P.L.n_sub) : 0;
+        // decoded codes of 128-position subchunks, 256 bytes per subchunk,
+        // for whole waves of 64 subchunks
+        w.qws = P.L.sub_size == 128 ? take(cur, 256ull * ((P.L.n_sub + 63) / 64 * 64)) : 0;
         w.total = align_up(cur, 256);
         return w;
     }

@@ -39,7 +39,7 @@ struct DecArgs {
     uint32_t qstride;   // LDS code-buffer stride per subchunk (sub_size + 2: spreads lanes over banks)
     uint32_t win_words; // LDS stream-window words per wave
     uint32_t trace;     // record phase durations into tab->phase
-    uint4 *qws;         // 128-position subchunks: 16 x 16 bytes of codes per subchunk
+    uint4 *qws;         // 128-position subchunks: 16 x 16 bytes of codes per subchunk, lane-interleaved
     uint32_t *hstatus;  // status word in pinned host memory, read after the stream ends
 };
 
@@ -765,6 +765,7 @@ __global__ __launch_bounds__(64 * kDecMaxWaves) void k_decode(DecArgs a) {
 constexpr uint32_t kG128Waves = 4;       // waves per workgroup (they share the lookup table)
 constexpr uint32_t kG128Win = 2432;      // LDS stream-window slots per wave (9.5 KiB)
 constexpr uint32_t kG128Out = 512;       // outlier records staged per wave (position u16 + delta u32)
+constexpr uint32_t kG128Pat = 128;       // patch records staged per wave (position u16 + value u32)
 
 // The lane's 128 deltas from its codes in the workspace slot; outliers (code
 // 0) take their deltas from the wave's staged outlier list, or from the
@@ -779,7 +780,7 @@ __device__ __forceinline__ void deltas_from_slot(const DecArgs &a, const uint4 *
     if (has) {
 #pragma unroll
         for (uint32_t g = 0; g < 16; g++) {
-            const uint4 q4 = qslot[g];
+            const uint4 q4 = qslot[g * 64];
             const uint32_t u[4] = {q4.x, q4.y, q4.z, q4.w};
 #pragma unroll
             for (uint32_t k = 0; k < 4; k++) {
@@ -846,7 +847,7 @@ __device__ __forceinline__ void recon128g(const DecArgs &a, const uint4 *qslot, 
 // per CU (two waves per SIMD).
 // ---------------------------------------------------------------------------
 
-// Inflate the lane's 128 positions into 16 packed 16-byte groups of dst.
+// Inflate the lane's 128 positions into 16 packed 16-byte groups dst[64 g].
 // Same steps as inflate(); the inner loop over a group of eight positions is
 // unrolled so that the codes pack into registers.
 __device__ __forceinline__ uint32_t inflate128(const DecArgs &a, const lds_u32 *win, uint32_t nwin, uint64_t wlo,
@@ -924,7 +925,7 @@ __device__ __forceinline__ uint32_t inflate128(const DecArgs &a, const lds_u32 *
             used += len;
             pk[j >> 1] |= (real ? sym : R) << (16 * (j & 1u));
         }
-        dst[g] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
+        dst[g * 64] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
     }
     return used;
 }
@@ -938,8 +939,10 @@ __global__ __launch_bounds__(64 * kG128Waves) __attribute__((amdgpu_waves_per_eu
     lds_u32 *s_win = (lds_u32 *)(s_sorted + a.L.nsym);                // waves * win_words
     lds_u32 *s_oval = s_win + kG128Waves * a.win_words;               // waves * kG128Out
     lds_u16 *s_opos = (lds_u16 *)(s_oval + kG128Waves * kG128Out);    // waves * kG128Out
+    lds_u32 *s_pval = (lds_u32 *)(s_opos + kG128Waves * kG128Out);    // waves * kG128Pat
+    lds_u16 *s_ppos = (lds_u16 *)(s_pval + kG128Waves * kG128Pat);    // waves * kG128Pat
     if (a.tab->status) return;   // the code lengths failed validation: tables are not usable
-    uint64_t tm[7];
+    uint64_t tm[9];
     tm[0] = a.trace ? wall_clock64() : 0;
     tables_to_lds(a, s_lut, s_sorted, s_t);
     __syncthreads();
@@ -955,33 +958,39 @@ __global__ __launch_bounds__(64 * kG128Waves) __attribute__((amdgpu_waves_per_eu
     lds_u32 *win = s_win + w * a.win_words;
     lds_u32 *oval = s_oval + w * kG128Out;
     lds_u16 *opos = s_opos + w * kG128Out;
+    lds_u32 *pval = s_pval + w * kG128Pat;
+    lds_u16 *ppos = s_ppos + w * kG128Pat;
     bool bad = false;
     WaveStream ws = {0, 0, 0, 0};
-    uint32_t e0 = 0, e1 = 0, n_out = 0;
+    uint32_t e0 = 0, e1 = 0, n_out = 0, n_pat = 0;
     if (active) {
         ws = wave_stream(a, sub0, lane, has, win);
         e0 = wave_lower_bound(a.exc, a.n_exc, 2ull * P0, lane);
         e1 = wave_lower_bound(a.exc, a.n_exc, 2ull * P1, lane);
-        // the wave's outlier records, compacted in position order
+        // the wave's outlier and patch records, each kind compacted in
+        // position order (positions relative to the wave's first)
         for (uint32_t eb = e0; eb < e1; eb += 64) {
             const uint32_t e = eb + lane;
-            uint2 r = make_uint2(1u, 0u);
+            uint2 r = make_uint2(0u, 0u);
             if (e < e1) r = a.exc[e];
-            const bool is_out = !(r.x & 1u);
-            const uint64_t m = __ballot(is_out);
-            const uint32_t k = n_out + (uint32_t)__popcll(m & lanes_below(lane));
-            if (is_out) {
-                const uint32_t rp = (r.x >> 1) - P0;   // wraps for keys below the range (damaged list)
-                if (rp >= P1 - P0) bad = true;
-                else if (k < kG128Out) { opos[k] = (uint16_t)rp; oval[k] = r.y; }
-            }
-            n_out += (uint32_t)__popcll(m);
+            const bool is_out = e < e1 && !(r.x & 1u), is_pat = e < e1 && (r.x & 1u);
+            const uint64_t mo = __ballot(is_out), mp = __ballot(is_pat);
+            const uint32_t ko = n_out + (uint32_t)__popcll(mo & lanes_below(lane));
+            const uint32_t kp = n_pat + (uint32_t)__popcll(mp & lanes_below(lane));
+            const uint32_t rp = (r.x >> 1) - P0;   // wraps for keys below the range (damaged list)
+            if ((is_out || is_pat) && rp >= P1 - P0) bad = true;
+            else if (is_out && ko < kG128Out) { opos[ko] = (uint16_t)rp; oval[ko] = r.y; }
+            else if (is_pat && kp < kG128Pat) { ppos[kp] = (uint16_t)rp; pval[kp] = r.y; }
+            n_out += (uint32_t)__popcll(mo);
+            n_pat += (uint32_t)__popcll(mp);
         }
     }
     __syncthreads();
     if (a.trace) tm[2] = wall_clock64();
 
-    uint4 *qslot = a.qws + (sub0 + lane) * 16;
+    // the wave's 64 x 16 groups, lane-interleaved: group g of lane l at
+    // [16 sub0 + 64 g + l], so each store and load covers 1 KB contiguously
+    uint4 *qslot = a.qws + sub0 * 16 + lane;
     if (has) {
         const uint32_t max_len = a.tab->max_len < 63u ? a.tab->max_len : 63u;
         const uint32_t used = inflate128(a, win, ws.nwin, ws.wlo, ws.start, P0 + lane * 128u, qslot, s_lut, s_t,
@@ -989,17 +998,45 @@ __global__ __launch_bounds__(64 * kG128Waves) __attribute__((amdgpu_waves_per_eu
         if (used != ws.bits) bad = true;
     }
     if (a.trace) tm[3] = wall_clock64();
-    if (a.trace) tm[4] = tm[3];
-    if (active) recon128g<NDIM>(a, qslot, lane, P0, e0, e1, n_out, opos, oval, has, bad);
-    __syncthreads();   // all regular values are stored before patches overwrite some
-    if (a.trace) tm[5] = wall_clock64();
     if (active) {
-        for (uint32_t e = e0 + lane; e < e1; e += 64) {
-            const uint2 r = a.exc[e];
-            if (!(r.x & 1u)) continue;
-            const uint64_t p = r.x >> 1;
-            if (!pos_real(a.g, p)) { bad = true; continue; }
-            a.out[pos_to_index(a.g, p)] = __uint_as_float(r.y);
+        int32_t v[128];
+        deltas_from_slot(a, qslot, lane, P0, e0, e1, n_out, opos, oval, kG128Out, has, bad, v);
+        if (a.trace) tm[4] = wall_clock64();
+        recon128<NDIM>(a, v, lane, P0, has);
+    } else if (a.trace) {
+        tm[4] = wall_clock64();
+    }
+    if (a.trace) tm[5] = wall_clock64();
+    if (a.trace) tm[6] = tm[5];
+    // patches of the lane's own positions, after its regular stores (program
+    // order of one thread: no barrier needed)
+    if (has && n_pat) {
+        const uint32_t rel0 = lane * 128u;
+        if (n_pat <= kG128Pat) {
+            uint32_t lo = 0, hi = n_pat;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (ppos[mid] < rel0) lo = mid + 1; else hi = mid;
+            }
+            for (uint32_t k = lo; k < n_pat && ppos[k] < rel0 + 128u; k++) {
+                const uint64_t p = P0 + ppos[k];
+                if (!pos_real(a.g, p)) { bad = true; continue; }
+                a.out[pos_to_index(a.g, p)] = __uint_as_float(pval[k]);
+            }
+        } else {
+            uint32_t lo = e0, hi = e1;
+            while (lo < hi) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if ((uint64_t)a.exc[mid].x < 2ull * (P0 + rel0)) lo = mid + 1; else hi = mid;
+            }
+            for (uint32_t e = lo; e < e1; e++) {
+                const uint2 r = a.exc[e];
+                if ((r.x >> 1) >= P0 + rel0 + 128u) break;
+                if (!(r.x & 1u)) continue;
+                const uint64_t p = r.x >> 1;
+                if (!pos_real(a.g, p)) { bad = true; continue; }
+                a.out[pos_to_index(a.g, p)] = __uint_as_float(r.y);
+            }
         }
     }
     if (bad) {
@@ -1007,16 +1044,21 @@ __global__ __launch_bounds__(64 * kG128Waves) __attribute__((amdgpu_waves_per_eu
         *a.hstatus = ST_ECORRUPT;
     }
     if (a.trace && active && lane == 0) {
-        tm[6] = wall_clock64();
+        tm[7] = wall_clock64();
         uint64_t *ph = const_cast<uint64_t *>(a.tab->phase);
         atomicMin((unsigned long long *)&ph[8], (unsigned long long)tm[0]);
-        atomicMax((unsigned long long *)&ph[9], (unsigned long long)tm[6]);
-        for (int k = 0; k < 6; k++) atomicAdd((unsigned long long *)&ph[10 + k], (unsigned long long)(tm[k + 1] - tm[k]));
+        atomicMax((unsigned long long *)&ph[9], (unsigned long long)tm[7]);
+        // tables, window + search, inflate, code read-back, reconstruction +
+        // stores, barrier, patches
+        const int slot[7] = {10, 11, 12, 13, 14, 15, 3};
+        for (int k = 0; k < 7; k++)
+            atomicAdd((unsigned long long *)&ph[slot[k]], (unsigned long long)(tm[k + 1] - tm[k]));
     }
 }
 
 static size_t decode_g128_lds_bytes(const Layout &L) {
-    return sizeof(uint16_t) * ((1u << kLutBits) + L.nsym) + (size_t)kG128Waves * (4 * kG128Win + 6 * kG128Out);
+    return sizeof(uint16_t) * ((1u << kLutBits) + L.nsym) +
+           (size_t)kG128Waves * (4 * kG128Win + 6 * kG128Out + 6 * kG128Pat);
 }
 
 static uint32_t decode_waves(const Layout &L) { return L.sub_size <= 256 ? kDecMaxWaves : 1u; }

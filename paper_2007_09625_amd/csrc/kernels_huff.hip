@@ -551,6 +551,7 @@ __global__ __launch_bounds__(kTableThreads) void k_decode_tables(const uint8_t *
     if (tid == 0) {
         s_bad = 0;
         tab->phase[0] = wall_clock64();
+        tab->phase[3] = 0;
         tab->phase[8] = ~0ull;
         for (uint32_t k = 9; k < 16; k++) tab->phase[k] = 0;
     }
