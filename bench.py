@@ -38,7 +38,7 @@ WORKLOADS = {
 
 
 KERNEL_OF_STAGE = {"range_eb": ("k_minmax", "kernels_quant.hip"), "quantize": ("k_quant", "kernels_quant.hip"),
-                   "encode": ("k_enc_pack", "kernels_encode.hip"), "decode": ("k_decode", "kernels_decode.hip")}
+                   "encode": ("k_enc_pack", "kernels_encode.hip"), "decode": ("k_decode_g128", "kernels_decode.hip")}
 
 
 def counted_traffic(stage, workload):

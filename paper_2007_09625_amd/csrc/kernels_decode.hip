@@ -778,9 +778,14 @@ __device__ __forceinline__ void deltas_from_slot(const DecArgs &a, const uint4 *
     const uint32_t R = a.L.radius;
     uint32_t zero = 0;
     if (has) {
+        // all sixteen loads issue before any is used
+        uint4 q[16];
+#pragma unroll
+        for (uint32_t g = 0; g < 16; g++) q[g] = qslot[g * 64];
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (uint32_t g = 0; g < 16; g++) {
-            const uint4 q4 = qslot[g * 64];
+            const uint4 q4 = q[g];
             const uint32_t u[4] = {q4.x, q4.y, q4.z, q4.w};
 #pragma unroll
             for (uint32_t k = 0; k < 4; k++) {
@@ -856,10 +861,14 @@ __device__ __forceinline__ uint32_t inflate128(const DecArgs &a, const lds_u32 *
     const uint64_t sw = start >> 5;
     const uint32_t relw = (sw >= wlo && sw - wlo < nwin) ? (uint32_t)(sw - wlo) : nwin;
     const uint32_t wlast = nwin ? nwin - 1 : 0;
+    // Words read off the fast path are waited for where they are read: a
+    // global load left pending into the loop would make every step wait for
+    // all vector memory traffic, the previous group's store included.
     auto word = [&](uint32_t kr) -> uint32_t {
         const uint32_t k = relw + kr;
-        return (k < nwin) ? win[win_slot(k)] : ld_word(a, sw + kr);
+        return pinned((k < nwin) ? win[win_slot(k)] : ld_word(a, sw + kr));
     };
+    auto gword = [&](uint64_t i) -> uint32_t { return pinned(ld_word(a, i)); };
     const uint32_t R = a.L.radius;
     uint32_t used = 0, kr = 2;
     uint32_t o = (uint32_t)(start & 31u);
@@ -885,7 +894,7 @@ __device__ __forceinline__ uint32_t inflate128(const DecArgs &a, const lds_u32 *
             const bool slow = real && ((e & 0x8000u) || len == 0);
             bool moved = false;
             if (__any((int)(slow || k >= nwin))) {
-                if (k >= nwin) nxt = ld_word(a, sw + kr);
+                if (k >= nwin) nxt = gword(sw + kr);
                 if (slow && !(e & 0x8000u)) {   // no code starts with these bits
                     bad = true;
                     len = 1;
@@ -897,8 +906,8 @@ __device__ __forceinline__ uint32_t inflate128(const DecArgs &a, const lds_u32 *
                         const uint64_t bp = start + used;
                         const uint64_t ww = bp >> 5;
                         const uint32_t ob = (uint32_t)(bp & 31u);
-                        const uint64_t h2 = ((uint64_t)ld_word(a, ww) << 32) | ld_word(a, ww + 1);
-                        wv = ob ? ((h2 << ob) | (ld_word(a, ww + 2) >> (32 - ob))) : h2;
+                        const uint64_t h2 = ((uint64_t)gword(ww) << 32) | gword(ww + 1);
+                        wv = ob ? ((h2 << ob) | (gword(ww + 2) >> (32 - ob))) : h2;
                     }
                     while (l < max_len && wv >= t.limit[l]) l++;
                     const uint64_t c = wv >> (64 - l);
