@@ -154,7 +154,7 @@ struct WsLayout {
     uint64_t hist_sum, book, book32, parts;
     uint64_t qval[2], qexcl[2], qseg_total[2];
     uint64_t eval, eexcl, eseg_total;
-    uint64_t stage, codes, qws, total;
+    uint64_t stage, codes, qws, unit_exc, total;
     uint32_t n_segs_q, n_segs_e, cap;
 };
 
@@ -172,9 +172,10 @@ WsLayout ws_layout(const Plan &P, bool compress, uint32_t cap) {
     w.ctl = take(cur, sizeof(Ctl));
     w.tab = take(cur, sizeof(DecodeTables));
     if (!compress) {
-        // decoded codes of 128-position subchunks, 256 bytes per subchunk,
-        // for whole waves of 64 subchunks
+        // 128-position subchunks: decoded codes, 256 bytes per subchunk for
+        // whole waves of 64 subchunks, and the exception index per unit
         w.qws = P.L.sub_size == 128 ? take(cur, 256ull * ((P.L.n_sub + 63) / 64 * 64)) : 0;
+        w.unit_exc = P.L.sub_size == 128 ? take(cur, 4ull * (recon_units(P.g) + 1)) : 0;
         w.total = align_up(cur, 256);
         return w;
     }
@@ -541,12 +542,18 @@ dqz_status dqz_decompress(dqz_ctx *ctx, const void *d_archive, uint64_t archive_
     ctx->ev_ready[1] = false;
     mark(ctx, 1, 0, s);
     ctx->h_ctl->status = 0;   // the decoding kernels set it on damage
-    launch_decode_tables(s, P.L, arc, hi.max_len, tab, &ctx->d_hctl->status);
+    const bool two_pass = P.L.sub_size == 128;
+    uint4 *qws = two_pass ? reinterpret_cast<uint4 *>(ws + W.qws) : nullptr;
+    uint32_t *unit_exc = two_pass ? reinterpret_cast<uint32_t *>(ws + W.unit_exc) : nullptr;
+    launch_decode_tables(s, P.L, arc, hi.max_len, tab, &ctx->d_hctl->status, (uint32_t)hi.n_exc, unit_exc,
+                         recon_units(P.g));
     mark(ctx, 1, 1, s);
-    uint4 *qws = P.L.sub_size == 128 ? reinterpret_cast<uint4 *>(ws + W.qws) : nullptr;
     launch_decode(s, P.g, P.L, arc, hi.off_str, hi.n_words, (uint32_t)hi.n_exc, hi.h, tab, d_field, ctx->trace, qws,
                   &ctx->d_hctl->status);
     mark(ctx, 1, 2, s);
+    if (two_pass)
+        launch_recon(s, P.g, P.L, arc, (uint32_t)hi.n_exc, hi.h, tab, qws, unit_exc, d_field, &ctx->d_hctl->status);
+    mark(ctx, 1, 3, s);
     HIP_TRY(ctx, hipGetLastError());
     HIP_TRY(ctx, wait_stream(s));
     ctx->ev_ready[1] = ctx->timing;

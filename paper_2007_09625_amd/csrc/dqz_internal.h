@@ -12,6 +12,8 @@ constexpr uint32_t kMagic = 0x315A5144u;   // bytes 'D' 'Q' 'Z' '1'
 constexpr uint32_t kVersion = 1;
 constexpr uint32_t kTile = 4096;           // padded positions per quantize / encode tile
 constexpr uint32_t kLutBits = 13;          // decode table width (u16 entries: len << 11 | sym)
+constexpr uint32_t kLut2Max = 3072;        // second-level decode table entries (codes longer than kLutBits)
+constexpr uint32_t kUnitShift = 9;         // reconstruction unit: 512 padded positions (four 128-position subchunks)
 constexpr uint32_t kHistReplicas = 16;     // global histogram copies (spreads the flush atomics)
 constexpr uint32_t kExcCap = 512;          // staged exception records per quantize tile (first attempt)
 constexpr uint32_t kMaxRadius = 1024;      // codebook kernel keeps 2R <= 2048 symbols in LDS
@@ -77,7 +79,13 @@ struct Ctl {
 // Decoder tables built from the archive's code lengths.
 struct DecodeTables {
     uint16_t lut[1u << kLutBits];   // (len << 11) | sym for codes of <= kLutBits bits;
-                                    // (min_len << 11) | 0x8000 for a prefix of longer codes
+                                    // 0x8000 | shortest length for a prefix of longer codes
+    // Second level, flat: the top kLutBits + lut2_bits stream bits v index
+    // lut2[v - (lut2_v0 << lut2_bits)] for v >= lut2_v0 << lut2_bits (the
+    // long-code prefixes start at lut2_v0); entries (len << 11) | sym, 0 for
+    // a code longer than kLutBits + lut2_bits or beyond the table
+    uint16_t lut2[kLut2Max];
+    uint32_t lut2_v0, lut2_bits, lut2_n;
     uint64_t limit[65];             // left-aligned end of the codes of length <= l
     uint64_t first_code[65];        // canonical first code of each length
     uint32_t count[65];             // codes of each length
@@ -265,10 +273,18 @@ struct EncodeBufs {
 void launch_encode(hipStream_t s, const Geom &g, const Layout &L, Ctl *ctl, const EncodeBufs &b, uint8_t *archive);
 uint32_t encode_tiles(const Geom &g);
 void launch_decode_tables(hipStream_t s, const Layout &L, const uint8_t *archive, uint32_t max_len_hdr,
-                          DecodeTables *tab, uint32_t *hstatus);
+                          DecodeTables *tab, uint32_t *hstatus, uint32_t n_exc, uint32_t *unit_exc,
+                          uint32_t n_units);
 size_t decode_lds_bytes(const Layout &L);
+// Subchunks of 128 positions: launch_decode inflates into `qws` (u16 per
+// padded position) and launch_recon reconstructs from it; other subchunk
+// sizes decode in one kernel (qws unused).
 void launch_decode(hipStream_t s, const Geom &g, const Layout &L, const uint8_t *archive, uint64_t off_str,
                    uint64_t n_words, uint32_t n_exc, float h, DecodeTables *tab, float *out, bool trace,
                    uint4 *qws, uint32_t *hstatus);
+void launch_recon(hipStream_t s, const Geom &g, const Layout &L, const uint8_t *archive, uint32_t n_exc, float h,
+                  const DecodeTables *tab, const uint4 *qws, const uint32_t *unit_exc, float *out, uint32_t *hstatus);
+// reconstruction units of 512 padded positions
+inline uint32_t recon_units(const Geom &g) { return (g.padded + (1u << kUnitShift) - 1) >> kUnitShift; }
 
 }  // namespace dqz

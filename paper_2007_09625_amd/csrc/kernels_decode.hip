@@ -60,49 +60,6 @@ struct DecLds {
     uint32_t first_index[65];
 };
 
-// Decode one symbol from the top of `cur` (more than 32 valid bits, so every
-// code of up to 32 bits is present); `used` counts the lane's consumed bits.
-// Codes longer than 32 bits (possible only when max_len > 32) are read from
-// a fresh 64-bit window in memory and set `reinit`: the caller then restarts
-// its reader at the new position.
-__device__ __forceinline__ uint32_t decode_sym(const DecArgs &a, uint64_t &cur, int32_t &avail, uint32_t &used,
-                                               uint64_t start, const lds_u16 *lut, const DecLds &t,
-                                               const lds_u16 *sorted, uint32_t max_len, bool &bad, bool &reinit) {
-    const uint32_t e = lut[(uint32_t)(cur >> (64 - kLutBits))];
-    uint32_t len, sym;
-    if (!(e & 0x8000u)) {
-        len = e >> 11;
-        sym = e & 0x7FFu;
-        if (len == 0) { bad = true; len = 1; }
-    } else {
-        // a longer code: canonical limits from the shortest possible length
-        uint32_t l = e & 63u;
-        uint64_t win = cur;
-        if (max_len > 32) {
-            const uint64_t bp = start + used;
-            const uint64_t w = bp >> 5;
-            const uint32_t o = (uint32_t)(bp & 31u);
-            const uint64_t hi = ((uint64_t)ld_word(a, w) << 32) | ld_word(a, w + 1);
-            win = o ? ((hi << o) | (ld_word(a, w + 2) >> (32 - o))) : hi;
-        }
-        while (l < max_len && win >= t.limit[l]) l++;
-        const uint64_t c = win >> (64 - l);
-        const uint64_t idx = t.first_index[l] + (c - t.first_code[l]);
-        if (idx >= a.L.nsym) { bad = true; sym = a.L.radius; }
-        else sym = sorted[idx];
-        len = l;
-        if ((int32_t)l > avail) {   // only possible for codes over 32 bits
-            used += l;
-            reinit = true;
-            return sym;
-        }
-    }
-    cur <<= len;
-    avail -= (int32_t)len;
-    used += len;
-    return sym;
-}
-
 // Is padded position p inside the field?
 __device__ __forceinline__ bool pos_real(const Geom &g, uint64_t p) {
     if (g.ndim == 1) return p < g.nelem;
@@ -397,6 +354,7 @@ __device__ __forceinline__ void tables_to_lds(const DecArgs &a, lds_u16 *s_lut, 
 struct WaveStream {
     uint64_t start, wlo;
     uint32_t bits, nwin;
+    bool whole;   // the window holds every word a lane of the wave reads
 };
 __device__ __forceinline__ WaveStream wave_stream(const DecArgs &a, uint64_t sub0, uint32_t lane, bool has,
                                                   lds_u32 *win) {
@@ -426,6 +384,7 @@ __device__ __forceinline__ WaveStream wave_stream(const DecArgs &a, uint64_t sub
     const uint64_t whi = wave_max<uint64_t>(has ? ((r.start + r.bits) >> 5) + 3 : 0);
     const uint32_t cap = a.win_words / 17 * 16;   // logical words whose padded slots fit
     r.nwin = whi > r.wlo ? (uint32_t)(whi - r.wlo < cap ? whi - r.wlo : cap) : 0u;
+    r.whole = whi <= r.wlo || whi - r.wlo <= cap;
     for (uint32_t b = 0; b < r.nwin; b += 64 * 8) {
         uint32_t v[8];
 #pragma unroll
@@ -439,174 +398,12 @@ __device__ __forceinline__ WaveStream wave_stream(const DecArgs &a, uint64_t sub
     return r;
 }
 
-// ---- reconstruction for subchunks of 128 positions, in registers ----------
-//
-// The lane reads back its own 128 codes.  In 3D they are two z-planes of one
-// 8^3 block, and the block's four subchunks sit in one DPP quad: the 2D
-// prefix sums of each plane are in-lane, the z prefix crosses the quad by two
-// lane shifts.  In 2D they are 8 rows of a 16^2 block (a lane pair per block);
-// in 1D four whole 32-blocks, all in-lane.
-
 // lane j - 1 (j - 2) of the lane's quad; quad_perm [0,0,1,2] and [0,0,0,1]
 __device__ __forceinline__ uint32_t quad_shr1(uint32_t v) {
     return pinned((uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x90, 0xF, 0xF, false));
 }
 __device__ __forceinline__ uint32_t quad_shr2(uint32_t v) {
     return pinned((uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x40, 0xF, 0xF, false));
-}
-// lanes 1 and 3 of the quad receive lanes 0 and 2: quad_perm [0,0,2,2]
-__device__ __forceinline__ uint32_t quad_pair_lo(uint32_t v) {
-    return pinned((uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xA0, 0xF, 0xF, false));
-}
-
-// The lane's 128 deltas from its codes in the LDS code buffer (outlier slots
-// marked with their index in the exception list).
-__device__ __forceinline__ void deltas_from_lds(const DecArgs &a, const lds_u16 *wq, uint32_t lane, uint32_t e0,
-                                                const lds_u32 *xp, bool has, bool &bad, int32_t (&v)[128]) {
-    const uint32_t R = a.L.radius;
-    // the lane's codes: 64 aligned pairs (the code-buffer stride is even)
-    const lds_u32 *src = (const lds_u32 *)(wq + lane * a.qstride);
-    uint32_t special = 0;
-#pragma unroll
-    for (uint32_t k = 0; k < 64; k++) {
-        const uint32_t two = has ? src[k] : (R | (R << 16));
-        const uint32_t q0 = two & 0xFFFFu, q1 = two >> 16;
-        v[2 * k] = (int32_t)q0 - (int32_t)R;
-        v[2 * k + 1] = (int32_t)q1 - (int32_t)R;
-        // code 0 (an unmarked outlier) or a marked outlier slot
-        special |= ((q0 - 1u) >= 0x7FFFu ? 1u : 0u) | ((q1 - 1u) >= 0x7FFFu ? 1u : 0u);
-    }
-    if (special) {
-#pragma unroll
-        for (uint32_t i = 0; i < 128; i++) {
-            const uint32_t q = (uint32_t)(v[i] + (int32_t)R);
-            if (q & 0x8000u) v[i] = (int32_t)slot_delta(a, (uint16_t)q, e0, xp, bad);
-            else if (q == 0) bad = true;
-        }
-    }
-}
-
-// Reconstruction of the lane's 128 deltas in place, dequantization and the
-// stores of its in-field values.  Called by whole active waves (the
-// cross-lane steps need every lane).
-template <uint32_t NDIM>
-__device__ __forceinline__ void recon128(const DecArgs &a, int32_t (&v)[128], uint32_t lane, uint32_t P0, bool has) {
-    const Geom &g = a.g;
-    const float h = a.h;
-    const uint32_t pa = P0 + lane * 128u;
-    const uint32_t n1 = g.n[1], n2 = g.n[2];
-    const bool vec = (n2 % 4u == 0) && ((reinterpret_cast<uintptr_t>(a.out) & 15u) == 0);
-    if (NDIM == 3) {
-        const uint32_t blk = pa >> 9;
-        const uint32_t Bx = blk % g.nb[2], By = (blk / g.nb[2]) % g.nb[1], Bz = blk / (g.nb[2] * g.nb[1]);
-        const uint32_t vx = min(8u, n2 - 8 * Bx), vy = min(8u, n1 - 8 * By), vz = min(8u, g.n[0] - 8 * Bz);
-#pragma unroll
-        for (uint32_t zi = 0; zi < 2; zi++) {
-#pragma unroll
-            for (uint32_t y = 0; y < 8; y++)
-#pragma unroll
-                for (uint32_t x = 1; x < 8; x++) v[zi * 64 + y * 8 + x] += v[zi * 64 + y * 8 + x - 1];
-#pragma unroll
-            for (uint32_t y = 1; y < 8; y++)
-#pragma unroll
-                for (uint32_t x = 0; x < 8; x++) v[zi * 64 + y * 8 + x] += v[zi * 64 + (y - 1) * 8 + x];
-        }
-        // z prefix across the quad, one row of the two planes at a time; each
-        // row is stored as soon as it is final (keeps few rows live)
-        const uint32_t jq = lane & 3u, z0 = 2 * jq;
-        const bool okA = has && z0 < vz, okB = has && z0 + 1 < vz;
-        float *oA = a.out + ((8ull * Bz + z0) * n1 + 8 * By) * n2 + 8 * Bx;
-        float *oB = oA + (uint64_t)n1 * n2;
-#pragma unroll
-        for (uint32_t y = 0; y < 8; y++) {
-#pragma unroll
-            for (uint32_t x = 0; x < 8; x++) {
-                const uint32_t k = y * 8 + x;
-                const uint32_t b = (uint32_t)(v[64 + k] + v[k]);   // planes 2j and 2j + 1
-                const uint32_t s1 = quad_shr1(b);
-                const uint32_t t1 = b + (jq >= 1 ? s1 : 0u);
-                const uint32_t s2 = quad_shr2(t1);
-                const uint32_t t = t1 + (jq >= 2 ? s2 : 0u);       // inclusive over the quad
-                v[k] += (int32_t)(t - b);
-                v[64 + k] = (int32_t)t;
-            }
-            if (y < vy) {
-#pragma unroll
-                for (uint32_t zi = 0; zi < 2; zi++) {
-                    if (!(zi ? okB : okA)) continue;
-                    float *o = (zi ? oB : oA) + (uint64_t)y * n2;
-                    const uint32_t r = zi * 64 + y * 8;
-                    if (vx == 8 && vec) {
-                        reinterpret_cast<float4 *>(o)[0] = make_float4(dequant(v[r], h), dequant(v[r + 1], h),
-                                                                       dequant(v[r + 2], h), dequant(v[r + 3], h));
-                        reinterpret_cast<float4 *>(o)[1] = make_float4(dequant(v[r + 4], h), dequant(v[r + 5], h),
-                                                                       dequant(v[r + 6], h), dequant(v[r + 7], h));
-                    } else {
-#pragma unroll
-                        for (uint32_t x = 0; x < 8; x++)
-                            if (x < vx) o[x] = dequant(v[r + x], h);
-                    }
-                }
-            }
-        }
-    } else if (NDIM == 2) {
-        const uint32_t blk = pa >> 8;
-        const uint32_t Bx = blk % g.nb[2], By = blk / g.nb[2];
-        const uint32_t vx = min(16u, n2 - 16 * Bx), vy = min(16u, n1 - 16 * By);
-#pragma unroll
-        for (uint32_t y = 0; y < 8; y++)
-#pragma unroll
-            for (uint32_t x = 1; x < 16; x++) v[y * 16 + x] += v[y * 16 + x - 1];
-#pragma unroll
-        for (uint32_t y = 1; y < 8; y++)
-#pragma unroll
-            for (uint32_t x = 0; x < 16; x++) v[y * 16 + x] += v[(y - 1) * 16 + x];
-        const uint32_t j2 = lane & 1u;
-#pragma unroll
-        for (uint32_t x = 0; x < 16; x++) {
-            const uint32_t lower = quad_pair_lo((uint32_t)v[7 * 16 + x]);   // the lower half-block's column sums
-            const int32_t add = j2 ? (int32_t)lower : 0;
-#pragma unroll
-            for (uint32_t y = 0; y < 8; y++) v[y * 16 + x] += add;
-        }
-        if (!has) return;
-        const uint32_t y0 = 8 * j2;
-#pragma unroll
-        for (uint32_t y = 0; y < 8; y++) {
-            if (y0 + y >= vy) continue;
-            float *o = a.out + (uint64_t)(16 * By + y0 + y) * n2 + 16 * Bx;
-            const uint32_t r = y * 16;
-            if (vx == 16 && vec) {
-#pragma unroll
-                for (uint32_t qd = 0; qd < 4; qd++)
-                    reinterpret_cast<float4 *>(o)[qd] =
-                        make_float4(dequant(v[r + 4 * qd], h), dequant(v[r + 4 * qd + 1], h),
-                                    dequant(v[r + 4 * qd + 2], h), dequant(v[r + 4 * qd + 3], h));
-            } else {
-#pragma unroll
-                for (uint32_t x = 0; x < 16; x++)
-                    if (x < vx) o[x] = dequant(v[r + x], h);
-            }
-        }
-    } else {
-#pragma unroll
-        for (uint32_t i = 1; i < 128; i++)
-            if (i & 31u) v[i] += v[i - 1];
-        if (!has) return;
-        float *o = a.out + pa;
-        const uint64_t c64 = g.nelem > pa ? g.nelem - pa : 0;
-        if (c64 >= 128 && ((reinterpret_cast<uintptr_t>(a.out) & 15u) == 0)) {
-#pragma unroll
-            for (uint32_t qd = 0; qd < 32; qd++)
-                reinterpret_cast<float4 *>(o)[qd] = make_float4(dequant(v[4 * qd], h), dequant(v[4 * qd + 1], h),
-                                                                dequant(v[4 * qd + 2], h), dequant(v[4 * qd + 3], h));
-        } else {
-            const uint32_t c = (uint32_t)c64;
-#pragma unroll
-            for (uint32_t i = 0; i < 128; i++)
-                if (i < c) o[i] = dequant(v[i], h);
-        }
-    }
 }
 
 __global__ __launch_bounds__(64 * kDecMaxWaves) void k_decode(DecArgs a) {
@@ -679,13 +476,7 @@ __global__ __launch_bounds__(64 * kDecMaxWaves) void k_decode(DecArgs a) {
     }
     __syncthreads();
     if (a.trace) tm[4] = wall_clock64();
-    if (active && S == 128) {
-        int32_t v[128];
-        deltas_from_lds(a, wq, lane, e0, xp, has, bad, v);
-        if (a.g.ndim == 3) recon128<3>(a, v, lane, (uint32_t)P0, has);
-        else if (a.g.ndim == 2) recon128<2>(a, v, lane, (uint32_t)P0, has);
-        else recon128<1>(a, v, lane, (uint32_t)P0, has);
-    } else if (active) {
+    if (active) {
         const Geom &g = a.g;
         const float h = a.h;
         auto qat = [&](uint64_t loc) -> uint16_t { return wq[(loc >> sh) * a.qstride + (loc & (S - 1))]; };
@@ -762,168 +553,159 @@ __global__ __launch_bounds__(64 * kDecMaxWaves) void k_decode(DecArgs a) {
     }
 }
 
-constexpr uint32_t kG128Waves = 4;       // waves per workgroup (they share the lookup table)
-constexpr uint32_t kG128Win = 2432;      // LDS stream-window slots per wave (9.5 KiB)
-constexpr uint32_t kG128Out = 512;       // outlier records staged per wave (position u16 + delta u32)
-constexpr uint32_t kG128Pat = 128;       // patch records staged per wave (position u16 + value u32)
+// ---------------------------------------------------------------------------
+// Subchunks of 128 positions (the default size) take two kernels.
+//
+// k_inflate128: one wave decodes 64 subchunks, one per lane, into 16-bit
+// codes in a workspace array (position order, eight codes per 16-byte
+// store).  Six waves share the lookup tables in LDS, each with its stream
+// window, so two workgroups fit one CU (three waves per SIMD).  Every step
+// reads both table levels at once and selects, so codes of up to
+// kLutBits + b2 bits take no branch; only longer codes and invalid entries
+// go on to the canonical limits.
+//
+// k_recon<NDIM>: one wave per unit of 512 padded positions (one 8^3 block,
+// two 16^2 blocks or sixteen 32-blocks).  Each lane loads eight consecutive
+// codes (a piece of an x-row), takes its outliers from the unit's exception
+// records, and the inverse of the Lorenzo prediction is a prefix sum along
+// every axis: in-lane along x; in 3D the block then goes through LDS twice
+// so that y and z are in-lane too, in 2D and 1D the other axes are scans
+// across lanes.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kInfWaves = 6;     // waves per inflate workgroup (they share the lookup tables)
+constexpr uint32_t kInfWin = 2432;    // LDS stream-window slots per wave (9.5 KiB)
+constexpr uint32_t kReconWaves = 4;   // units (one per wave) per reconstruction workgroup
 
-// The lane's 128 deltas from its codes in the workspace slot; outliers (code
-// 0) take their deltas from the wave's staged outlier list, or from the
-// archive's exception list when the wave had more outliers than were staged.
-// Every outlier record must be used exactly once.
-__device__ __forceinline__ void deltas_from_slot(const DecArgs &a, const uint4 *qslot, uint32_t lane, uint32_t P0,
-                                                 uint32_t e0, uint32_t e1, uint32_t n_out, const lds_u16 *opos,
-                                                 const lds_u32 *oval, uint32_t cap, bool has, bool &bad,
-                                                 int32_t (&v)[128]) {
-    const uint32_t R = a.L.radius;
-    uint32_t zero = 0;
-    if (has) {
-        // all sixteen loads issue before any is used
-        uint4 q[16];
+// Both lookup-table levels into LDS: 16-byte copies, eight of a thread's
+// loads in flight (the tables are 256-byte aligned, the second level starts
+// 16 KiB in).
+__device__ __forceinline__ void luts_to_lds(const DecodeTables *tab, lds_u16 *s_lut, lds_u16 *s_lut2) {
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    typedef __attribute__((address_space(3))) u32x4 lds_u32x4;
+    const u32x4 *src = reinterpret_cast<const u32x4 *>(tab->lut);
+    lds_u32x4 *dst = (lds_u32x4 *)s_lut;
+    constexpr uint32_t kVec = (1u << kLutBits) * 2 / 16;
+    for (uint32_t i0 = threadIdx.x; i0 < kVec; i0 += 8 * blockDim.x) {
+        u32x4 v[8];
 #pragma unroll
-        for (uint32_t g = 0; g < 16; g++) q[g] = qslot[g * 64];
-        __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-        for (uint32_t g = 0; g < 16; g++) {
-            const uint4 q4 = q[g];
-            const uint32_t u[4] = {q4.x, q4.y, q4.z, q4.w};
-#pragma unroll
-            for (uint32_t k = 0; k < 4; k++) {
-                const uint32_t q0 = u[k] & 0xFFFFu, q1 = u[k] >> 16;
-                v[8 * g + 2 * k] = (int32_t)q0 - (int32_t)R;
-                v[8 * g + 2 * k + 1] = (int32_t)q1 - (int32_t)R;
-                zero |= (q0 == 0 ? 1u : 0u) | (q1 == 0 ? 1u : 0u);
-            }
-        }
-    } else {
-#pragma unroll
-        for (uint32_t i = 0; i < 128; i++) v[i] = 0;
-    }
-    uint32_t hits = 0;
-    if (zero) {
-        const uint32_t rel0 = lane * 128u;
-        const bool ovf = n_out > cap;
-        uint32_t oc;
-        {
-            uint32_t lo = ovf ? e0 : 0u, hi = ovf ? e1 : n_out;
-            while (lo < hi) {
-                const uint32_t mid = (lo + hi) >> 1;
-                const bool below = ovf ? ((uint64_t)a.exc[mid].x < 2ull * (P0 + rel0)) : (opos[mid] < rel0);
-                if (below) lo = mid + 1; else hi = mid;
-            }
-            oc = lo;
+        for (uint32_t j = 0; j < 8; j++) {
+            const uint32_t i = i0 + j * blockDim.x;
+            v[j] = src[i < kVec ? i : 0];
         }
 #pragma unroll
-        for (uint32_t i = 0; i < 128; i++) {
-            if (v[i] != -(int32_t)R) continue;   // code 0 marks an outlier
-            int32_t d = 0;
-            if (!ovf) {
-                if (oc < n_out && opos[oc] == rel0 + i) d = (int32_t)oval[oc];
-                else bad = true;
-            } else {
-                while (oc < e1 && (a.exc[oc].x & 1u)) oc++;
-                if (oc < e1 && (a.exc[oc].x >> 1) == P0 + rel0 + i) d = (int32_t)a.exc[oc].y;
-                else bad = true;
-            }
-            v[i] = d;
-            oc++;
-            hits++;
+        for (uint32_t j = 0; j < 8; j++) {
+            const uint32_t i = i0 + j * blockDim.x;
+            if (i < kVec) dst[i] = v[j];
         }
     }
-    if (wave_sum<uint32_t>(hits) != n_out) bad = true;
+    const uint32_t n2 = tab->lut2_n ? (tab->lut2_n < kLut2Max ? (tab->lut2_n + 7) / 8 : kLut2Max / 8) : 1u;
+    const u32x4 *src2 = reinterpret_cast<const u32x4 *>(tab->lut2);
+    lds_u32x4 *dst2 = (lds_u32x4 *)s_lut2;
+    for (uint32_t i = threadIdx.x; i < n2; i += blockDim.x) dst2[i] = src2[i];
 }
 
-template <uint32_t NDIM>
-__device__ __forceinline__ void recon128g(const DecArgs &a, const uint4 *qslot, uint32_t lane, uint32_t P0, uint32_t e0,
-                                          uint32_t e1, uint32_t n_out, const lds_u16 *opos, const lds_u32 *oval,
-                                          bool has, bool &bad) {
-    int32_t v[128];
-    deltas_from_slot(a, qslot, lane, P0, e0, e1, n_out, opos, oval, kG128Out, has, bad, v);
-    recon128<NDIM>(a, v, lane, P0, has);
+// Does the 128-position subchunk at padded position pa lie inside the field?
+// (It lies in one block: 32-blocks in 1D are whole subchunk quarters.)
+__device__ __forceinline__ bool sub128_full(const Geom &g, uint32_t pa) {
+    if (g.ndim == 1) return (uint64_t)pa + 128 <= g.nelem;
+    return block_full(g, pa / g.bvol);
 }
 
-// ---------------------------------------------------------------------------
-// Decoder for subchunks of 128 positions (the default S) without an LDS code
-// buffer.  Each lane's codes go to a per-subchunk slot of a workspace array
-// (eight codes per 16-byte store) and come back to the same lane for the
-// register reconstruction, which also substitutes the lane's outliers from
-// the wave's staged outlier list.  Only the lookup tables, the stream window
-// and the staged outliers stay in LDS, so workgroups of four waves fit two
-// per CU (two waves per SIMD).
-// ---------------------------------------------------------------------------
-
-// Inflate the lane's 128 positions into 16 packed 16-byte groups dst[64 g].
-// Same steps as inflate(); the inner loop over a group of eight positions is
-// unrolled so that the codes pack into registers.
-__device__ __forceinline__ uint32_t inflate128(const DecArgs &a, const lds_u32 *win, uint32_t nwin, uint64_t wlo,
-                                               uint64_t start, uint32_t pa, uint4 *dst, const lds_u16 *lut,
-                                               const DecLds &t, const lds_u16 *sorted, uint32_t max_len, bool &bad) {
-    const uint64_t sw = start >> 5;
+// Inflate the lane's 128 positions (padded positions pa ..) into 16 packed
+// 16-byte groups dst[g]; returns the stream bits consumed.  ALLREAL: every
+// position of the wave lies inside the field (none is tested).  WHOLE: the
+// window holds every word the wave's lanes read (no bounds test per word).
+//
+// The bit buffer `cur` holds `avail` valid bits from its top; window word kk
+// is the next to enter (read ahead into `nxt`), so the stream position is
+// 32 (sw + kk - relw) - avail.  Each step refills first (at most 32 bits
+// left: the next word enters), so a lookup always sees more than 32 bits.
+// Both table levels are read every step, from the top kLutBits and
+// kLutBits + b2 bits, and the first level's long-prefix flag selects between
+// them: a code of up to kLutBits + b2 bits costs no branch.  Longer codes
+// and invalid entries take one uniform branch.
+template <bool ALLREAL, bool WHOLE>
+__device__ __forceinline__ uint32_t inflate_codes(const DecArgs &a, const lds_u32 *win, uint32_t nwin, uint64_t wlo,
+                                                  uint64_t start, uint32_t pa, uint4 *dst, const lds_u16 *lut,
+                                                  const lds_u16 *lut2, uint32_t b2, uint32_t base2, uint32_t last2,
+                                                  uint32_t max_len, bool &bad) {
+    const uint64_t sw = start >> 5;   // the lane's first stream word
+    // window index of word sw + kr is relw + kr; a lane outside the window
+    // (only with damaged chunk offsets) misses on every read
     const uint32_t relw = (sw >= wlo && sw - wlo < nwin) ? (uint32_t)(sw - wlo) : nwin;
     const uint32_t wlast = nwin ? nwin - 1 : 0;
-    // Words read off the fast path are waited for where they are read: a
-    // global load left pending into the loop would make every step wait for
-    // all vector memory traffic, the previous group's store included.
+    // words read off the common step are waited for where they are read: a
+    // global load left pending would make later steps wait for every vector
+    // memory operation, the group stores included
     auto word = [&](uint32_t kr) -> uint32_t {
         const uint32_t k = relw + kr;
         return pinned((k < nwin) ? win[win_slot(k)] : ld_word(a, sw + kr));
     };
-    auto gword = [&](uint64_t i) -> uint32_t { return pinned(ld_word(a, i)); };
     const uint32_t R = a.L.radius;
-    uint32_t used = 0, kr = 2;
-    uint32_t o = (uint32_t)(start & 31u);
+    const uint32_t o = (uint32_t)(start & 31u);
     uint64_t cur = (((uint64_t)word(0) << 32) | word(1)) << o;
     int32_t avail = 64 - (int32_t)o;
-    uint32_t nxt = word(kr);
-    uint32_t rmask = 0;
+    uint32_t kk = relw + 2;
+    uint32_t nxt = word(2);
+    uint32_t rmask = ~0u;
     for (uint32_t g = 0; g < 16; g++) {
-        if ((g & 3u) == 0) rmask = real_mask32(a.g, pa + g * 8);
-        uint32_t pk[4] = {0u, 0u, 0u, 0u};
+        if (!ALLREAL && (g & 3u) == 0) rmask = real_mask32(a.g, pa + g * 8);
+        uint32_t pk[4];
 #pragma unroll
         for (uint32_t j = 0; j < 8; j++) {
-            const bool need = avail <= 32;
-            const uint32_t shl = need ? (uint32_t)(32 - avail) : 0u;
-            cur |= need ? ((uint64_t)nxt << shl) : 0ull;
-            avail += need ? 32 : 0;
-            kr += need ? 1u : 0u;
-            const uint32_t k = relw + kr;
-            nxt = win[win_slot(k < nwin ? k : wlast)];
-            const bool real = (rmask >> ((g & 3u) * 8 + j)) & 1u;
-            const uint32_t e = lut[(uint32_t)(cur >> (64 - kLutBits))];
-            uint32_t len = (e >> 11) & 15u, sym = e & 0x7FFu;
-            const bool slow = real && ((e & 0x8000u) || len == 0);
+            {   // refill (a zero word and a shift past the buffer when not needed)
+                const bool need = avail <= 32;
+                const uint32_t src = need ? nxt : 0u;
+                cur |= (uint64_t)src << ((uint32_t)(32 - avail) & 63u);
+                avail += need ? 32 : 0;
+                kk += need ? 1u : 0u;
+                if (WHOLE) {
+                    nxt = win[win_slot(kk)];
+                } else {
+                    nxt = win[win_slot(kk < nwin ? kk : wlast)];
+                    if (__builtin_expect(__any((int)(kk >= nwin)), 0)) {
+                        if (kk >= nwin) nxt = pinned(ld_word(a, sw + (kk - relw)));
+                    }
+                }
+            }
+            const bool real = ALLREAL || ((rmask >> ((g & 3u) * 8 + j)) & 1u);
+            const uint32_t top = (uint32_t)(cur >> 32);
+            const uint32_t e1 = lut[top >> (32 - kLutBits)];
+            const uint32_t v2 = (top >> (32 - kLutBits - b2)) - base2;
+            const uint32_t e2 = lut2[v2 < last2 ? v2 : last2];
+            const uint32_t e = (e1 & 0x8000u) ? e2 : e1;
+            uint32_t len = e >> 11, sym = e & 0x7FFu;
             bool moved = false;
-            if (__any((int)(slow || k >= nwin))) {
-                if (k >= nwin) nxt = gword(sw + kr);
-                if (slow && !(e & 0x8000u)) {   // no code starts with these bits
+            const bool other = real && len == 0;   // longer than the second level, or no code
+            if (__builtin_expect(__any((int)other), 0)) {
+                if (other && !(e1 & 0x8000u)) {   // no code starts with these bits
                     bad = true;
                     len = 1;
                     sym = R;
-                } else if (slow) {
-                    uint32_t l = e & 63u;
-                    uint64_t wv = cur;
-                    if (max_len > 32) {
-                        const uint64_t bp = start + used;
-                        const uint64_t ww = bp >> 5;
-                        const uint32_t ob = (uint32_t)(bp & 31u);
-                        const uint64_t h2 = ((uint64_t)gword(ww) << 32) | gword(ww + 1);
-                        wv = ob ? ((h2 << ob) | (gword(ww + 2) >> (32 - ob))) : h2;
-                    }
-                    while (l < max_len && wv >= t.limit[l]) l++;
+                } else if (other) {
+                    // canonical limits from the shortest length past both levels,
+                    // on 64 fresh bits at the lane's position
+                    const uint64_t bp = (sw << 5) + 32ull * (kk - relw) - (uint32_t)avail;
+                    const uint32_t rk = (uint32_t)((bp >> 5) - sw), ob = (uint32_t)(bp & 31u);
+                    const uint64_t h2 = ((uint64_t)word(rk) << 32) | word(rk + 1);
+                    const uint64_t wv = ob ? ((h2 << ob) | (word(rk + 2) >> (32 - ob))) : h2;
+                    const uint32_t lmin = e1 & 63u;
+                    uint32_t l = lmin > kLutBits + b2 ? lmin : kLutBits + b2 + 1;
+                    l = l < 63u ? l : 63u;
+                    while (l < max_len && wv >= a.tab->limit[l]) l++;
                     const uint64_t c = wv >> (64 - l);
-                    const uint64_t idx = t.first_index[l] + (c - t.first_code[l]);
+                    const uint64_t idx = a.tab->first_index[l] + (c - a.tab->first_code[l]);
                     if (idx >= a.L.nsym) { bad = true; sym = R; }
-                    else sym = sorted[idx];
+                    else sym = a.tab->sorted[idx];
                     len = l;
-                    if ((int32_t)l > avail) {
-                        used += l;
-                        const uint64_t bp = start + used;
-                        o = (uint32_t)(bp & 31u);
-                        kr = (uint32_t)((bp >> 5) - sw);
-                        cur = (((uint64_t)word(kr) << 32) | word(kr + 1)) << o;
-                        avail = 64 - (int32_t)o;
-                        kr += 2;
-                        nxt = word(kr);
+                    if ((int32_t)l > avail) {   // past the buffer: restart the reader after the code
+                        const uint64_t np = bp + l;
+                        const uint32_t o2 = (uint32_t)(np & 31u);
+                        const uint32_t kr = (uint32_t)((np >> 5) - sw);
+                        cur = (((uint64_t)word(kr) << 32) | word(kr + 1)) << o2;
+                        avail = 64 - (int32_t)o2;
+                        kk = relw + kr + 2;
+                        nxt = word(kr + 2);
                         moved = true;
                     }
                 }
@@ -931,143 +713,327 @@ __device__ __forceinline__ uint32_t inflate128(const DecArgs &a, const lds_u32 *
             if (!real || moved) len = 0;
             cur <<= len;
             avail -= (int32_t)len;
-            used += len;
-            pk[j >> 1] |= (real ? sym : R) << (16 * (j & 1u));
+            const uint32_t s16 = real ? sym : R;
+            pk[j >> 1] = (j & 1u) ? (pk[j >> 1] | (s16 << 16)) : s16;
         }
-        dst[g * 64] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
+        dst[g] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
     }
-    return used;
+    return 32u * (kk - relw) - (uint32_t)avail - o;
 }
 
-template <uint32_t NDIM>
-__global__ __launch_bounds__(64 * kG128Waves) __attribute__((amdgpu_waves_per_eu(2))) void k_decode_g128(DecArgs a) {
+__global__ __launch_bounds__(64 * kInfWaves) void k_inflate128(DecArgs a) {
     extern __shared__ uint32_t s_dyn[];
-    __shared__ DecLds s_t;
-    lds_u16 *s_lut = (lds_u16 *)s_dyn;                                 // 1 << kLutBits
-    lds_u16 *s_sorted = s_lut + (1u << kLutBits);                     // nsym
-    lds_u32 *s_win = (lds_u32 *)(s_sorted + a.L.nsym);                // waves * win_words
-    lds_u32 *s_oval = s_win + kG128Waves * a.win_words;               // waves * kG128Out
-    lds_u16 *s_opos = (lds_u16 *)(s_oval + kG128Waves * kG128Out);    // waves * kG128Out
-    lds_u32 *s_pval = (lds_u32 *)(s_opos + kG128Waves * kG128Out);    // waves * kG128Pat
-    lds_u16 *s_ppos = (lds_u16 *)(s_pval + kG128Waves * kG128Pat);    // waves * kG128Pat
+    // the second level first: the first level's reads then fold its base
+    // into the instruction offset
+    lds_u16 *s_lut2 = (lds_u16 *)s_dyn;                 // kLut2Max
+    lds_u16 *s_lut = s_lut2 + kLut2Max;                 // 1 << kLutBits
+    lds_u32 *s_win = (lds_u32 *)(s_lut + (1u << kLutBits));   // kInfWaves * kInfWin
     if (a.tab->status) return;   // the code lengths failed validation: tables are not usable
-    uint64_t tm[9];
-    tm[0] = a.trace ? wall_clock64() : 0;
-    tables_to_lds(a, s_lut, s_sorted, s_t);
-    __syncthreads();
-    if (a.trace) tm[1] = wall_clock64();
-
+    const uint64_t t0 = a.trace ? wall_clock64() : 0;
+    luts_to_lds(a.tab, s_lut, s_lut2);
     const uint32_t lane = lane_id(), w = threadIdx.x / 64;
-    const uint32_t gw = blockIdx.x * kG128Waves + w;
+    const uint32_t gw = blockIdx.x * kInfWaves + w;
     const bool active = gw < a.wave_tasks;
     const uint64_t sub0 = (uint64_t)gw * 64;
-    const uint32_t P0 = (uint32_t)(sub0 << 7);                        // padded positions are < 2^31
-    const uint32_t P1 = active ? (a.g.padded - P0 < 8192u ? a.g.padded : P0 + 8192u) : P0;
     const bool has = active && sub0 + lane < a.L.n_sub;
-    lds_u32 *win = s_win + w * a.win_words;
-    lds_u32 *oval = s_oval + w * kG128Out;
-    lds_u16 *opos = s_opos + w * kG128Out;
-    lds_u32 *pval = s_pval + w * kG128Pat;
-    lds_u16 *ppos = s_ppos + w * kG128Pat;
-    bool bad = false;
+    lds_u32 *win = s_win + w * kInfWin;
     WaveStream ws = {0, 0, 0, 0};
-    uint32_t e0 = 0, e1 = 0, n_out = 0, n_pat = 0;
-    if (active) {
-        ws = wave_stream(a, sub0, lane, has, win);
-        e0 = wave_lower_bound(a.exc, a.n_exc, 2ull * P0, lane);
-        e1 = wave_lower_bound(a.exc, a.n_exc, 2ull * P1, lane);
-        // the wave's outlier and patch records, each kind compacted in
-        // position order (positions relative to the wave's first)
-        for (uint32_t eb = e0; eb < e1; eb += 64) {
-            const uint32_t e = eb + lane;
-            uint2 r = make_uint2(0u, 0u);
-            if (e < e1) r = a.exc[e];
-            const bool is_out = e < e1 && !(r.x & 1u), is_pat = e < e1 && (r.x & 1u);
-            const uint64_t mo = __ballot(is_out), mp = __ballot(is_pat);
-            const uint32_t ko = n_out + (uint32_t)__popcll(mo & lanes_below(lane));
-            const uint32_t kp = n_pat + (uint32_t)__popcll(mp & lanes_below(lane));
-            const uint32_t rp = (r.x >> 1) - P0;   // wraps for keys below the range (damaged list)
-            if ((is_out || is_pat) && rp >= P1 - P0) bad = true;
-            else if (is_out && ko < kG128Out) { opos[ko] = (uint16_t)rp; oval[ko] = r.y; }
-            else if (is_pat && kp < kG128Pat) { ppos[kp] = (uint16_t)rp; pval[kp] = r.y; }
-            n_out += (uint32_t)__popcll(mo);
-            n_pat += (uint32_t)__popcll(mp);
-        }
-    }
+    if (active) ws = wave_stream(a, sub0, lane, has, win);
     __syncthreads();
-    if (a.trace) tm[2] = wall_clock64();
-
-    // the wave's 64 x 16 groups, lane-interleaved: group g of lane l at
-    // [16 sub0 + 64 g + l], so each store and load covers 1 KB contiguously
-    uint4 *qslot = a.qws + sub0 * 16 + lane;
+    const uint64_t t1 = a.trace ? wall_clock64() : 0;
+    bool bad = false;
     if (has) {
+        const uint32_t pa = (uint32_t)((sub0 + lane) << 7);
         const uint32_t max_len = a.tab->max_len < 63u ? a.tab->max_len : 63u;
-        const uint32_t used = inflate128(a, win, ws.nwin, ws.wlo, ws.start, P0 + lane * 128u, qslot, s_lut, s_t,
-                                         s_sorted, max_len, bad);
+        // second level: width, first index and last entry (an empty table
+        // keeps one zero entry, read by short codes only)
+        const uint32_t b2 = a.tab->lut2_bits, base2 = a.tab->lut2_v0 << b2;
+        const uint32_t last2 = a.tab->lut2_n ? a.tab->lut2_n - 1 : 0u;
+        uint4 *dst = a.qws + (sub0 + lane) * 16;
+        uint32_t used;
+        if (ws.whole && __all((int)sub128_full(a.g, pa)))
+            used = inflate_codes<true, true>(a, win, ws.nwin, ws.wlo, ws.start, pa, dst, s_lut, s_lut2, b2, base2,
+                                             last2, max_len, bad);
+        else if (ws.whole)
+            used = inflate_codes<false, true>(a, win, ws.nwin, ws.wlo, ws.start, pa, dst, s_lut, s_lut2, b2, base2,
+                                              last2, max_len, bad);
+        else
+            used = inflate_codes<false, false>(a, win, ws.nwin, ws.wlo, ws.start, pa, dst, s_lut, s_lut2, b2, base2,
+                                               last2, max_len, bad);
         if (used != ws.bits) bad = true;
-    }
-    if (a.trace) tm[3] = wall_clock64();
-    if (active) {
-        int32_t v[128];
-        deltas_from_slot(a, qslot, lane, P0, e0, e1, n_out, opos, oval, kG128Out, has, bad, v);
-        if (a.trace) tm[4] = wall_clock64();
-        recon128<NDIM>(a, v, lane, P0, has);
-    } else if (a.trace) {
-        tm[4] = wall_clock64();
-    }
-    if (a.trace) tm[5] = wall_clock64();
-    if (a.trace) tm[6] = tm[5];
-    // patches of the lane's own positions, after its regular stores (program
-    // order of one thread: no barrier needed)
-    if (has && n_pat) {
-        const uint32_t rel0 = lane * 128u;
-        if (n_pat <= kG128Pat) {
-            uint32_t lo = 0, hi = n_pat;
-            while (lo < hi) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if (ppos[mid] < rel0) lo = mid + 1; else hi = mid;
-            }
-            for (uint32_t k = lo; k < n_pat && ppos[k] < rel0 + 128u; k++) {
-                const uint64_t p = P0 + ppos[k];
-                if (!pos_real(a.g, p)) { bad = true; continue; }
-                a.out[pos_to_index(a.g, p)] = __uint_as_float(pval[k]);
-            }
-        } else {
-            uint32_t lo = e0, hi = e1;
-            while (lo < hi) {
-                const uint32_t mid = (lo + hi) >> 1;
-                if ((uint64_t)a.exc[mid].x < 2ull * (P0 + rel0)) lo = mid + 1; else hi = mid;
-            }
-            for (uint32_t e = lo; e < e1; e++) {
-                const uint2 r = a.exc[e];
-                if ((r.x >> 1) >= P0 + rel0 + 128u) break;
-                if (!(r.x & 1u)) continue;
-                const uint64_t p = r.x >> 1;
-                if (!pos_real(a.g, p)) { bad = true; continue; }
-                a.out[pos_to_index(a.g, p)] = __uint_as_float(r.y);
-            }
-        }
     }
     if (bad) {
         atomicOr(a.status, ST_ECORRUPT);
         *a.hstatus = ST_ECORRUPT;
     }
     if (a.trace && active && lane == 0) {
-        tm[7] = wall_clock64();
+        const uint64_t t2 = wall_clock64();
         uint64_t *ph = const_cast<uint64_t *>(a.tab->phase);
-        atomicMin((unsigned long long *)&ph[8], (unsigned long long)tm[0]);
-        atomicMax((unsigned long long *)&ph[9], (unsigned long long)tm[7]);
-        // tables, window + search, inflate, code read-back, reconstruction +
-        // stores, barrier, patches
-        const int slot[7] = {10, 11, 12, 13, 14, 15, 3};
-        for (int k = 0; k < 7; k++)
-            atomicAdd((unsigned long long *)&ph[slot[k]], (unsigned long long)(tm[k + 1] - tm[k]));
+        atomicMin((unsigned long long *)&ph[8], (unsigned long long)t0);
+        atomicMax((unsigned long long *)&ph[9], (unsigned long long)t2);
+        atomicAdd((unsigned long long *)&ph[10], (unsigned long long)(t1 - t0));
+        atomicAdd((unsigned long long *)&ph[11], (unsigned long long)(t2 - t1));
     }
 }
 
-static size_t decode_g128_lds_bytes(const Layout &L) {
-    return sizeof(uint16_t) * ((1u << kLutBits) + L.nsym) +
-           (size_t)kG128Waves * (4 * kG128Win + 6 * kG128Out + 6 * kG128Pat);
+struct ReconArgs {
+    Geom g;
+    const uint4 *codes;         // u16 code per padded position, eight per 16 bytes
+    const uint2 *exc;           // exception records {key = 2 pos + kind, payload}
+    const uint32_t *unit_exc;   // first record of each 512-position unit (n_units + 1 entries)
+    const DecodeTables *tab;
+    float *out;
+    uint32_t *status;
+    uint32_t *hstatus;          // status word in pinned host memory
+    uint32_t n_exc, n_units, radius;
+    float h;
+};
+
+// The lane's piece of the unit: eight consecutive positions 8 slot .. 8 slot + 7.
+// 3D: lane = 8 z + y holds row y of plane z; 1D: lane = 4 b + q holds quarter q
+// of block b; both in position order.  2D: lane = 32 b + 16 h + y holds half h
+// of row y of block b (slot 32 b + 2 y + h), so each y-column is one 16-lane row.
+template <uint32_t NDIM>
+__device__ __forceinline__ uint32_t unit_slot(uint32_t lane) {
+    return NDIM == 2 ? ((lane & 32u) | ((lane & 15u) << 1) | ((lane >> 4) & 1u)) : lane;
+}
+template <uint32_t NDIM>
+__device__ __forceinline__ uint32_t slot_lane(uint32_t slot) {
+    return NDIM == 2 ? ((slot & 32u) | ((slot & 1u) << 4) | ((slot >> 1) & 15u)) : slot;
+}
+
+// One unit: its lane piece d[] (deltas, outliers still 0) and code-0 mask,
+// records [rs, re) of the exception list.
+template <uint32_t NDIM>
+__device__ __forceinline__ void recon_unit(const ReconArgs &a, uint32_t u, uint32_t lane, int32_t (&d)[8],
+                                           uint32_t zmask, uint32_t rs, uint32_t re, bool &bad) {
+    const Geom &g = a.g;
+    const uint32_t P0 = u << kUnitShift;
+    if (rs > re || re > a.n_exc) {
+        bad = true;
+        rs = re = 0;
+    }
+    // outlier deltas (records are wave-uniform); patches come last
+    uint32_t n_out = 0;
+    for (uint32_t i = rs; i < re; i++) {
+        const uint2 r = a.exc[i];
+        const uint32_t rel = (r.x >> 1) - P0;
+        if (rel >= 512u) {
+            bad = true;
+            continue;
+        }
+        if (r.x & 1u) continue;
+        n_out++;
+        const uint32_t x = rel & 7u;
+        if (lane == slot_lane<NDIM>(rel >> 3)) {
+            if (!((zmask >> x) & 1u)) bad = true;
+#pragma unroll
+            for (uint32_t k = 0; k < 8; k++)
+                if (k == x) d[k] = (int32_t)r.y;
+        }
+    }
+    // every code 0 takes exactly one record (keys increase)
+    if (wave_sum<uint32_t>(__popc(zmask)) != n_out) bad = true;
+
+    // inverse Lorenzo prediction: inclusive prefix sums along every axis
+#pragma unroll
+    for (uint32_t x = 1; x < 8; x++) d[x] += d[x - 1];
+    if (NDIM == 3) {
+#pragma unroll
+        for (uint32_t x = 0; x < 8; x++) d[x] = (int32_t)stride8_scan(seg_scan<8>((uint32_t)d[x], lane), lane);
+    } else if (NDIM == 2) {
+        uint32_t ofe, efo;
+        row_swap16((uint32_t)d[7], ofe, efo);   // the left half-row's total, for the right half
+        const int32_t left = ((lane >> 4) & 1u) ? (int32_t)ofe : 0;
+#pragma unroll
+        for (uint32_t x = 0; x < 8; x++) d[x] = (int32_t)seg_scan<16>((uint32_t)(d[x] + left), lane);
+    } else {
+        // exclusive prefix of the lane totals within the block's quad
+        const uint32_t t = (uint32_t)d[7], q4 = lane & 3u;
+        const uint32_t s1 = quad_shr1(t);
+        const uint32_t i1 = t + (q4 >= 1 ? s1 : 0u);
+        const uint32_t s2 = quad_shr2(i1);
+        const int32_t ex = (int32_t)(i1 + (q4 >= 2 ? s2 : 0u) - t);
+#pragma unroll
+        for (uint32_t x = 0; x < 8; x++) d[x] += ex;
+    }
+    float f[8];
+#pragma unroll
+    for (uint32_t x = 0; x < 8; x++) f[x] = dequant(d[x], a.h);
+
+    // output index of the lane's first position and how many of its eight lie in the field
+    uint64_t o0 = 0;
+    uint32_t cnt = 0;
+    if (NDIM == 3) {
+        const uint32_t Bx = u % g.nb[2], By = (u / g.nb[2]) % g.nb[1], Bz = u / (g.nb[2] * g.nb[1]);
+        const uint32_t z = lane >> 3, y = lane & 7u;
+        const uint32_t vx = min(8u, g.n[2] - 8 * Bx), vy = min(8u, g.n[1] - 8 * By), vz = min(8u, g.n[0] - 8 * Bz);
+        cnt = (z < vz && y < vy) ? vx : 0u;
+        o0 = ((uint64_t)(8 * Bz + z) * g.n[1] + 8 * By + y) * g.n[2] + 8 * Bx;
+    } else if (NDIM == 2) {
+        const uint32_t B = 2 * u + (lane >> 5), y = lane & 15u, xh = (lane >> 4) & 1u;
+        if (B < g.nb[1] * g.nb[2]) {
+            const uint32_t Bx = B % g.nb[2], By = B / g.nb[2];
+            const uint32_t vx = min(16u, g.n[2] - 16 * Bx), vy = min(16u, g.n[1] - 16 * By);
+            cnt = (y < vy && vx > 8 * xh) ? min(8u, vx - 8 * xh) : 0u;
+            o0 = (uint64_t)(16 * By + y) * g.n[2] + 16 * Bx + 8 * xh;
+        }
+    } else {
+        o0 = (uint64_t)P0 + 8 * lane;
+        cnt = g.nelem > o0 ? (g.nelem - o0 < 8 ? (uint32_t)(g.nelem - o0) : 8u) : 0u;
+    }
+    // patches replace the lane's values before they are stored
+    for (uint32_t i = rs; i < re; i++) {
+        const uint2 r = a.exc[i];
+        if (!(r.x & 1u)) continue;
+        const uint32_t rel = (r.x >> 1) - P0;
+        if (rel >= 512u) continue;   // reported above
+        const uint32_t x = rel & 7u;
+        if (lane == slot_lane<NDIM>(rel >> 3)) {
+            if (x >= cnt) bad = true;   // a patch outside the field
+#pragma unroll
+            for (uint32_t k = 0; k < 8; k++)
+                if (k == x) f[k] = __uint_as_float(r.y);
+        }
+    }
+    float *o = a.out + o0;
+    const bool vec = ((reinterpret_cast<uintptr_t>(a.out) & 15u) == 0) && (NDIM == 1 || (g.n[2] & 3u) == 0);
+    if (cnt == 8 && vec) {
+        reinterpret_cast<float4 *>(o)[0] = make_float4(f[0], f[1], f[2], f[3]);
+        reinterpret_cast<float4 *>(o)[1] = make_float4(f[4], f[5], f[6], f[7]);
+    } else {
+#pragma unroll
+        for (uint32_t x = 0; x < 8; x++)
+            if (x < cnt) o[x] = f[x];
+    }
+}
+
+// 3D units: the lane's x-row piece (x-prefix in-lane) goes through an LDS
+// copy of the block twice, so that the y and then the z prefix are in-lane
+// too: lane 8 z + x holds a y-column, then lane 8 y + x a z-column.  Rows of
+// the copy are 9 words apart (bank spread for the column reads).
+__device__ __forceinline__ void recon_block3(const ReconArgs &a, uint32_t u, uint32_t lane, int32_t (&d)[8],
+                                             uint32_t zmask, uint32_t rs, uint32_t re, lds_u32 *blk, bool &bad) {
+    const Geom &g = a.g;
+    const uint32_t P0 = u << kUnitShift;
+    if (rs > re || re > a.n_exc) {
+        bad = true;
+        rs = re = 0;
+    }
+    const bool any_rec = rs < re;
+    uint32_t n_out = 0;
+    if (any_rec) {
+        for (uint32_t i = rs; i < re; i++) {
+            const uint2 r = a.exc[i];
+            const uint32_t rel = (r.x >> 1) - P0;
+            if (rel >= 512u) {
+                bad = true;
+                continue;
+            }
+            if (r.x & 1u) continue;
+            n_out++;
+            const uint32_t x = rel & 7u;
+            if (lane == (rel >> 3)) {
+                if (!((zmask >> x) & 1u)) bad = true;
+#pragma unroll
+                for (uint32_t k = 0; k < 8; k++)
+                    if (k == x) d[k] = (int32_t)r.y;
+            }
+        }
+    }
+    // every code 0 takes exactly one record (keys increase)
+    if (__any((int)(zmask != 0)) || any_rec) {
+        uint32_t nz = 0;
+#pragma unroll
+        for (uint32_t x = 0; x < 8; x++) nz += (uint32_t)__popcll(__ballot((int)((zmask >> x) & 1u)));
+        if (nz != n_out) bad = true;
+    }
+    // x in-lane (lane = 8 z + y)
+#pragma unroll
+    for (uint32_t x = 1; x < 8; x++) d[x] += d[x - 1];
+    const uint32_t hi = lane >> 3, lo = lane & 7u;
+#pragma unroll
+    for (uint32_t x = 0; x < 8; x++) blk[72 * hi + 9 * lo + x] = (uint32_t)d[x];   // (z, y) = (hi, lo)
+    // a wave's LDS accesses complete in order; the barriers keep the compiler
+    // from moving the column reads above the other lanes' writes
+    __builtin_amdgcn_wave_barrier();
+    // y: lane 8 z + x reads the column (z, ., x)
+#pragma unroll
+    for (uint32_t y = 0; y < 8; y++) d[y] = (int32_t)blk[72 * hi + 9 * y + lo];
+#pragma unroll
+    for (uint32_t y = 1; y < 8; y++) d[y] += d[y - 1];
+#pragma unroll
+    for (uint32_t y = 0; y < 8; y++) blk[72 * hi + 9 * y + lo] = (uint32_t)d[y];
+    __builtin_amdgcn_wave_barrier();
+    // z: lane 8 y + x reads the column (., y, x)
+#pragma unroll
+    for (uint32_t z = 0; z < 8; z++) d[z] = (int32_t)blk[72 * z + 9 * hi + lo];
+#pragma unroll
+    for (uint32_t z = 1; z < 8; z++) d[z] += d[z - 1];
+    float f[8];
+#pragma unroll
+    for (uint32_t z = 0; z < 8; z++) f[z] = dequant(d[z], a.h);
+    // lane (y, x) = (hi, lo) holds the z-column
+    const uint32_t Bx = u % g.nb[2], By = (u / g.nb[2]) % g.nb[1], Bz = u / (g.nb[2] * g.nb[1]);
+    const uint32_t vx = min(8u, g.n[2] - 8 * Bx), vy = min(8u, g.n[1] - 8 * By), vz = min(8u, g.n[0] - 8 * Bz);
+    const bool in_col = hi < vy && lo < vx;
+    if (any_rec) {
+        for (uint32_t i = rs; i < re; i++) {
+            const uint2 r = a.exc[i];
+            if (!(r.x & 1u)) continue;
+            const uint32_t rel = (r.x >> 1) - P0;
+            if (rel >= 512u) continue;   // reported above
+            const uint32_t z = rel >> 6;
+            if (lane == (rel & 63u)) {
+                if (!in_col || z >= vz) bad = true;   // a patch outside the field
+#pragma unroll
+                for (uint32_t k = 0; k < 8; k++)
+                    if (k == z) f[k] = __uint_as_float(r.y);
+            }
+        }
+    }
+    if (in_col) {
+        const uint64_t plane = (uint64_t)g.n[1] * g.n[2];
+        float *o = a.out + ((uint64_t)(8 * Bz) * g.n[1] + 8 * By + hi) * g.n[2] + 8 * Bx + lo;
+#pragma unroll
+        for (uint32_t z = 0; z < 8; z++)
+            if (z < vz) o[z * plane] = f[z];
+    }
+}
+
+// One unit per wave.
+template <uint32_t NDIM>
+__global__ __launch_bounds__(64 * kReconWaves) void k_recon(ReconArgs a) {
+    __shared__ uint32_t s_blk[kReconWaves][576];   // 3D: the block, rows 9 words apart
+    if (a.tab->status) return;   // the inflate kernel did not run
+    const uint32_t lane = lane_id(), w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
+    const uint32_t u = blockIdx.x * kReconWaves + w;
+    if (u >= a.n_units) return;   // whole waves
+    const uint32_t slot = unit_slot<NDIM>(lane);
+    const uint4 q = a.codes[(uint64_t)u * 64 + slot];
+    const uint32_t rs = a.unit_exc[u], re = a.unit_exc[u + 1];
+    const int32_t R = (int32_t)a.radius;
+    const bool lv = (u << kUnitShift) + 8 * slot < a.g.padded;
+    int32_t d[8];
+    uint32_t zmask = 0;   // code 0: an outlier
+    {
+        const uint32_t w4[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (uint32_t m = 0; m < 4; m++) {
+            const uint32_t c0 = w4[m] & 0xFFFFu, c1 = w4[m] >> 16;
+            d[2 * m] = lv ? (int32_t)c0 - R : 0;
+            d[2 * m + 1] = lv ? (int32_t)c1 - R : 0;
+            zmask |= ((lv && c0 == 0) ? 1u : 0u) << (2 * m);
+            zmask |= ((lv && c1 == 0) ? 1u : 0u) << (2 * m + 1);
+        }
+    }
+    bool bad = false;
+    if (NDIM == 3) recon_block3(a, u, lane, d, zmask, rs, re, (lds_u32 *)s_blk[w], bad);
+    else recon_unit<NDIM>(a, u, lane, d, zmask, rs, re, bad);
+    if (bad) {
+        atomicOr(a.status, ST_ECORRUPT);
+        *a.hstatus = ST_ECORRUPT;
+    }
 }
 
 static uint32_t decode_waves(const Layout &L) { return L.sub_size <= 256 ? kDecMaxWaves : 1u; }
@@ -1116,15 +1082,12 @@ void launch_decode(hipStream_t s, const Geom &g, const Layout &L, const uint8_t 
     a.hstatus = hstatus;
     if (a.wave_tasks == 0) return;
     if (L.sub_size == 128 && qws) {
-        a.win_words = kG128Win;
-        const uint32_t blocks = (a.wave_tasks + kG128Waves - 1) / kG128Waves;
-        const size_t lds = decode_g128_lds_bytes(L);
-        const void *fn = g.ndim == 3 ? (const void *)k_decode_g128<3>
-                                     : (g.ndim == 2 ? (const void *)k_decode_g128<2> : (const void *)k_decode_g128<1>);
-        if (lds > 65536) (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (g.ndim == 3) hipLaunchKernelGGL(k_decode_g128<3>, dim3(blocks), dim3(64 * kG128Waves), lds, s, a);
-        else if (g.ndim == 2) hipLaunchKernelGGL(k_decode_g128<2>, dim3(blocks), dim3(64 * kG128Waves), lds, s, a);
-        else hipLaunchKernelGGL(k_decode_g128<1>, dim3(blocks), dim3(64 * kG128Waves), lds, s, a);
+        // codes only; launch_recon finishes
+        a.win_words = kInfWin;
+        const uint32_t blocks = (a.wave_tasks + kInfWaves - 1) / kInfWaves;
+        const size_t lds = 2ull * ((1u << kLutBits) + kLut2Max) + 4ull * kInfWaves * kInfWin;
+        (void)hipFuncSetAttribute((const void *)k_inflate128, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        hipLaunchKernelGGL(k_inflate128, dim3(blocks), dim3(64 * kInfWaves), lds, s, a);
         return;
     }
 
@@ -1133,6 +1096,28 @@ void launch_decode(hipStream_t s, const Geom &g, const Layout &L, const uint8_t 
     const size_t lds = decode_lds_bytes(L);
     if (lds > 65536) (void)hipFuncSetAttribute((const void *)k_decode, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k_decode, dim3(blocks), dim3(64 * waves), lds, s, a);
+}
+
+void launch_recon(hipStream_t s, const Geom &g, const Layout &L, const uint8_t *archive, uint32_t n_exc, float h,
+                  const DecodeTables *tab, const uint4 *qws, const uint32_t *unit_exc, float *out, uint32_t *hstatus) {
+    ReconArgs a;
+    a.g = g;
+    a.codes = qws;
+    a.exc = reinterpret_cast<const uint2 *>(archive + L.off_exc);
+    a.unit_exc = unit_exc;
+    a.tab = tab;
+    a.out = out;
+    a.status = const_cast<uint32_t *>(&tab->status);
+    a.hstatus = hstatus;
+    a.n_exc = n_exc;
+    a.n_units = recon_units(g);
+    a.radius = L.radius;
+    a.h = h;
+    if (a.n_units == 0) return;
+    const uint32_t blocks = (a.n_units + kReconWaves - 1) / kReconWaves;
+    if (g.ndim == 3) hipLaunchKernelGGL(k_recon<3>, dim3(blocks), dim3(64 * kReconWaves), 0, s, a);
+    else if (g.ndim == 2) hipLaunchKernelGGL(k_recon<2>, dim3(blocks), dim3(64 * kReconWaves), 0, s, a);
+    else hipLaunchKernelGGL(k_recon<1>, dim3(blocks), dim3(64 * kReconWaves), 0, s, a);
 }
 
 }  // namespace dqz

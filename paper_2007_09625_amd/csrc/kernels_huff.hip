@@ -539,11 +539,78 @@ void launch_codebook(hipStream_t st, const Geom &g, const Layout &L, Ctl *ctl, c
 }
 
 // ---------------------------------------------------------------------------
-// D0: archive code lengths -> canonical decoding tables.  Validates that the
-// lengths describe a complete prefix code (or one symbol of length 1).
+// D0: archive code lengths -> canonical decoding tables (workgroup 0).
+// Validates that the lengths describe a complete prefix code (or one symbol
+// of length 1).  The other workgroups index the exception list by
+// reconstruction unit (512 padded positions): unit_exc[u] is the first
+// record at or after the unit's first position, found by binary search, and
+// every adjacent pair of keys is checked to increase.
 // ---------------------------------------------------------------------------
+__device__ void exception_index(const uint2 *exc, uint32_t n_exc, uint32_t *unit_exc, uint32_t n_units,
+                                uint32_t *hstatus) {
+    const uint32_t i = (blockIdx.x - 1) * blockDim.x + threadIdx.x;
+    if (i <= n_units) {
+        const uint64_t key = 2ull * ((uint64_t)i << kUnitShift);
+        uint32_t lo = 0, hi = n_exc;
+        while (lo < hi) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if ((uint64_t)exc[mid].x < key) lo = mid + 1; else hi = mid;
+        }
+        unit_exc[i] = lo;
+    }
+    if (i > 0 && i < n_exc && exc[i - 1].x >= exc[i].x) *hstatus = ST_ECORRUPT;
+    // with increasing keys, every record then lies in some unit
+    if (i + 1 == n_exc && ((exc[i].x >> 1) >> kUnitShift) >= n_units) *hstatus = ST_ECORRUPT;
+}
+
+// Second-level table: the long-code prefixes are the top of the first
+// level, [V0, 2^kLutBits) (canonical codes of <= kLutBits bits come first).
+// With b the largest width in 1..7 for which all of them fit kLut2Max
+// entries (or as many as fit at width 1), entry (v - V0) * 2^b + i holds the
+// code whose first kLutBits + b bits are v, i, when it is that short (0
+// otherwise: the decoder then takes the canonical limits).
+__device__ void build_lut2(const CanonScratch &c, DecodeTables *tab, uint64_t *lim) {
+    const uint32_t tid = threadIdx.x, T = blockDim.x;
+    const uint32_t max_len = c.max_len;
+    for (uint32_t l = tid; l < 65; l += T)
+        lim[l] = (l == 0) ? 0ull : (l == 64 ? ~0ull : ((c.first_code[l] + c.count[l]) << (64 - l)));
+    __syncthreads();
+    // codes of <= kLutBits bits fill [0, V0) of the prefixes; no long codes: V0 = 2^kLutBits
+    const uint32_t V0 = max_len > kLutBits ? (uint32_t)(lim[kLutBits] >> (64 - kLutBits)) : (1u << kLutBits);
+    const uint32_t n_long = (1u << kLutBits) - V0;
+    uint32_t b = 7;
+    while (b > 1 && (n_long << b) > kLut2Max) b--;
+    const uint32_t n2 = (n_long << b) < kLut2Max ? (n_long << b) : kLut2Max;
+    if (tid == 0) {
+        tab->lut2_v0 = V0;
+        tab->lut2_bits = b;
+        tab->lut2_n = n2;
+    }
+    for (uint32_t j = tid; j < n2; j += T) {
+        const uint64_t wv = (uint64_t)((V0 << b) + j) << (64 - kLutBits - b);
+        uint32_t l = kLutBits + 1;
+        while (l < max_len && wv >= lim[l]) l++;
+        uint32_t e = 0;
+        if (l <= kLutBits + b) {
+            const uint64_t code = wv >> (64 - l);
+            const uint64_t d = code - c.first_code[l];
+            if (code >= c.first_code[l] && d < c.count[l])
+                e = (l << 11) | (uint32_t)(c.key[c.first_index[l] + (uint32_t)d] & 0x7FF);
+        }
+        // when not every long prefix fits, the last entry stands for the rest
+        // (lookups past the table are clamped to it): it must send them on
+        if (j + 1 == n2 && (n_long << b) > kLut2Max) e = 0;
+        tab->lut2[j] = (uint16_t)e;
+    }
+}
+
 __global__ __launch_bounds__(kTableThreads) void k_decode_tables(const uint8_t *__restrict__ archive, Layout L,
-                                                                uint32_t max_len_hdr, DecodeTables *tab, uint32_t *hstatus) {
+                                                                uint32_t max_len_hdr, DecodeTables *tab, uint32_t *hstatus,
+                                                                uint32_t n_exc, uint32_t *unit_exc, uint32_t n_units) {
+    if (blockIdx.x > 0) {
+        exception_index(reinterpret_cast<const uint2 *>(archive + L.off_exc), n_exc, unit_exc, n_units, hstatus);
+        return;
+    }
     __shared__ CanonScratch c;
     __shared__ uint8_t len[kMaxSyms];
     __shared__ uint32_t s_bad;
@@ -615,6 +682,7 @@ __global__ __launch_bounds__(kTableThreads) void k_decode_tables(const uint8_t *
                 e = (l << 11) | (uint32_t)(k & 0x7FF);
             }
         } else if (c.max_len > kLutBits) {
+            // a long-code prefix: the shortest length that can follow
             const uint64_t w = (uint64_t)v << (64 - kLutBits);
             uint32_t ll = kLutBits + 1;
             while (ll < c.max_len && w >= ((c.first_code[ll] + c.count[ll]) << (64 - ll))) ll++;
@@ -623,12 +691,20 @@ __global__ __launch_bounds__(kTableThreads) void k_decode_tables(const uint8_t *
         tab->lut[v] = (uint16_t)e;
     }
     __syncthreads();
+    // the second-level table (its limits reuse the sort exchange buffer)
+    build_lut2(c, tab, c.xch);
+    __syncthreads();
     if (tid == 0) tab->phase[2] = wall_clock64();
 }
 
 void launch_decode_tables(hipStream_t st, const Layout &L, const uint8_t *archive, uint32_t max_len_hdr,
-                          DecodeTables *tab, uint32_t *hstatus) {
-    hipLaunchKernelGGL(k_decode_tables, dim3(1), dim3(kTableThreads), 0, st, archive, L, max_len_hdr, tab, hstatus);
+                          DecodeTables *tab, uint32_t *hstatus, uint32_t n_exc, uint32_t *unit_exc,
+                          uint32_t n_units) {
+    // workgroup 0 builds the tables; the others index the exception list
+    const uint32_t idx_items = unit_exc ? (n_units + 1 > n_exc ? n_units + 1 : n_exc) : 0u;
+    const uint32_t blocks = 1 + (idx_items + kTableThreads - 1) / kTableThreads;
+    hipLaunchKernelGGL(k_decode_tables, dim3(blocks), dim3(kTableThreads), 0, st, archive, L, max_len_hdr, tab,
+                       hstatus, n_exc, unit_exc, n_units);
 }
 
 }  // namespace dqz

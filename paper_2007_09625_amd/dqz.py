@@ -25,7 +25,7 @@ EXPORTED = ("dqz_ctx_create", "dqz_ctx_destroy", "dqz_compress_bound", "dqz_comp
             "dqz_stage_times")
 DQZ_MAX_STAGES = 8
 COMPRESS_STAGES = ("init", "range_eb", "quantize", "codebook", "encode")
-DECOMPRESS_STAGES = ("decode_tables", "decode")
+DECOMPRESS_STAGES = ("decode_tables", "inflate", "reconstruct")
 
 
 class DqzError(RuntimeError):
