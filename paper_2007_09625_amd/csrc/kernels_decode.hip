@@ -356,6 +356,7 @@ struct WaveStream {
     uint32_t bits, nwin;
     bool whole;   // the window holds every word a lane of the wave reads
 };
+template <bool PAD>
 __device__ __forceinline__ WaveStream wave_stream(const DecArgs &a, uint64_t sub0, uint32_t lane, bool has,
                                                   lds_u32 *win) {
     WaveStream r;
@@ -382,7 +383,7 @@ __device__ __forceinline__ WaveStream wave_stream(const DecArgs &a, uint64_t sub
     // subchunk's end plus the two words a reader may look past it
     r.wlo = __shfl(r.start, 0, 64) >> 5;
     const uint64_t whi = wave_max<uint64_t>(has ? ((r.start + r.bits) >> 5) + 3 : 0);
-    const uint32_t cap = a.win_words / 17 * 16;   // logical words whose padded slots fit
+    const uint32_t cap = PAD ? a.win_words / 17 * 16 : a.win_words;   // logical words whose slots fit
     r.nwin = whi > r.wlo ? (uint32_t)(whi - r.wlo < cap ? whi - r.wlo : cap) : 0u;
     r.whole = whi <= r.wlo || whi - r.wlo <= cap;
     for (uint32_t b = 0; b < r.nwin; b += 64 * 8) {
@@ -392,7 +393,7 @@ __device__ __forceinline__ WaveStream wave_stream(const DecArgs &a, uint64_t sub
 #pragma unroll
         for (uint32_t j = 0; j < 8; j++) {
             const uint32_t k = b + j * 64 + lane;
-            if (k < r.nwin) win[win_slot(k)] = v[j];
+            if (k < r.nwin) win[PAD ? win_slot(k) : k] = v[j];
         }
     }
     return r;
@@ -440,7 +441,7 @@ __global__ __launch_bounds__(64 * kDecMaxWaves) void k_decode(DecArgs a) {
     lds_u32 *win = s_win + w * a.win_words;
     lds_u32 *xp = s_win + (blockDim.x / 64) * a.win_words + w * kDecXp;   // exception payloads
     if (active) {
-        const WaveStream ws = wave_stream(a, sub0, lane, has, win);
+        const WaveStream ws = wave_stream<true>(a, sub0, lane, has, win);
         bits_s = ws.bits;
         start = ws.start;
         wlo = ws.wlo;
@@ -558,8 +559,10 @@ __global__ __launch_bounds__(64 * kDecMaxWaves) void k_decode(DecArgs a) {
 //
 // k_inflate128: one wave decodes 64 subchunks, one per lane, into 16-bit
 // codes in a workspace array (position order, eight codes per 16-byte
-// store).  Six waves share the lookup tables in LDS, each with its stream
-// window, so two workgroups fit one CU (three waves per SIMD).  Every step
+// store).  The waves of a workgroup share the lookup tables in LDS, each
+// with its stream window; one workgroup per CU with as many waves as spread
+// the launch over all CUs (up to 14: tables plus windows fill the 160 KiB)
+// keeps every wave of a large field resident at once.  Every step
 // reads both table levels at once and selects, so codes of up to
 // kLutBits + b2 bits take no branch; only longer codes and invalid entries
 // go on to the canonical limits.
@@ -572,8 +575,8 @@ __global__ __launch_bounds__(64 * kDecMaxWaves) void k_decode(DecArgs a) {
 // so that y and z are in-lane too, in 2D and 1D the other axes are scans
 // across lanes.
 // ---------------------------------------------------------------------------
-constexpr uint32_t kInfWaves = 6;     // waves per inflate workgroup (they share the lookup tables)
-constexpr uint32_t kInfWin = 2432;    // LDS stream-window slots per wave (9.5 KiB)
+constexpr uint32_t kInfMaxWaves = 14; // waves per inflate workgroup, at most (they share the lookup tables)
+constexpr uint32_t kInfWin = 2432;    // LDS stream-window words per wave (9.5 KiB)
 constexpr uint32_t kReconWaves = 4;   // units (one per wave) per reconstruction workgroup
 
 // Both lookup-table levels into LDS: 16-byte copies, eight of a thread's
@@ -615,15 +618,16 @@ __device__ __forceinline__ bool sub128_full(const Geom &g, uint32_t pa) {
 // 16-byte groups dst[g]; returns the stream bits consumed.  ALLREAL: every
 // position of the wave lies inside the field (none is tested).  WHOLE: the
 // window holds every word the wave's lanes read (no bounds test per word).
+// The window is unpadded: word k at win[k].
 //
-// The bit buffer `cur` holds `avail` valid bits from its top; window word kk
-// is the next to enter (read ahead into `nxt`), so the stream position is
-// 32 (sw + kk - relw) - avail.  Each step refills first (at most 32 bits
-// left: the next word enters), so a lookup always sees more than 32 bits.
+// The reader keeps two stream words w0, w1 and nb = 32 - b, b in [1, 32] the
+// bits of w0 already consumed: the next 32 stream bits are one funnel shift,
+// alignbit(w0, w1, nb).  Window word kk follows w1 (read ahead into `nxt`);
+// the stream position is 32 (sw + kk - relw - 2) + b.  A code (at most
+// kLutBits + b2 <= 20 bits on the common step) moves past w0 at most once.
 // Both table levels are read every step, from the top kLutBits and
 // kLutBits + b2 bits, and the first level's long-prefix flag selects between
-// them: a code of up to kLutBits + b2 bits costs no branch.  Longer codes
-// and invalid entries take one uniform branch.
+// them.  Longer codes and invalid entries take one uniform branch.
 template <bool ALLREAL, bool WHOLE>
 __device__ __forceinline__ uint32_t inflate_codes(const DecArgs &a, const lds_u32 *win, uint32_t nwin, uint64_t wlo,
                                                   uint64_t start, uint32_t pa, uint4 *dst, const lds_u16 *lut,
@@ -639,43 +643,29 @@ __device__ __forceinline__ uint32_t inflate_codes(const DecArgs &a, const lds_u3
     // memory operation, the group stores included
     auto word = [&](uint32_t kr) -> uint32_t {
         const uint32_t k = relw + kr;
-        return pinned((k < nwin) ? win[win_slot(k)] : ld_word(a, sw + kr));
+        return pinned((k < nwin) ? win[k] : ld_word(a, sw + kr));
     };
     const uint32_t R = a.L.radius;
     const uint32_t o = (uint32_t)(start & 31u);
-    uint64_t cur = (((uint64_t)word(0) << 32) | word(1)) << o;
-    int32_t avail = 64 - (int32_t)o;
-    uint32_t kk = relw + 2;
-    uint32_t nxt = word(2);
+    // b = o, or b = 32 with w0 the word before the first when o = 0
+    uint32_t w0, w1, nxt, kk;
+    if (o) { w0 = word(0); w1 = word(1); nxt = word(2); kk = relw + 2; }
+    else { w0 = 0; w1 = word(0); nxt = word(1); kk = relw + 1; }
+    const lds_u32 *wp = win + kk;   // window word kk (stepped with kk)
+    uint32_t nb = (32u - o) & 31u;
     uint32_t rmask = ~0u;
     for (uint32_t g = 0; g < 16; g++) {
         if (!ALLREAL && (g & 3u) == 0) rmask = real_mask32(a.g, pa + g * 8);
         uint32_t pk[4];
 #pragma unroll
         for (uint32_t j = 0; j < 8; j++) {
-            {   // refill (a zero word and a shift past the buffer when not needed)
-                const bool need = avail <= 32;
-                const uint32_t src = need ? nxt : 0u;
-                cur |= (uint64_t)src << ((uint32_t)(32 - avail) & 63u);
-                avail += need ? 32 : 0;
-                kk += need ? 1u : 0u;
-                if (WHOLE) {
-                    nxt = win[win_slot(kk)];
-                } else {
-                    nxt = win[win_slot(kk < nwin ? kk : wlast)];
-                    if (__builtin_expect(__any((int)(kk >= nwin)), 0)) {
-                        if (kk >= nwin) nxt = pinned(ld_word(a, sw + (kk - relw)));
-                    }
-                }
-            }
             const bool real = ALLREAL || ((rmask >> ((g & 3u) * 8 + j)) & 1u);
-            const uint32_t top = (uint32_t)(cur >> 32);
-            const uint32_t e1 = lut[top >> (32 - kLutBits)];
-            const uint32_t v2 = (top >> (32 - kLutBits - b2)) - base2;
+            const uint32_t peek = __builtin_amdgcn_alignbit(w0, w1, nb);
+            const uint32_t e1 = lut[peek >> (32 - kLutBits)];   // zero-extended
+            const uint32_t v2 = (peek >> (32 - kLutBits - b2)) - base2;
             const uint32_t e2 = lut2[v2 < last2 ? v2 : last2];
-            const uint32_t e = (e1 & 0x8000u) ? e2 : e1;
+            const uint32_t e = e1 < 0x8000u ? e1 : e2;
             uint32_t len = e >> 11, sym = e & 0x7FFu;
-            bool moved = false;
             const bool other = real && len == 0;   // longer than the second level, or no code
             if (__builtin_expect(__any((int)other), 0)) {
                 if (other && !(e1 & 0x8000u)) {   // no code starts with these bits
@@ -685,7 +675,8 @@ __device__ __forceinline__ uint32_t inflate_codes(const DecArgs &a, const lds_u3
                 } else if (other) {
                     // canonical limits from the shortest length past both levels,
                     // on 64 fresh bits at the lane's position
-                    const uint64_t bp = (sw << 5) + 32ull * (kk - relw) - (uint32_t)avail;
+                    kk = (uint32_t)(wp - win);
+                    const uint64_t bp = (sw << 5) + 32ull * (kk - relw - 2) + (32u - nb);
                     const uint32_t rk = (uint32_t)((bp >> 5) - sw), ob = (uint32_t)(bp & 31u);
                     const uint64_t h2 = ((uint64_t)word(rk) << 32) | word(rk + 1);
                     const uint64_t wv = ob ? ((h2 << ob) | (word(rk + 2) >> (32 - ob))) : h2;
@@ -697,48 +688,62 @@ __device__ __forceinline__ uint32_t inflate_codes(const DecArgs &a, const lds_u3
                     const uint64_t idx = a.tab->first_index[l] + (c - a.tab->first_code[l]);
                     if (idx >= a.L.nsym) { bad = true; sym = R; }
                     else sym = a.tab->sorted[idx];
-                    len = l;
-                    if ((int32_t)l > avail) {   // past the buffer: restart the reader after the code
-                        const uint64_t np = bp + l;
-                        const uint32_t o2 = (uint32_t)(np & 31u);
-                        const uint32_t kr = (uint32_t)((np >> 5) - sw);
-                        cur = (((uint64_t)word(kr) << 32) | word(kr + 1)) << o2;
-                        avail = 64 - (int32_t)o2;
-                        kk = relw + kr + 2;
-                        nxt = word(kr + 2);
-                        moved = true;
-                    }
+                    // restart the reader after the code
+                    const uint64_t np = bp + l;
+                    const uint32_t kr = (uint32_t)((np >> 5) - sw), o2 = (uint32_t)(np & 31u);
+                    if (o2) { w0 = word(kr); w1 = word(kr + 1); nxt = word(kr + 2); kk = relw + kr + 2; }
+                    else { w1 = word(kr); nxt = word(kr + 1); kk = relw + kr + 1; }
+                    wp = win + kk;
+                    nb = (32u - o2) & 31u;
+                    len = 0;
                 }
             }
-            if (!real || moved) len = 0;
-            cur <<= len;
-            avail -= (int32_t)len;
+            if (!real) len = 0;
+            // consume: past w0 (nb below zero) shifts the words by one
+            const int32_t nn = (int32_t)nb - (int32_t)len;
+            const bool adv = nn < 0;
+            w0 = adv ? w1 : w0;
+            w1 = adv ? nxt : w1;
+            nb = (uint32_t)nn & 31u;
+            wp += adv ? 1 : 0;
+            if (WHOLE) {
+                nxt = *wp;
+            } else {
+                kk = (uint32_t)(wp - win);
+                nxt = win[kk < nwin ? kk : wlast];
+                if (__builtin_expect(__any((int)(kk >= nwin)), 0)) {
+                    if (kk >= nwin) nxt = pinned(ld_word(a, sw + (kk - relw)));
+                }
+            }
             const uint32_t s16 = real ? sym : R;
             pk[j >> 1] = (j & 1u) ? (pk[j >> 1] | (s16 << 16)) : s16;
         }
         dst[g] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
     }
-    return 32u * (kk - relw) - (uint32_t)avail - o;
+    kk = (uint32_t)(wp - win);
+    return 32u * (kk - relw - 2) + (32u - nb) - o;
 }
 
-__global__ __launch_bounds__(64 * kInfWaves) void k_inflate128(DecArgs a) {
+__global__ __launch_bounds__(64 * kInfMaxWaves) void k_inflate128(DecArgs a) {
+    // static tables (their addresses fold into the instruction offsets),
+    // the stream windows in dynamic LDS
+    __shared__ __attribute__((aligned(16))) uint16_t s_lut_[1u << kLutBits];
+    __shared__ __attribute__((aligned(16))) uint16_t s_lut2_[kLut2Max];
     extern __shared__ uint32_t s_dyn[];
-    // the second level first: the first level's reads then fold its base
-    // into the instruction offset
-    lds_u16 *s_lut2 = (lds_u16 *)s_dyn;                 // kLut2Max
-    lds_u16 *s_lut = s_lut2 + kLut2Max;                 // 1 << kLutBits
-    lds_u32 *s_win = (lds_u32 *)(s_lut + (1u << kLutBits));   // kInfWaves * kInfWin
+    lds_u16 *s_lut = (lds_u16 *)s_lut_;
+    lds_u16 *s_lut2 = (lds_u16 *)s_lut2_;
+    lds_u32 *s_win = (lds_u32 *)s_dyn;   // waves * kInfWin
     if (a.tab->status) return;   // the code lengths failed validation: tables are not usable
     const uint64_t t0 = a.trace ? wall_clock64() : 0;
     luts_to_lds(a.tab, s_lut, s_lut2);
     const uint32_t lane = lane_id(), w = threadIdx.x / 64;
-    const uint32_t gw = blockIdx.x * kInfWaves + w;
+    const uint32_t gw = blockIdx.x * (blockDim.x / 64) + w;
     const bool active = gw < a.wave_tasks;
     const uint64_t sub0 = (uint64_t)gw * 64;
     const bool has = active && sub0 + lane < a.L.n_sub;
     lds_u32 *win = s_win + w * kInfWin;
     WaveStream ws = {0, 0, 0, 0};
-    if (active) ws = wave_stream(a, sub0, lane, has, win);
+    if (active) ws = wave_stream<false>(a, sub0, lane, has, win);
     __syncthreads();
     const uint64_t t1 = a.trace ? wall_clock64() : 0;
     bool bad = false;
@@ -1084,10 +1089,15 @@ void launch_decode(hipStream_t s, const Geom &g, const Layout &L, const uint8_t 
     if (L.sub_size == 128 && qws) {
         // codes only; launch_recon finishes
         a.win_words = kInfWin;
-        const uint32_t blocks = (a.wave_tasks + kInfWaves - 1) / kInfWaves;
-        const size_t lds = 2ull * ((1u << kLutBits) + kLut2Max) + 4ull * kInfWaves * kInfWin;
-        (void)hipFuncSetAttribute((const void *)k_inflate128, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        hipLaunchKernelGGL(k_inflate128, dim3(blocks), dim3(64 * kInfWaves), lds, s, a);
+        // one workgroup per CU, waves spread evenly over the CUs
+        constexpr uint32_t kCus = 256;
+        uint32_t waves = (a.wave_tasks + kCus - 1) / kCus;
+        waves = waves < 1 ? 1 : (waves > kInfMaxWaves ? kInfMaxWaves : waves);
+        const uint32_t blocks = (a.wave_tasks + waves - 1) / waves;
+        const size_t lds = 4ull * waves * kInfWin;   // the windows (the tables are static)
+        (void)hipFuncSetAttribute((const void *)k_inflate128, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)(4ull * kInfMaxWaves * kInfWin));
+        hipLaunchKernelGGL(k_inflate128, dim3(blocks), dim3(64 * waves), lds, s, a);
         return;
     }
 
