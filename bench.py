@@ -38,7 +38,18 @@ WORKLOADS = {
 
 
 KERNEL_OF_STAGE = {"range_eb": ("k_minmax", "kernels_quant.hip"), "quantize": ("k_quant", "kernels_quant.hip"),
-                   "encode": ("k_enc_pack", "kernels_encode.hip"), "decode": ("k_decode_g128", "kernels_decode.hip")}
+                   "encode_count": ("k_enc_count", "kernels_encode.hip"),
+                   "encode_pack": ("k_enc_pack", "kernels_encode.hip"),
+                   "inflate": ("k_inflate128", "kernels_decode.hip"), "reconstruct": ("k_recon", "kernels_decode.hip")}
+
+
+def padded_positions(shape):
+    """Positions of the zero-padded blocks (32, 16x16 or 8x8x8 points)."""
+    b = {1: (32,), 2: (16, 16), 3: (8, 8, 8)}[len(shape)]
+    p = 1
+    for n, k in zip(shape, b):
+        p *= (n + k - 1) // k * k
+    return p
 
 
 def counted_traffic(stage, workload):
@@ -172,14 +183,22 @@ def main() -> int:
     psnr = 20 * math.log10(vrange / rmse) if rmse > 0 else float("inf")
     A = float(nbytes)
 
-    # algorithmic bytes per launch of each kernel
+    # algorithmic bytes per launch of each stage's kernel (u16 codes per
+    # padded position, 128-position subchunks, 64-subchunk chunks, 512-position
+    # reconstruction units)
     stream_bytes = 4.0 * ((total_bits + 31) // 32)
     exc_bytes = 8.0 * (n_out + n_patch)
+    padded = padded_positions(shape)
+    n_sub = (padded + 127) // 128
+    n_chunks = (n_sub + 63) // 64
+    n_units = (padded + 511) // 512
     algo = {
         "range_eb": 4.0 * n,
-        "quantize": 4.0 * n + 2.0 * n + exc_bytes,
-        "encode": 2.0 * n + stream_bytes,
-        "decode": A + 4.0 * n,
+        "quantize": 4.0 * n + 2.0 * padded + exc_bytes,
+        "encode_count": 2.0 * padded,
+        "encode_pack": 2.0 * padded + stream_bytes,
+        "inflate": stream_bytes + 2.0 * n_sub + 8.0 * n_chunks + 2.0 * padded,
+        "reconstruct": 2.0 * padded + exc_bytes + 4.0 * n + 4.0 * (n_units + 1),
     }
     stages_us = {}
     for k, v in list(st_c.items()) + list(st_d.items()):

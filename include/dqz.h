@@ -142,10 +142,13 @@ const char *dqz_ctx_last_error(const dqz_ctx *ctx);
  * dqz_stage_times returns the elapsed microseconds of
  * each stage of the most recent call of that kind:
  *   compress   (which = 0): [0] init, [1] value range + eb (0 in absolute
- *              mode), [2] dual-quantization + histogram + exceptions (with
- *              their tile scan), [3] codebook + header, [4] encode + deflate
- *              (width count + tile scan + packing)
- *   decompress (which = 1): [0] decoding tables, [1] inflate + reconstruct
+ *              mode), [2] dual-quantization + histogram + exceptions, [3] their
+ *              tile scan (and the histogram sum), [4] codebook + header,
+ *              [5] code-width count + tile scan, [6] encode + deflate (packing)
+ *   decompress (which = 1): [0] decoding tables (and, for 128-position
+ *              subchunks, the exception index), [1] inflate (other subchunk
+ *              sizes: inflate + reconstruct), [2] reconstruct (128-position
+ *              subchunks; 0 otherwise)
  * `us` must hold DQZ_MAX_STAGES doubles; *n_stages receives the count. */
 #define DQZ_MAX_STAGES 8
 dqz_status dqz_ctx_set_timing(dqz_ctx *ctx, int level);
@@ -157,17 +160,19 @@ dqz_status dqz_stage_times(dqz_ctx *ctx, int which, double *us, int *n_stages);
  *   DQZ_DBG_HISTOGRAM  u32[2R]
  *   DQZ_DBG_CODEBOOK   u64[2R], (length << 56) | canonical code
  *   DQZ_DBG_PHASES     u64[32], phase timestamps of the one-workgroup kernels and
- *                      decode-phase durations (recorded at timing level 2)
+ *                      decoding-wave durations (recorded at timing level 2)
  * `bytes` must equal the buffer's size. */
 #define DQZ_DBG_CODES 1
 #define DQZ_DBG_HISTOGRAM 2
 #define DQZ_DBG_CODEBOOK 3
 #define DQZ_DBG_PHASES 4     /* u64[32], wall clock at 100 MHz: marks inside the codebook
                                 kernel [0..15] and the decoding-table kernel [16..18];
-                                first decode-wave start [24], last decode-wave end [25],
-                                decode-phase durations summed over the decode waves
-                                [26..31]: tables, stream window + exception search,
-                                inflate, outlier marks, reconstruct, patches */
+                                first decoding-wave start [24], last decoding-wave end
+                                [25], phase durations summed over the decoding waves
+                                [26..31]: for 128-position subchunks (inflate kernel)
+                                tables + stream window, inflate; otherwise tables,
+                                stream window + exception search, inflate, outlier
+                                marks, reconstruct, patches */
 dqz_status dqz_debug_copy(dqz_ctx *ctx, int what, void *h_dst, uint64_t bytes);
 
 #ifdef __cplusplus

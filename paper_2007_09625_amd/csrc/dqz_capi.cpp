@@ -468,11 +468,15 @@ dqz_status dqz_compress(dqz_ctx *ctx, const float *d_field, const dqz_shape *sha
         mark(ctx, 0, 2, s);
         launch_quantize(s, d_field, P.g, P.L, ctl, qb);
         mark(ctx, 0, 3, s);
+        launch_quantize_scan(s, P.g, P.L, qb);
+        mark(ctx, 0, 4, s);
         launch_codebook(s, P.g, P.L, ctl, qb.hist_sum, book, book32, arc, params->eb_mode, params->eb, qs,
                         ctx->d_hctl);
-        mark(ctx, 0, 4, s);
-        launch_encode(s, P.g, P.L, ctl, eb, arc);
         mark(ctx, 0, 5, s);
+        launch_encode_count(s, P.g, P.L, ctl, eb, arc);
+        mark(ctx, 0, 6, s);
+        launch_encode_pack(s, P.g, P.L, ctl, eb, arc);
+        mark(ctx, 0, 7, s);
         HIP_TRY(ctx, hipGetLastError());
         HIP_TRY(ctx, wait_stream(s));
         ctx->ev_ready[0] = ctx->timing;

@@ -255,6 +255,7 @@ struct QuantBufs {
     TileScan scan;         // exception count (0) and outlier count (1) per tile
 };
 void launch_quantize(hipStream_t s, const float *x, const Geom &g, const Layout &L, Ctl *ctl, const QuantBufs &b);
+void launch_quantize_scan(hipStream_t s, const Geom &g, const Layout &L, const QuantBufs &b);
 uint32_t quantize_tiles(const Geom &g);
 void launch_codebook(hipStream_t s, const Geom &g, const Layout &L, Ctl *ctl, const uint32_t *hist,
                      uint64_t *book, uint32_t *book32, uint8_t *archive, int eb_mode, double eb_param,
@@ -270,7 +271,10 @@ struct EncodeBufs {
     TileScan escan;        // bits per encode tile
     uint32_t n_tiles_q;
 };
-void launch_encode(hipStream_t s, const Geom &g, const Layout &L, Ctl *ctl, const EncodeBufs &b, uint8_t *archive);
+void launch_encode_count(hipStream_t s, const Geom &g, const Layout &L, Ctl *ctl, const EncodeBufs &b,
+                         uint8_t *archive);
+void launch_encode_pack(hipStream_t s, const Geom &g, const Layout &L, Ctl *ctl, const EncodeBufs &b,
+                        uint8_t *archive);
 uint32_t encode_tiles(const Geom &g);
 void launch_decode_tables(hipStream_t s, const Layout &L, const uint8_t *archive, uint32_t max_len_hdr,
                           DecodeTables *tab, uint32_t *hstatus, uint32_t n_exc, uint32_t *unit_exc,

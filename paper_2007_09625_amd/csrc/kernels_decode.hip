@@ -558,8 +558,9 @@ __global__ __launch_bounds__(64 * kDecMaxWaves) void k_decode(DecArgs a) {
 // Subchunks of 128 positions (the default size) take two kernels.
 //
 // k_inflate128: one wave decodes 64 subchunks, one per lane, into 16-bit
-// codes in a workspace array (position order, eight codes per 16-byte
-// store).  The waves of a workgroup share the lookup tables in LDS, each
+// codes in a workspace array: eight codes per 16-byte group, group g of the
+// wave's lane l at [(16 w + g) 64 + l] for wave w of 64 subchunks, so every
+// store instruction writes 1 KiB contiguously.  The waves of a workgroup share the lookup tables in LDS, each
 // with its stream window; one workgroup per CU with as many waves as spread
 // the launch over all CUs (up to 14: tables plus windows fill the 160 KiB)
 // keeps every wave of a large field resident at once.  Every step
@@ -615,7 +616,7 @@ __device__ __forceinline__ bool sub128_full(const Geom &g, uint32_t pa) {
 }
 
 // Inflate the lane's 128 positions (padded positions pa ..) into 16 packed
-// 16-byte groups dst[g]; returns the stream bits consumed.  ALLREAL: every
+// 16-byte groups dst[64 g]; returns the stream bits consumed.  ALLREAL: every
 // position of the wave lies inside the field (none is tested).  WHOLE: the
 // window holds every word the wave's lanes read (no bounds test per word).
 // The window is unpadded: word k at win[k].
@@ -718,7 +719,7 @@ __device__ __forceinline__ uint32_t inflate_codes(const DecArgs &a, const lds_u3
             const uint32_t s16 = real ? sym : R;
             pk[j >> 1] = (j & 1u) ? (pk[j >> 1] | (s16 << 16)) : s16;
         }
-        dst[g] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
+        dst[g * 64] = make_uint4(pk[0], pk[1], pk[2], pk[3]);
     }
     kk = (uint32_t)(wp - win);
     return 32u * (kk - relw - 2) + (32u - nb) - o;
@@ -754,7 +755,7 @@ __global__ __launch_bounds__(64 * kInfMaxWaves) void k_inflate128(DecArgs a) {
         // keeps one zero entry, read by short codes only)
         const uint32_t b2 = a.tab->lut2_bits, base2 = a.tab->lut2_v0 << b2;
         const uint32_t last2 = a.tab->lut2_n ? a.tab->lut2_n - 1 : 0u;
-        uint4 *dst = a.qws + (sub0 + lane) * 16;
+        uint4 *dst = a.qws + sub0 * 16 + lane;   // lane-interleaved groups
         uint32_t used;
         if (ws.whole && __all((int)sub128_full(a.g, pa)))
             used = inflate_codes<true, true>(a, win, ws.nwin, ws.wlo, ws.start, pa, dst, s_lut, s_lut2, b2, base2,
@@ -1015,7 +1016,8 @@ __global__ __launch_bounds__(64 * kReconWaves) void k_recon(ReconArgs a) {
     const uint32_t u = blockIdx.x * kReconWaves + w;
     if (u >= a.n_units) return;   // whole waves
     const uint32_t slot = unit_slot<NDIM>(lane);
-    const uint4 q = a.codes[(uint64_t)u * 64 + slot];
+    // group slot % 16 of subchunk 4 u + slot / 16, lane-interleaved by wave of 64 subchunks
+    const uint4 q = a.codes[((uint64_t)(u >> 4) * 16 + (slot & 15u)) * 64 + (u & 15u) * 4 + (slot >> 4)];
     const uint32_t rs = a.unit_exc[u], re = a.unit_exc[u + 1];
     const int32_t R = (int32_t)a.radius;
     const bool lv = (u << kUnitShift) + 8 * slot < a.g.padded;

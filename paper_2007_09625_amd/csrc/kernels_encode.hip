@@ -321,7 +321,7 @@ void launch_seg_scan(hipStream_t s, const TileScan &S, const HistJob *hj) {
 
 uint32_t encode_tiles(const Geom &g) { return (uint32_t)((g.padded + kTile - 1) / kTile); }
 
-void launch_encode(hipStream_t s, const Geom &g, const Layout &L, Ctl *ctl, const EncodeBufs &b, uint8_t *archive) {
+static EncArgs enc_args(const Geom &g, const Layout &L, Ctl *ctl, const EncodeBufs &b, uint8_t *archive) {
     EncArgs a;
     a.g = g;
     a.L = L;
@@ -329,10 +329,22 @@ void launch_encode(hipStream_t s, const Geom &g, const Layout &L, Ctl *ctl, cons
     a.b = b;
     a.archive = archive;
     a.n_tiles_e = encode_tiles(g);
+    return a;
+}
+
+void launch_encode_count(hipStream_t s, const Geom &g, const Layout &L, Ctl *ctl, const EncodeBufs &b,
+                         uint8_t *archive) {
+    const EncArgs a = enc_args(g, L, ctl, b, archive);
     if (a.n_tiles_e == 0) return;
     const uint32_t grid1 = a.n_tiles_e > b.n_tiles_q ? a.n_tiles_e : b.n_tiles_q;
     hipLaunchKernelGGL(k_enc_count, dim3(grid1), dim3(256), 0, s, a);
     launch_seg_scan(s, b.escan);
+}
+
+void launch_encode_pack(hipStream_t s, const Geom &g, const Layout &L, Ctl *ctl, const EncodeBufs &b,
+                        uint8_t *archive) {
+    const EncArgs a = enc_args(g, L, ctl, b, archive);
+    if (a.n_tiles_e == 0) return;
     const size_t lds = sizeof(uint64_t) * ((kPackWords + 1) / 2 + L.nsym);
     hipLaunchKernelGGL(k_enc_pack, dim3(a.n_tiles_e), dim3(256), lds, s, a);
 }

@@ -587,6 +587,10 @@ void launch_quantize(hipStream_t s, const float *x, const Geom &g, const Layout 
         a.tiles_per_row = 1;
         hipLaunchKernelGGL(k_quant1d, dim3(a.n_tiles), dim3(256), lds, s, a);
     }
+}
+
+void launch_quantize_scan(hipStream_t s, const Geom &g, const Layout &L, const QuantBufs &b) {
+    if (quantize_tiles(g) == 0) return;
     HistJob hj;
     hj.replicas = b.hist;
     hj.hist_out = b.hist_sum;
