@@ -46,21 +46,26 @@ template <> struct Codeword<true> {
     static __device__ __forceinline__ uint64_t code(uint64_t e) { return e & 0x00FFFFFFFFFFFFFFull; }
 };
 
-// 16 consecutive codes of this thread (padding -> kNoSymbol)
-__device__ __forceinline__ void load_codes(const EncArgs &a, uint64_t my0, uint16_t (&q)[kEncPer]) {
+// N consecutive codes of this thread from padded position my0 (padding ->
+// kNoSymbol); N a multiple of 8
+template <uint32_t N>
+__device__ __forceinline__ void load_codes(const EncArgs &a, uint64_t my0, uint16_t (&q)[N]) {
     const uint32_t padded = a.g.padded;
-    if (my0 + kEncPer <= padded) {
+    if (my0 + N <= padded) {
         const uint4 *src = reinterpret_cast<const uint4 *>(a.b.codes + my0);
-        const uint4 v0 = src[0], v1 = src[1];
-        const uint32_t u[8] = {v0.x, v0.y, v0.z, v0.w, v1.x, v1.y, v1.z, v1.w};
 #pragma unroll
-        for (uint32_t i = 0; i < 8; i++) {
-            q[2 * i] = (uint16_t)(u[i] & 0xFFFF);
-            q[2 * i + 1] = (uint16_t)(u[i] >> 16);
+        for (uint32_t v = 0; v < N / 8; v++) {
+            const uint4 u4 = src[v];
+            const uint32_t u[4] = {u4.x, u4.y, u4.z, u4.w};
+#pragma unroll
+            for (uint32_t i = 0; i < 4; i++) {
+                q[8 * v + 2 * i] = (uint16_t)(u[i] & 0xFFFF);
+                q[8 * v + 2 * i + 1] = (uint16_t)(u[i] >> 16);
+            }
         }
     } else {
 #pragma unroll
-        for (uint32_t i = 0; i < kEncPer; i++) q[i] = (my0 + i < padded) ? a.b.codes[my0 + i] : kNoSymbol;
+        for (uint32_t i = 0; i < N; i++) q[i] = (my0 + i < padded) ? a.b.codes[my0 + i] : kNoSymbol;
     }
 }
 
@@ -74,6 +79,12 @@ __global__ __launch_bounds__(256) void k_enc_count(EncArgs a) {
     Ctl *ctl = a.ctl;
     if (ctl->status & kBadStatus) return;
     const uint32_t tid = threadIdx.x, t = blockIdx.x;
+    // the tile's codes are in flight during the copies below and while the
+    // length table goes to LDS
+    const uint64_t p0 = (uint64_t)t * kTile;
+    const uint64_t my0 = p0 + (uint64_t)kEncPer * tid;
+    uint16_t q[kEncPer];
+    if (t < a.n_tiles_e) load_codes(a, my0, q);
 
     // staged exception records of quantize tile t -> archive
     if (t < a.b.n_tiles_q) {
@@ -95,10 +106,6 @@ __global__ __launch_bounds__(256) void k_enc_count(EncArgs a) {
     for (uint32_t i = tid; i < a.L.nsym; i += 256) s_len[i] = a.archive[a.L.off_len + i];
     for (uint32_t i = tid; i < kTile / 32; i += 256) s_sub[i] = 0;
     __syncthreads();
-    const uint64_t p0 = (uint64_t)t * kTile;
-    const uint64_t my0 = p0 + (uint64_t)kEncPer * tid;
-    uint16_t q[kEncPer];
-    load_codes(a, my0, q);
     uint32_t my_bits = 0;
 #pragma unroll
     for (uint32_t i = 0; i < kEncPer; i++)
@@ -134,30 +141,13 @@ __global__ __launch_bounds__(256) void k_enc_count(EncArgs a) {
 // shared with the neighbouring passes and merged into the stream by atomic OR.
 // Returns the pass's bit count.
 template <bool WIDE, uint32_t PER>
-__device__ __forceinline__ uint32_t pack_pass(const EncArgs &a, uint64_t p0, uint64_t base,
+__device__ __forceinline__ uint32_t pack_pass(const EncArgs &a, uint64_t p0, uint64_t base, const uint16_t (&q)[PER],
                                               const typename Codeword<WIDE>::T *s_book, uint32_t *s_words,
                                               uint64_t *s_scan) {
     typedef Codeword<WIDE> CW;
     typedef typename CW::T Entry;
     const uint32_t tid = threadIdx.x;
     const uint64_t my0 = p0 + (uint64_t)PER * tid;
-    uint16_t q[PER];
-    if (my0 + PER <= a.g.padded) {
-        const uint4 *src = reinterpret_cast<const uint4 *>(a.b.codes + my0);
-#pragma unroll
-        for (uint32_t v = 0; v < PER / 8; v++) {
-            const uint4 u4 = src[v];
-            const uint32_t u[4] = {u4.x, u4.y, u4.z, u4.w};
-#pragma unroll
-            for (uint32_t i = 0; i < 4; i++) {
-                q[8 * v + 2 * i] = (uint16_t)(u[i] & 0xFFFF);
-                q[8 * v + 2 * i + 1] = (uint16_t)(u[i] >> 16);
-            }
-        }
-    } else {
-#pragma unroll
-        for (uint32_t i = 0; i < PER; i++) q[i] = (my0 + i < a.g.padded) ? a.b.codes[my0 + i] : kNoSymbol;
-    }
     uint32_t my_bits = 0;
 #pragma unroll
     for (uint32_t i = 0; i < PER; i++)
@@ -239,6 +229,13 @@ __device__ __forceinline__ void pack_tile(const EncArgs &a, uint32_t *s_words, u
     Entry *s_book = reinterpret_cast<Entry *>(s_book_raw);
     const uint32_t tid = threadIdx.x, t = blockIdx.x;
     const Entry *gbook = WIDE ? reinterpret_cast<const Entry *>(a.b.book) : reinterpret_cast<const Entry *>(a.b.book32);
+    const uint64_t p0 = (uint64_t)t * kTile;
+    // the tile's codes are in flight while the codebook goes to LDS (the
+    // 64-bit path packs the tile in two halves)
+    constexpr uint32_t PER = WIDE ? kEncPer / 2 : kEncPer;
+    uint16_t q0[PER], q1[PER];
+    load_codes(a, p0 + (uint64_t)PER * tid, q0);
+    if (WIDE) load_codes(a, p0 + kTile / 2 + (uint64_t)PER * tid, q1);
     {
         // codebook into LDS: all loads of a thread in flight
         Entry e[kMaxSyms / 256];
@@ -263,15 +260,14 @@ __device__ __forceinline__ void pack_tile(const EncArgs &a, uint32_t *s_words, u
     }
     __syncthreads();
     const uint64_t G = *s_G;
-    const uint64_t p0 = (uint64_t)t * kTile;
     if (!WIDE) {
-        (void)pack_pass<false, kEncPer>(a, p0, G, reinterpret_cast<const uint32_t *>(s_book), s_words, s_scan);
+        (void)pack_pass<false, PER>(a, p0, G, q0, reinterpret_cast<const uint32_t *>(s_book), s_words, s_scan);
     } else {
-        const uint32_t b0 = pack_pass<true, kEncPer / 2>(a, p0, G, reinterpret_cast<const uint64_t *>(s_book),
-                                                         s_words, s_scan);
+        const uint32_t b0 = pack_pass<true, PER>(a, p0, G, q0, reinterpret_cast<const uint64_t *>(s_book), s_words,
+                                                 s_scan);
         __syncthreads();   // the word buffer is reused
-        (void)pack_pass<true, kEncPer / 2>(a, p0 + kTile / 2, G + b0, reinterpret_cast<const uint64_t *>(s_book),
-                                           s_words, s_scan);
+        (void)pack_pass<true, PER>(a, p0 + kTile / 2, G + b0, q1, reinterpret_cast<const uint64_t *>(s_book),
+                                   s_words, s_scan);
     }
 }
 

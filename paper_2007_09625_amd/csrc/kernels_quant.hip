@@ -253,6 +253,7 @@ __global__ __launch_bounds__(256) void k_quant3d(QuantArgs a) {
     if (ctl->status & ST_EINVAL) return;
     const float r = ctl->r, h = ctl->h;
     const double eb = ctl->eb_abs;
+    const float thr = patch_threshold(eb);
     const int32_t R = (int32_t)a.L.radius;
     for (uint32_t b = threadIdx.x; b < a.L.nsym; b += blockDim.x) sh_hist[b] = 0;
 
@@ -312,7 +313,7 @@ __global__ __launch_bounds__(256) void k_quant3d(QuantArgs a) {
             delta[j][z] = del;
             const bool incap = del > -R && del < R;
             const bool o = real && !incap;
-            const bool p = real && needs_patch(v, d, h, eb);
+            const bool p = needs_patch_wave(real, v, d, h, eb, thr);
             uint16_t q = kNoSymbol;
             if (real) {
                 q = incap ? (uint16_t)(del + R) : (uint16_t)0;
@@ -372,6 +373,7 @@ __global__ __launch_bounds__(256) void k_quant2d(QuantArgs a) {
     if (ctl->status & ST_EINVAL) return;
     const float r = ctl->r, h = ctl->h;
     const double eb = ctl->eb_abs;
+    const float thr = patch_threshold(eb);
     const int32_t R = (int32_t)a.L.radius;
     for (uint32_t b = threadIdx.x; b < a.L.nsym; b += blockDim.x) sh_hist[b] = 0;
 
@@ -416,7 +418,7 @@ __global__ __launch_bounds__(256) void k_quant2d(QuantArgs a) {
         delta[y] = del;
         const bool incap = del > -R && del < R;
         const bool o = real && !incap;
-        const bool p = real && needs_patch(v, d, h, eb);
+        const bool p = needs_patch_wave(real, v, d, h, eb, thr);
         uint16_t q = kNoSymbol;
         if (real) {
             q = incap ? (uint16_t)(del + R) : (uint16_t)0;
@@ -474,6 +476,7 @@ __global__ __launch_bounds__(256) void k_quant1d(QuantArgs a) {
     if (ctl->status & ST_EINVAL) return;
     const float r = ctl->r, h = ctl->h;
     const double eb = ctl->eb_abs;
+    const float thr = patch_threshold(eb);
     const int32_t R = (int32_t)a.L.radius;
     for (uint32_t b = threadIdx.x; b < a.L.nsym; b += blockDim.x) sh_hist[b] = 0;
 
@@ -512,7 +515,7 @@ __global__ __launch_bounds__(256) void k_quant1d(QuantArgs a) {
         const bool real = pos < n;
         const bool incap = del > -R && del < R;
         const bool o = real && !incap;
-        const bool p = real && needs_patch(s_tile[16 * t + i], d[i], h, eb);
+        const bool p = needs_patch_wave(real, s_tile[16 * t + i], d[i], h, eb, thr);
         uint16_t qq = kNoSymbol;
         if (real) {
             qq = incap ? (uint16_t)(del + R) : (uint16_t)0;
