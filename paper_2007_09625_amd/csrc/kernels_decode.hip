@@ -2,15 +2,18 @@
 //
 // One wave decodes 64 consecutive subchunks, one per lane: the lane starts
 // at the subchunk's bit offset (chunk offset + prefix of subchunk bit
-// counts) and decodes every point of the subchunk with a 2^12-entry LDS
-// lookup table (longer codes by the canonical first-code rule) into an LDS
-// code buffer.  The wave then marks outliers in that buffer from the sorted
-// exception list, and reconstructs each block: the inverse of the Lorenzo
-// mixed difference is a prefix sum along every axis (Algorithm 2's cascading
-// reconstruction, reorganised), done in registers along the slow axis and
-// with cross-lane scans along the fast axes, in wrapping int32.  Values are
-// dequantized as fl32(d°) * fl32(2 eb) and written row-major; patches
-// (verbatim values) are applied last.
+// counts) and decodes every point of the subchunk with a 2^13-entry LDS
+// lookup table (longer codes by a second-level table or the canonical
+// first-code rule).  The inverse of the Lorenzo mixed difference is a prefix
+// sum along every axis (Algorithm 2's cascading reconstruction,
+// reorganised), in wrapping int32; values are dequantized as
+// fl32(d°) * fl32(2 eb) and written row-major, outliers take their deltas
+// from the exception list and patches (verbatim values) replace values last.
+//
+// Subchunks of 128 positions (the default) go through two kernels: inflate
+// into a code array, then one wave per 512-position unit reconstructs
+// (k_inflate128, k_recon).  Other subchunk sizes decode and reconstruct in
+// one kernel with an LDS code buffer (k_decode).
 #include "dqz_internal.h"
 
 namespace dqz {
