@@ -127,77 +127,77 @@ struct CanonScratch {
     uint64_t first_code[66];
     uint32_t count[66];
     uint32_t first_index[66];
+    uint32_t wave_max[16];
     uint32_t n_used;
     uint32_t max_len;
 };
 
+constexpr uint32_t kCanonGroups = kMaxSyms / 64;   // (chunk, wave) groups of 64 symbols
+constexpr uint32_t kCanonStride = kCanonGroups + 1;
+
 __device__ void canonical_order(const uint8_t *len, uint32_t ns, CanonScratch &c) {
-    // counting sort of the symbols by code length, stable in the symbol:
-    // within a wave, ballots give each symbol its rank among the wave's
-    // symbols of equal length; per-(chunk, length) counts give the rest
-    // any block of 256..1024 threads (a multiple of 64); symbol tid + B * r
+    // stable counting sort of the symbols by code length.  Symbol tid + B * r
+    // belongs to group (r, wave); the group's lanes of equal length are found
+    // from eight ballots (one per bit of the length), which give each symbol
+    // its rank within its group and lane L - 1 the group's count of length L.
+    // One wave then turns the counts into per-length offsets of the groups.
     const uint32_t tid = threadIdx.x, lane = lane_id(), w = tid / 64, B = blockDim.x, W = B / 64;
     const uint32_t nk = ns < B ? B : ns;
-    const uint32_t chunks = nk / B;
-    uint32_t *cnt = reinterpret_cast<uint32_t *>(c.xch);   // [chunks * W waves][65]
-    for (uint32_t l = tid; l < 66; l += blockDim.x) {
-        c.count[l] = 0;
-        c.first_index[l] = 0;
-        c.first_code[l] = 0;
+    const uint32_t chunks = nk / B, groups = chunks * W;   // groups <= kCanonGroups
+    uint32_t *cnt = reinterpret_cast<uint32_t *>(c.xch);   // [length - 1][group], row stride kCanonStride
+    if (tid == 0) {
+        c.count[0] = c.count[65] = 0;
+        c.first_index[0] = c.first_index[65] = 0;
+        c.first_code[0] = c.first_code[65] = 0;
     }
-    uint32_t ml = 0;
-    for (uint32_t r = 0; r < chunks; r++) {
-        const uint32_t sym = tid + B * r;
-        const uint32_t l = sym < ns ? len[sym] : 0u;
-        ml = l > ml ? l : ml;
-    }
-    ml = wave_max<uint32_t>(ml);
-    if (lane == 0) cnt[w] = ml;
-    __syncthreads();
-    uint32_t max_len = 0;
-    for (uint32_t k = 0; k < W; k++) max_len = cnt[k] > max_len ? cnt[k] : max_len;
-    __syncthreads();
-    // lengths above 64 (only reachable from damaged input) are reported through
-    // max_len and otherwise left out of the order
-    const uint32_t lmax = max_len > 64 ? 64 : max_len;
     constexpr uint32_t kChunks = kMaxSyms / 256;
-    uint32_t myrank[kChunks];
+    const uint64_t below = lanes_below(lane);
+    uint32_t myrank[kChunks], mylen[kChunks];
+    uint32_t ml = 0;
 #pragma unroll
     for (uint32_t r = 0; r < kChunks; r++) {
         myrank[r] = 0;
+        mylen[r] = 0;
         if (r >= chunks) continue;
         const uint32_t sym = tid + B * r;
         const uint32_t l = sym < ns ? len[sym] : 0u;
-        const uint64_t below = lanes_below(lane);
-        uint32_t rk = 0;
-        for (uint32_t L = 1; L <= lmax; L++) {
-            const uint64_t m = __ballot(l == L);
-            if (l == L) rk = __popcll(m & below);
-            if (lane == 0) cnt[(r * W + w) * 65 + L] = __popcll(m);
+        ml = l > ml ? l : ml;
+        uint64_t same = ~0ull, mine = ~0ull;
+        const uint32_t L = lane + 1;
+#pragma unroll
+        for (uint32_t b = 0; b < 8; b++) {
+            const uint64_t m = __ballot((l >> b) & 1u);
+            same &= ((l >> b) & 1u) ? m : ~m;
+            mine &= ((L >> b) & 1u) ? m : ~m;
         }
-        myrank[r] = rk;
+        myrank[r] = (uint32_t)__popcll(same & below);
+        mylen[r] = l;
+        cnt[lane * kCanonStride + r * W + w] = (uint32_t)__popcll(mine);
     }
-    __syncthreads();
-    // per length: exclusive prefix over the (chunk, wave) groups, in symbol order
-    const uint32_t groups = chunks * W;
-    for (uint32_t L = 1 + tid; L <= lmax; L += blockDim.x) {
-        uint32_t run = 0;
-        for (uint32_t gi = 0; gi < groups; gi++) {
-            const uint32_t v = cnt[gi * 65 + L];
-            cnt[gi * 65 + L] = run;
-            run += v;
-        }
-        c.count[L] = run;
-    }
+    ml = wave_max<uint32_t>(ml);
+    if (lane == 0) c.wave_max[w] = ml;
     __syncthreads();
     if (tid < 64) {
-        // lane l stands for length l + 1: first_index is the exclusive prefix
+        // lane l - 1 stands for length l: exclusive prefix of its row over the
+        // groups (in symbol order), then first_index is the exclusive prefix
         // of the counts; first_code[b] = sum_{j<b} count[j] << (b - j) (the
         // RFC 1951 recurrence code_b = (code_{b-1} + count_{b-1}) << 1, unrolled)
         // comes from a shift-weighted scan S_l = count_l + (S_{l-1} << 1),
         // first_code[l + 1] = S_l << 1; no partial sum exceeds 2^63 for l <= 62
+        uint32_t max_len = 0;
+        for (uint32_t k = 0; k < W; k++) max_len = c.wave_max[k] > max_len ? c.wave_max[k] : max_len;
+        uint32_t v[kCanonGroups];
+#pragma unroll
+        for (uint32_t g = 0; g < kCanonGroups; g++) v[g] = g < groups ? cnt[tid * kCanonStride + g] : 0u;
+        uint32_t run = 0;
+#pragma unroll
+        for (uint32_t g = 0; g < kCanonGroups; g++) {
+            if (g < groups) cnt[tid * kCanonStride + g] = run;
+            run += v[g];
+        }
         const uint32_t l = tid + 1;
-        const uint32_t cl = c.count[l];
+        const uint32_t cl = run;
+        c.count[l] = cl;
         const uint32_t incl = wave_incl_scan<uint32_t>(cl);
         c.first_index[l] = incl - cl;
         uint64_t S = cl;
@@ -211,18 +211,16 @@ __device__ void canonical_order(const uint8_t *len, uint32_t ns, CanonScratch &c
         if (tid == 63) { c.n_used = incl; c.max_len = max_len; }
     }
     __syncthreads();
-    for (uint32_t i = tid; i < nk; i += blockDim.x) c.key[i] = ~0ull;
-    __syncthreads();
+    // lengths above 64 (only reachable from damaged input) are reported
+    // through max_len and otherwise left out of the order
+    const uint32_t n_used = c.n_used;
 #pragma unroll
     for (uint32_t r = 0; r < kChunks; r++) {
         if (r >= chunks) continue;
-        const uint32_t sym = tid + B * r;
-        const uint32_t l = sym < ns ? len[sym] : 0u;
-        if (l && l <= lmax) {
-            const uint32_t pos = c.first_index[l] + cnt[(r * W + w) * 65 + l] + myrank[r];
-            c.key[pos] = ((uint64_t)l << 16) | sym;
-        }
+        const uint32_t sym = tid + B * r, l = mylen[r];
+        if (l && l <= 64) c.key[c.first_index[l] + cnt[(l - 1) * kCanonStride + r * W + w] + myrank[r]] = ((uint64_t)l << 16) | sym;
     }
+    for (uint32_t i = n_used + tid; i < nk; i += B) c.key[i] = ~0ull;
     __syncthreads();
 }
 
@@ -247,23 +245,39 @@ struct BookLds {
     unsigned long long total_bits;
 };
 
-// Number of entries <= t in the ascending array A[0, m) (a prefix), found
-// by one wave with 64-way probes: about log64(m) dependent LDS reads.  The
-// probe positions are uniform arithmetic, so no lane exchange is needed.
-__device__ __forceinline__ uint32_t wave_count_le(const uint32_t *A, uint32_t m, uint32_t t, uint32_t lane) {
-    uint32_t lo = 0, hi = m;   // the count lies in [lo, hi]
-    while (hi - lo > 64) {
-        const uint64_t span = hi - lo;
-        const uint32_t idx = lo + (uint32_t)((span * (lane + 1)) / 65);   // strictly increasing in lane
-        const uint32_t c = (uint32_t)__popcll(__ballot(A[idx] <= t));
-        const uint32_t nlo = c ? lo + (uint32_t)((span * c) / 65) + 1 : lo;
-        const uint32_t nhi = c < 64 ? lo + (uint32_t)((span * (c + 1)) / 65) : hi;
-        lo = nlo;
-        hi = nhi;
+// Numbers of entries <= t in the ascending arrays A[0, ma) and B[0, mb),
+// found by one wave with 64-way probes of both arrays at once: about
+// log64(m) dependent LDS reads.  The probe positions are uniform arithmetic,
+// so no lane exchange is needed.
+__device__ __forceinline__ void wave_count_le2(const uint32_t *A, uint32_t ma, const uint32_t *B, uint32_t mb,
+                                               uint32_t t, uint32_t lane, uint32_t &ca, uint32_t &cb) {
+    uint32_t loa = 0, hia = ma, lob = 0, hib = mb;   // each count lies in [lo, hi]
+    while (hia - loa > 64 || hib - lob > 64) {
+        const uint32_t sa = hia - loa, sb = hib - lob;
+        const uint32_t ia = loa + (sa * (lane + 1)) / 65, ib = lob + (sb * (lane + 1)) / 65;
+        const uint32_t va = A[sa > 64 ? ia : 0], vb = B[sb > 64 ? ib : 0];
+        const uint32_t na = (uint32_t)__popcll(__ballot(va <= t)), nb = (uint32_t)__popcll(__ballot(vb <= t));
+        if (sa > 64) {
+            const uint32_t lo = na ? loa + (sa * na) / 65 + 1 : loa;
+            hia = na < 64 ? loa + (sa * (na + 1)) / 65 : hia;
+            loa = lo;
+        }
+        if (sb > 64) {
+            const uint32_t lo = nb ? lob + (sb * nb) / 65 + 1 : lob;
+            hib = nb < 64 ? lob + (sb * (nb + 1)) / 65 : hib;
+            lob = lo;
+        }
     }
-    const uint32_t idx = lo + lane;
-    return lo + (uint32_t)__popcll(__ballot(idx < hi && A[idx < hi ? idx : lo] <= t));
+    const uint32_t ia = loa + lane, ib = lob + lane;
+    const uint32_t va = A[ia < hia ? ia : 0], vb = B[ib < hib ? ib : 0];
+    ca = loa + (uint32_t)__popcll(__ballot(ia < hia && va <= t));
+    cb = lob + (uint32_t)__popcll(__ballot(ib < hib && vb <= t));
 }
+
+// LDS read at a clamped index: loads that may fall past a queue's end are
+// issued unconditionally (their values are discarded), so independent
+// reads go out together
+__device__ __forceinline__ uint32_t ldc(const uint32_t *A, uint32_t i) { return A[i < kMaxSyms ? i : kMaxSyms - 1]; }
 
 __global__ __launch_bounds__(kBookThreads) void k_codebook(const uint32_t *__restrict__ hist, Ctl *ctl,
                                                            uint64_t *__restrict__ book, uint32_t *__restrict__ book32,
@@ -335,8 +349,8 @@ __global__ __launch_bounds__(kBookThreads) void k_codebook(const uint32_t *__res
         for (;;) {
             if ((n - la) + (ic - ib) <= 1) break;
             // T, from the first two items of each queue
-            const uint32_t l0 = la < n ? s.leaf_w[la] : 0u, l1 = la + 1 < n ? s.leaf_w[la + 1] : 0u;
-            const uint32_t i0 = ib < ic ? s.int_w[ib] : 0u, i1 = ib + 1 < ic ? s.int_w[ib + 1] : 0u;
+            const uint32_t l0 = ldc(s.leaf_w, la), l1 = ldc(s.leaf_w, la + 1);
+            const uint32_t i0 = ldc(s.int_w, ib), i1 = ldc(s.int_w, ib + 1);
             uint32_t Tw;
             {
                 uint32_t a = 0, b = 0, t = 0;
@@ -352,43 +366,62 @@ __global__ __launch_bounds__(kBookThreads) void k_codebook(const uint32_t *__res
             }
             // items of weight <= T: prefixes of both sorted queues (each wave
             // finds them itself, so no barrier is needed)
-            uint32_t nl = wave_count_le(s.leaf_w + la, n - la, Tw, lane);
-            uint32_t ni = wave_count_le(s.int_w + ib, ic - ib, Tw, lane);
+            uint32_t nl, ni;
+            wave_count_le2(s.leaf_w + la, n - la, s.int_w + ib, ic - ib, Tw, lane, nl, ni);
             if ((nl + ni) & 1u) {   // odd: the last item of the merged order waits
-                const bool int_last = ni > 0 && (nl == 0 || s.int_w[ib + ni - 1] >= s.leaf_w[la + nl - 1]);
+                const uint32_t lastl = ldc(s.leaf_w, la + nl - 1), lasti = ldc(s.int_w, ib + ni - 1);
+                const bool int_last = ni > 0 && (nl == 0 || lasti >= lastl);
                 if (int_last) ni--; else nl--;
             }
             // the round's items in the stable merge of the two queues (leaf
             // first on equal weight), paired in order: thread tid takes merged
             // positions [d0, d0 + c), c even, found by a merge-path split
-            // (binary search over the shorter queue), then merges them in turn
+            // (4-way search over the shorter queue), then makes their nodes
             const uint32_t m = nl + ni;
-            const uint32_t c = 2 * ((m + 2 * T - 1) / (2 * T));
+            const uint32_t c = 2 * ((m + 2 * kBookThreads - 1) / (2 * kBookThreads));
             const uint32_t d0 = tid * c;
             if (d0 < m) {
-                // i leaves + j internals precede position d0: the largest i with
-                // leaf[i-1] <= int[d0-i] (or no such comparison)
+                // i leaves + (d0 - i) internals precede position d0: the largest
+                // i with leaf[i-1] <= int[d0-i] (or no such comparison)
                 uint32_t lo = d0 > ni ? d0 - ni : 0u, hi = d0 < nl ? d0 : nl;
                 while (lo < hi) {
-                    const uint32_t mid = (lo + hi + 1) >> 1, j = d0 - mid;
-                    if (j >= ni || s.leaf_w[la + mid - 1] <= s.int_w[ib + j]) lo = mid; else hi = mid - 1;
-                }
-                uint32_t i = lo, j = d0 - lo, wa = 0;
-                const uint32_t d1 = d0 + c < m ? d0 + c : m;
-                for (uint32_t r = d0; r < d1; r++) {
-                    const bool leaf = i < nl && (j >= ni || s.leaf_w[la + i] <= s.int_w[ib + j]);
-                    uint32_t w;
-                    if (leaf) {
-                        w = s.leaf_w[la + i];
-                        s.parent_leaf[la + i] = (uint16_t)(ic + r / 2);
-                        i++;
-                    } else {
-                        w = s.int_w[ib + j];
-                        s.parent_int[ib + j] = (uint16_t)(ic + r / 2);
-                        j++;
+                    const uint32_t span = hi - lo;
+                    uint32_t p[3];
+                    bool ok[3];
+#pragma unroll
+                    for (int k = 0; k < 3; k++) p[k] = lo + (span * (k + 1) + 3) / 4;
+                    uint32_t lv[3], iv[3];
+#pragma unroll
+                    for (int k = 0; k < 3; k++) {
+                        lv[k] = ldc(s.leaf_w, la + p[k] - 1);
+                        iv[k] = ldc(s.int_w, ib + d0 - p[k]);
                     }
-                    if (r & 1u) s.int_w[ic + r / 2] = wa + w;
-                    else wa = w;
+#pragma unroll
+                    for (int k = 0; k < 3; k++) ok[k] = d0 - p[k] >= ni || lv[k] <= iv[k];
+                    if (ok[2]) lo = p[2];
+                    else if (ok[1]) { lo = p[1]; hi = p[2] - 1; }
+                    else if (ok[0]) { lo = p[0]; hi = p[1] - 1; }
+                    else hi = p[0] - 1;
+                }
+                uint32_t i = lo, j = d0 - lo;
+                const uint32_t d1 = d0 + c < m ? d0 + c : m;
+                for (uint32_t r = d0; r < d1; r += 2) {
+                    // one node from merged positions r, r + 1 (m is even)
+                    const uint32_t L0 = ldc(s.leaf_w, la + i), L1 = ldc(s.leaf_w, la + i + 1);
+                    const uint32_t I0 = ldc(s.int_w, ib + j), I1 = ldc(s.int_w, ib + j + 1);
+                    const uint16_t node = (uint16_t)(ic + r / 2);
+                    const bool f0 = i < nl && (j >= ni || L0 <= I0);
+                    const uint32_t w0 = f0 ? L0 : I0;
+                    if (f0) s.parent_leaf[la + i] = node; else s.parent_int[ib + j] = node;
+                    i += f0 ? 1u : 0u;
+                    j += f0 ? 0u : 1u;
+                    const uint32_t Lh = f0 ? L1 : L0, Ih = f0 ? I0 : I1;
+                    const bool f1 = i < nl && (j >= ni || Lh <= Ih);
+                    const uint32_t w1 = f1 ? Lh : Ih;
+                    if (f1) s.parent_leaf[la + i] = node; else s.parent_int[ib + j] = node;
+                    i += f1 ? 1u : 0u;
+                    j += f1 ? 0u : 1u;
+                    s.int_w[ic + r / 2] = w0 + w1;
                 }
             }
             la += nl;
