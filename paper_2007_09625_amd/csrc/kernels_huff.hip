@@ -25,13 +25,55 @@ namespace dqz {
 constexpr uint32_t kBookThreads = 256;
 constexpr uint32_t kTableThreads = 1024;   // decoding tables: one workgroup fills the 8192-entry table
 
-// Bitonic sort of 256 * E 64-bit keys held E per thread (thread t holds
+// Value of lane (lane ^ D) within the wave: DPP quad permutes for D = 1, 2,
+// row shifts for 4, a row rotate for 8, the row-pair and half-wave swaps
+// for 16 and 32 (all in the VALU, no LDS round trip).
+template <uint32_t D>
+__device__ __forceinline__ uint32_t xor_lane32(uint32_t v, uint32_t lane) {
+    static_assert(D == 1 || D == 2 || D == 4 || D == 8 || D == 16 || D == 32, "lane distance");
+    if (D == 1) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+    if (D == 2) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+    if (D == 4) {
+        const uint32_t up = (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x104, 0xF, 0xF, false);   // row_shl:4
+        const uint32_t dn = (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x114, 0xF, 0xF, false);   // row_shr:4
+        return (lane & 4u) ? dn : up;
+    }
+    if (D == 8) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x128, 0xF, 0xF, false);   // row_ror:8
+    if (D == 16) {
+        const auto p = __builtin_amdgcn_permlane16_swap(v, v, false, false);
+        return (lane & 16u) ? p[0] : p[1];
+    }
+    const auto p = __builtin_amdgcn_permlane32_swap(v, v, false, false);
+    return (lane & 32u) ? p[0] : p[1];
+}
+template <uint32_t D>
+__device__ __forceinline__ uint64_t xor_lane64(uint64_t v, uint32_t lane) {
+    const uint32_t lo = xor_lane32<D>((uint32_t)v, lane), hi = xor_lane32<D>((uint32_t)(v >> 32), lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+template <uint32_t D>
+__device__ __forceinline__ uint32_t xor_lane_t(uint32_t v, uint32_t lane) { return xor_lane32<D>(v, lane); }
+template <uint32_t D>
+__device__ __forceinline__ uint64_t xor_lane_t(uint64_t v, uint32_t lane) { return xor_lane64<D>(v, lane); }
+template <typename K>
+__device__ __forceinline__ K xor_lane(K v, uint32_t lane, uint32_t d) {   // d a compile-time constant
+    switch (d) {
+    case 1: return xor_lane_t<1>(v, lane);
+    case 2: return xor_lane_t<2>(v, lane);
+    case 4: return xor_lane_t<4>(v, lane);
+    case 8: return xor_lane_t<8>(v, lane);
+    case 16: return xor_lane_t<16>(v, lane);
+    default: return xor_lane_t<32>(v, lane);
+    }
+}
+
+// Bitonic sort of 256 * E keys (32- or 64-bit) held E per thread (thread t holds
 // elements t*E .. t*E + E - 1).  Partners within a thread are compared in
-// registers, partners within a wave through cross-lane shuffles, and only
+// registers, partners within a wave through cross-lane exchanges, and only
 // the strides spanning waves go through LDS (`xch`, 256 * E entries).  Every
 // loop has a compile-time trip count, so register indices stay static.
-template <int E>
-__device__ __forceinline__ void sort_keys(uint64_t (&k)[E], uint64_t *xch) {
+template <int E, typename K>
+__device__ __forceinline__ void sort_keys(K (&k)[E], K *xch) {
     constexpr uint32_t NS = 256u * E;
     const uint32_t t = threadIdx.x;
 #pragma unroll
@@ -44,16 +86,16 @@ __device__ __forceinline__ void sort_keys(uint64_t (&k)[E], uint64_t *xch) {
                     if (r & j) continue;
                     const uint32_t e = t * E + r;
                     const bool asc = (e & kk) == 0;
-                    const uint64_t a = k[r], b = k[r | j];
+                    const K a = k[r], b = k[r | j];
                     if ((a > b) == asc) { k[r] = b; k[r | j] = a; }
                 }
             } else if (j < 64u * E) {
 #pragma unroll
                 for (uint32_t r = 0; r < (uint32_t)E; r++) {
                     const uint32_t e = t * E + r;
-                    const uint64_t o = __shfl_xor(k[r], (int)(j / E), 64);
+                    const K o = xor_lane(k[r], t & 63u, j / E);
                     const bool lower = (e & j) == 0, asc = (e & kk) == 0;
-                    const uint64_t mn = o < k[r] ? o : k[r], mx = o < k[r] ? k[r] : o;
+                    const K mn = o < k[r] ? o : k[r], mx = o < k[r] ? k[r] : o;
                     k[r] = (lower == asc) ? mn : mx;
                 }
             } else {
@@ -63,9 +105,9 @@ __device__ __forceinline__ void sort_keys(uint64_t (&k)[E], uint64_t *xch) {
 #pragma unroll
                 for (uint32_t r = 0; r < (uint32_t)E; r++) {
                     const uint32_t e = t * E + r;
-                    const uint64_t o = xch[e ^ j];
+                    const K o = xch[e ^ j];
                     const bool lower = (e & j) == 0, asc = (e & kk) == 0;
-                    const uint64_t mn = o < k[r] ? o : k[r], mx = o < k[r] ? k[r] : o;
+                    const K mn = o < k[r] ? o : k[r], mx = o < k[r] ? k[r] : o;
                     k[r] = (lower == asc) ? mn : mx;
                 }
                 __syncthreads();
@@ -74,36 +116,37 @@ __device__ __forceinline__ void sort_keys(uint64_t (&k)[E], uint64_t *xch) {
     }
 }
 
-// Sort `ns` keys produced by make(i) (i < ns; padding slots get ~0) into
-// out[0 .. max(ns, 256)).  ns is a power of two <= kMaxSyms.
-template <typename F>
-__device__ __forceinline__ void sort_into(uint32_t ns, uint64_t *out, uint64_t *xch, F make) {
+// Sort `ns` keys of type K produced by make(i) (i < ns; padding slots get
+// ~0) and store out(i, key) for i < max(ns, 256).  ns is a power of two <=
+// kMaxSyms.
+template <typename K, typename F, typename G>
+__device__ __forceinline__ void sort_into(uint32_t ns, K *xch, F make, G out) {
     const uint32_t t = threadIdx.x;
     if (ns <= 256) {
-        uint64_t k[1] = {t < ns ? make(t) : ~0ull};
+        K k[1] = {t < ns ? make(t) : (K)~(K)0};
         sort_keys<1>(k, xch);
-        out[t] = k[0];
+        out(t, k[0]);
     } else if (ns == 512) {
-        uint64_t k[2];
+        K k[2];
 #pragma unroll
         for (int r = 0; r < 2; r++) k[r] = make(t * 2 + r);
         sort_keys<2>(k, xch);
 #pragma unroll
-        for (int r = 0; r < 2; r++) out[t * 2 + r] = k[r];
+        for (int r = 0; r < 2; r++) out(t * 2 + r, k[r]);
     } else if (ns == 1024) {
-        uint64_t k[4];
+        K k[4];
 #pragma unroll
         for (int r = 0; r < 4; r++) k[r] = make(t * 4 + r);
         sort_keys<4>(k, xch);
 #pragma unroll
-        for (int r = 0; r < 4; r++) out[t * 4 + r] = k[r];
+        for (int r = 0; r < 4; r++) out(t * 4 + r, k[r]);
     } else {
-        uint64_t k[8];
+        K k[8];
 #pragma unroll
         for (int r = 0; r < 8; r++) k[r] = make(t * 8 + r);
         sort_keys<8>(k, xch);
 #pragma unroll
-        for (int r = 0; r < 8; r++) out[t * 8 + r] = k[r];
+        for (int r = 0; r < 8; r++) out(t * 8 + r, k[r]);
     }
     __syncthreads();
 }
@@ -230,6 +273,7 @@ __device__ void canonical_order(const uint8_t *len, uint32_t ns, CanonScratch &c
 struct BookLds {
     CanonScratch canon;                  // key / xch double as the leaf sort buffers
     uint32_t leaf_w[kMaxSyms];
+    uint32_t wave_fmax[kBookThreads / 64];
     uint16_t leaf_sym[kMaxSyms];
     uint32_t int_w[kMaxSyms];
     uint32_t merged_w[kMaxSyms];
@@ -303,11 +347,15 @@ __global__ __launch_bounds__(kBookThreads) void k_codebook(const uint32_t *__res
             const uint32_t i = tid + kBookThreads * k;
             f[k] = (i < ns) ? hist[i] : 0u;
         }
+        uint32_t fm = 0;
 #pragma unroll
         for (uint32_t k = 0; k < kPer; k++) {
             const uint32_t i = tid + kBookThreads * k;
             if (i < ns) { s.hist[i] = f[k]; s.len[i] = 0; }
+            fm = f[k] > fm ? f[k] : fm;
         }
+        fm = wave_max<uint32_t>(fm);
+        if (lane_id() == 0) s.wave_fmax[tid / 64] = fm;
     }
     if (tid == 0) { s.n = 0; s.total_bits = 0; s.nl[0] = s.nl[1] = s.ni[0] = s.ni[1] = 0; }
     __syncthreads();
@@ -318,10 +366,26 @@ __global__ __launch_bounds__(kBookThreads) void k_codebook(const uint32_t *__res
         if (tid == 0) { ctl->exc_total = exc; ctl->out_total = out; }
     }
     if (tid == 0) ctl->phase[1] = wall_clock64();
-    // leaves with nonzero frequency sorted by (frequency, symbol)
-    sort_into(ns, s.canon.key, s.canon.xch, [&](uint32_t i) -> uint64_t {
-        return (i < ns && s.hist[i]) ? (((uint64_t)s.hist[i] << 16) | i) : ~0ull;
-    });
+    // leaves with nonzero frequency sorted by (frequency, symbol), on 32-bit
+    // keys (frequency << symbol bits | symbol) when they fit, else 64-bit;
+    // sorted entries go to key[] as (frequency << 16) | symbol
+    {
+        uint32_t fmax = 0;
+        for (uint32_t k = 0; k < kBookThreads / 64; k++) fmax = s.wave_fmax[k] > fmax ? s.wave_fmax[k] : fmax;
+        const uint32_t sb = 32u - __clz(ns - 1u);   // symbol bits (ns is a power of two >= 2)
+        uint64_t *key = s.canon.key;
+        if (sb < 32u && (uint64_t)fmax + 1u < (1ull << (32u - sb))) {
+            sort_into<uint32_t>(ns, reinterpret_cast<uint32_t *>(s.canon.xch), [&](uint32_t i) -> uint32_t {
+                return (i < ns && s.hist[i]) ? ((s.hist[i] << sb) | i) : ~0u;
+            }, [&](uint32_t i, uint32_t k) {
+                key[i] = k == ~0u ? ~0ull : (((uint64_t)(k >> sb) << 16) | (k & ((1u << sb) - 1u)));
+            });
+        } else {
+            sort_into<uint64_t>(ns, s.canon.xch, [&](uint32_t i) -> uint64_t {
+                return (i < ns && s.hist[i]) ? (((uint64_t)s.hist[i] << 16) | i) : ~0ull;
+            }, [&](uint32_t i, uint64_t k) { key[i] = k; });
+        }
+    }
     const uint32_t nk = ns < 256 ? 256 : ns;
     for (uint32_t i = tid; i < nk; i += T) {
         const uint64_t k = s.canon.key[i];
@@ -372,6 +436,10 @@ __global__ __launch_bounds__(kBookThreads) void k_codebook(const uint32_t *__res
                 const uint32_t lastl = ldc(s.leaf_w, la + nl - 1), lasti = ldc(s.int_w, ib + ni - 1);
                 const bool int_last = ni > 0 && (nl == 0 || lasti >= lastl);
                 if (int_last) ni--; else nl--;
+            }
+            if (nl + ni < 2) {   // cannot happen for sorted queues: stop rather than spin
+                if (tid == 0) atomicOr(&ctl->status, ST_EINTERNAL);
+                break;
             }
             // the round's items in the stable merge of the two queues (leaf
             // first on equal weight), paired in order: thread tid takes merged

@@ -249,3 +249,18 @@ def test_parity_long_codes(ctx, k):
     x = _fibonacci_field(k, seed=k)
     arc = _check(ctx, x, 0.5, 0, radius=64)
     assert au.header(arc)["max_len"] == k - 1
+
+
+def test_parity_wide_sort_keys(ctx):
+    """A symbol count of 2^21 or more with 2048 symbols (radius 1024) leaves no
+    room for (count, symbol) in 32 bits: the codebook sorts its leaves on
+    64-bit keys.  Sparse integer spikes on a zero field at absolute eb 0.5."""
+    rng = np.random.default_rng(21)
+    n = (1 << 21) + 300_000
+    x = np.zeros(n, np.float32)
+    idx = rng.choice(n, n // 100, replace=False)
+    x[idx] = rng.integers(-400, 400, idx.size).astype(np.float32)
+    arc = _check(ctx, x, 0.5, 0, radius=1024)
+    import oracle
+    _, _, freq, _ = oracle.stages(x, 0.5, 0, 1024)
+    assert int(freq.max()) >= 1 << 21
