@@ -38,8 +38,7 @@ WORKLOADS = {
 
 
 KERNEL_OF_STAGE = {"range_eb": ("k_minmax", "kernels_quant.hip"), "quantize": ("k_quant", "kernels_quant.hip"),
-                   "encode_count": ("k_enc_count", "kernels_encode.hip"),
-                   "encode_pack": ("k_enc_pack", "kernels_encode.hip"),
+                   "encode": ("k_enc_stream", "kernels_encode.hip"),
                    "inflate": ("k_inflate128", "kernels_decode.hip"), "reconstruct": ("k_recon", "kernels_decode.hip")}
 
 
@@ -195,8 +194,7 @@ def main() -> int:
     algo = {
         "range_eb": 4.0 * n,
         "quantize": 4.0 * n + 2.0 * padded + exc_bytes,
-        "encode_count": 2.0 * padded,
-        "encode_pack": 2.0 * padded + stream_bytes,
+        "encode": 2.0 * padded + stream_bytes + 2.0 * n_sub + 8.0 * n_chunks,
         "inflate": stream_bytes + 2.0 * n_sub + 8.0 * n_chunks + 2.0 * padded,
         "reconstruct": 2.0 * padded + exc_bytes + 4.0 * n + 4.0 * (n_units + 1),
     }

@@ -144,7 +144,7 @@ const char *dqz_ctx_last_error(const dqz_ctx *ctx);
  *   compress   (which = 0): [0] init, [1] value range + eb (0 in absolute
  *              mode), [2] dual-quantization + histogram + exceptions, [3] their
  *              tile scan (and the histogram sum), [4] codebook + header,
- *              [5] code-width count + tile scan, [6] encode + deflate (packing)
+ *              [5] encode + deflate (widths, tile offsets, packing, one pass)
  *   decompress (which = 1): [0] decoding tables (and, for 128-position
  *              subchunks, the exception index), [1] inflate (other subchunk
  *              sizes: inflate + reconstruct), [2] reconstruct (128-position

@@ -153,9 +153,9 @@ struct WsLayout {
     uint64_t ctl, tab, hist, zero_end;
     uint64_t hist_sum, book, book32, parts;
     uint64_t qval[2], qexcl[2], qseg_total[2];
-    uint64_t eval, eexcl, eseg_total;
+    uint64_t eflag;
     uint64_t stage, codes, qws, unit_exc, total;
-    uint32_t n_segs_q, n_segs_e, cap;
+    uint32_t n_segs_q, cap;
 };
 
 WsLayout ws_layout(const Plan &P, bool compress, uint32_t cap) {
@@ -166,7 +166,6 @@ WsLayout ws_layout(const Plan &P, bool compress, uint32_t cap) {
         return at;
     };
     w.n_segs_q = (P.tiles_q + kSegTiles - 1) / kSegTiles;
-    w.n_segs_e = (P.tiles_e + kSegTiles - 1) / kSegTiles;
     w.cap = cap;
     uint64_t cur = 0;
     w.ctl = take(cur, sizeof(Ctl));
@@ -181,6 +180,7 @@ WsLayout ws_layout(const Plan &P, bool compress, uint32_t cap) {
     }
     w.hist = take(cur, 4ull * kHistReplicas * P.L.nsym);
     w.hist_sum = take(cur, 4ull * P.L.nsym);   // zeroed too: an empty field never writes it
+    w.eflag = take(cur, 8ull * P.tiles_e);      // encode look-back states start at zero
     w.zero_end = align_up(cur, 256);
     w.book = take(cur, 8ull * P.L.nsym);
     w.book32 = take(cur, 4ull * P.L.nsym);
@@ -190,9 +190,6 @@ WsLayout ws_layout(const Plan &P, bool compress, uint32_t cap) {
         w.qexcl[k] = take(cur, 4ull * P.tiles_q);
         w.qseg_total[k] = take(cur, 8ull * w.n_segs_q);
     }
-    w.eval = take(cur, 4ull * P.tiles_e);
-    w.eexcl = take(cur, 4ull * P.tiles_e);
-    w.eseg_total = take(cur, 8ull * w.n_segs_e);
     w.stage = take(cur, 8ull * cap * P.tiles_q);
     w.codes = take(cur, 2ull * P.g.padded);
     w.total = align_up(cur, 256);
@@ -449,15 +446,7 @@ dqz_status dqz_compress(dqz_ctx *ctx, const float *d_field, const dqz_shape *sha
         eb.cap = cap;
         eb.qscan = qs;
         eb.n_tiles_q = P.tiles_q;
-        TileScan &es = eb.escan;
-        es.val[0] = reinterpret_cast<uint32_t *>(ws + W.eval);
-        es.excl[0] = reinterpret_cast<uint32_t *>(ws + W.eexcl);
-        es.seg_total[0] = reinterpret_cast<uint64_t *>(ws + W.eseg_total);
-        es.val[1] = es.excl[1] = nullptr;
-        es.seg_total[1] = nullptr;
-        es.n_tiles = P.tiles_e;
-        es.n_segs = W.n_segs_e;
-        es.nvals = 1;
+        eb.eflag = reinterpret_cast<uint64_t *>(ws + W.eflag);
 
         ctx->ev_ready[0] = false;
         mark(ctx, 0, 0, s);
@@ -473,10 +462,8 @@ dqz_status dqz_compress(dqz_ctx *ctx, const float *d_field, const dqz_shape *sha
         launch_codebook(s, P.g, P.L, ctl, qb.hist_sum, book, book32, arc, params->eb_mode, params->eb, qs,
                         ctx->d_hctl);
         mark(ctx, 0, 5, s);
-        launch_encode_count(s, P.g, P.L, ctl, eb, arc);
+        launch_encode(s, P.g, P.L, ctl, ctx->d_hctl, eb, arc);
         mark(ctx, 0, 6, s);
-        launch_encode_pack(s, P.g, P.L, ctl, eb, arc);
-        mark(ctx, 0, 7, s);
         HIP_TRY(ctx, hipGetLastError());
         HIP_TRY(ctx, wait_stream(s));
         ctx->ev_ready[0] = ctx->timing;

@@ -281,13 +281,11 @@ struct EncodeBufs {
     const uint2 *stage;    // quantize staging
     uint32_t cap;
     TileScan qscan;        // offsets of the staged exceptions
-    TileScan escan;        // bits per encode tile
+    uint64_t *eflag;       // per encode tile: look-back state (zeroed before the launch)
     uint32_t n_tiles_q;
 };
-void launch_encode_count(hipStream_t s, const Geom &g, const Layout &L, Ctl *ctl, const EncodeBufs &b,
-                         uint8_t *archive);
-void launch_encode_pack(hipStream_t s, const Geom &g, const Layout &L, Ctl *ctl, const EncodeBufs &b,
-                        uint8_t *archive);
+void launch_encode(hipStream_t s, const Geom &g, const Layout &L, Ctl *ctl, Ctl *hctl, const EncodeBufs &b,
+                   uint8_t *archive);
 uint32_t encode_tiles(const Geom &g);
 void launch_decode_tables(hipStream_t s, const Layout &L, const uint8_t *archive, uint32_t max_len_hdr,
                           DecodeTables *tab, uint32_t *hstatus, uint32_t n_exc, uint32_t *unit_exc,

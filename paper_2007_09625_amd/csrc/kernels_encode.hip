@@ -2,22 +2,36 @@
 //
 // The paper encodes each symbol to a fixed-length (code, width) word in one
 // fine-grained pass and then concatenates the words chunk by chunk with one
-// thread per chunk.  Here the stream is produced by two tiled passes over
-// the code array (tile = kTile padded positions, one workgroup per tile):
+// thread per chunk.  Here one launch, k_enc_stream, produces the bit-dense
+// stream in a single pass over the code array (tile = kTile padded
+// positions, one workgroup per tile):
 //
-//   k_enc_count  code widths from the LDS length table -> subchunk bit
-//                counts (written to the archive) and the tile's bit count
-//                (scanned by k_seg_scan); the same launch copies the
-//                quantize tiles' staged exception records to their final
-//                place and clears the stream words.
-//   k_enc_pack   the tile's global bit offset is now known: look codes up in
-//                an LDS copy of the codebook (32-bit codewords when every
-//                code fits in 24 bits, the paper's adaptive representation,
-//                else 64-bit), scan widths across the workgroup, OR the
-//                codewords into an LDS word buffer and write it out as one
-//                contiguous run; the first and last words, shared with the
-//                neighbouring tiles, are merged with atomic OR.  Chunk
-//                offsets that fall inside the tile are written here.
+//   - workgroup b codes tile b.  Workgroups go to the XCDs round-robin and
+//     each XCD starts its own in order, so the lowest unfinished tile always
+//     holds a slot and waits on nothing unfinished: the look-back below
+//     always ends (its polls are bounded all the same, an overrun being
+//     reported as an internal error).  A shared tile counter would cost a
+//     same-address atomic per tile, and those serialize across the chip;
+//   - code widths from an LDS copy of the codebook (32-bit codewords when
+//     every code fits in 24 bits, the paper's adaptive representation, else
+//     64-bit) give the subchunk bit counts (written to the archive) and the
+//     tile's bit count;
+//   - the tile's stream offset comes from a decoupled look-back over one
+//     64-bit word per tile holding (state, value): the tile publishes its
+//     own count at once, then adds the counts of its predecessors back to
+//     the nearest one that has published its inclusive prefix, and
+//     publishes its own inclusive prefix.  The words are read and written
+//     with device-scope atomics only (no fences), so nothing else in
+//     memory has to become visible early;
+//   - the codewords are ORed into an LDS word buffer and leave as one
+//     contiguous run.  A stream word belongs to the tile in which its first
+//     bit lies: the tile leaves out a first word begun by an earlier tile and
+//     completes its last word with the first bits of the stream after it
+//     (encoded from the following codes), so every word is written once,
+//     whole, and the stream needs no clearing.
+//
+// The same launch copies the quantize tiles' staged exception records to
+// their final place and writes the chunk offsets.
 #include "dqz_internal.h"
 
 namespace dqz {
@@ -26,6 +40,7 @@ struct EncArgs {
     Geom g;
     Layout L;
     Ctl *ctl;
+    Ctl *hctl;        // the host's readback block: errors found here are reported there too
     EncodeBufs b;
     uint8_t *archive;
     uint32_t n_tiles_e;
@@ -70,94 +85,107 @@ __device__ __forceinline__ void load_codes(const EncArgs &a, uint64_t my0, uint1
 }
 
 // ---------------------------------------------------------------------------
-// pass 1
+// tile prefix states: one u64 per tile (zeroed before the launch), the top
+// two bits say what the low 62 hold
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_enc_count(EncArgs a) {
-    __shared__ uint8_t s_len[kMaxSyms];
-    __shared__ uint32_t s_sub[kTile / 32];
-    __shared__ uint64_t s_scan[10];
-    Ctl *ctl = a.ctl;
-    if (ctl->status & kBadStatus) return;
-    const uint32_t tid = threadIdx.x, t = blockIdx.x;
-    // the tile's codes are in flight during the copies below and while the
-    // length table goes to LDS
-    const uint64_t p0 = (uint64_t)t * kTile;
-    const uint64_t my0 = p0 + (uint64_t)kEncPer * tid;
-    uint16_t q[kEncPer];
-    if (t < a.n_tiles_e) load_codes(a, my0, q);
+constexpr uint64_t kAggregate = 1ull << 62;   // the tile's own bit count
+constexpr uint64_t kInclusive = 2ull << 62;   // bits of all tiles up to and including this one
+constexpr uint64_t kValMask = (1ull << 62) - 1;
+constexpr uint32_t kSpinLimit = 1u << 20;     // polls before a missing predecessor is an internal error
 
-    // staged exception records of quantize tile t -> archive
-    if (t < a.b.n_tiles_q) {
-        uint32_t cnt = a.b.qscan.val[0][t];
-        if (cnt > a.b.cap) cnt = a.b.cap;   // overflowed: the host compresses again with full staging
-        const uint64_t off = tile_offset(a.b.qscan, 0, t, s_scan);
-        uint2 *dst = reinterpret_cast<uint2 *>(a.archive + a.L.off_exc) + off;
-        const uint2 *src = a.b.stage + (uint64_t)t * a.b.cap;
-        for (uint32_t i = tid; i < cnt; i += 256) dst[i] = src[i];
-    }
-    // clear the stream words (the packing pass ORs the tile edges)
-    {
-        uint32_t *stream = reinterpret_cast<uint32_t *>(a.archive + ctl->off_str);
-        const uint64_t words = ctl->n_words;
-        for (uint64_t i = (uint64_t)t * 256 + tid; i < words; i += (uint64_t)gridDim.x * 256) stream[i] = 0u;
-    }
-    if (t >= a.n_tiles_e) return;
-
-    for (uint32_t i = tid; i < a.L.nsym; i += 256) s_len[i] = a.archive[a.L.off_len + i];
-    for (uint32_t i = tid; i < kTile / 32; i += 256) s_sub[i] = 0;
-    __syncthreads();
-    uint32_t my_bits = 0;
-#pragma unroll
-    for (uint32_t i = 0; i < kEncPer; i++)
-        if (q[i] != kNoSymbol) my_bits += s_len[q[i]];
-    // subchunk sums (a thread's positions never straddle a subchunk)
-    if (my_bits) atomicAdd(&s_sub[(kEncPer * tid) >> a.L.sub_shift], my_bits);
-    uint64_t tile_bits;
-    (void)block_excl_scan256(my_bits, s_scan, &tile_bits);
-    const uint32_t sub_per_tile = kTile >> a.L.sub_shift;
-    const uint64_t sub0 = p0 >> a.L.sub_shift;
-    for (uint32_t j = tid; j < sub_per_tile; j += 256) {
-        const uint64_t s = sub0 + j;
-        if (s < a.L.n_sub) {
-            const uint32_t v = s_sub[j];
-            uint8_t *dst = a.archive + a.L.off_sub + 2ull * s;
-            dst[0] = (uint8_t)v;
-            dst[1] = (uint8_t)(v >> 8);
-        }
-    }
-    tile_publish(a.b.escan, t, (uint32_t)tile_bits, 0u);
+__device__ __forceinline__ uint64_t flag_load(const uint64_t *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void flag_store(uint64_t *p, uint64_t v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// ---------------------------------------------------------------------------
-// pass 2
-// ---------------------------------------------------------------------------
-// One packing pass over PER consecutive positions per thread starting at
-// padded position p0 + PER * tid, the pass's first bit at stream bit `base`.
-// The thread's codewords are built MSB-first in a 64-bit register (current
-// word in bits 63..32); words wholly inside the thread's bit range are stored
-// plainly into the LDS word buffer, the first and last ones (shared with the
-// neighbouring threads when the range starts or ends mid-word) are ORed.
-// The buffer then leaves as one contiguous run; its first and last words are
-// shared with the neighbouring passes and merged into the stream by atomic OR.
-// Returns the pass's bit count.
-template <bool WIDE, uint32_t PER>
-__device__ __forceinline__ uint32_t pack_pass(const EncArgs &a, uint64_t p0, uint64_t base, const uint16_t (&q)[PER],
-                                              const typename Codeword<WIDE>::T *s_book, uint32_t *s_words,
-                                              uint64_t *s_scan) {
+__device__ __forceinline__ void report_internal(const EncArgs &a) {
+    atomicOr(&a.ctl->status, ST_EINTERNAL);
+    a.hctl->status = a.ctl->status | ST_EINTERNAL;
+}
+
+// Stream bit offset of tile t > 0 (one whole wave): predecessors are read 64
+// at a time, nearest first; their counts are summed back to the nearest one
+// with an inclusive prefix.  Before tile 0 the prefix is 0.
+__device__ uint64_t look_back(const EncArgs &a, const uint64_t *flags, uint32_t t) {
+    const uint32_t lane = lane_id();
+    uint64_t G = 0;
+    int64_t end = (int64_t)t - 1;   // nearest predecessor not yet added
+    uint32_t polls = 0;
+    for (;;) {
+        const int64_t j = end - (int64_t)lane;
+        const uint64_t v = j >= 0 ? flag_load(flags + j) : kInclusive;
+        const uint64_t inc = __ballot((v >> 62) == 2u), pub = __ballot((v >> 62) != 0u);
+        const uint32_t k = inc ? (uint32_t)__builtin_ctzll(inc) : 64u;   // nearest inclusive lane
+        const uint64_t need = k >= 63u ? ~0ull : ((2ull << k) - 1u);      // lanes 0 .. k
+        if ((pub & need) != need) {   // a nearer predecessor has not published yet
+            if (++polls > kSpinLimit) {
+                if (lane == 0) report_internal(a);
+                return G;
+            }
+            __builtin_amdgcn_s_sleep(2);
+            continue;
+        }
+        G += wave_sum<uint64_t>(lane <= k ? (v & kValMask) : 0ull);
+        if (k < 64u) return G;
+        end -= 64;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_or(T v) {
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v |= __shfl_xor(v, off, 64);
+    return v;
+}
+
+// The first 32 bits of the stream after padded position p (MSB-first, zero
+// past the end of the stream), one whole wave; c is the code at p + lane.
+template <bool WIDE>
+__device__ uint32_t stream_head(const EncArgs &a, const typename Codeword<WIDE>::T *s_book, uint64_t p, uint32_t c) {
     typedef Codeword<WIDE> CW;
-    typedef typename CW::T Entry;
+    const uint32_t lane = lane_id();
+    uint32_t word = 0, off = 0;
+    for (;;) {
+        const typename CW::T e = c != kNoSymbol ? s_book[c] : (typename CW::T)0;
+        const uint32_t len = CW::len(e);
+        const uint32_t incl = wave_incl_scan<uint32_t>(len);
+        const uint32_t start = off + incl - len;
+        uint32_t part = 0;
+        if (len && start < 32u) part = (uint32_t)(((CW::code(e) << (64u - len)) >> start) >> 32);
+        word |= wave_or<uint32_t>(part);
+        off += (uint32_t)__shfl(incl, 63, 64);
+        p += 64;
+        if (off >= 32u || p >= a.g.padded) return word;
+        c = p + lane < a.g.padded ? a.b.codes[p + lane] : kNoSymbol;
+    }
+}
+
+// One packing run: PER consecutive positions per thread from padded position
+// p0 + PER * tid, codes q[], the run's first bit at stream bit
+// `base`, the thread's bits at base + excl.  Codewords are built MSB-first
+// in a 64-bit register (current word in bits 63..32); words wholly inside
+// the thread's bit range are stored plainly into the LDS word buffer, the
+// first and last ones (shared with the neighbouring threads) are ORed.  The
+// run's words then leave in one contiguous pass, except: a first word begun
+// before the tile (its owner completes it), and a last word left partial,
+// which is carried into the tile's next run or, after the last run,
+// completed with `head` (the next 32 stream bits) when the tile owns it.
+template <bool WIDE, uint32_t PER>
+__device__ __forceinline__ void pack_run(const EncArgs &a, uint64_t p0, uint64_t base, uint32_t run_bits,
+                                         uint32_t excl, const uint16_t (&q)[PER],
+                                         const typename Codeword<WIDE>::T *s_book,
+                                         uint32_t *s_words, uint64_t tile_start, bool last_run,
+                                         const uint32_t *s_carry_in, uint32_t *s_carry_out, const uint32_t *s_head) {
+    typedef Codeword<WIDE> CW;
     const uint32_t tid = threadIdx.x;
     const uint64_t my0 = p0 + (uint64_t)PER * tid;
-    uint32_t my_bits = 0;
-#pragma unroll
-    for (uint32_t i = 0; i < PER; i++)
-        if (q[i] != kNoSymbol) my_bits += CW::len(s_book[q[i]]);
-    uint64_t pass_bits;
-    const uint32_t excl = (uint32_t)block_excl_scan256(my_bits, s_scan, &pass_bits);
     const uint32_t lead = (uint32_t)(base & 31u);
-    const uint32_t nwords = (lead + (uint32_t)pass_bits + 31u) >> 5;
+    const uint32_t nwords = (lead + run_bits + 31u) >> 5;
     for (uint32_t i = tid; i < nwords; i += 256) s_words[i] = 0u;
-    // chunk offsets that start inside this pass
+    if (tid == 0 && s_carry_out) *s_carry_out = 0u;
+    // chunk offsets that start inside this run
     if ((my0 & (a.L.sub_size - 1)) == 0 && my0 < a.g.padded) {
         const uint64_t sub = my0 >> a.L.sub_shift;
         if ((sub & (a.L.chunk_subs - 1)) == 0)
@@ -172,7 +200,7 @@ __device__ __forceinline__ uint32_t pack_pass(const EncArgs &a, uint64_t p0, uin
 #pragma unroll
         for (uint32_t i = 0; i < PER; i++) {
             if (q[i] == kNoSymbol) continue;
-            const Entry e = s_book[q[i]];
+            const typename CW::T e = s_book[q[i]];
             const uint32_t len = CW::len(e);
             const uint64_t code = CW::code(e);
 #pragma unroll
@@ -203,83 +231,164 @@ __device__ __forceinline__ uint32_t pack_pass(const EncArgs &a, uint64_t p0, uin
     __syncthreads();
     uint32_t *stream = reinterpret_cast<uint32_t *>(a.archive + a.ctl->off_str);
     const uint64_t W0 = base >> 5;
-    const bool shared_first = lead != 0;
-    const bool shared_last = ((lead + (uint32_t)pass_bits) & 31u) != 0;
+    const uint32_t tail = (lead + run_bits) & 31u;   // bits used in the last word (0: it is full)
     for (uint32_t i = tid; i < nwords; i += 256) {
-        const uint32_t v = s_words[i];
-        const bool edge = (i == 0 && shared_first) || (i == nwords - 1 && shared_last);
-        if (edge) {
-            if (v) atomicOr(stream + W0 + i, v);
-        } else {
-            stream[W0 + i] = v;
+        uint32_t v = s_words[i];
+        if (i == 0 && s_carry_in) v |= *s_carry_in;
+        if (i == nwords - 1 && tail) {
+            if (!last_run) {
+                *s_carry_out = v;
+                continue;
+            }
+            v |= *s_head >> tail;
         }
+        if (32ull * (W0 + i) >= tile_start && W0 + i < a.ctl->n_words) stream[W0 + i] = v;
     }
-    return (uint32_t)pass_bits;
 }
 
-// A pass spans at most kPackWords words: a whole tile of codes up to 32 bits,
+// A run spans at most kPackWords words: a whole tile of codes up to 32 bits,
 // or half a tile of codes up to 63 bits (the 64-bit codeword path packs a
-// tile in two halves).
+// tile in two runs).
 constexpr uint32_t kPackWords = kTile + 2;
 
+struct EncLds {
+    uint32_t sub[kTile / 32];
+    uint64_t scan[10];
+    uint64_t G;
+    uint32_t head;
+    uint32_t carry[2];
+};
+
+// Staged exception records of quantize tile t -> archive, by one wave (the
+// records' offset: the segment totals before the tile's, plus its offset
+// inside its segment).
+__device__ void copy_exceptions(const EncArgs &a, uint32_t t, uint32_t lane) {
+    uint32_t cnt = a.b.qscan.val[0][t];
+    if (cnt > a.b.cap) cnt = a.b.cap;   // overflowed: the host compresses again with full staging
+    uint64_t part = 0;
+    for (uint32_t i = lane; i < t / kSegTiles; i += 64) part += a.b.qscan.seg_total[0][i];
+    const uint64_t off = wave_sum<uint64_t>(part) + a.b.qscan.excl[0][t];
+    uint2 *dst = reinterpret_cast<uint2 *>(a.archive + a.L.off_exc) + off;
+    const uint2 *src = a.b.stage + (uint64_t)t * a.b.cap;
+    for (uint32_t i = lane; i < cnt; i += 64) dst[i] = src[i];
+}
+
 template <bool WIDE>
-__device__ __forceinline__ void pack_tile(const EncArgs &a, uint32_t *s_words, uint64_t *s_book_raw,
-                                          uint64_t *s_scan, uint64_t *s_G) {
-    typedef typename Codeword<WIDE>::T Entry;
+__device__ __forceinline__ void enc_tile(const EncArgs &a, uint32_t t, uint32_t *s_words, uint64_t *s_book_raw,
+                                         EncLds &S) {
+    typedef Codeword<WIDE> CW;
+    typedef typename CW::T Entry;
+    constexpr uint32_t RUNS = WIDE ? 2 : 1;
+    constexpr uint32_t PER = kEncPer / RUNS;
     Entry *s_book = reinterpret_cast<Entry *>(s_book_raw);
-    const uint32_t tid = threadIdx.x, t = blockIdx.x;
-    const Entry *gbook = WIDE ? reinterpret_cast<const Entry *>(a.b.book) : reinterpret_cast<const Entry *>(a.b.book32);
+    const uint32_t tid = threadIdx.x, lane = lane_id(), w = tid / 64;
     const uint64_t p0 = (uint64_t)t * kTile;
-    // the tile's codes are in flight while the codebook goes to LDS (the
-    // 64-bit path packs the tile in two halves)
-    constexpr uint32_t PER = WIDE ? kEncPer / 2 : kEncPer;
-    uint16_t q0[PER], q1[PER];
-    load_codes(a, p0 + (uint64_t)PER * tid, q0);
-    if (WIDE) load_codes(a, p0 + kTile / 2 + (uint64_t)PER * tid, q1);
+    const bool coder = t < a.n_tiles_e;
+    if (!coder) {   // a quantize tile past the last encode tile: its records only
+        if (w == 0 && t < a.b.n_tiles_q) copy_exceptions(a, t, lane);
+        return;
+    }
+    // the tile's codes, the codebook and (wave 1) the codes just after the
+    // tile are all in flight together
+    uint16_t q[RUNS][PER];
+#pragma unroll
+    for (uint32_t r = 0; r < RUNS; r++) load_codes(a, p0 + r * (kTile / RUNS) + (uint64_t)PER * tid, q[r]);
+    uint32_t after = kNoSymbol;
     {
-        // codebook into LDS: all loads of a thread in flight
-        Entry e[kMaxSyms / 256];
+        const uint64_t pn = p0 + kTile + lane;
+        if (w == 1 && pn < a.g.padded) after = a.b.codes[pn];
+    }
+    {
+        const Entry *gbook = WIDE ? reinterpret_cast<const Entry *>(a.b.book) : reinterpret_cast<const Entry *>(a.b.book32);
+        Entry ev[kMaxSyms / 256];
 #pragma unroll
         for (uint32_t k = 0; k < kMaxSyms / 256; k++) {
             const uint32_t i = tid + 256 * k;
-            if (i < a.L.nsym) e[k] = gbook[i];
+            if (i < a.L.nsym) ev[k] = gbook[i];
         }
-        // the tile's global bit offset: wave 0 sums the totals of the earlier segments
-        if (tid < 64) {
-            const uint32_t seg = t / kSegTiles;
-            uint64_t part = 0;
-            for (uint32_t i = tid; i < seg; i += 64) part += a.b.escan.seg_total[0][i];
-            part = wave_sum<uint64_t>(part);
-            if (tid == 0) *s_G = part + a.b.escan.excl[0][t];
-        }
+        for (uint32_t i = tid; i < kTile / 32; i += 256) S.sub[i] = 0;
 #pragma unroll
         for (uint32_t k = 0; k < kMaxSyms / 256; k++) {
             const uint32_t i = tid + 256 * k;
-            if (i < a.L.nsym) s_book[i] = e[k];
+            if (i < a.L.nsym) s_book[i] = ev[k];
         }
     }
     __syncthreads();
-    const uint64_t G = *s_G;
-    if (!WIDE) {
-        (void)pack_pass<false, PER>(a, p0, G, q0, reinterpret_cast<const uint32_t *>(s_book), s_words, s_scan);
-    } else {
-        const uint32_t b0 = pack_pass<true, PER>(a, p0, G, q0, reinterpret_cast<const uint64_t *>(s_book), s_words,
-                                                 s_scan);
-        __syncthreads();   // the word buffer is reused
-        (void)pack_pass<true, PER>(a, p0 + kTile / 2, G + b0, q1, reinterpret_cast<const uint64_t *>(s_book),
-                                   s_words, s_scan);
+    // widths, subchunk sums (a thread's positions never straddle a
+    // subchunk), the runs' scans and the tile's bit count
+    uint32_t bits[RUNS], excl[RUNS];
+    uint64_t tot[RUNS];
+#pragma unroll
+    for (uint32_t r = 0; r < RUNS; r++) {
+        bits[r] = 0;
+#pragma unroll
+        for (uint32_t i = 0; i < PER; i++)
+            if (q[r][i] != kNoSymbol) bits[r] += CW::len(s_book[q[r][i]]);
+        if (bits[r]) atomicAdd(&S.sub[(r * (kTile / RUNS) + PER * tid) >> a.L.sub_shift], bits[r]);
+    }
+#pragma unroll
+    for (uint32_t r = 0; r < RUNS; r++) excl[r] = (uint32_t)block_excl_scan256(bits[r], S.scan, &tot[r]);
+    uint64_t tile_bits = 0;
+#pragma unroll
+    for (uint32_t r = 0; r < RUNS; r++) tile_bits += tot[r];
+    // wave 0: the tile's stream offset; wave 1: the stream bits after the
+    // tile; wave 2: the quantize tile's exception records
+    uint64_t *flags = a.b.eflag;
+    if (w == 0) {
+        uint64_t G = 0;
+        if (t == 0) {
+            if (tid == 0) flag_store(flags, kInclusive | tile_bits);
+        } else {
+            if (tid == 0) flag_store(flags + t, kAggregate | tile_bits);
+            G = look_back(a, flags, t);
+            if (tid == 0) flag_store(flags + t, kInclusive | ((G + tile_bits) & kValMask));
+        }
+        if (tid == 0) {
+            S.G = G;
+            // the stream ends where the codebook's total says
+            if (t + 1 == a.n_tiles_e && G + tile_bits != a.ctl->total_bits) report_internal(a);
+        }
+    } else if (w == 1) {
+        const uint32_t hb = stream_head<WIDE>(a, s_book, p0 + kTile, after);
+        if (lane == 0) S.head = hb;
+    } else if (w == 2) {
+        if (t < a.b.n_tiles_q) copy_exceptions(a, t, lane);
+    }
+    __syncthreads();
+    // subchunk bit counts (u16, little-endian)
+    {
+        const uint32_t sub_per_tile = kTile >> a.L.sub_shift;
+        const uint64_t sub0 = p0 >> a.L.sub_shift;
+        for (uint32_t j = tid; j < sub_per_tile; j += 256) {
+            const uint64_t s2 = sub0 + j;
+            if (s2 < a.L.n_sub) {
+                const uint32_t v = S.sub[j];
+                uint8_t *dst = a.archive + a.L.off_sub + 2ull * s2;
+                dst[0] = (uint8_t)v;
+                dst[1] = (uint8_t)(v >> 8);
+            }
+        }
+    }
+    const uint64_t G = S.G;
+    uint64_t base = G;
+#pragma unroll
+    for (uint32_t r = 0; r < RUNS; r++) {
+        if (r) __syncthreads();   // the word buffer is reused
+        pack_run<WIDE, PER>(a, p0 + r * (kTile / RUNS), base, (uint32_t)tot[r], excl[r], q[r], s_book, s_words, G,
+                            r + 1 == RUNS, r ? &S.carry[0] : nullptr, r + 1 < RUNS ? &S.carry[0] : nullptr, &S.head);
+        base += tot[r];
     }
 }
 
-__global__ __launch_bounds__(256) void k_enc_pack(EncArgs a) {
+__global__ __launch_bounds__(256) void k_enc_stream(EncArgs a) {
     extern __shared__ uint64_t s_dyn[];
-    __shared__ uint64_t s_scan[10];
-    __shared__ uint64_t s_G;
+    __shared__ EncLds S;
     if (a.ctl->status & kBadStatus) return;
+    const uint32_t t = blockIdx.x;
     uint32_t *s_words = reinterpret_cast<uint32_t *>(s_dyn);               // kPackWords
     uint64_t *s_book = s_dyn + (kPackWords + 1) / 2;                       // nsym entries
-    if (a.ctl->max_len <= 24) pack_tile<false>(a, s_words, s_book, s_scan, &s_G);
-    else pack_tile<true>(a, s_words, s_book, s_scan, &s_G);
+    if (a.ctl->max_len <= 24) enc_tile<false>(a, t, s_words, s_book, S);
+    else enc_tile<true>(a, t, s_words, s_book, S);
 }
 
 // One workgroup per segment: exclusive prefix of the tile values inside
@@ -317,32 +426,20 @@ void launch_seg_scan(hipStream_t s, const TileScan &S, const HistJob *hj) {
 
 uint32_t encode_tiles(const Geom &g) { return (uint32_t)((g.padded + kTile - 1) / kTile); }
 
-static EncArgs enc_args(const Geom &g, const Layout &L, Ctl *ctl, const EncodeBufs &b, uint8_t *archive) {
+void launch_encode(hipStream_t s, const Geom &g, const Layout &L, Ctl *ctl, Ctl *hctl, const EncodeBufs &b,
+                   uint8_t *archive) {
     EncArgs a;
     a.g = g;
     a.L = L;
     a.ctl = ctl;
+    a.hctl = hctl;
     a.b = b;
     a.archive = archive;
     a.n_tiles_e = encode_tiles(g);
-    return a;
-}
-
-void launch_encode_count(hipStream_t s, const Geom &g, const Layout &L, Ctl *ctl, const EncodeBufs &b,
-                         uint8_t *archive) {
-    const EncArgs a = enc_args(g, L, ctl, b, archive);
-    if (a.n_tiles_e == 0) return;
-    const uint32_t grid1 = a.n_tiles_e > b.n_tiles_q ? a.n_tiles_e : b.n_tiles_q;
-    hipLaunchKernelGGL(k_enc_count, dim3(grid1), dim3(256), 0, s, a);
-    launch_seg_scan(s, b.escan);
-}
-
-void launch_encode_pack(hipStream_t s, const Geom &g, const Layout &L, Ctl *ctl, const EncodeBufs &b,
-                        uint8_t *archive) {
-    const EncArgs a = enc_args(g, L, ctl, b, archive);
-    if (a.n_tiles_e == 0) return;
+    const uint32_t grid = a.n_tiles_e > b.n_tiles_q ? a.n_tiles_e : b.n_tiles_q;
+    if (grid == 0) return;
     const size_t lds = sizeof(uint64_t) * ((kPackWords + 1) / 2 + L.nsym);
-    hipLaunchKernelGGL(k_enc_pack, dim3(a.n_tiles_e), dim3(256), lds, s, a);
+    hipLaunchKernelGGL(k_enc_stream, dim3(grid), dim3(256), lds, s, a);
 }
 
 }  // namespace dqz

@@ -166,7 +166,7 @@ __global__ __launch_bounds__(256) void k_minmax_final(const uint32_t *partials, 
 
 void launch_minmax(hipStream_t s, const float *x, uint64_t n, Ctl *ctl, uint32_t *partials, double valrel, int ncu) {
     uint64_t want = (n / 4 + 255) / 256;
-    uint64_t cap = (uint64_t)ncu * 4;
+    uint64_t cap = (uint64_t)ncu * 8;
     if (cap > kMinmaxMaxBlocks) cap = kMinmaxMaxBlocks;
     uint32_t blocks = (uint32_t)(want < cap ? want : cap);
     if (blocks < 1) blocks = 1;

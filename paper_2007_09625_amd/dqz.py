@@ -24,7 +24,7 @@ EXPORTED = ("dqz_ctx_create", "dqz_ctx_destroy", "dqz_compress_bound", "dqz_comp
             "dqz_decompress", "dqz_status_str", "dqz_ctx_last_error", "dqz_debug_copy", "dqz_ctx_set_timing",
             "dqz_stage_times")
 DQZ_MAX_STAGES = 8
-COMPRESS_STAGES = ("init", "range_eb", "quantize", "quantize_scan", "codebook", "encode_count", "encode_pack")
+COMPRESS_STAGES = ("init", "range_eb", "quantize", "quantize_scan", "codebook", "encode")
 DECOMPRESS_STAGES = ("decode_tables", "inflate", "reconstruct")
 
 
