@@ -136,9 +136,11 @@ const char *dqz_ctx_last_error(const dqz_ctx *ctx);
 
 /* Per-stage timing.  `level` 0 turns it off.  At level 1 every dqz_compress /
  * dqz_decompress on this context records HIP events on its stream between its
- * kernels (a small per-call cost); level 2 also sums per-wave phase durations
- * inside the decoding kernel (DQZ_DBG_PHASES), which costs a few
- * same-address atomics per wave and slows that kernel noticeably.
+ * kernels (a small per-call cost, about a microsecond per event); level 2
+ * also sums per-wave phase durations inside the decoding kernel
+ * (DQZ_DBG_PHASES), which costs a few same-address atomics per wave and slows
+ * that kernel noticeably.  DQZ_TIMING_STAGE(which, stage) records only the
+ * two events around one stage of one call kind (the other stages read 0).
  * dqz_stage_times returns the elapsed microseconds of
  * each stage of the most recent call of that kind:
  *   compress   (which = 0): [0] init, [1] value range + eb (0 in absolute
@@ -151,6 +153,7 @@ const char *dqz_ctx_last_error(const dqz_ctx *ctx);
  *              subchunks; 0 otherwise)
  * `us` must hold DQZ_MAX_STAGES doubles; *n_stages receives the count. */
 #define DQZ_MAX_STAGES 8
+#define DQZ_TIMING_STAGE(which, stage) (0x100 | ((which) << 4) | (stage))
 dqz_status dqz_ctx_set_timing(dqz_ctx *ctx, int level);
 dqz_status dqz_stage_times(dqz_ctx *ctx, int which, double *us, int *n_stages);
 

@@ -41,6 +41,8 @@ struct dqz_ctx {
     bool trace = false;
     hipEvent_t ev[2][DQZ_MAX_STAGES + 1] = {};
     int n_ev[2] = {0, 0};
+    bool ev_rec[2][DQZ_MAX_STAGES + 1] = {};
+    int only_stage[2] = {-1, -1};   // >= 0: events only around this stage (-2: none)
     bool ev_ready[2] = {false, false};
 };
 
@@ -217,7 +219,13 @@ dqz_status ensure_ws(dqz_ctx *ctx, size_t bytes) {
 // stage marks: mark(ctx, which, i) records event i of call kind `which`
 void mark(dqz_ctx *ctx, int which, int i, hipStream_t s) {
     if (!ctx->timing) return;
-    (void)hipEventRecord(ctx->ev[which][i], s);
+    if (i == 0)
+        for (int k = 0; k <= DQZ_MAX_STAGES; k++) ctx->ev_rec[which][k] = false;
+    const int only = ctx->only_stage[which];
+    if (only == -1 || i == only || i == only + 1) {
+        (void)hipEventRecord(ctx->ev[which][i], s);
+        ctx->ev_rec[which][i] = true;
+    }
     ctx->n_ev[which] = i + 1;
 }
 
@@ -553,7 +561,16 @@ dqz_status dqz_decompress(dqz_ctx *ctx, const void *d_archive, uint64_t archive_
 
 dqz_status dqz_ctx_set_timing(dqz_ctx *ctx, int level) {
     if (!ctx) return DQZ_EINVAL;
-    if (level < 0 || level > 2) return fail(ctx, DQZ_EINVAL, "timing level must be 0, 1 or 2");
+    int only[2] = {-1, -1};
+    if (level >= 0x100) {
+        const int which = (level >> 4) & 0xF, stage = level & 0xF;
+        if (level > 0x1FF || which > 1 || stage >= DQZ_MAX_STAGES)
+            return fail(ctx, DQZ_EINVAL, "DQZ_TIMING_STAGE: which must be 0 or 1 and stage below DQZ_MAX_STAGES");
+        only[which] = stage;
+        only[1 - which] = -2;
+    } else if (level < 0 || level > 2) {
+        return fail(ctx, DQZ_EINVAL, "timing level must be 0, 1, 2 or DQZ_TIMING_STAGE(which, stage)");
+    }
     const bool enable = level > 0;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     if (enable && !ctx->ev[0][0]) {
@@ -562,6 +579,8 @@ dqz_status dqz_ctx_set_timing(dqz_ctx *ctx, int level) {
     }
     ctx->timing = enable;
     ctx->trace = level == 2;
+    ctx->only_stage[0] = only[0];
+    ctx->only_stage[1] = only[1];
     ctx->ev_ready[0] = ctx->ev_ready[1] = false;
     return DQZ_OK;
 }
@@ -573,7 +592,8 @@ dqz_status dqz_stage_times(dqz_ctx *ctx, int which, double *us, int *n_stages) {
     const int n = ctx->n_ev[which] - 1;
     for (int i = 0; i < n; i++) {
         float ms = 0.0f;
-        HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev[which][i], ctx->ev[which][i + 1]));
+        if (ctx->ev_rec[which][i] && ctx->ev_rec[which][i + 1])
+            HIP_TRY(ctx, hipEventElapsedTime(&ms, ctx->ev[which][i], ctx->ev[which][i + 1]));
         us[i] = 1000.0 * ms;
     }
     *n_stages = n;

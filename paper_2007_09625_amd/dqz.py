@@ -28,6 +28,13 @@ COMPRESS_STAGES = ("init", "range_eb", "quantize", "quantize_scan", "codebook", 
 DECOMPRESS_STAGES = ("decode_tables", "inflate", "reconstruct")
 
 
+def timing_stage(which: int, stage) -> int:
+    """Timing level that records only the events around one stage (index or name)."""
+    if isinstance(stage, str):
+        stage = (COMPRESS_STAGES if which == 0 else DECOMPRESS_STAGES).index(stage)
+    return 0x100 | (int(which) << 4) | int(stage)
+
+
 class DqzError(RuntimeError):
     def __init__(self, status: int, msg: str):
         super().__init__(msg)
@@ -193,7 +200,8 @@ class Context:
                                   ctypes.c_void_p(field_ptr), int(field_cap_elems), self._stream(stream))
 
     def dqz_ctx_set_timing(self, level):
-        """0 off, 1 (or True) stage events, 2 also the decoding kernel's per-wave phase sums."""
+        """0 off, 1 (or True) stage events, 2 also the decoding kernel's per-wave phase sums,
+        timing_stage(which, stage): the two events around one stage only."""
         self._check(lib.dqz_ctx_set_timing(self.handle, int(level)), "dqz_ctx_set_timing")
 
     def dqz_stage_times(self, which: int) -> dict:

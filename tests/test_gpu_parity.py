@@ -264,3 +264,25 @@ def test_parity_wide_sort_keys(ctx):
     import oracle
     _, _, freq, _ = oracle.stages(x, 0.5, 0, 1024)
     assert int(freq.max()) >= 1 << 21
+
+
+def test_stage_timing_modes(ctx):
+    """Timing level 1 reports every stage; DQZ_TIMING_STAGE(which, stage)
+    reports the chosen stage only; the archive is the same either way."""
+    import torch
+    from paper_2007_09625_amd import dqz
+    from synth import fields
+    x = torch.from_numpy(fields.hurricane3d((24, 40, 52), seed=3)).cuda()
+    ctx.dqz_ctx_set_timing(1)
+    a1 = ctx.compress(x, 1e-4).archive.cpu().numpy()
+    full = ctx.dqz_stage_times(0)
+    assert list(full) == list(dqz.COMPRESS_STAGES)
+    assert full["quantize"] > 0 and full["encode"] > 0
+    ctx.dqz_ctx_set_timing(dqz.timing_stage(0, "encode"))
+    a2 = ctx.compress(x, 1e-4).archive.cpu().numpy()
+    one = ctx.dqz_stage_times(0)
+    assert one["encode"] > 0 and all(v == 0 for k, v in one.items() if k != "encode")
+    ctx.dqz_ctx_set_timing(0)
+    assert np.array_equal(a1, a2)
+    with pytest.raises(Exception):
+        ctx.dqz_ctx_set_timing(0x100 | (2 << 4))
