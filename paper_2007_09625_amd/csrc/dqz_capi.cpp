@@ -182,7 +182,7 @@ WsLayout ws_layout(const Plan &P, bool compress, uint32_t cap) {
     }
     w.hist = take(cur, 4ull * kHistReplicas * P.L.nsym);
     w.hist_sum = take(cur, 4ull * P.L.nsym);   // zeroed too: an empty field never writes it
-    w.eflag = take(cur, 8ull * P.tiles_e);      // encode look-back states start at zero
+    w.eflag = take(cur, 128ull * P.tiles_e);    // encode look-back states (one line each) start at zero
     w.zero_end = align_up(cur, 256);
     w.book = take(cur, 8ull * P.L.nsym);
     w.book32 = take(cur, 4ull * P.L.nsym);

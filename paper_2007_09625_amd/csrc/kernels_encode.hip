@@ -92,6 +92,7 @@ constexpr uint64_t kAggregate = 1ull << 62;   // the tile's own bit count
 constexpr uint64_t kInclusive = 2ull << 62;   // bits of all tiles up to and including this one
 constexpr uint64_t kValMask = (1ull << 62) - 1;
 constexpr uint32_t kSpinLimit = 1u << 20;     // polls before a missing predecessor is an internal error
+constexpr uint32_t kFlagStride = 16;          // u64 per tile state: one 128-byte line each
 
 __device__ __forceinline__ uint64_t flag_load(const uint64_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -115,7 +116,7 @@ __device__ uint64_t look_back(const EncArgs &a, const uint64_t *flags, uint32_t 
     uint32_t polls = 0;
     for (;;) {
         const int64_t j = end - (int64_t)lane;
-        const uint64_t v = j >= 0 ? flag_load(flags + j) : kInclusive;
+        const uint64_t v = j >= 0 ? flag_load(flags + (uint64_t)j * kFlagStride) : kInclusive;
         const uint64_t inc = __ballot((v >> 62) == 2u), pub = __ballot((v >> 62) != 0u);
         const uint32_t k = inc ? (uint32_t)__builtin_ctzll(inc) : 64u;   // nearest inclusive lane
         const uint64_t need = k >= 63u ? ~0ull : ((2ull << k) - 1u);      // lanes 0 .. k
@@ -339,9 +340,9 @@ __device__ __forceinline__ void enc_tile(const EncArgs &a, uint32_t t, uint32_t 
         if (t == 0) {
             if (tid == 0) flag_store(flags, kInclusive | tile_bits);
         } else {
-            if (tid == 0) flag_store(flags + t, kAggregate | tile_bits);
+            if (tid == 0) flag_store(flags + (uint64_t)t * kFlagStride, kAggregate | tile_bits);
             G = look_back(a, flags, t);
-            if (tid == 0) flag_store(flags + t, kInclusive | ((G + tile_bits) & kValMask));
+            if (tid == 0) flag_store(flags + (uint64_t)t * kFlagStride, kInclusive | ((G + tile_bits) & kValMask));
         }
         if (tid == 0) {
             S.G = G;
