@@ -62,21 +62,32 @@ template <> struct Codeword<true> {
 };
 
 // N consecutive codes of this thread from padded position my0 (padding ->
-// kNoSymbol); N a multiple of 8
+// kNoSymbol); N a multiple of 8, or 4
 template <uint32_t N>
 __device__ __forceinline__ void load_codes(const EncArgs &a, uint64_t my0, uint16_t (&q)[N]) {
+    static_assert(N % 8 == 0 || N == 4, "codes per thread");
     const uint32_t padded = a.g.padded;
     if (my0 + N <= padded) {
-        const uint4 *src = reinterpret_cast<const uint4 *>(a.b.codes + my0);
+        uint32_t u[N / 2];
+        if (N % 8 == 0) {
+            const uint4 *src = reinterpret_cast<const uint4 *>(a.b.codes + my0);
 #pragma unroll
-        for (uint32_t v = 0; v < N / 8; v++) {
-            const uint4 u4 = src[v];
-            const uint32_t u[4] = {u4.x, u4.y, u4.z, u4.w};
-#pragma unroll
-            for (uint32_t i = 0; i < 4; i++) {
-                q[8 * v + 2 * i] = (uint16_t)(u[i] & 0xFFFF);
-                q[8 * v + 2 * i + 1] = (uint16_t)(u[i] >> 16);
+            for (uint32_t v = 0; v < N / 8; v++) {
+                const uint4 u4 = src[v];
+                u[4 * v] = u4.x;
+                u[4 * v + 1] = u4.y;
+                u[4 * v + 2] = u4.z;
+                u[4 * v + 3] = u4.w;
             }
+        } else {
+            const uint2 u2 = *reinterpret_cast<const uint2 *>(a.b.codes + my0);
+            u[0] = u2.x;
+            u[1] = u2.y;
+        }
+#pragma unroll
+        for (uint32_t i = 0; i < N / 2; i++) {
+            q[2 * i] = (uint16_t)(u[i] & 0xFFFF);
+            q[2 * i + 1] = (uint16_t)(u[i] >> 16);
         }
     } else {
 #pragma unroll
@@ -186,12 +197,18 @@ __device__ __forceinline__ void pack_run(const EncArgs &a, uint64_t p0, uint64_t
     const uint32_t nwords = (lead + run_bits + 31u) >> 5;
     for (uint32_t i = tid; i < nwords; i += 256) s_words[i] = 0u;
     if (tid == 0 && s_carry_out) *s_carry_out = 0u;
-    // chunk offsets that start inside this run
+    // chunk offsets that start inside this run (chunk_subs is a power of two)
     if ((my0 & (a.L.sub_size - 1)) == 0 && my0 < a.g.padded) {
         const uint64_t sub = my0 >> a.L.sub_shift;
         if ((sub & (a.L.chunk_subs - 1)) == 0)
-            *reinterpret_cast<uint64_t *>(a.archive + a.L.off_chunk + 8ull * (sub / a.L.chunk_subs)) = base + excl;
+            *reinterpret_cast<uint64_t *>(a.archive + a.L.off_chunk + 8ull * (sub >> (__ffs(a.L.chunk_subs) - 1))) =
+                base + excl;
     }
+    // the thread's codewords, all lookups in flight together (a padding
+    // position reads entry 0 and counts as an empty codeword)
+    typename CW::T ent[PER];
+#pragma unroll
+    for (uint32_t i = 0; i < PER; i++) ent[i] = s_book[q[i] != kNoSymbol ? q[i] : 0u];
     __syncthreads();
     {
         const uint32_t bit = lead + excl;
@@ -200,10 +217,9 @@ __device__ __forceinline__ void pack_run(const EncArgs &a, uint64_t p0, uint64_t
         uint64_t acc = 0;
 #pragma unroll
         for (uint32_t i = 0; i < PER; i++) {
-            if (q[i] == kNoSymbol) continue;
-            const typename CW::T e = s_book[q[i]];
-            const uint32_t len = CW::len(e);
-            const uint64_t code = CW::code(e);
+            const bool real = q[i] != kNoSymbol;
+            const uint32_t len = real ? CW::len(ent[i]) : 0u;
+            const uint64_t code = real ? CW::code(ent[i]) : 0u;
 #pragma unroll
             for (uint32_t part = 0; part < (WIDE ? 2u : 1u); part++) {
                 // WIDE codes over 32 bits go in two parts, high part first
@@ -213,8 +229,8 @@ __device__ __forceinline__ void pack_run(const EncArgs &a, uint64_t p0, uint64_t
                     if (part == 0) { l = len > 32u ? len - 32u : 0u; c = code >> 32; }
                     else { l = len > 32u ? 32u : len; c = code & 0xFFFFFFFFull; }
                 }
-                if (l == 0) continue;
-                acc |= (c << (64u - l)) >> fill;
+                if (WIDE && l == 0) continue;
+                acc |= (c << ((64u - l) & 63u)) >> fill;   // an empty codeword adds nothing
                 fill += l;
                 if (fill >= 32u) {
                     const uint32_t v = (uint32_t)(acc >> 32);
@@ -247,10 +263,21 @@ __device__ __forceinline__ void pack_run(const EncArgs &a, uint64_t p0, uint64_t
     }
 }
 
-// A run spans at most kPackWords words: a whole tile of codes up to 32 bits,
-// or half a tile of codes up to 63 bits (the 64-bit codeword path packs a
-// tile in two runs).
-constexpr uint32_t kPackWords = kTile + 2;
+// A run spans at most kPackWords<WIDE> words: a whole tile of codes up to 24
+// bits (32-bit codewords), or a quarter tile of codes up to 64 bits (the
+// 64-bit codeword path packs a tile in four runs).  Both word buffers and
+// their codebooks take the same LDS.
+constexpr uint32_t kRuns64 = 4;
+template <bool WIDE> struct PackWords { static constexpr uint32_t n = kTile * 24 / 32 + 2; };
+template <> struct PackWords<true> { static constexpr uint32_t n = kTile / kRuns64 * 64 / 32 + 2; };
+__host__ __device__ constexpr uint32_t book_offset_u64(bool wide) {
+    return ((wide ? PackWords<true>::n : PackWords<false>::n) + 1) / 2;
+}
+size_t enc_lds_bytes(uint32_t nsym) {
+    const size_t narrow = 8 * (size_t)book_offset_u64(false) + 4 * (size_t)nsym;
+    const size_t wide = 8 * (size_t)book_offset_u64(true) + 8 * (size_t)nsym;
+    return narrow > wide ? narrow : wide;
+}
 
 struct EncLds {
     uint32_t sub[kTile / 32];
@@ -279,7 +306,7 @@ __device__ __forceinline__ void enc_tile(const EncArgs &a, uint32_t t, uint32_t 
                                          EncLds &S) {
     typedef Codeword<WIDE> CW;
     typedef typename CW::T Entry;
-    constexpr uint32_t RUNS = WIDE ? 2 : 1;
+    constexpr uint32_t RUNS = WIDE ? kRuns64 : 1;
     constexpr uint32_t PER = kEncPer / RUNS;
     Entry *s_book = reinterpret_cast<Entry *>(s_book_raw);
     const uint32_t tid = threadIdx.x, lane = lane_id(), w = tid / 64;
@@ -322,9 +349,11 @@ __device__ __forceinline__ void enc_tile(const EncArgs &a, uint32_t t, uint32_t 
 #pragma unroll
     for (uint32_t r = 0; r < RUNS; r++) {
         bits[r] = 0;
+        Entry ent[PER];
 #pragma unroll
-        for (uint32_t i = 0; i < PER; i++)
-            if (q[r][i] != kNoSymbol) bits[r] += CW::len(s_book[q[r][i]]);
+        for (uint32_t i = 0; i < PER; i++) ent[i] = s_book[q[r][i] != kNoSymbol ? q[r][i] : 0u];
+#pragma unroll
+        for (uint32_t i = 0; i < PER; i++) bits[r] += q[r][i] != kNoSymbol ? CW::len(ent[i]) : 0u;
         if (bits[r]) atomicAdd(&S.sub[(r * (kTile / RUNS) + PER * tid) >> a.L.sub_shift], bits[r]);
     }
 #pragma unroll
@@ -376,20 +405,23 @@ __device__ __forceinline__ void enc_tile(const EncArgs &a, uint32_t t, uint32_t 
     for (uint32_t r = 0; r < RUNS; r++) {
         if (r) __syncthreads();   // the word buffer is reused
         pack_run<WIDE, PER>(a, p0 + r * (kTile / RUNS), base, (uint32_t)tot[r], excl[r], q[r], s_book, s_words, G,
-                            r + 1 == RUNS, r ? &S.carry[0] : nullptr, r + 1 < RUNS ? &S.carry[0] : nullptr, &S.head);
+                            r + 1 == RUNS, r ? &S.carry[(r - 1) & 1] : nullptr,
+                            r + 1 < RUNS ? &S.carry[r & 1] : nullptr, &S.head);
         base += tot[r];
     }
 }
 
+// One kernel per codeword width, both launched: the width is a device value
+// (the longest code), and the one that does not apply returns at once.
+// Apart, the 32-bit path needs few enough registers for eight workgroups
+// per CU.
+template <bool WIDE>
 __global__ __launch_bounds__(256) void k_enc_stream(EncArgs a) {
     extern __shared__ uint64_t s_dyn[];
     __shared__ EncLds S;
-    if (a.ctl->status & kBadStatus) return;
-    const uint32_t t = blockIdx.x;
-    uint32_t *s_words = reinterpret_cast<uint32_t *>(s_dyn);               // kPackWords
-    uint64_t *s_book = s_dyn + (kPackWords + 1) / 2;                       // nsym entries
-    if (a.ctl->max_len <= 24) enc_tile<false>(a, t, s_words, s_book, S);
-    else enc_tile<true>(a, t, s_words, s_book, S);
+    if ((a.ctl->status & kBadStatus) || (a.ctl->max_len > 24) != WIDE) return;
+    uint32_t *s_words = reinterpret_cast<uint32_t *>(s_dyn);   // PackWords<WIDE>::n, then nsym codewords
+    enc_tile<WIDE>(a, blockIdx.x, s_words, s_dyn + book_offset_u64(WIDE), S);
 }
 
 // One workgroup per segment: exclusive prefix of the tile values inside
@@ -439,8 +471,9 @@ void launch_encode(hipStream_t s, const Geom &g, const Layout &L, Ctl *ctl, Ctl 
     a.n_tiles_e = encode_tiles(g);
     const uint32_t grid = a.n_tiles_e > b.n_tiles_q ? a.n_tiles_e : b.n_tiles_q;
     if (grid == 0) return;
-    const size_t lds = sizeof(uint64_t) * ((kPackWords + 1) / 2 + L.nsym);
-    hipLaunchKernelGGL(k_enc_stream, dim3(grid), dim3(256), lds, s, a);
+    const size_t lds = enc_lds_bytes(L.nsym);
+    hipLaunchKernelGGL(k_enc_stream<false>, dim3(grid), dim3(256), lds, s, a);
+    hipLaunchKernelGGL(k_enc_stream<true>, dim3(grid), dim3(256), lds, s, a);
 }
 
 }  // namespace dqz
