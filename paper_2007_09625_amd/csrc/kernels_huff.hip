@@ -173,6 +173,7 @@ struct CanonScratch {
     uint32_t wave_max[16];
     uint32_t n_used;
     uint32_t max_len;
+    uint32_t kraft;   // 0: the lengths fill the code space exactly, 1: they overfill it, 2: they leave room
 };
 
 constexpr uint32_t kCanonGroups = kMaxSyms / 64;   // (chunk, wave) groups of 64 symbols
@@ -251,7 +252,16 @@ __device__ void canonical_order(const uint8_t *len, uint32_t ns, CanonScratch &c
         }
         if (l + 1 <= 64) c.first_code[l + 1] = S << 1;
         if (tid == 0) c.first_code[1] = 0;
-        if (tid == 63) { c.n_used = incl; c.max_len = max_len; }
+        // Kraft: S_l = sum_{j<=l} count_j 2^(l-j) may not exceed 2^l at any l
+        // <= 63 (the first l that does is computed without overflow) and must
+        // equal 2^max_len at the end
+        const bool over = __ballot(l <= 63u && S > (1ull << (l & 63u))) != 0;
+        const uint64_t S_top = __shfl(S, (int)((max_len >= 1u && max_len <= 64u ? max_len : 1u) - 1u), 64);
+        if (tid == 63) {
+            c.n_used = incl;
+            c.max_len = max_len;
+            c.kraft = over ? 1u : ((max_len >= 1u && max_len <= 63u && S_top == (1ull << max_len)) ? 0u : 2u);
+        }
     }
     __syncthreads();
     // lengths above 64 (only reachable from damaged input) are reported
@@ -737,16 +747,10 @@ __global__ __launch_bounds__(kTableThreads) void k_decode_tables(const uint8_t *
     if (tid == 0) {
         tab->phase[1] = wall_clock64();
         // Kraft: the code space must be exactly filled (or a lone symbol of length 1)
-        int64_t left = 1;
-        bool over = false;
-        for (uint32_t l = 1; l <= 63; l++) {
-            left = 2 * left - (int64_t)c.count[l];
-            if (left < 0) { over = true; break; }
-            if (left > (1ll << 40)) left = 1ll << 40;   // stays positive: incomplete
-        }
         const bool lone = c.n_used == 1 && c.count[1] == 1;
         uint32_t st = 0;
-        if (over || (!lone && c.n_used > 0 && left != 0) || c.max_len != max_len_hdr || c.max_len > 63) st = ST_ECORRUPT;
+        if (c.kraft == 1u || (!lone && c.n_used > 0 && c.kraft != 0u) || c.max_len != max_len_hdr || c.max_len > 63)
+            st = ST_ECORRUPT;
         tab->status = st;
         if (st) *hstatus = st;   // pinned host memory, read after the stream ends
         tab->max_len = c.max_len;
@@ -766,22 +770,45 @@ __global__ __launch_bounds__(kTableThreads) void k_decode_tables(const uint8_t *
     // 1 + the number of lengths l <= kLutBits whose codes all lie below v
     // (canonical codes of length <= l fill [0, limit_l)); longer codes get the
     // shortest length that can follow the prefix
+    // (the slot's code of length l is its top l bits; the codes of length l
+    // are those of [lim_{l-1}, lim_l), so it is the code of canonical index
+    // first_index_l + code - first_code_l)
     uint32_t lim[kLutBits + 1];
+    int32_t base[kLutBits + 1];
 #pragma unroll
-    for (uint32_t l = 1; l <= kLutBits; l++)
+    for (uint32_t l = 1; l <= kLutBits; l++) {
         lim[l] = (uint32_t)((c.first_code[l] + c.count[l]) << (kLutBits - l));
-    for (uint32_t v = tid; v < (1u << kLutBits); v += T) {
+        base[l] = (int32_t)c.first_index[l] - (int32_t)c.first_code[l];
+    }
+    // the shortest length after a long-code prefix (computed once per
+    // workgroup for the prefixes, which are the top of the table)
+    constexpr uint32_t kPer = (1u << kLutBits) / kTableThreads;
+    static_assert(kPer * kTableThreads == (1u << kLutBits), "table slots per thread");
+    uint32_t slot_len[kPer];
+#pragma unroll
+    for (uint32_t i = 0; i < kPer; i++) {
+        const uint32_t v = tid + kTableThreads * i;
         uint32_t l = 1;
 #pragma unroll
         for (uint32_t k = 1; k <= kLutBits; k++) l += (lim[k] <= v) ? 1u : 0u;
+        slot_len[i] = l;
+    }
+    uint64_t key[kPer];
+#pragma unroll
+    for (uint32_t i = 0; i < kPer; i++) {
+        const uint32_t v = tid + kTableThreads * i, l = slot_len[i];
+        int32_t b = 0;
+#pragma unroll
+        for (uint32_t k = 1; k <= kLutBits; k++) b = (l == k) ? base[k] : b;
+        const uint32_t idx = (uint32_t)(b + (int32_t)(v >> ((kLutBits - l) & 31u)));
+        key[i] = l <= kLutBits ? c.key[idx < kMaxSyms ? idx : 0u] : 0ull;
+    }
+#pragma unroll
+    for (uint32_t i = 0; i < kPer; i++) {
+        const uint32_t v = tid + kTableThreads * i, l = slot_len[i];
         uint32_t e = 0;
         if (l <= kLutBits) {
-            const uint64_t code = (uint64_t)(v >> (kLutBits - l));
-            const uint64_t d = code - c.first_code[l];
-            if (code >= c.first_code[l] && d < c.count[l]) {
-                const uint64_t k = c.key[c.first_index[l] + (uint32_t)d];
-                e = (l << 11) | (uint32_t)(k & 0x7FF);
-            }
+            e = (l << 11) | (uint32_t)(key[i] & 0x7FF);
         } else if (c.max_len > kLutBits) {
             // a long-code prefix: the shortest length that can follow
             const uint64_t w = (uint64_t)v << (64 - kLutBits);
