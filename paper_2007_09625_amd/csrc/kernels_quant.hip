@@ -268,14 +268,19 @@ __global__ __launch_bounds__(256) void k_quant3d(QuantArgs a) {
     // stage the tile: 64 rows (z, y) of 64 floats, one wave per row; all 16
     // loads of a thread are issued before any is used
     {
+        // row rr = w0 + 4k is (z, y) = (k / 2, w0 + 4 (k & 1)): one base
+        // address per thread plus uniform plane and 4-row strides
         float v[16];
         const uint32_t xx = lane_id(), w0 = threadIdx.x / 64;
+        const float *base = a.x + ((uint64_t)z0 * ny + (y0 + w0)) * nx + (x0 + xx);
+        const uint64_t plane = (uint64_t)ny * nx, four_rows = 4ull * nx;
+        const bool x_ok = x0 + xx < nx;
 #pragma unroll
         for (uint32_t k = 0; k < 16; k++) {
-            const uint32_t rr = w0 + 4 * k, z = rr / 8, y = rr % 8;
+            const uint32_t z = k / 2, y = w0 + 4 * (k & 1);
             v[k] = 0.0f;
-            if (z0 + z < nz && y0 + y < ny && x0 + xx < nx)
-                v[k] = __builtin_nontemporal_load(a.x + ((uint64_t)(z0 + z) * ny + (y0 + y)) * nx + (x0 + xx));
+            if (z0 + z < nz && y0 + y < ny && x_ok)
+                v[k] = __builtin_nontemporal_load(base + (uint64_t)z * plane + ((k & 1) ? four_rows : 0ull));
         }
 #pragma unroll
         for (uint32_t k = 0; k < 16; k++) {
@@ -289,7 +294,6 @@ __global__ __launch_bounds__(256) void k_quant3d(QuantArgs a) {
     const uint32_t ly = lane / 8, lx = lane % 8;
     int32_t delta[2][8];
     uint32_t flags_o = 0, flags_p = 0;   // bit (j*8 + z)
-    uint32_t wave_count = 0, wave_out = 0, wave_patch = 0;
 #pragma unroll
     for (uint32_t j = 0; j < 2; j++) {
         const uint32_t bxl = 2 * w + j;              // block within tile
@@ -297,41 +301,63 @@ __global__ __launch_bounds__(256) void k_quant3d(QuantArgs a) {
         const bool blk_ok = Bx < a.g.nb[2];
         const uint32_t gx = x0 + bxl * 8 + lx, gy = y0 + ly;
         const uint64_t blk = ((uint64_t)Bz * a.g.nb[1] + By) * a.g.nb[2] + Bx;
-        int32_t prev = 0;   // d° of (z-1) in this column; padding layer is 0
+        const bool col_ok = blk_ok && gx < nx && gy < ny;
+        // the block column's eight values and prequantized codes (LDS reads
+        // all in flight), then the mixed backward difference: z in registers,
+        // y and x across lanes, each axis for all eight z at once
+        float v[8];
+        int32_t d[8];
+#pragma unroll
+        for (uint32_t z = 0; z < 8; z++) v[z] = s_tile[z][ly][bxl * 8 + lx];
+#pragma unroll
+        for (uint32_t z = 0; z < 8; z++) d[z] = prequant(v[z], r);
+        uint32_t t[8];
+#pragma unroll
+        for (uint32_t z = 0; z < 8; z++) t[z] = (uint32_t)d[z] - (z ? (uint32_t)d[z - 1] : 0u);   // padding layer is 0
+        uint32_t up[8];
+#pragma unroll
+        for (uint32_t z = 0; z < 8; z++) up[z] = __shfl_up(t[z], 8, 64);
+#pragma unroll
+        for (uint32_t z = 0; z < 8; z++) t[z] -= ly > 0 ? up[z] : 0u;
+#pragma unroll
+        for (uint32_t z = 0; z < 8; z++) up[z] = __shfl_up(t[z], 1, 64);
 #pragma unroll
         for (uint32_t z = 0; z < 8; z++) {
-            const bool real = blk_ok && gx < nx && gy < ny && (z0 + z) < nz;
-            const float v = s_tile[z][ly][bxl * 8 + lx];
-            const int32_t d = prequant(v, r);
-            // mixed backward difference: z (registers), then y, x (lanes)
-            const uint32_t dz = (uint32_t)d - (uint32_t)prev;
-            prev = d;
-            const uint32_t up_y = __shfl_up(dz, 8, 64);
-            const uint32_t dyz = dz - (ly > 0 ? up_y : 0u);
-            const uint32_t up_x = __shfl_up(dyz, 1, 64);
-            const int32_t del = (int32_t)(dyz - (lx > 0 ? up_x : 0u));
+            const int32_t del = (int32_t)(t[z] - (lx > 0 ? up[z] : 0u));
             delta[j][z] = del;
+            const bool real = col_ok && (z0 + z) < nz;
             const bool incap = del > -R && del < R;
-            const bool o = real && !incap;
-            const bool p = needs_patch_wave(real, v, d, h, eb, thr);
+            // the patch test in single precision (the exact one, for the few
+            // values it cannot settle, runs after the loop)
+            const bool pre = real && !(fabsf(__fsub_rn(v[z], dequant(d[z], h))) <= thr);
             uint16_t q = kNoSymbol;
             if (real) {
                 q = incap ? (uint16_t)(del + R) : (uint16_t)0;
                 atomicAdd(&sh_hist[q], 1u);
             }
             if (blk_ok) a.b.codes[blk * 512 + z * 64 + lane] = q;
-            flags_o |= (o ? 1u : 0u) << (j * 8 + z);
-            flags_p |= (p ? 1u : 0u) << (j * 8 + z);
-            const uint64_t mo = __ballot(o), mp = __ballot(p);
-            wave_count += __popcll(mo) + __popcll(mp);
-            wave_out += __popcll(mo);
-            wave_patch += __popcll(mp);
+            flags_o |= (real && !incap ? 1u : 0u) << (j * 8 + z);
+            flags_p |= (pre ? 1u : 0u) << (j * 8 + z);
         }
     }
+    if (__builtin_expect(__any((int)(flags_p != 0u)), 0)) {
+        // values the single-precision test could not settle: the exact test
+#pragma unroll
+        for (uint32_t j = 0; j < 2; j++) {
+            const uint32_t bxl = 2 * w + j;
+#pragma unroll
+            for (uint32_t z = 0; z < 8; z++) {
+                if (!((flags_p >> (j * 8 + z)) & 1u)) continue;
+                const float v = s_tile[z][ly][bxl * 8 + lx];
+                if (!needs_patch(v, prequant(v, r), h, eb)) flags_p &= ~(1u << (j * 8 + z));
+            }
+        }
+    }
+    const uint32_t wave_out = wave_sum<uint32_t>((uint32_t)__popc(flags_o));
+    const uint32_t wave_count = wave_out + wave_sum<uint32_t>((uint32_t)__popc(flags_p));
 
     uint32_t tile_count, tile_out;
     const uint32_t base0 = wave_base_in_tile(wave_count, wave_out, s_misc, tile_count, tile_out);
-    (void)wave_patch;
     if (wave_count) {
         uint32_t base = base0;
         const uint64_t below = lanes_below(lane);
