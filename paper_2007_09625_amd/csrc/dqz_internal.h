@@ -239,19 +239,12 @@ __device__ __forceinline__ bool needs_patch(float v, int32_t d, float h, double 
     const float xr = dequant(d, h);
     return !(fabs(__dsub_rn((double)v, (double)xr)) <= eb);
 }
-// The same decision, wave-wide, with the double-precision test only where a
-// single-precision one cannot settle it: |v - xr| rounded to fp32 is within
-// 2^-24 of the exact difference, so a rounded value <= thr (an fp32 at most
-// eb (1 - 2^-20)) means no patch; non-finite values fail that test and go
-// on to the exact one.
+// The quantize kernels take the same decision with the double-precision test
+// only where a single-precision one cannot settle it: |v - xr| rounded to
+// fp32 is within 2^-24 of the exact difference, so a rounded value <= thr
+// (an fp32 at most eb (1 - 2^-20)) means no patch; non-finite values fail
+// that test and go on to the exact one.
 __device__ __forceinline__ float patch_threshold(double eb) { return (float)(eb * (1.0 - 0x1p-20)); }
-__device__ __forceinline__ bool needs_patch_wave(bool real, float v, int32_t d, float h, double eb, float thr) {
-    bool p = real && !(fabsf(__fsub_rn(v, dequant(d, h))) <= thr);
-    if (__builtin_expect(__any((int)p), 0)) {
-        if (p) p = needs_patch(v, d, h, eb);
-    }
-    return p;
-}
 
 // ---------------------------------------------------------------------------
 // Launchers (defined in the kernel translation units).

@@ -430,33 +430,53 @@ __global__ __launch_bounds__(256) void k_quant2d(QuantArgs a) {
     const uint64_t blk = (uint64_t)By * a.g.nb[2] + Bx;
     int32_t delta[16];
     uint32_t flags_o = 0, flags_p = 0;
-    uint32_t my_count = 0, wave_out = 0, wave_patch = 0;
-    int32_t prev = 0;
+    const bool col_ok = blk_ok && gx < nx;
+    int32_t prev = 0;   // d° of (y-1) in this column; padding row is 0
 #pragma unroll
-    for (uint32_t y = 0; y < 16; y++) {
-        const bool real = blk_ok && gx < nx && (y0 + y) < ny;
-        const float v = s_tile[y][bxl * 16 + lx];
-        const int32_t d = prequant(v, r);
-        const uint32_t dy = (uint32_t)d - (uint32_t)prev;
-        prev = d;
-        const uint32_t up = __shfl_up(dy, 1, 64);
-        const int32_t del = (int32_t)(dy - (lx > 0 ? up : 0u));
-        delta[y] = del;
-        const bool incap = del > -R && del < R;
-        const bool o = real && !incap;
-        const bool p = needs_patch_wave(real, v, d, h, eb, thr);
-        uint16_t q = kNoSymbol;
-        if (real) {
-            q = incap ? (uint16_t)(del + R) : (uint16_t)0;
-            atomicAdd(&sh_hist[q], 1u);
+    for (uint32_t y0h = 0; y0h < 16; y0h += 8) {
+        // eight rows at a time: LDS reads, prequantization and the x
+        // exchanges of the eight in flight together
+        float v[8];
+        int32_t d[8];
+        uint32_t t[8], up[8];
+#pragma unroll
+        for (uint32_t k = 0; k < 8; k++) v[k] = s_tile[y0h + k][bxl * 16 + lx];
+#pragma unroll
+        for (uint32_t k = 0; k < 8; k++) d[k] = prequant(v[k], r);
+#pragma unroll
+        for (uint32_t k = 0; k < 8; k++) t[k] = (uint32_t)d[k] - (uint32_t)(k ? d[k - 1] : prev);
+        prev = d[7];
+#pragma unroll
+        for (uint32_t k = 0; k < 8; k++) up[k] = __shfl_up(t[k], 1, 64);
+#pragma unroll
+        for (uint32_t k = 0; k < 8; k++) {
+            const uint32_t y = y0h + k;
+            const int32_t del = (int32_t)(t[k] - (lx > 0 ? up[k] : 0u));
+            delta[y] = del;
+            const bool real = col_ok && (y0 + y) < ny;
+            const bool incap = del > -R && del < R;
+            // single-precision patch test; the exact one runs after the loop
+            const bool pre = real && !(fabsf(__fsub_rn(v[k], dequant(d[k], h))) <= thr);
+            uint16_t q = kNoSymbol;
+            if (real) {
+                q = incap ? (uint16_t)(del + R) : (uint16_t)0;
+                atomicAdd(&sh_hist[q], 1u);
+            }
+            if (blk_ok) a.b.codes[blk * 256 + y * 16 + lx] = q;
+            flags_o |= (real && !incap ? 1u : 0u) << y;
+            flags_p |= (pre ? 1u : 0u) << y;
         }
-        if (blk_ok) a.b.codes[blk * 256 + y * 16 + lx] = q;
-        flags_o |= (o ? 1u : 0u) << y;
-        flags_p |= (p ? 1u : 0u) << y;
-        my_count += (o ? 1u : 0u) + (p ? 1u : 0u);
-        wave_out += __popcll(__ballot(o));
-        wave_patch += __popcll(__ballot(p));
     }
+    if (__builtin_expect(__any((int)(flags_p != 0u)), 0)) {
+#pragma unroll
+        for (uint32_t y = 0; y < 16; y++) {
+            if (!((flags_p >> y) & 1u)) continue;
+            const float v = s_tile[y][bxl * 16 + lx];
+            if (!needs_patch(v, prequant(v, r), h, eb)) flags_p &= ~(1u << y);
+        }
+    }
+    const uint32_t my_count = (uint32_t)__popc(flags_o) + (uint32_t)__popc(flags_p);
+    const uint32_t wave_out = wave_sum<uint32_t>((uint32_t)__popc(flags_o));
     // records are ordered block by block: group totals, then exclusive over groups
     uint32_t grp_total = my_count;
 #pragma unroll
@@ -467,7 +487,6 @@ __global__ __launch_bounds__(256) void k_quant2d(QuantArgs a) {
     const uint32_t grp_off = (grp > 0 ? g0 : 0u) + (grp > 1 ? g1 : 0u) + (grp > 2 ? g2 : 0u);
     uint32_t tile_count, tile_out;
     const uint32_t base0 = wave_base_in_tile(wave_count, wave_out, s_misc, tile_count, tile_out);
-    (void)wave_patch;
     if (wave_count) {
         uint32_t base = base0 + grp_off;
         const uint64_t gmask = 0xFFFFull << (16 * grp);
@@ -541,7 +560,8 @@ __global__ __launch_bounds__(256) void k_quant1d(QuantArgs a) {
         const bool real = pos < n;
         const bool incap = del > -R && del < R;
         const bool o = real && !incap;
-        const bool p = needs_patch_wave(real, s_tile[16 * t + i], d[i], h, eb, thr);
+        // single-precision patch test; the exact one runs after the loop
+        const bool pre = real && !(fabsf(__fsub_rn(s_tile[16 * t + i], dequant(d[i], h))) <= thr);
         uint16_t qq = kNoSymbol;
         if (real) {
             qq = incap ? (uint16_t)(del + R) : (uint16_t)0;
@@ -549,9 +569,14 @@ __global__ __launch_bounds__(256) void k_quant1d(QuantArgs a) {
         }
         q[i] = qq;
         flags_o |= (o ? 1u : 0u) << i;
-        flags_p |= (p ? 1u : 0u) << i;
-        my_count += (o ? 1u : 0u) + (p ? 1u : 0u);
+        flags_p |= (pre ? 1u : 0u) << i;
     }
+    if (__builtin_expect(__any((int)(flags_p != 0u)), 0)) {
+#pragma unroll
+        for (uint32_t i = 0; i < 16; i++)
+            if (((flags_p >> i) & 1u) && !needs_patch(s_tile[16 * t + i], d[i], h, eb)) flags_p &= ~(1u << i);
+    }
+    my_count = (uint32_t)__popc(flags_o) + (uint32_t)__popc(flags_p);
     // codes: 16 consecutive u16 per thread (two 16-byte stores)
     {
         const uint64_t pos0 = p0 + 16 * t;
