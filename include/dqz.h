@@ -143,8 +143,9 @@ const char *dqz_ctx_last_error(const dqz_ctx *ctx);
  * two events around one stage of one call kind (the other stages read 0).
  * dqz_stage_times returns the elapsed microseconds of
  * each stage of the most recent call of that kind:
- *   compress   (which = 0): [0] init, [1] value range + eb (0 in absolute
- *              mode), [2] dual-quantization + histogram + exceptions, [3] their
+ *   compress   (which = 0): [0] scratch clearing (absolute mode; in the
+ *              value-range-relative mode the range kernel clears it and this
+ *              stage is 0), [1] value range + eb (0 in absolute mode), [2] dual-quantization + histogram + exceptions, [3] their
  *              tile scan (and the histogram sum), [4] codebook + header,
  *              [5] encode + deflate (widths, tile offsets, packing, one pass)
  *   decompress (which = 1): [0] decoding tables (and, for 128-position

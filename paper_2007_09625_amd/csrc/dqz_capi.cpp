@@ -459,9 +459,11 @@ dqz_status dqz_compress(dqz_ctx *ctx, const float *d_field, const dqz_shape *sha
         ctx->ev_ready[0] = false;
         mark(ctx, 0, 0, s);
         ctx->h_ctl->status = kNoReadback;   // the codebook kernel overwrites it
-        launch_init(s, ctl, ws + W.hist, W.zero_end - W.hist, params->eb_mode, params->eb);
+        // value-range-relative mode: the range kernel also clears the scratch
+        if (params->eb_mode != DQZ_EB_VALREL) launch_init(s, ctl, ws + W.hist, W.zero_end - W.hist, params->eb_mode, params->eb);
         mark(ctx, 0, 1, s);
-        if (params->eb_mode == DQZ_EB_VALREL) launch_minmax(s, d_field, P.g.nelem, ctl, parts, params->eb, ctx->ncu);
+        if (params->eb_mode == DQZ_EB_VALREL)
+            launch_minmax(s, d_field, P.g.nelem, ctl, parts, params->eb, ctx->ncu, ws + W.hist, W.zero_end - W.hist);
         mark(ctx, 0, 2, s);
         launch_quantize(s, d_field, P.g, P.L, ctl, qb);
         mark(ctx, 0, 3, s);

@@ -250,7 +250,9 @@ __device__ __forceinline__ float patch_threshold(double eb) { return (float)(eb 
 // Launchers (defined in the kernel translation units).
 // ---------------------------------------------------------------------------
 void launch_init(hipStream_t s, Ctl *ctl, void *zero_base, uint64_t zero_bytes, int eb_mode, double eb);
-void launch_minmax(hipStream_t s, const float *x, uint64_t n, Ctl *ctl, uint32_t *partials, double valrel, int ncu);
+// (also clears the control block and [zero_base, +zero_bytes), as launch_init does)
+void launch_minmax(hipStream_t s, const float *x, uint64_t n, Ctl *ctl, uint32_t *partials, double valrel, int ncu,
+                   void *zero_base, uint64_t zero_bytes);
 constexpr uint32_t kMinmaxMaxBlocks = 2048;
 struct QuantBufs {
     uint16_t *codes;

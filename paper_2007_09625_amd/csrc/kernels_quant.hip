@@ -41,7 +41,10 @@ __device__ void derive_eb(Ctl *ctl, double e) {
     ctl->r = r;
 }
 
-__global__ void k_init(Ctl *ctl, uint32_t *zero_base, uint64_t zero_words, int eb_mode, double eb) {
+// Clears the control block and the zeroed scratch (histogram replicas and
+// their sum, encoder look-back states); shared by k_init and, in the
+// value-range-relative mode, the range kernel (which saves a launch).
+__device__ __forceinline__ void clear_scratch(Ctl *ctl, uint32_t *zero_base, uint64_t zero_words) {
     const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t i = tid; i < zero_words; i += stride) zero_base[i] = 0u;
@@ -50,8 +53,12 @@ __global__ void k_init(Ctl *ctl, uint32_t *zero_base, uint64_t zero_words, int e
         for (uint32_t i = 0; i < sizeof(Ctl) / 4; i++) c[i] = 0u;
         ctl->vmin_key = 0xFFFFFFFFu;
         ctl->vmax_key = 0u;
-        if (eb_mode == 0) derive_eb(ctl, eb);
     }
+}
+
+__global__ void k_init(Ctl *ctl, uint32_t *zero_base, uint64_t zero_words, int eb_mode, double eb) {
+    clear_scratch(ctl, zero_base, zero_words);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && eb_mode == 0) derive_eb(ctl, eb);
 }
 
 void launch_init(hipStream_t s, Ctl *ctl, void *zero_base, uint64_t zero_bytes, int eb_mode, double eb) {
@@ -73,7 +80,9 @@ __device__ __forceinline__ void key_acc(uint32_t u, uint32_t &lo, uint32_t &hi) 
 // Pass 1: each workgroup reduces its grid-stride share and writes one
 // (min key, max key) pair; no atomics (same-address device atomics
 // serialize across the whole chip).
-__global__ __launch_bounds__(256) void k_minmax(const float *__restrict__ x, uint64_t n, uint32_t *partials) {
+__global__ __launch_bounds__(256) void k_minmax(const float *__restrict__ x, uint64_t n, uint32_t *partials, Ctl *ctl,
+                                                uint32_t *zero_base, uint64_t zero_words) {
+    clear_scratch(ctl, zero_base, zero_words);
     uint32_t lo = 0xFFFFFFFFu, hi = 0u;
     const uint64_t tid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -164,13 +173,15 @@ __global__ __launch_bounds__(256) void k_minmax_final(const uint32_t *partials, 
     }
 }
 
-void launch_minmax(hipStream_t s, const float *x, uint64_t n, Ctl *ctl, uint32_t *partials, double valrel, int ncu) {
+void launch_minmax(hipStream_t s, const float *x, uint64_t n, Ctl *ctl, uint32_t *partials, double valrel, int ncu,
+                   void *zero_base, uint64_t zero_bytes) {
     uint64_t want = (n / 4 + 255) / 256;
     uint64_t cap = (uint64_t)ncu * 8;
     if (cap > kMinmaxMaxBlocks) cap = kMinmaxMaxBlocks;
     uint32_t blocks = (uint32_t)(want < cap ? want : cap);
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_minmax, dim3(blocks), dim3(256), 0, s, x, n, partials);
+    hipLaunchKernelGGL(k_minmax, dim3(blocks), dim3(256), 0, s, x, n, partials, ctl, (uint32_t *)zero_base,
+                       zero_bytes / 4);
     hipLaunchKernelGGL(k_minmax_final, dim3(1), dim3(256), 0, s, partials, blocks, ctl, valrel);
 }
 
