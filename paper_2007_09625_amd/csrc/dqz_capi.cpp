@@ -472,7 +472,7 @@ dqz_status dqz_compress(dqz_ctx *ctx, const float *d_field, const dqz_shape *sha
         launch_codebook(s, P.g, P.L, ctl, qb.hist_sum, book, book32, arc, params->eb_mode, params->eb, qs,
                         ctx->d_hctl);
         mark(ctx, 0, 5, s);
-        launch_encode(s, P.g, P.L, ctl, ctx->d_hctl, eb, arc);
+        launch_encode(s, P.g, P.L, ctl, ctx->d_hctl, eb, arc, ctx->ncu);
         mark(ctx, 0, 6, s);
         HIP_TRY(ctx, hipGetLastError());
         HIP_TRY(ctx, wait_stream(s));

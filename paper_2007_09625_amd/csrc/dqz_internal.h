@@ -280,7 +280,7 @@ struct EncodeBufs {
     uint32_t n_tiles_q;
 };
 void launch_encode(hipStream_t s, const Geom &g, const Layout &L, Ctl *ctl, Ctl *hctl, const EncodeBufs &b,
-                   uint8_t *archive);
+                   uint8_t *archive, int ncu);
 uint32_t encode_tiles(const Geom &g);
 void launch_decode_tables(hipStream_t s, const Layout &L, const uint8_t *archive, uint32_t max_len_hdr,
                           DecodeTables *tab, uint32_t *hstatus, uint32_t n_exc, uint32_t *unit_exc,

@@ -414,14 +414,25 @@ __device__ __forceinline__ void enc_tile(const EncArgs &a, uint32_t t, uint32_t 
 // One kernel per codeword width, both launched: the width is a device value
 // (the longest code), and the one that does not apply returns at once.
 // Apart, the 32-bit path needs few enough registers for eight workgroups
-// per CU.
+// per CU.  The 64-bit path (codes over 24 bits, rare) is persistent with
+// one workgroup per CU taking tiles b, b + grid, ...: all its workgroups
+// are resident together, so every look-back still ends, and when it does
+// not apply only one workgroup per CU is dispatched to return.
 template <bool WIDE>
 __global__ __launch_bounds__(256) void k_enc_stream(EncArgs a) {
     extern __shared__ uint64_t s_dyn[];
     __shared__ EncLds S;
     if ((a.ctl->status & kBadStatus) || (a.ctl->max_len > 24) != WIDE) return;
     uint32_t *s_words = reinterpret_cast<uint32_t *>(s_dyn);   // PackWords<WIDE>::n, then nsym codewords
-    enc_tile<WIDE>(a, blockIdx.x, s_words, s_dyn + book_offset_u64(WIDE), S);
+    if (!WIDE) {
+        enc_tile<WIDE>(a, blockIdx.x, s_words, s_dyn + book_offset_u64(WIDE), S);
+        return;
+    }
+    const uint32_t tiles = a.n_tiles_e > a.b.n_tiles_q ? a.n_tiles_e : a.b.n_tiles_q;
+    for (uint32_t t = blockIdx.x; t < tiles; t += gridDim.x) {
+        enc_tile<WIDE>(a, t, s_words, s_dyn + book_offset_u64(WIDE), S);
+        __syncthreads();   // LDS is reused by the next tile
+    }
 }
 
 // One workgroup per segment: exclusive prefix of the tile values inside
@@ -460,7 +471,7 @@ void launch_seg_scan(hipStream_t s, const TileScan &S, const HistJob *hj) {
 uint32_t encode_tiles(const Geom &g) { return (uint32_t)((g.padded + kTile - 1) / kTile); }
 
 void launch_encode(hipStream_t s, const Geom &g, const Layout &L, Ctl *ctl, Ctl *hctl, const EncodeBufs &b,
-                   uint8_t *archive) {
+                   uint8_t *archive, int ncu) {
     EncArgs a;
     a.g = g;
     a.L = L;
@@ -473,7 +484,8 @@ void launch_encode(hipStream_t s, const Geom &g, const Layout &L, Ctl *ctl, Ctl 
     if (grid == 0) return;
     const size_t lds = enc_lds_bytes(L.nsym);
     hipLaunchKernelGGL(k_enc_stream<false>, dim3(grid), dim3(256), lds, s, a);
-    hipLaunchKernelGGL(k_enc_stream<true>, dim3(grid), dim3(256), lds, s, a);
+    const uint32_t wide_grid = ncu > 0 && (uint32_t)ncu < grid ? (uint32_t)ncu : grid;
+    hipLaunchKernelGGL(k_enc_stream<true>, dim3(wide_grid), dim3(256), lds, s, a);
 }
 
 }  // namespace dqz
