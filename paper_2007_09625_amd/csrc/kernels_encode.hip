@@ -263,20 +263,18 @@ __device__ __forceinline__ void pack_run(const EncArgs &a, uint64_t p0, uint64_t
     }
 }
 
-// A run spans at most kPackWords<WIDE> words: a whole tile of codes up to 24
-// bits (32-bit codewords), or a quarter tile of codes up to 64 bits (the
-// 64-bit codeword path packs a tile in four runs).  Both word buffers and
-// their codebooks take the same LDS.
-constexpr uint32_t kRuns64 = 4;
+// A run spans at most PackWords<WIDE>::n words: a whole tile of codes up to
+// 24 bits (32-bit codewords), or half a tile of codes up to 64 bits (the
+// 64-bit codeword path packs a tile in two runs).  Each kernel's LDS holds
+// its word buffer and its codebook.
+constexpr uint32_t kRuns64 = 2;
 template <bool WIDE> struct PackWords { static constexpr uint32_t n = kTile * 24 / 32 + 2; };
 template <> struct PackWords<true> { static constexpr uint32_t n = kTile / kRuns64 * 64 / 32 + 2; };
 __host__ __device__ constexpr uint32_t book_offset_u64(bool wide) {
     return ((wide ? PackWords<true>::n : PackWords<false>::n) + 1) / 2;
 }
-size_t enc_lds_bytes(uint32_t nsym) {
-    const size_t narrow = 8 * (size_t)book_offset_u64(false) + 4 * (size_t)nsym;
-    const size_t wide = 8 * (size_t)book_offset_u64(true) + 8 * (size_t)nsym;
-    return narrow > wide ? narrow : wide;
+size_t enc_lds_bytes(bool wide, uint32_t nsym) {
+    return 8 * (size_t)book_offset_u64(wide) + (wide ? 8 : 4) * (size_t)nsym;
 }
 
 struct EncLds {
@@ -412,27 +410,17 @@ __device__ __forceinline__ void enc_tile(const EncArgs &a, uint32_t t, uint32_t 
 }
 
 // One kernel per codeword width, both launched: the width is a device value
-// (the longest code), and the one that does not apply returns at once.
-// Apart, the 32-bit path needs few enough registers for eight workgroups
-// per CU.  The 64-bit path (codes over 24 bits, rare) is persistent with
-// one workgroup per CU taking tiles b, b + grid, ...: all its workgroups
-// are resident together, so every look-back still ends, and when it does
-// not apply only one workgroup per CU is dispatched to return.
+// (the longest code; over 24 bits is common at larger error bounds, where
+// rare symbols get long codes), and the one that does not apply returns at
+// once.  Apart, the 32-bit path needs few enough registers for eight
+// workgroups per CU.
 template <bool WIDE>
 __global__ __launch_bounds__(256) void k_enc_stream(EncArgs a) {
     extern __shared__ uint64_t s_dyn[];
     __shared__ EncLds S;
     if ((a.ctl->status & kBadStatus) || (a.ctl->max_len > 24) != WIDE) return;
     uint32_t *s_words = reinterpret_cast<uint32_t *>(s_dyn);   // PackWords<WIDE>::n, then nsym codewords
-    if (!WIDE) {
-        enc_tile<WIDE>(a, blockIdx.x, s_words, s_dyn + book_offset_u64(WIDE), S);
-        return;
-    }
-    const uint32_t tiles = a.n_tiles_e > a.b.n_tiles_q ? a.n_tiles_e : a.b.n_tiles_q;
-    for (uint32_t t = blockIdx.x; t < tiles; t += gridDim.x) {
-        enc_tile<WIDE>(a, t, s_words, s_dyn + book_offset_u64(WIDE), S);
-        __syncthreads();   // LDS is reused by the next tile
-    }
+    enc_tile<WIDE>(a, blockIdx.x, s_words, s_dyn + book_offset_u64(WIDE), S);
 }
 
 // One workgroup per segment: exclusive prefix of the tile values inside
@@ -482,10 +470,9 @@ void launch_encode(hipStream_t s, const Geom &g, const Layout &L, Ctl *ctl, Ctl 
     a.n_tiles_e = encode_tiles(g);
     const uint32_t grid = a.n_tiles_e > b.n_tiles_q ? a.n_tiles_e : b.n_tiles_q;
     if (grid == 0) return;
-    const size_t lds = enc_lds_bytes(L.nsym);
-    hipLaunchKernelGGL(k_enc_stream<false>, dim3(grid), dim3(256), lds, s, a);
-    const uint32_t wide_grid = ncu > 0 && (uint32_t)ncu < grid ? (uint32_t)ncu : grid;
-    hipLaunchKernelGGL(k_enc_stream<true>, dim3(wide_grid), dim3(256), lds, s, a);
+    (void)ncu;
+    hipLaunchKernelGGL(k_enc_stream<false>, dim3(grid), dim3(256), enc_lds_bytes(false, L.nsym), s, a);
+    hipLaunchKernelGGL(k_enc_stream<true>, dim3(grid), dim3(256), enc_lds_bytes(true, L.nsym), s, a);
 }
 
 }  // namespace dqz

@@ -303,8 +303,11 @@ struct BookLds {
 // found by one wave with 64-way probes of both arrays at once: about
 // log64(m) dependent LDS reads.  The probe positions are uniform arithmetic,
 // so no lane exchange is needed.
+// Also returns A[ca - 1] and B[cb - 1] when ca, cb > 0 (read from the last
+// probe window when they lie in it).
 __device__ __forceinline__ void wave_count_le2(const uint32_t *A, uint32_t ma, const uint32_t *B, uint32_t mb,
-                                               uint32_t t, uint32_t lane, uint32_t &ca, uint32_t &cb) {
+                                               uint32_t t, uint32_t lane, uint32_t &ca, uint32_t &cb,
+                                               uint32_t &lasta, uint32_t &lastb) {
     uint32_t loa = 0, hia = ma, lob = 0, hib = mb;   // each count lies in [lo, hi]
     while (hia - loa > 64 || hib - lob > 64) {
         const uint32_t sa = hia - loa, sb = hib - lob;
@@ -326,6 +329,8 @@ __device__ __forceinline__ void wave_count_le2(const uint32_t *A, uint32_t ma, c
     const uint32_t va = A[ia < hia ? ia : 0], vb = B[ib < hib ? ib : 0];
     ca = loa + (uint32_t)__popcll(__ballot(ia < hia && va <= t));
     cb = lob + (uint32_t)__popcll(__ballot(ib < hib && vb <= t));
+    lasta = ca > loa ? (uint32_t)__builtin_amdgcn_readlane((int)va, (int)(ca - loa - 1)) : (ca ? A[ca - 1] : 0u);
+    lastb = cb > lob ? (uint32_t)__builtin_amdgcn_readlane((int)vb, (int)(cb - lob - 1)) : (cb ? B[cb - 1] : 0u);
 }
 
 // LDS read at a clamped index: loads that may fall past a queue's end are
@@ -422,9 +427,13 @@ __global__ __launch_bounds__(kBookThreads) void k_codebook(const uint32_t *__res
         uint32_t la = 0, ib = 0, ic = 0, rounds = 0;
         for (;;) {
             if ((n - la) + (ic - ib) <= 1) break;
-            // T, from the first two items of each queue
-            const uint32_t l0 = ldc(s.leaf_w, la), l1 = ldc(s.leaf_w, la + 1);
-            const uint32_t i0 = ldc(s.int_w, ib), i1 = ldc(s.int_w, ib + 1);
+            // T, from the first two items of each queue (lanes 0..3 read
+            // them together)
+            const uint32_t hv = lane < 2u ? ldc(s.leaf_w, la + lane) : ldc(s.int_w, ib + (lane & 1u));
+            const uint32_t l0 = (uint32_t)__builtin_amdgcn_readlane((int)hv, 0);
+            const uint32_t l1 = (uint32_t)__builtin_amdgcn_readlane((int)hv, 1);
+            const uint32_t i0 = (uint32_t)__builtin_amdgcn_readlane((int)hv, 2);
+            const uint32_t i1 = (uint32_t)__builtin_amdgcn_readlane((int)hv, 3);
             uint32_t Tw;
             {
                 uint32_t a = 0, b = 0, t = 0;
@@ -440,10 +449,9 @@ __global__ __launch_bounds__(kBookThreads) void k_codebook(const uint32_t *__res
             }
             // items of weight <= T: prefixes of both sorted queues (each wave
             // finds them itself, so no barrier is needed)
-            uint32_t nl, ni;
-            wave_count_le2(s.leaf_w + la, n - la, s.int_w + ib, ic - ib, Tw, lane, nl, ni);
+            uint32_t nl, ni, lastl, lasti;
+            wave_count_le2(s.leaf_w + la, n - la, s.int_w + ib, ic - ib, Tw, lane, nl, ni, lastl, lasti);
             if ((nl + ni) & 1u) {   // odd: the last item of the merged order waits
-                const uint32_t lastl = ldc(s.leaf_w, la + nl - 1), lasti = ldc(s.int_w, ib + ni - 1);
                 const bool int_last = ni > 0 && (nl == 0 || lasti >= lastl);
                 if (int_last) ni--; else nl--;
             }
