@@ -688,12 +688,28 @@ __device__ void exception_index(const uint2 *exc, uint32_t n_exc, uint32_t *unit
 // entries (or as many as fit at width 1), entry (v - V0) * 2^b + i holds the
 // code whose first kLutBits + b bits are v, i, when it is that short (0
 // otherwise: the decoder then takes the canonical limits).
-__device__ void build_lut2(const CanonScratch &c, DecodeTables *tab, uint64_t *lim) {
+// The length of the code that a left-aligned stream window w starts with,
+// given that it is longer than kLutBits: the first l in (kLutBits, max_len)
+// with w < lim[l], else max_len (lim is nondecreasing: the left-aligned end
+// of the codes of length <= l), by binary search.
+__device__ __forceinline__ uint32_t long_code_len(const uint64_t *lim, uint64_t w, uint32_t max_len) {
+    uint32_t lo = kLutBits + 1, hi = max_len > lo ? max_len : lo;
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (w >= lim[mid]) lo = mid + 1; else hi = mid;
+    }
+    return lo;
+}
+
+// lim[l] for l = 0..64 (lim[0] = 0, lim[64] = ~0), one workgroup
+__device__ void build_limits(const CanonScratch &c, uint64_t *lim) {
+    for (uint32_t l = threadIdx.x; l < 65; l += blockDim.x)
+        lim[l] = (l == 0) ? 0ull : (l == 64 ? ~0ull : ((c.first_code[l] + c.count[l]) << (64 - l)));
+}
+
+__device__ void build_lut2(const CanonScratch &c, DecodeTables *tab, const uint64_t *lim) {
     const uint32_t tid = threadIdx.x, T = blockDim.x;
     const uint32_t max_len = c.max_len;
-    for (uint32_t l = tid; l < 65; l += T)
-        lim[l] = (l == 0) ? 0ull : (l == 64 ? ~0ull : ((c.first_code[l] + c.count[l]) << (64 - l)));
-    __syncthreads();
     // codes of <= kLutBits bits fill [0, V0) of the prefixes; no long codes: V0 = 2^kLutBits
     const uint32_t V0 = max_len > kLutBits ? (uint32_t)(lim[kLutBits] >> (64 - kLutBits)) : (1u << kLutBits);
     const uint32_t n_long = (1u << kLutBits) - V0;
@@ -707,8 +723,7 @@ __device__ void build_lut2(const CanonScratch &c, DecodeTables *tab, uint64_t *l
     }
     for (uint32_t j = tid; j < n2; j += T) {
         const uint64_t wv = (uint64_t)((V0 << b) + j) << (64 - kLutBits - b);
-        uint32_t l = kLutBits + 1;
-        while (l < max_len && wv >= lim[l]) l++;
+        const uint32_t l = long_code_len(lim, wv, max_len);
         uint32_t e = 0;
         if (l <= kLutBits + b) {
             const uint64_t code = wv >> (64 - l);
@@ -774,6 +789,9 @@ __global__ __launch_bounds__(kTableThreads) void k_decode_tables(const uint8_t *
         const uint64_t k = c.key[i];
         tab->sorted[i] = (k == ~0ull) ? 0 : (uint16_t)(k & 0xFFFF);
     }
+    // the left-aligned limits (the long-code searches below read them)
+    build_limits(c, c.xch);
+    __syncthreads();
     // each table slot v (the next kLutBits stream bits): its code length is
     // 1 + the number of lengths l <= kLutBits whose codes all lie below v
     // (canonical codes of length <= l fill [0, limit_l)); longer codes get the
@@ -819,15 +837,13 @@ __global__ __launch_bounds__(kTableThreads) void k_decode_tables(const uint8_t *
             e = (l << 11) | (uint32_t)(key[i] & 0x7FF);
         } else if (c.max_len > kLutBits) {
             // a long-code prefix: the shortest length that can follow
-            const uint64_t w = (uint64_t)v << (64 - kLutBits);
-            uint32_t ll = kLutBits + 1;
-            while (ll < c.max_len && w >= ((c.first_code[ll] + c.count[ll]) << (64 - ll))) ll++;
-            e = 0x8000u | ll;
+            e = 0x8000u | long_code_len(c.xch, (uint64_t)v << (64 - kLutBits), c.max_len);
         }
         tab->lut[v] = (uint16_t)e;
     }
     __syncthreads();
-    // the second-level table (its limits reuse the sort exchange buffer)
+    // the second-level table (its limits, in the sort exchange buffer, were
+    // built before the first level)
     build_lut2(c, tab, c.xch);
     __syncthreads();
     if (tid == 0) tab->phase[2] = wall_clock64();
