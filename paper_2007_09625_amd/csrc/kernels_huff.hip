@@ -25,27 +25,6 @@ namespace dqz {
 constexpr uint32_t kBookThreads = 256;
 constexpr uint32_t kTableThreads = 1024;   // decoding tables: one workgroup fills the 8192-entry table
 
-// Value of lane (lane ^ D) within the wave: DPP quad permutes for D = 1, 2,
-// row shifts for 4, a row rotate for 8, the row-pair and half-wave swaps
-// for 16 and 32 (all in the VALU, no LDS round trip).
-template <uint32_t D>
-__device__ __forceinline__ uint32_t xor_lane32(uint32_t v, uint32_t lane) {
-    static_assert(D == 1 || D == 2 || D == 4 || D == 8 || D == 16 || D == 32, "lane distance");
-    if (D == 1) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
-    if (D == 2) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
-    if (D == 4) {
-        const uint32_t up = (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x104, 0xF, 0xF, false);   // row_shl:4
-        const uint32_t dn = (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x114, 0xF, 0xF, false);   // row_shr:4
-        return (lane & 4u) ? dn : up;
-    }
-    if (D == 8) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x128, 0xF, 0xF, false);   // row_ror:8
-    if (D == 16) {
-        const auto p = __builtin_amdgcn_permlane16_swap(v, v, false, false);
-        return (lane & 16u) ? p[0] : p[1];
-    }
-    const auto p = __builtin_amdgcn_permlane32_swap(v, v, false, false);
-    return (lane & 32u) ? p[0] : p[1];
-}
 template <uint32_t D>
 __device__ __forceinline__ uint64_t xor_lane64(uint64_t v, uint32_t lane) {
     const uint32_t lo = xor_lane32<D>((uint32_t)v, lane), hi = xor_lane32<D>((uint32_t)(v >> 32), lane);

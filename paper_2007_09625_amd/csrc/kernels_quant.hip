@@ -305,6 +305,7 @@ __global__ __launch_bounds__(256) void k_quant3d(QuantArgs a) {
     const uint32_t ly = lane / 8, lx = lane % 8;
     int32_t delta[2][8];
     uint32_t flags_o = 0, flags_p = 0;   // bit (j*8 + z)
+    uint32_t n_zero = 0;   // codes of delta 0 (bin R), added once per wave
 #pragma unroll
     for (uint32_t j = 0; j < 2; j++) {
         const uint32_t bxl = 2 * w + j;              // block within tile
@@ -344,7 +345,8 @@ __global__ __launch_bounds__(256) void k_quant3d(QuantArgs a) {
             uint16_t q = kNoSymbol;
             if (real) {
                 q = incap ? (uint16_t)(del + R) : (uint16_t)0;
-                atomicAdd(&sh_hist[q], 1u);
+                if (del == 0) n_zero++;   // the usually hottest bin: counted in a register
+                else atomicAdd(&sh_hist[q], 1u);
             }
             if (blk_ok) a.b.codes[blk * 512 + z * 64 + lane] = q;
             flags_o |= (real && !incap ? 1u : 0u) << (j * 8 + z);
@@ -364,8 +366,8 @@ __global__ __launch_bounds__(256) void k_quant3d(QuantArgs a) {
             }
         }
     }
-    const uint32_t wave_out = wave_sum<uint32_t>((uint32_t)__popc(flags_o));
-    const uint32_t wave_count = wave_out + wave_sum<uint32_t>((uint32_t)__popc(flags_p));
+    const uint32_t wave_out = wave_sum_xor((uint32_t)__popc(flags_o));
+    const uint32_t wave_count = wave_out + wave_sum_xor((uint32_t)__popc(flags_p));
 
     uint32_t tile_count, tile_out;
     const uint32_t base0 = wave_base_in_tile(wave_count, wave_out, s_misc, tile_count, tile_out);
@@ -389,6 +391,8 @@ __global__ __launch_bounds__(256) void k_quant3d(QuantArgs a) {
             }
         }
     }
+    n_zero = wave_sum_xor(n_zero);
+    if (lane_id() == 0 && n_zero) atomicAdd(&sh_hist[R], n_zero);
     tile_epilogue(a, tile, tile_count, tile_out, sh_hist, s_scan);
 }
 
@@ -441,6 +445,7 @@ __global__ __launch_bounds__(256) void k_quant2d(QuantArgs a) {
     const uint64_t blk = (uint64_t)By * a.g.nb[2] + Bx;
     int32_t delta[16];
     uint32_t flags_o = 0, flags_p = 0;
+    uint32_t n_zero = 0;   // codes of delta 0 (bin R), added once per wave
     const bool col_ok = blk_ok && gx < nx;
     int32_t prev = 0;   // d° of (y-1) in this column; padding row is 0
 #pragma unroll
@@ -471,7 +476,8 @@ __global__ __launch_bounds__(256) void k_quant2d(QuantArgs a) {
             uint16_t q = kNoSymbol;
             if (real) {
                 q = incap ? (uint16_t)(del + R) : (uint16_t)0;
-                atomicAdd(&sh_hist[q], 1u);
+                if (del == 0) n_zero++;   // the usually hottest bin: counted in a register
+                else atomicAdd(&sh_hist[q], 1u);
             }
             if (blk_ok) a.b.codes[blk * 256 + y * 16 + lx] = q;
             flags_o |= (real && !incap ? 1u : 0u) << y;
@@ -487,7 +493,7 @@ __global__ __launch_bounds__(256) void k_quant2d(QuantArgs a) {
         }
     }
     const uint32_t my_count = (uint32_t)__popc(flags_o) + (uint32_t)__popc(flags_p);
-    const uint32_t wave_out = wave_sum<uint32_t>((uint32_t)__popc(flags_o));
+    const uint32_t wave_out = wave_sum_xor((uint32_t)__popc(flags_o));
     // records are ordered block by block: group totals, then exclusive over groups
     uint32_t grp_total = my_count;
 #pragma unroll
@@ -514,6 +520,8 @@ __global__ __launch_bounds__(256) void k_quant2d(QuantArgs a) {
             base += __popcll(mo & gmask) + __popcll(mp & gmask);
         }
     }
+    n_zero = wave_sum_xor(n_zero);
+    if (lane_id() == 0 && n_zero) atomicAdd(&sh_hist[R], n_zero);
     tile_epilogue(a, tile, tile_count, tile_out, sh_hist, s_scan);
 }
 
@@ -559,6 +567,7 @@ __global__ __launch_bounds__(256) void k_quant1d(QuantArgs a) {
     const uint32_t nb_prev = __shfl_up((uint32_t)d[15], 1, 64);
     int32_t delta[16];
     uint32_t flags_o = 0, flags_p = 0, my_count = 0;
+    uint32_t n_zero = 0;   // codes of delta 0 (bin R), added once per wave
     uint16_t q[16];
 #pragma unroll
     for (uint32_t i = 0; i < 16; i++) {
@@ -576,7 +585,8 @@ __global__ __launch_bounds__(256) void k_quant1d(QuantArgs a) {
         uint16_t qq = kNoSymbol;
         if (real) {
             qq = incap ? (uint16_t)(del + R) : (uint16_t)0;
-            atomicAdd(&sh_hist[qq], 1u);
+            if (del == 0) n_zero++;   // the usually hottest bin: counted in a register
+            else atomicAdd(&sh_hist[qq], 1u);
         }
         q[i] = qq;
         flags_o |= (o ? 1u : 0u) << i;
@@ -608,8 +618,8 @@ __global__ __launch_bounds__(256) void k_quant1d(QuantArgs a) {
     }
     const uint32_t incl = wave_incl_scan<uint32_t>(my_count);
     const uint32_t wave_count = __shfl(incl, 63, 64);
-    const uint32_t wave_out = wave_sum<uint32_t>(__popc(flags_o));
-    const uint32_t wave_patch = wave_sum<uint32_t>(__popc(flags_p));
+    const uint32_t wave_out = wave_sum_xor(__popc(flags_o));
+    const uint32_t wave_patch = wave_sum_xor(__popc(flags_p));
     uint32_t tile_count, tile_out;
     const uint32_t base0 = wave_base_in_tile(wave_count, wave_out, s_misc, tile_count, tile_out);
     (void)wave_patch;
@@ -622,6 +632,8 @@ __global__ __launch_bounds__(256) void k_quant1d(QuantArgs a) {
             if ((flags_p >> i) & 1u) put_exc(a, tile, idx++, 2u * pos + 1u, __float_as_uint(s_tile[16 * t + i]));
         }
     }
+    n_zero = wave_sum_xor(n_zero);
+    if (lane_id() == 0 && n_zero) atomicAdd(&sh_hist[R], n_zero);
     tile_epilogue(a, tile, tile_count, tile_out, sh_hist, s_scan);
 }
 
