@@ -581,7 +581,7 @@ __global__ __launch_bounds__(64 * kDecMaxWaves) void k_decode(DecArgs a) {
 // ---------------------------------------------------------------------------
 constexpr uint32_t kInfMaxWaves = 14; // waves per inflate workgroup, at most (they share the lookup tables)
 constexpr uint32_t kInfWin = 2432;    // LDS stream-window words per wave (9.5 KiB)
-constexpr uint32_t kReconWaves = 4;   // units (one per wave) per reconstruction workgroup
+constexpr uint32_t kReconWaves = 8;   // units (one per wave) per reconstruction workgroup (8 measured best against 2, 4, 16)
 
 // Both lookup-table levels into LDS: 16-byte copies, eight of a thread's
 // loads in flight (the tables are 256-byte aligned, the second level starts
