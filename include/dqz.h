@@ -15,21 +15,30 @@
  *   -> encode + deflate into one bit-dense stream (Sec. 3.2.4).
  * Decompression (Sec. 3.3): inflate, then reversed dual-quantization.
  *
- * Guarantee: every finite input element comes back within eb_abs,
- * |x - x'| <= eb_abs evaluated in double precision; non-finite elements
- * come back bit-exact.  Elements whose fp32 reconstruction would miss the
- * bound are stored verbatim ("patches", the paper's rehearsal/watchdog idea
- * of Algorithm 1 applied to the final fp32 value).
+ * Guarantee (the error-bounded problem statement of Sec. 2): every finite
+ * input element comes back within eb_abs, |x - x'| <= eb_abs evaluated in
+ * double precision; non-finite elements come back bit-exact.  Elements whose
+ * fp32 reconstruction would miss the bound are stored verbatim ("patches",
+ * the rehearsal/watchdog idea of Algorithm 1 applied to the final fp32
+ * value).
  *
  * Conventions for every entry point:
  *   - Pointers named d_* are device pointers on the context's GPU; h_* are
  *     host pointers.  The caller owns all of them; the library never frees
  *     caller memory and never writes outside [ptr, ptr + capacity).
  *   - `stream` is a hipStream_t (NULL = the legacy default stream).  Work is
- *     stream-ordered; dqz_compress blocks only to read back the archive
- *     size and status (a few hundred bytes) at its end.
- *   - Calls on one context must not overlap (the context owns the device
- *     scratch); separate contexts are independent.
+ *     stream-ordered.  dqz_compress / dqz_decompress wait for their own work
+ *     at the end (to read back size and status, a few hundred bytes); the
+ *     _async variants return after enqueueing and write the same facts into
+ *     a caller-provided dqz_result, so a sequence of them can be captured in
+ *     a HIP graph.
+ *   - Device memory: a context owns one device workspace, allocated by
+ *     dqz_ctx_create / dqz_ctx_reserve only.  dqz_compress, dqz_decompress
+ *     and their _async variants never allocate or free memory; a call that
+ *     needs more workspace than the context holds fails with DQZ_ENOMEM and
+ *     dqz_ctx_workspace then reports the size that would have sufficed.
+ *   - Calls on one context must not overlap (they share its workspace);
+ *     separate contexts are independent.
  *   - Every function returns DQZ_OK (0) or a negative dqz_status; no C++
  *     exception crosses this boundary.  On error, output buffers hold
  *     unspecified bytes and the context stays usable.
@@ -64,7 +73,7 @@ typedef int32_t dqz_status;
 #define DQZ_OK 0
 #define DQZ_EINVAL (-1)       /* bad argument: shape, eb, radius, sizes, null pointer */
 #define DQZ_ETOOSMALL (-2)    /* archive or field capacity too small */
-#define DQZ_ENOMEM (-3)       /* device or pinned host allocation failed */
+#define DQZ_ENOMEM (-3)       /* workspace too small, or a device / pinned host allocation failed */
 #define DQZ_ECORRUPT (-4)     /* archive fails validation */
 #define DQZ_EUNSUPPORTED (-5) /* valid request outside this build's limits */
 #define DQZ_EHIP (-6)         /* a HIP runtime call failed (message in dqz_ctx_last_error) */
@@ -89,32 +98,87 @@ typedef struct {
 typedef struct {
     double eb;           /* error bound, finite and > 0 */
     int32_t eb_mode;     /* DQZ_EB_ABS or DQZ_EB_VALREL */
-    uint32_t radius;     /* code cap R: power of two in [1, 4096]; 2R quantization bins (default 512) */
+    uint32_t radius;     /* code cap R: power of two in [1, 1024]; 2R quantization bins (default 512) */
     uint32_t sub_size;   /* positions per subchunk: power of two in [32, 1024] (default 128) */
     uint32_t chunk_subs; /* subchunks per chunk: power of two in [1, 65536] (default 64) */
 } dqz_params;
 
+/* What an _async call reports, written by its kernels into device-visible
+ * memory (device memory, or mapped pinned host memory), 8-byte aligned:
+ *   status          dqz_status of the device-side work (DQZ_OK, DQZ_ETOOSMALL,
+ *                   DQZ_ENOMEM, DQZ_ECORRUPT, DQZ_EUNSUPPORTED, DQZ_EINVAL,
+ *                   DQZ_EINTERNAL)
+ *   archive_bytes   compression: the archive size (also with DQZ_ETOOSMALL);
+ *                   decompression: the archive size read from its header
+ *   workspace_need  with DQZ_ENOMEM: the workspace bytes that would have sufficed
+ *   header          compression: the archive's 128-byte header
+ * The fields are final once the stream has passed the call's work. */
+typedef struct {
+    uint32_t flags;      /* device status flags (diagnostic) */
+    int32_t status;
+    uint64_t archive_bytes;
+    uint64_t workspace_need;
+    uint64_t reserved;
+    uint8_t header[DQZ_HEADER_BYTES];
+} dqz_result;
+
 typedef struct dqz_ctx dqz_ctx;
 
-/* Create a context on HIP device `device`; device scratch is allocated on
- * first use and kept (grown on demand) until dqz_ctx_destroy. */
-dqz_status dqz_ctx_create(int device, dqz_ctx **out);
+/* Create a context on HIP device `device` holding `workspace_cap` bytes of
+ * device workspace (0: none yet; reserve before the first call).  The
+ * workspace holds every intermediate of a call (control block, histogram,
+ * codebook, scan states, staged exception records, code array, decoding
+ * tables) and stays resident across calls.  DQZ_ENOMEM if it cannot be
+ * allocated.  Supports the paper's GPU-resident pipeline (Sec. 3, data kept
+ * on the device, Sec. 4.2.1). */
+dqz_status dqz_ctx_create(int device, uint64_t workspace_cap, dqz_ctx **out);
 void dqz_ctx_destroy(dqz_ctx *ctx);
 
+/* Grow the context's workspace to at least `workspace_bytes` (no-op if it is
+ * already that large).  The only place besides dqz_ctx_create that allocates
+ * device memory; must not overlap a call on this context.  DQZ_ENOMEM on
+ * failure (the old workspace is kept). */
+dqz_status dqz_ctx_reserve(dqz_ctx *ctx, uint64_t workspace_bytes);
+
+/* Host-only: the workspace the context holds, and the workspace the most
+ * recent call on it needed (after DQZ_ENOMEM: the size that would have
+ * sufficed).  Either output may be NULL. */
+dqz_status dqz_ctx_workspace(const dqz_ctx *ctx, uint64_t *workspace_bytes, uint64_t *last_need);
+
 /* Host-only: worst-case archive size for this shape and parameters (every
- * element an outlier and a patch, longest codes) and the device scratch the
- * context will hold for it.  Either output pointer may be NULL. */
+ * element an outlier and a patch, longest codes) and the workspace with
+ * which dqz_compress never fails with DQZ_ENOMEM (a typical field needs
+ * about 3 bytes per element of it; exception records past a tile's staging
+ * slot take the rest).  Either output pointer may be NULL.  Sizes follow
+ * the archive layout above (Sec. 3.2.4 deflate output plus tables). */
 dqz_status dqz_compress_bound(const dqz_shape *shape, const dqz_params *params,
                               uint64_t *archive_max, uint64_t *workspace_bytes);
 
+/* Host-only: the workspace dqz_decompress needs for the archive whose
+ * 128-byte header is at h_header.  DQZ_ECORRUPT for a bad header. */
+dqz_status dqz_decompress_bound(const void *h_header, uint64_t header_bytes, uint64_t *workspace_bytes);
+
 /* Compress the fp32 field at d_field (row-major, `shape`) into d_archive
- * (capacity archive_cap bytes).  On success *archive_bytes holds the archive
- * size; if h_header is non-NULL the 128-byte header is copied there too.  If
- * the archive does not fit, returns DQZ_ETOOSMALL and *archive_bytes holds
- * the size that would have been needed when it is known (0 otherwise). */
+ * (capacity archive_cap bytes): the whole of Sec. 3.1-3.2 (range and error
+ * bound, dual-quantization with outliers, histogram, codebook, encode +
+ * deflate).  On success *archive_bytes holds the archive size; if h_header
+ * is non-NULL the 128-byte header is copied there too.  If the archive does
+ * not fit, returns DQZ_ETOOSMALL and *archive_bytes holds the size that
+ * would have been needed when it is known (0 otherwise).  DQZ_ENOMEM when
+ * the workspace is too small (dqz_ctx_workspace tells how much is needed). */
 dqz_status dqz_compress(dqz_ctx *ctx, const float *d_field, const dqz_shape *shape,
                         const dqz_params *params, void *d_archive, uint64_t archive_cap,
                         uint64_t *archive_bytes, void *h_header, void *stream);
+
+/* dqz_compress without waiting: enqueues the same kernels on `stream` and
+ * returns; status, archive size and header arrive in *d_result (see
+ * dqz_result).  The return value covers only the host-side checks (arguments,
+ * workspace size).  Nothing in it synchronizes, allocates or sets memory, so
+ * a stream capture of it is a valid HIP graph; field, archive, result and
+ * the context's workspace must stay valid while the work runs. */
+dqz_status dqz_compress_async(dqz_ctx *ctx, const float *d_field, const dqz_shape *shape,
+                              const dqz_params *params, void *d_archive, uint64_t archive_cap,
+                              dqz_result *d_result, void *stream);
 
 /* Host-only: parse and validate a 128-byte header.  Any output may be NULL.
  * field_elems = product of the dims. */
@@ -122,27 +186,37 @@ dqz_status dqz_archive_info(const void *h_header, uint64_t header_bytes, dqz_sha
                             dqz_params *params, uint64_t *field_elems, uint64_t *archive_bytes);
 
 /* Decompress the archive at d_archive (archive_bytes long) into d_field
- * (capacity field_cap_elems floats, row-major).  h_header may point to a
- * host copy of the archive's 128-byte header (skips a device->host read);
- * NULL reads it from d_archive.  Returns DQZ_ECORRUPT for an archive that
- * fails validation (the field then holds unspecified values). */
+ * (capacity field_cap_elems floats, row-major): inflate and reversed
+ * dual-quantization (Sec. 3.3, the decompression half of Algorithm 2).
+ * h_header may point to a host copy of the archive's 128-byte header (skips
+ * a device->host read); NULL reads it from d_archive.  Returns DQZ_ECORRUPT
+ * for an archive that fails validation (the field then holds unspecified
+ * values), DQZ_ENOMEM when the workspace is too small. */
 dqz_status dqz_decompress(dqz_ctx *ctx, const void *d_archive, uint64_t archive_bytes,
                           const void *h_header, float *d_field, uint64_t field_cap_elems,
                           void *stream);
+
+/* dqz_decompress without waiting (h_header is required); the device-side
+ * status arrives in d_result->status.  Graph-capturable like
+ * dqz_compress_async. */
+dqz_status dqz_decompress_async(dqz_ctx *ctx, const void *d_archive, uint64_t archive_bytes,
+                                const void *h_header, float *d_field, uint64_t field_cap_elems,
+                                dqz_result *d_result, void *stream);
 
 const char *dqz_status_str(dqz_status status);
 /* Text of the last error on this context ("" if none). */
 const char *dqz_ctx_last_error(const dqz_ctx *ctx);
 
-/* Per-stage timing.  `level` 0 turns it off.  At level 1 every dqz_compress /
- * dqz_decompress on this context records HIP events on its stream between its
- * kernels (a small per-call cost, about a microsecond per event); level 2
- * also sums per-wave phase durations inside the decoding kernel
- * (DQZ_DBG_PHASES), which costs a few same-address atomics per wave and slows
- * that kernel noticeably.  DQZ_TIMING_STAGE(which, stage) records only the
- * two events around one stage of one call kind (the other stages read 0).
- * dqz_stage_times returns the elapsed microseconds of
- * each stage of the most recent call of that kind:
+/* Per-stage timing (the paper's per-kernel breakdown, Sec. 4.2).  `level` 0
+ * turns it off.  At level 1 every dqz_compress / dqz_decompress on this
+ * context records HIP events on its stream between its kernels (a small
+ * per-call cost, about a microsecond per event); level 2 also sums per-wave
+ * phase durations inside the decoding kernel (DQZ_DBG_PHASES), which costs a
+ * few same-address atomics per wave and slows that kernel noticeably.
+ * DQZ_TIMING_STAGE(which, stage) records only the two events around one
+ * stage of one call kind (the other stages read 0).  dqz_stage_times
+ * returns the elapsed microseconds of each stage of the most recent call of
+ * that kind:
  *   compress   (which = 0): [0] scratch clearing (absolute mode; in the
  *              value-range-relative mode the range kernel clears it and this
  *              stage is 0), [1] value range + eb (0 in absolute mode), [2] dual-quantization + histogram + exceptions, [3] their
@@ -158,8 +232,10 @@ const char *dqz_ctx_last_error(const dqz_ctx *ctx);
 dqz_status dqz_ctx_set_timing(dqz_ctx *ctx, int level);
 dqz_status dqz_stage_times(dqz_ctx *ctx, int which, double *us, int *n_stages);
 
-/* Stage dumps for parity testing: copy an intermediate buffer of the most
- * recent dqz_compress on this context to host memory.
+/* Stage dumps for parity testing (the intermediates of Sec. 3.1-3.2): copy a
+ * buffer of the most recent dqz_compress on this context to host memory
+ * (DQZ_EINVAL after a decompression or a workspace reallocation, which
+ * overwrite them).
  *   DQZ_DBG_CODES      u16 per padded position (0xFFFF outside the field)
  *   DQZ_DBG_HISTOGRAM  u32[2R]
  *   DQZ_DBG_CODEBOOK   u64[2R], (length << 56) | canonical code
@@ -178,6 +254,12 @@ dqz_status dqz_stage_times(dqz_ctx *ctx, int which, double *us, int *n_stages);
                                 stream window + exception search, inflate, outlier
                                 marks, reconstruct, patches */
 dqz_status dqz_debug_copy(dqz_ctx *ctx, int what, void *h_dst, uint64_t bytes);
+
+/* Test hook for failure handling: with what = DQZ_INJECT_ALLOC_FAIL the next
+ * `count` workspace allocations of this context (dqz_ctx_reserve) fail with
+ * DQZ_ENOMEM as if the device were out of memory; 0 clears it. */
+#define DQZ_INJECT_ALLOC_FAIL 1
+dqz_status dqz_debug_inject(dqz_ctx *ctx, int what, int count);
 
 #ifdef __cplusplus
 }

@@ -1,17 +1,25 @@
 // dqz_capi.cpp -- the C ABI of libdqz: argument validation, geometry and
-// archive layout, device scratch, and the stream-ordered launch sequence.
+// archive layout, the context's device workspace, and the stream-ordered
+// launch sequence.
 //
-// Compression:   init -> [range + eb (valrel)] -> quantize -> codebook ->
-//                zero stream + encode -> one small readback (status, size,
-//                header).
-// Decompression: decoding tables -> inflate + reconstruct -> status readback.
+// Compression:   [clear scratch | range + eb (valrel)] -> quantize -> tile
+//                scan -> codebook + header -> encode + deflate -> readback
+//                (status, size, header) through a small block the kernels
+//                write into host-visible memory.
+// Decompression: decoding tables -> inflate -> reconstruct -> readback.
+//
+// The workspace is allocated when the context is created or reserved,
+// never inside dqz_compress / dqz_decompress: a call whose layout does not
+// fit returns DQZ_ENOMEM and reports the size that would have sufficed.
 #include "../../include/dqz.h"
 #include "dqz_internal.h"
 
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
+#include <chrono>
 #include <cmath>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -19,15 +27,25 @@
 
 using namespace dqz;
 
+static_assert(sizeof(dqz_result) == sizeof(Readback), "dqz_result mirrors the kernels' readback block");
+static_assert(offsetof(dqz_result, status) == offsetof(Readback, code), "dqz_result layout");
+static_assert(offsetof(dqz_result, archive_bytes) == offsetof(Readback, archive_bytes), "dqz_result layout");
+static_assert(offsetof(dqz_result, workspace_need) == offsetof(Readback, workspace_need), "dqz_result layout");
+static_assert(offsetof(dqz_result, header) == offsetof(Readback, header), "dqz_result layout");
+
 struct dqz_ctx {
     int device = 0;
     int ncu = 256;
-    void *ws = nullptr;        // device scratch
-    size_t ws_bytes = 0;
-    Ctl *h_ctl = nullptr;      // readback block in pinned host memory, written by the kernels
-    Ctl *d_hctl = nullptr;     // the same block's device address
+    void *ws = nullptr;        // device workspace
+    uint64_t ws_bytes = 0;
+    uint64_t last_need = 0;    // workspace the most recent call needed
+    Readback *h_rb = nullptr;  // readback block in pinned host memory, written by the kernels
+    Readback *d_rb = nullptr;  // the same block's device address
+    int inject_alloc_fail = 0; // test hook: workspace allocations that fail on purpose
     std::string last_error;
-    // most recent compression, for the stage dumps
+    // most recent compression, for the stage dumps (cleared by a decompression,
+    // whose scratch overlaps these buffers, and by a workspace reallocation)
+    bool last_valid = false;
     uint16_t *last_codes = nullptr;
     uint32_t *last_hist = nullptr;
     uint64_t *last_book = nullptr;
@@ -126,6 +144,7 @@ dqz_status make_layout(const Geom &g, uint32_t radius, uint32_t sub, uint32_t cs
     L.off_exc = align_up(L.off_sub + 2 * n_sub, 8);
     L.cap = 0;
     L.pad = 0;
+    L.ws_fixed = 0;
     return DQZ_OK;
 }
 
@@ -135,40 +154,46 @@ void fill_params(const dqz_params *p, uint32_t &radius, uint32_t &sub, uint32_t 
     csubs = p->chunk_subs ? p->chunk_subs : kDefaultChunkSubs;
 }
 
-// device scratch layout: control block and decoding tables at fixed
-// offsets, then the zeroed region (histogram replicas, scan counters), then
-// the compression buffers (so a decompression never overwrites the last
-// compression's stage buffers kept for dqz_debug_copy)
-// Wait for the stream by polling: the end of each call is on the critical
-// path, and a polling wait returns sooner than a blocking one.
+// Wait for the stream: poll for up to a millisecond (the end of each call is
+// on the critical path, and a polling wait returns sooner than a blocking
+// one), then block so that a long call does not hold a host core.
 hipError_t wait_stream(hipStream_t s) {
+    const auto t0 = std::chrono::steady_clock::now();
     for (;;) {
         const hipError_t e = hipStreamQuery(s);
         if (e != hipErrorNotReady) return e;
+        if (std::chrono::steady_clock::now() - t0 > std::chrono::microseconds(1000)) return hipStreamSynchronize(s);
     }
 }
 
 // readback status before the codebook kernel has written the block
 constexpr uint32_t kNoReadback = 0xFFFFFFFFu;
 
+// Workspace layout.  Compression: control block, decoding tables, the zeroed
+// region (histogram replicas and their sum, encoder look-back states), the
+// codebooks, range partials, the quantize tiles' scan arrays and overflow
+// bases, the per-tile exception slots, the code array, then (from
+// `fixed`) the exception overflow pool, which takes the rest of the
+// workspace.  Decompression: control block, tables, the decoded code array
+// and the per-unit exception index (over the compression buffers).
 struct WsLayout {
     uint64_t ctl, tab, hist, zero_end;
     uint64_t hist_sum, book, book32, parts;
     uint64_t qval[2], qexcl[2], qseg_total[2];
-    uint64_t eflag;
-    uint64_t stage, codes, qws, unit_exc, total;
-    uint32_t n_segs_q, cap;
+    uint64_t ovf_base, eflag;
+    uint64_t stage, codes, fixed, qws, unit_exc, total;
+    uint32_t n_segs_q;
 };
 
-WsLayout ws_layout(const Plan &P, bool compress, uint32_t cap) {
+WsLayout ws_layout(const Plan &P, bool compress) {
     WsLayout w;
+    memset(&w, 0, sizeof(w));
     auto take = [](uint64_t &cur, uint64_t bytes) {
         const uint64_t at = align_up(cur, 256);
         cur = at + bytes;
         return at;
     };
     w.n_segs_q = (P.tiles_q + kSegTiles - 1) / kSegTiles;
-    w.cap = cap;
     uint64_t cur = 0;
     w.ctl = take(cur, sizeof(Ctl));
     w.tab = take(cur, sizeof(DecodeTables));
@@ -177,7 +202,7 @@ WsLayout ws_layout(const Plan &P, bool compress, uint32_t cap) {
         // whole waves of 64 subchunks, and the exception index per unit
         w.qws = P.L.sub_size == 128 ? take(cur, 256ull * ((P.L.n_sub + 63) / 64 * 64)) : 0;
         w.unit_exc = P.L.sub_size == 128 ? take(cur, 4ull * (recon_units(P.g) + 1)) : 0;
-        w.total = align_up(cur, 256);
+        w.total = w.fixed = align_up(cur, 256);
         return w;
     }
     w.hist = take(cur, 4ull * kHistReplicas * P.L.nsym);
@@ -192,28 +217,13 @@ WsLayout ws_layout(const Plan &P, bool compress, uint32_t cap) {
         w.qexcl[k] = take(cur, 4ull * P.tiles_q);
         w.qseg_total[k] = take(cur, 8ull * w.n_segs_q);
     }
-    w.stage = take(cur, 8ull * cap * P.tiles_q);
+    w.ovf_base = take(cur, 4ull * P.tiles_q);
+    w.stage = take(cur, 8ull * kExcCap * P.tiles_q);
     w.codes = take(cur, 2ull * P.g.padded);
-    w.total = align_up(cur, 256);
+    w.fixed = align_up(cur, 256);
+    // worst case: every element an outlier and a patch, all past the slots
+    w.total = w.fixed + 16ull * P.g.nelem;
     return w;
-}
-
-dqz_status ensure_ws(dqz_ctx *ctx, size_t bytes) {
-    if (ctx->ws_bytes >= bytes) return DQZ_OK;
-    if (ctx->ws) {
-        (void)hipFree(ctx->ws);
-        ctx->ws = nullptr;
-        ctx->ws_bytes = 0;
-    }
-    size_t want = bytes + bytes / 8;
-    hipError_t e = hipMalloc(&ctx->ws, want);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        ctx->ws = nullptr;
-        return fail(ctx, DQZ_ENOMEM, "device scratch allocation failed");
-    }
-    ctx->ws_bytes = want;
-    return DQZ_OK;
 }
 
 // stage marks: mark(ctx, which, i) records event i of call kind `which`
@@ -229,13 +239,16 @@ void mark(dqz_ctx *ctx, int which, int i, hipStream_t s) {
     ctx->n_ev[which] = i + 1;
 }
 
-dqz_status status_from_device(dqz_ctx *ctx, uint32_t st) {
-    if (st & ST_EINTERNAL) return fail(ctx, DQZ_EINTERNAL, "internal consistency check failed");
-    if (st & ST_EINVAL) return fail(ctx, DQZ_EINVAL, "error bound out of range for this field");
-    if (st & ST_EUNSUPPORTED) return fail(ctx, DQZ_EUNSUPPORTED, "code length above 64 bits");
-    if (st & ST_ECORRUPT) return fail(ctx, DQZ_ECORRUPT, "archive failed validation");
-    if (st & ST_ETOOSMALL) return fail(ctx, DQZ_ETOOSMALL, "archive capacity too small");
-    return DQZ_OK;
+const char *status_message(dqz_status st) {
+    switch (st) {
+        case DQZ_EINTERNAL: return "internal consistency check failed";
+        case DQZ_EINVAL: return "error bound out of range for this field";
+        case DQZ_ENOMEM: return "workspace too small for this field's exception records";
+        case DQZ_EUNSUPPORTED: return "code length above 64 bits";
+        case DQZ_ECORRUPT: return "archive failed validation";
+        case DQZ_ETOOSMALL: return "archive capacity too small";
+        default: return "";
+    }
 }
 
 uint32_t rd_u32(const uint8_t *p, int off) {
@@ -306,6 +319,159 @@ dqz_status parse_header(const uint8_t *hb, uint64_t n, HeaderInfo &hi, Plan *P, 
     return DQZ_OK;
 }
 
+dqz_status alloc_workspace(dqz_ctx *ctx, uint64_t bytes) {
+    if (ctx->inject_alloc_fail > 0) {
+        ctx->inject_alloc_fail--;
+        return fail(ctx, DQZ_ENOMEM, "device workspace allocation failed (injected)");
+    }
+    void *p = nullptr;
+    const hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(ctx, DQZ_ENOMEM, "device workspace allocation failed");
+    }
+    if (ctx->ws) (void)hipFree(ctx->ws);
+    ctx->ws = p;
+    ctx->ws_bytes = bytes;
+    ctx->last_valid = false;
+    return DQZ_OK;
+}
+
+// Validate the arguments of a compression and plan it (host only).
+dqz_status plan_compress(dqz_ctx *ctx, const float *d_field, const dqz_shape *shape, const dqz_params *params,
+                         const void *d_archive, uint64_t archive_cap, Plan &P, WsLayout &W) {
+    if (!params || !d_archive) return fail(ctx, DQZ_EINVAL, "null argument");
+    if (!(params->eb > 0.0) || !std::isfinite(params->eb)) return fail(ctx, DQZ_EINVAL, "eb must be finite and > 0");
+    if (params->eb_mode != DQZ_EB_ABS && params->eb_mode != DQZ_EB_VALREL) return fail(ctx, DQZ_EINVAL, "bad eb_mode");
+    std::string why;
+    dqz_status st = make_geom(shape, P.g, why);
+    if (st != DQZ_OK) return fail(ctx, st, why);
+    if (P.g.nelem && !d_field) return fail(ctx, DQZ_EINVAL, "null field");
+    uint32_t radius, sub, csubs;
+    fill_params(params, radius, sub, csubs);
+    if ((st = make_layout(P.g, radius, sub, csubs, P.L, why)) != DQZ_OK) return fail(ctx, st, why);
+    if (params->eb_mode == DQZ_EB_ABS) {
+        const double e = params->eb;
+        const float h = (float)(2.0 * e), r = (float)(1.0 / (2.0 * e));
+        if (e < (double)FLT_MIN || !std::isfinite(h) || !(r >= FLT_MIN) || !std::isfinite(r))
+            return fail(ctx, DQZ_EINVAL, "eb out of the fp32 range");
+    }
+    P.L.cap = archive_cap;
+    if (archive_cap < P.L.off_exc) return fail(ctx, DQZ_ETOOSMALL, "archive capacity below the fixed sections");
+    P.tiles_q = quantize_tiles(P.g);
+    P.tiles_e = encode_tiles(P.g);
+    W = ws_layout(P, true);
+    P.L.ws_fixed = W.fixed;
+    ctx->last_need = W.fixed;
+    if (ctx->ws_bytes < W.fixed)
+        return fail(ctx, DQZ_ENOMEM, "workspace too small: this field needs at least " + std::to_string(W.fixed) +
+                                          " bytes (dqz_ctx_reserve)");
+    return DQZ_OK;
+}
+
+// Enqueue the compression kernels; they write status, size and header to rb.
+void enqueue_compress(dqz_ctx *ctx, const float *d_field, const dqz_params *params, uint8_t *arc, const Plan &P,
+                      const WsLayout &W, Readback *rb, hipStream_t s) {
+    uint8_t *ws = reinterpret_cast<uint8_t *>(ctx->ws);
+    Ctl *ctl = reinterpret_cast<Ctl *>(ws + W.ctl);
+    uint32_t *hist = reinterpret_cast<uint32_t *>(ws + W.hist);
+    uint64_t *book = reinterpret_cast<uint64_t *>(ws + W.book);
+    uint32_t *book32 = reinterpret_cast<uint32_t *>(ws + W.book32);
+    uint32_t *parts = reinterpret_cast<uint32_t *>(ws + W.parts);
+    uint16_t *codes = reinterpret_cast<uint16_t *>(ws + W.codes);
+    QuantBufs qb;
+    qb.codes = codes;
+    qb.hist = hist;
+    qb.hist_sum = reinterpret_cast<uint32_t *>(ws + W.hist_sum);
+    qb.stage = reinterpret_cast<uint2 *>(ws + W.stage);
+    qb.cap = kExcCap;
+    qb.pool = reinterpret_cast<uint2 *>(ws + W.fixed);
+    qb.pool_cap = (ctx->ws_bytes - W.fixed) / 8;
+    qb.ovf_base = reinterpret_cast<uint32_t *>(ws + W.ovf_base);
+    TileScan &qs = qb.scan;
+    for (int k = 0; k < 2; k++) {
+        qs.val[k] = reinterpret_cast<uint32_t *>(ws + W.qval[k]);
+        qs.excl[k] = reinterpret_cast<uint32_t *>(ws + W.qexcl[k]);
+        qs.seg_total[k] = reinterpret_cast<uint64_t *>(ws + W.qseg_total[k]);
+    }
+    qs.n_tiles = P.tiles_q;
+    qs.n_segs = W.n_segs_q;
+    qs.nvals = 2;
+    EncodeBufs eb;
+    eb.codes = codes;
+    eb.book = book;
+    eb.book32 = book32;
+    eb.stage = qb.stage;
+    eb.cap = kExcCap;
+    eb.pool = qb.pool;
+    eb.ovf_base = qb.ovf_base;
+    eb.qscan = qs;
+    eb.n_tiles_q = P.tiles_q;
+    eb.eflag = reinterpret_cast<uint64_t *>(ws + W.eflag);
+
+    ctx->ev_ready[0] = false;
+    mark(ctx, 0, 0, s);
+    // value-range-relative mode: the range kernel also clears the scratch
+    if (params->eb_mode != DQZ_EB_VALREL) launch_init(s, ctl, ws + W.hist, W.zero_end - W.hist, params->eb_mode, params->eb);
+    mark(ctx, 0, 1, s);
+    if (params->eb_mode == DQZ_EB_VALREL)
+        launch_minmax(s, d_field, P.g.nelem, ctl, parts, params->eb, ctx->ncu, ws + W.hist, W.zero_end - W.hist);
+    mark(ctx, 0, 2, s);
+    launch_quantize(s, d_field, P.g, P.L, ctl, qb);
+    mark(ctx, 0, 3, s);
+    launch_quantize_scan(s, P.g, P.L, qb);
+    mark(ctx, 0, 4, s);
+    launch_codebook(s, P.g, P.L, ctl, qb.hist_sum, book, book32, arc, params->eb_mode, params->eb, qs, rb);
+    mark(ctx, 0, 5, s);
+    launch_encode(s, P.g, P.L, ctl, rb, eb, arc, ctx->ncu);
+    mark(ctx, 0, 6, s);
+    ctx->last_valid = true;
+    ctx->last_codes = codes;
+    ctx->last_hist = hist;
+    ctx->last_book = book;
+    ctx->last_ctl = ctl;
+    ctx->last_tab = reinterpret_cast<DecodeTables *>(ws + W.tab);
+    ctx->last_padded = P.g.padded;
+    ctx->last_nsym = P.L.nsym;
+}
+
+// Validate a decompression and plan it (host only).
+dqz_status plan_decompress(dqz_ctx *ctx, const void *d_archive, uint64_t archive_bytes, const uint8_t *hb,
+                           float *d_field, uint64_t field_cap_elems, HeaderInfo &hi, Plan &P, WsLayout &W) {
+    std::string why;
+    dqz_status st = parse_header(hb, kHeaderBytes, hi, &P, why);
+    if (st != DQZ_OK) return fail(ctx, st, why);
+    if (hi.archive_bytes != archive_bytes) return fail(ctx, DQZ_ECORRUPT, "archive length differs from its header");
+    if (field_cap_elems < hi.nelem) return fail(ctx, DQZ_ETOOSMALL, "field capacity too small");
+    if (hi.nelem && !d_field) return fail(ctx, DQZ_EINVAL, "null field");
+    (void)d_archive;
+    W = ws_layout(P, false);
+    ctx->last_need = hi.nelem ? W.total : 0;
+    if (hi.nelem && ctx->ws_bytes < W.total)
+        return fail(ctx, DQZ_ENOMEM, "workspace too small: this archive needs " + std::to_string(W.total) +
+                                          " bytes (dqz_ctx_reserve)");
+    return DQZ_OK;
+}
+
+void enqueue_decompress(dqz_ctx *ctx, const uint8_t *arc, float *d_field, const HeaderInfo &hi, const Plan &P,
+                        const WsLayout &W, Readback *rb, hipStream_t s) {
+    uint8_t *ws = reinterpret_cast<uint8_t *>(ctx->ws);
+    DecodeTables *tab = reinterpret_cast<DecodeTables *>(ws + W.tab);
+    ctx->last_valid = false;   // the decompression scratch overlaps the compression's
+    ctx->ev_ready[1] = false;
+    mark(ctx, 1, 0, s);
+    const bool two_pass = P.L.sub_size == 128;
+    uint4 *qws = two_pass ? reinterpret_cast<uint4 *>(ws + W.qws) : nullptr;
+    uint32_t *unit_exc = two_pass ? reinterpret_cast<uint32_t *>(ws + W.unit_exc) : nullptr;
+    launch_decode_tables(s, P.L, arc, hi.max_len, tab, rb, (uint32_t)hi.n_exc, unit_exc, recon_units(P.g));
+    mark(ctx, 1, 1, s);
+    launch_decode(s, P.g, P.L, arc, hi.off_str, hi.n_words, (uint32_t)hi.n_exc, hi.h, tab, d_field, ctx->trace, qws,
+                  rb, ctx->ncu);
+    mark(ctx, 1, 2, s);
+    if (two_pass) launch_recon(s, P.g, P.L, arc, (uint32_t)hi.n_exc, hi.h, tab, qws, unit_exc, d_field, rb);
+    mark(ctx, 1, 3, s);
+}
+
 }  // namespace
 
 extern "C" {
@@ -326,7 +492,7 @@ const char *dqz_status_str(dqz_status s) {
 
 const char *dqz_ctx_last_error(const dqz_ctx *ctx) { return ctx ? ctx->last_error.c_str() : ""; }
 
-dqz_status dqz_ctx_create(int device, dqz_ctx **out) {
+dqz_status dqz_ctx_create(int device, uint64_t workspace_cap, dqz_ctx **out) {
     if (!out) return DQZ_EINVAL;
     *out = nullptr;
     int count = 0;
@@ -342,16 +508,26 @@ dqz_status dqz_ctx_create(int device, dqz_ctx **out) {
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
         ctx->ncu = ncu;
-    if (hipHostMalloc((void **)&ctx->h_ctl, sizeof(Ctl), hipHostMallocDefault) != hipSuccess) {
+    if (decode_kernel_attributes() != hipSuccess) {
+        (void)hipGetLastError();
+        delete ctx;
+        return DQZ_EHIP;
+    }
+    if (hipHostMalloc((void **)&ctx->h_rb, sizeof(Readback), hipHostMallocDefault) != hipSuccess) {
         (void)hipGetLastError();
         delete ctx;
         return DQZ_ENOMEM;
     }
-    if (hipHostGetDevicePointer((void **)&ctx->d_hctl, ctx->h_ctl, 0) != hipSuccess) {
+    if (hipHostGetDevicePointer((void **)&ctx->d_rb, ctx->h_rb, 0) != hipSuccess) {
         (void)hipGetLastError();
-        (void)hipHostFree(ctx->h_ctl);
+        (void)hipHostFree(ctx->h_rb);
         delete ctx;
         return DQZ_EHIP;
+    }
+    if (workspace_cap && alloc_workspace(ctx, workspace_cap) != DQZ_OK) {
+        (void)hipHostFree(ctx->h_rb);
+        delete ctx;
+        return DQZ_ENOMEM;
     }
     *out = ctx;
     return DQZ_OK;
@@ -361,11 +537,26 @@ void dqz_ctx_destroy(dqz_ctx *ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     if (ctx->ws) (void)hipFree(ctx->ws);
-    if (ctx->h_ctl) (void)hipHostFree(ctx->h_ctl);
+    if (ctx->h_rb) (void)hipHostFree(ctx->h_rb);
     for (int k = 0; k < 2; k++)
         for (int i = 0; i <= DQZ_MAX_STAGES; i++)
             if (ctx->ev[k][i]) (void)hipEventDestroy(ctx->ev[k][i]);
     delete ctx;
+}
+
+dqz_status dqz_ctx_reserve(dqz_ctx *ctx, uint64_t workspace_bytes) {
+    if (!ctx) return DQZ_EINVAL;
+    ctx->last_error.clear();
+    if (workspace_bytes <= ctx->ws_bytes) return DQZ_OK;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    return alloc_workspace(ctx, workspace_bytes);
+}
+
+dqz_status dqz_ctx_workspace(const dqz_ctx *ctx, uint64_t *workspace_bytes, uint64_t *last_need) {
+    if (!ctx) return DQZ_EINVAL;
+    if (workspace_bytes) *workspace_bytes = ctx->ws_bytes;
+    if (last_need) *last_need = ctx->last_need;
+    return DQZ_OK;
 }
 
 dqz_status dqz_compress_bound(const dqz_shape *shape, const dqz_params *params, uint64_t *archive_max,
@@ -382,7 +573,17 @@ dqz_status dqz_compress_bound(const dqz_shape *shape, const dqz_params *params, 
     P.tiles_e = encode_tiles(P.g);
     // every element an outlier and a patch (16 bytes) and a 64-bit code
     if (archive_max) *archive_max = P.L.off_exc + 16ull * P.g.nelem + 8ull * P.g.nelem + 8;
-    if (workspace_bytes) *workspace_bytes = ws_layout(P, true, kExcCap).total;
+    if (workspace_bytes) *workspace_bytes = ws_layout(P, true).total;
+    return DQZ_OK;
+}
+
+dqz_status dqz_decompress_bound(const void *h_header, uint64_t header_bytes, uint64_t *workspace_bytes) {
+    HeaderInfo hi;
+    Plan P;
+    std::string why;
+    dqz_status st = parse_header(reinterpret_cast<const uint8_t *>(h_header), header_bytes, hi, &P, why);
+    if (st != DQZ_OK) return st;
+    if (workspace_bytes) *workspace_bytes = hi.nelem ? ws_layout(P, false).total : 0;
     return DQZ_OK;
 }
 
@@ -391,110 +592,51 @@ dqz_status dqz_compress(dqz_ctx *ctx, const float *d_field, const dqz_shape *sha
                         void *stream) {
     if (!ctx) return DQZ_EINVAL;
     ctx->last_error.clear();
-    if (archive_bytes) *archive_bytes = 0;
-    if (!params || !d_archive || !archive_bytes) return fail(ctx, DQZ_EINVAL, "null argument");
-    if (!(params->eb > 0.0) || !std::isfinite(params->eb)) return fail(ctx, DQZ_EINVAL, "eb must be finite and > 0");
-    if (params->eb_mode != DQZ_EB_ABS && params->eb_mode != DQZ_EB_VALREL) return fail(ctx, DQZ_EINVAL, "bad eb_mode");
+    if (!archive_bytes) return fail(ctx, DQZ_EINVAL, "null argument");
+    *archive_bytes = 0;
     Plan P;
-    std::string why;
-    dqz_status st = make_geom(shape, P.g, why);
-    if (st != DQZ_OK) return fail(ctx, st, why);
-    if (P.g.nelem && !d_field) return fail(ctx, DQZ_EINVAL, "null field");
-    uint32_t radius, sub, csubs;
-    fill_params(params, radius, sub, csubs);
-    if ((st = make_layout(P.g, radius, sub, csubs, P.L, why)) != DQZ_OK) return fail(ctx, st, why);
-    if (params->eb_mode == DQZ_EB_ABS) {
-        const double e = params->eb;
-        const float h = (float)(2.0 * e), r = (float)(1.0 / (2.0 * e));
-        if (e < (double)FLT_MIN || !std::isfinite(h) || !(r >= FLT_MIN) || !std::isfinite(r))
-            return fail(ctx, DQZ_EINVAL, "eb out of the fp32 range");
-    }
-    P.L.cap = archive_cap;
-    if (archive_cap < P.L.off_exc) {
-        *archive_bytes = 0;
-        return fail(ctx, DQZ_ETOOSMALL, "archive capacity below the fixed sections");
-    }
-    P.tiles_q = quantize_tiles(P.g);
-    P.tiles_e = encode_tiles(P.g);
+    WsLayout W;
+    dqz_status st = plan_compress(ctx, d_field, shape, params, d_archive, archive_cap, P, W);
+    if (st != DQZ_OK) return st;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    uint8_t *arc = reinterpret_cast<uint8_t *>(d_archive);
-    // first attempt with kExcCap staged exception records per quantize tile;
-    // a tile with more sends the call round again with room for every element
-    for (uint32_t cap : {kExcCap, 2 * kTile}) {
-        const WsLayout W = ws_layout(P, true, cap);
-        if ((st = ensure_ws(ctx, W.total)) != DQZ_OK) return st;
-        uint8_t *ws = reinterpret_cast<uint8_t *>(ctx->ws);
-        Ctl *ctl = reinterpret_cast<Ctl *>(ws + W.ctl);
-        uint32_t *hist = reinterpret_cast<uint32_t *>(ws + W.hist);
-        uint64_t *book = reinterpret_cast<uint64_t *>(ws + W.book);
-        uint32_t *book32 = reinterpret_cast<uint32_t *>(ws + W.book32);
-        uint32_t *parts = reinterpret_cast<uint32_t *>(ws + W.parts);
-        uint16_t *codes = reinterpret_cast<uint16_t *>(ws + W.codes);
-        QuantBufs qb;
-        qb.codes = codes;
-        qb.hist = hist;
-        qb.hist_sum = reinterpret_cast<uint32_t *>(ws + W.hist_sum);
-        qb.stage = reinterpret_cast<uint2 *>(ws + W.stage);
-        qb.cap = cap;
-        TileScan &qs = qb.scan;
-        for (int k = 0; k < 2; k++) {
-            qs.val[k] = reinterpret_cast<uint32_t *>(ws + W.qval[k]);
-            qs.excl[k] = reinterpret_cast<uint32_t *>(ws + W.qexcl[k]);
-            qs.seg_total[k] = reinterpret_cast<uint64_t *>(ws + W.qseg_total[k]);
-        }
-        qs.n_tiles = P.tiles_q;
-        qs.n_segs = W.n_segs_q;
-        qs.nvals = 2;
-        EncodeBufs eb;
-        eb.codes = codes;
-        eb.book = book;
-        eb.book32 = book32;
-        eb.stage = qb.stage;
-        eb.cap = cap;
-        eb.qscan = qs;
-        eb.n_tiles_q = P.tiles_q;
-        eb.eflag = reinterpret_cast<uint64_t *>(ws + W.eflag);
-
-        ctx->ev_ready[0] = false;
-        mark(ctx, 0, 0, s);
-        ctx->h_ctl->status = kNoReadback;   // the codebook kernel overwrites it
-        // value-range-relative mode: the range kernel also clears the scratch
-        if (params->eb_mode != DQZ_EB_VALREL) launch_init(s, ctl, ws + W.hist, W.zero_end - W.hist, params->eb_mode, params->eb);
-        mark(ctx, 0, 1, s);
-        if (params->eb_mode == DQZ_EB_VALREL)
-            launch_minmax(s, d_field, P.g.nelem, ctl, parts, params->eb, ctx->ncu, ws + W.hist, W.zero_end - W.hist);
-        mark(ctx, 0, 2, s);
-        launch_quantize(s, d_field, P.g, P.L, ctl, qb);
-        mark(ctx, 0, 3, s);
-        launch_quantize_scan(s, P.g, P.L, qb);
-        mark(ctx, 0, 4, s);
-        launch_codebook(s, P.g, P.L, ctl, qb.hist_sum, book, book32, arc, params->eb_mode, params->eb, qs,
-                        ctx->d_hctl);
-        mark(ctx, 0, 5, s);
-        launch_encode(s, P.g, P.L, ctl, ctx->d_hctl, eb, arc, ctx->ncu);
-        mark(ctx, 0, 6, s);
-        HIP_TRY(ctx, hipGetLastError());
-        HIP_TRY(ctx, wait_stream(s));
-        ctx->ev_ready[0] = ctx->timing;
-        ctx->last_codes = codes;
-        ctx->last_hist = hist;
-        ctx->last_book = book;
-        ctx->last_ctl = ctl;
-        ctx->last_tab = reinterpret_cast<DecodeTables *>(ws + W.tab);
-        ctx->last_padded = P.g.padded;
-        ctx->last_nsym = P.L.nsym;
-        const Ctl &c = *ctx->h_ctl;
-        if (c.status == kNoReadback) return fail(ctx, DQZ_EINTERNAL, "the codebook kernel did not report");
-        if ((c.status & ST_RETRY) && cap < 2 * kTile) continue;
-        if (c.status & ST_ETOOSMALL) *archive_bytes = c.archive_bytes;
-        st = status_from_device(ctx, c.status);
-        if (st != DQZ_OK) return st;
-        *archive_bytes = c.archive_bytes;
-        if (h_header) memcpy(h_header, c.header, kHeaderBytes);
-        return DQZ_OK;
+    ctx->h_rb->bits = kNoReadback;   // the codebook kernel overwrites it
+    ctx->h_rb->code = 0;
+    enqueue_compress(ctx, d_field, params, reinterpret_cast<uint8_t *>(d_archive), P, W, ctx->d_rb, s);
+    HIP_TRY(ctx, hipGetLastError());
+    HIP_TRY(ctx, wait_stream(s));
+    ctx->ev_ready[0] = ctx->timing;
+    const Readback &rb = *ctx->h_rb;
+    if (rb.bits == kNoReadback) return fail(ctx, DQZ_EINTERNAL, "the codebook kernel did not report");
+    st = (dqz_status)rb.code;
+    if (st == DQZ_ETOOSMALL) *archive_bytes = rb.archive_bytes;
+    if (st == DQZ_ENOMEM) ctx->last_need = rb.workspace_need;
+    if (st != DQZ_OK) {
+        std::string msg = status_message(st);
+        if (st == DQZ_ENOMEM) msg += ": needs " + std::to_string(rb.workspace_need) + " bytes (dqz_ctx_reserve)";
+        return fail(ctx, st, msg);
     }
-    return fail(ctx, DQZ_EINTERNAL, "exception staging overflowed twice");
+    *archive_bytes = rb.archive_bytes;
+    if (h_header) memcpy(h_header, rb.header, kHeaderBytes);
+    return DQZ_OK;
+}
+
+dqz_status dqz_compress_async(dqz_ctx *ctx, const float *d_field, const dqz_shape *shape, const dqz_params *params,
+                              void *d_archive, uint64_t archive_cap, dqz_result *d_result, void *stream) {
+    if (!ctx) return DQZ_EINVAL;
+    ctx->last_error.clear();
+    if (!d_result || (reinterpret_cast<uintptr_t>(d_result) & 7u)) return fail(ctx, DQZ_EINVAL, "result must be 8-byte aligned");
+    Plan P;
+    WsLayout W;
+    dqz_status st = plan_compress(ctx, d_field, shape, params, d_archive, archive_cap, P, W);
+    if (st != DQZ_OK) return st;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    enqueue_compress(ctx, d_field, params, reinterpret_cast<uint8_t *>(d_archive), P, W,
+                     reinterpret_cast<Readback *>(d_result), s);
+    HIP_TRY(ctx, hipGetLastError());
+    ctx->ev_ready[0] = false;
+    return DQZ_OK;
 }
 
 dqz_status dqz_archive_info(const void *h_header, uint64_t header_bytes, dqz_shape *shape, dqz_params *params,
@@ -522,43 +664,47 @@ dqz_status dqz_decompress(dqz_ctx *ctx, const void *d_archive, uint64_t archive_
     if (h_header) {
         memcpy(hb, h_header, kHeaderBytes);
     } else {
-        HIP_TRY(ctx, hipMemcpyAsync(ctx->h_ctl->header, d_archive, kHeaderBytes, hipMemcpyDeviceToHost, s));
+        HIP_TRY(ctx, hipMemcpyAsync(ctx->h_rb->header, d_archive, kHeaderBytes, hipMemcpyDeviceToHost, s));
         HIP_TRY(ctx, hipStreamSynchronize(s));
-        memcpy(hb, ctx->h_ctl->header, kHeaderBytes);
+        memcpy(hb, ctx->h_rb->header, kHeaderBytes);
     }
     HeaderInfo hi;
     Plan P;
-    std::string why;
-    dqz_status st = parse_header(hb, kHeaderBytes, hi, &P, why);
-    if (st != DQZ_OK) return fail(ctx, st, why);
-    if (hi.archive_bytes != archive_bytes) return fail(ctx, DQZ_ECORRUPT, "archive length differs from its header");
-    if (field_cap_elems < hi.nelem) return fail(ctx, DQZ_ETOOSMALL, "field capacity too small");
-    if (hi.nelem && !d_field) return fail(ctx, DQZ_EINVAL, "null field");
+    WsLayout W;
+    dqz_status st = plan_decompress(ctx, d_archive, archive_bytes, hb, d_field, field_cap_elems, hi, P, W);
+    if (st != DQZ_OK) return st;
     if (hi.nelem == 0) return DQZ_OK;
-    const WsLayout W = ws_layout(P, false, 0);
-    if ((st = ensure_ws(ctx, W.total)) != DQZ_OK) return st;
-    uint8_t *ws = reinterpret_cast<uint8_t *>(ctx->ws);
-    DecodeTables *tab = reinterpret_cast<DecodeTables *>(ws + W.tab);
-    const uint8_t *arc = reinterpret_cast<const uint8_t *>(d_archive);
-    ctx->ev_ready[1] = false;
-    mark(ctx, 1, 0, s);
-    ctx->h_ctl->status = 0;   // the decoding kernels set it on damage
-    const bool two_pass = P.L.sub_size == 128;
-    uint4 *qws = two_pass ? reinterpret_cast<uint4 *>(ws + W.qws) : nullptr;
-    uint32_t *unit_exc = two_pass ? reinterpret_cast<uint32_t *>(ws + W.unit_exc) : nullptr;
-    launch_decode_tables(s, P.L, arc, hi.max_len, tab, &ctx->d_hctl->status, (uint32_t)hi.n_exc, unit_exc,
-                         recon_units(P.g));
-    mark(ctx, 1, 1, s);
-    launch_decode(s, P.g, P.L, arc, hi.off_str, hi.n_words, (uint32_t)hi.n_exc, hi.h, tab, d_field, ctx->trace, qws,
-                  &ctx->d_hctl->status);
-    mark(ctx, 1, 2, s);
-    if (two_pass)
-        launch_recon(s, P.g, P.L, arc, (uint32_t)hi.n_exc, hi.h, tab, qws, unit_exc, d_field, &ctx->d_hctl->status);
-    mark(ctx, 1, 3, s);
+    ctx->h_rb->bits = 0;   // the decoding kernels set it on damage
+    ctx->h_rb->code = 0;
+    enqueue_decompress(ctx, reinterpret_cast<const uint8_t *>(d_archive), d_field, hi, P, W, ctx->d_rb, s);
     HIP_TRY(ctx, hipGetLastError());
     HIP_TRY(ctx, wait_stream(s));
     ctx->ev_ready[1] = ctx->timing;
-    return status_from_device(ctx, ctx->h_ctl->status);
+    st = (dqz_status)ctx->h_rb->code;
+    return st == DQZ_OK ? DQZ_OK : fail(ctx, st, status_message(st));
+}
+
+dqz_status dqz_decompress_async(dqz_ctx *ctx, const void *d_archive, uint64_t archive_bytes, const void *h_header,
+                                float *d_field, uint64_t field_cap_elems, dqz_result *d_result, void *stream) {
+    if (!ctx) return DQZ_EINVAL;
+    ctx->last_error.clear();
+    if (!d_archive || !h_header) return fail(ctx, DQZ_EINVAL, "null archive or header");
+    if (!d_result || (reinterpret_cast<uintptr_t>(d_result) & 7u)) return fail(ctx, DQZ_EINVAL, "result must be 8-byte aligned");
+    if (archive_bytes < kHeaderBytes) return fail(ctx, DQZ_ECORRUPT, "archive shorter than its header");
+    HeaderInfo hi;
+    Plan P;
+    WsLayout W;
+    dqz_status st = plan_decompress(ctx, d_archive, archive_bytes, reinterpret_cast<const uint8_t *>(h_header),
+                                    d_field, field_cap_elems, hi, P, W);
+    if (st != DQZ_OK) return st;
+    HIP_TRY(ctx, hipSetDevice(ctx->device));
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    Readback *rb = reinterpret_cast<Readback *>(d_result);
+    launch_publish(s, rb, 0u, hi.archive_bytes);   // the decoding kernels overwrite it on damage
+    if (hi.nelem) enqueue_decompress(ctx, reinterpret_cast<const uint8_t *>(d_archive), d_field, hi, P, W, rb, s);
+    HIP_TRY(ctx, hipGetLastError());
+    ctx->ev_ready[1] = false;
+    return DQZ_OK;
 }
 
 dqz_status dqz_ctx_set_timing(dqz_ctx *ctx, int level) {
@@ -604,13 +750,14 @@ dqz_status dqz_stage_times(dqz_ctx *ctx, int which, double *us, int *n_stages) {
 
 dqz_status dqz_debug_copy(dqz_ctx *ctx, int what, void *h_dst, uint64_t bytes) {
     if (!ctx || !h_dst) return DQZ_EINVAL;
+    if (!ctx->last_valid)
+        return fail(ctx, DQZ_EINVAL, "no compression on this context since its last decompression or reallocation");
     const void *src = nullptr;
     uint64_t need = 0;
     switch (what) {
         case DQZ_DBG_CODES: src = ctx->last_codes; need = 2 * ctx->last_padded; break;
         case DQZ_DBG_HISTOGRAM: {
             // the kernels keep kHistReplicas partial copies; return their sum
-            if (!ctx->last_hist) return fail(ctx, DQZ_EINVAL, "no compression has run on this context");
             need = 4ull * ctx->last_nsym;
             if (bytes != need) return fail(ctx, DQZ_EINVAL, "size mismatch");
             std::string buf(4ull * kHistReplicas * ctx->last_nsym, '\0');
@@ -627,7 +774,6 @@ dqz_status dqz_debug_copy(dqz_ctx *ctx, int what, void *h_dst, uint64_t bytes) {
         }
         case DQZ_DBG_CODEBOOK: src = ctx->last_book; need = 8ull * ctx->last_nsym; break;
         case DQZ_DBG_PHASES: {
-            if (!ctx->last_ctl) return fail(ctx, DQZ_EINVAL, "no compression has run on this context");
             if (bytes != 8 * 32) return fail(ctx, DQZ_EINVAL, "size mismatch");
             HIP_TRY(ctx, hipSetDevice(ctx->device));
             uint64_t *dst = reinterpret_cast<uint64_t *>(h_dst);
@@ -637,10 +783,16 @@ dqz_status dqz_debug_copy(dqz_ctx *ctx, int what, void *h_dst, uint64_t bytes) {
         }
         default: return fail(ctx, DQZ_EINVAL, "unknown stage");
     }
-    if (!src) return fail(ctx, DQZ_EINVAL, "no compression has run on this context");
     if (bytes != need) return fail(ctx, DQZ_EINVAL, "size mismatch");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     HIP_TRY(ctx, hipMemcpy(h_dst, src, bytes, hipMemcpyDeviceToHost));
+    return DQZ_OK;
+}
+
+dqz_status dqz_debug_inject(dqz_ctx *ctx, int what, int count) {
+    if (!ctx || count < 0) return DQZ_EINVAL;
+    if (what != DQZ_INJECT_ALLOC_FAIL) return fail(ctx, DQZ_EINVAL, "unknown injection");
+    ctx->inject_alloc_fail = count;
     return DQZ_OK;
 }
 

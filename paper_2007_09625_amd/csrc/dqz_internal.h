@@ -15,21 +15,49 @@ constexpr uint32_t kLutBits = 13;          // decode table width (u16 entries: l
 constexpr uint32_t kLut2Max = 3072;        // second-level decode table entries (codes longer than kLutBits)
 constexpr uint32_t kUnitShift = 9;         // reconstruction unit: 512 padded positions (four 128-position subchunks)
 constexpr uint32_t kHistReplicas = 16;     // global histogram copies (spreads the flush atomics)
-constexpr uint32_t kExcCap = 512;          // staged exception records per quantize tile (first attempt)
+constexpr uint32_t kExcCap = 512;          // staged exception records per quantize tile; more go to the overflow pool
 constexpr uint32_t kMaxRadius = 1024;      // codebook kernel keeps 2R <= 2048 symbols in LDS
 constexpr uint32_t kMaxSyms = 2 * kMaxRadius;
 constexpr uint16_t kNoSymbol = 0xFFFF;     // code slot of a padded position outside the field
 constexpr uint32_t kDecodeWaveSubs = 64;   // subchunks decoded by one wave (one per lane)
 
-// Device status bits (Ctl::status), mapped to dqz_status on the host.
+// Device status bits (Ctl::status); status_code maps them to a dqz_status.
 enum : uint32_t {
     ST_EINVAL = 1u,        // eb / derived h, r out of range
     ST_ETOOSMALL = 2u,     // archive capacity exceeded
     ST_EUNSUPPORTED = 4u,  // code longer than 64 bits
     ST_ECORRUPT = 8u,      // archive fails validation during decode
     ST_EINTERNAL = 16u,    // internal consistency check failed
-    ST_RETRY = 32u,        // exception staging overflowed: compress again with full staging
+    ST_ENOMEM = 32u,       // the workspace's exception overflow pool is too small for this field
 };
+
+// Readback block: status, archive size and header of a call, written by the
+// kernels into memory the host can read (pinned host memory, or the caller's
+// dqz_result for the asynchronous entry points).  `bits` holds the ST_* flags,
+// `code` the dqz_status they map to.
+struct Readback {
+    uint32_t bits;
+    int32_t code;
+    uint64_t archive_bytes;
+    uint64_t workspace_need;   // with ST_ENOMEM: the workspace bytes that would have sufficed
+    uint64_t reserved;
+    uint8_t header[128];
+};
+
+// dqz_status of a set of ST_* flags (the first applicable, most severe first)
+__host__ __device__ inline int32_t status_code(uint32_t b) {
+    if (b & ST_EINTERNAL) return -7;
+    if (b & ST_EINVAL) return -1;
+    if (b & ST_ENOMEM) return -3;
+    if (b & ST_EUNSUPPORTED) return -5;
+    if (b & ST_ECORRUPT) return -4;
+    if (b & ST_ETOOSMALL) return -2;
+    return 0;
+}
+__device__ __forceinline__ void publish_status(Readback *rb, uint32_t bits) {
+    rb->bits = bits;
+    rb->code = status_code(bits);
+}
 
 // Geometry: every field is viewed as (nz, ny, nx) with block extents
 // (bz, by, bx) = (1,1,32) for 1D, (1,16,16) for 2D, (8,8,8) for 3D.
@@ -52,6 +80,7 @@ struct Layout {
     uint32_t radius, nsym;
     uint32_t sub_shift;    // log2(sub_size)
     uint32_t pad;
+    uint64_t ws_fixed;     // compression workspace bytes before the exception overflow pool
 };
 
 // Control block in device scratch: the values that only the device knows.
@@ -62,8 +91,8 @@ struct Ctl {
     uint32_t status;
     uint32_t n_out, n_patch, n_exc;
     uint32_t max_len;
-    uint32_t exc_overflow;          // a quantize tile had more exceptions than its staging slots
-    uint32_t pad1;
+    uint32_t pad0, pad1;
+    uint64_t pool_used;             // overflow-pool records taken by the quantize tiles
     uint64_t exc_total, out_total;  // written by the last quantize segment
     uint64_t bits_total;            // written by the last encode-count segment
     uint64_t total_bits;
@@ -283,6 +312,7 @@ __device__ __forceinline__ float patch_threshold(double eb) { return (float)(eb 
 // Launchers (defined in the kernel translation units).
 // ---------------------------------------------------------------------------
 void launch_init(hipStream_t s, Ctl *ctl, void *zero_base, uint64_t zero_bytes, int eb_mode, double eb);
+void launch_publish(hipStream_t s, Readback *rb, uint32_t bits, uint64_t archive_bytes);
 // (also clears the control block and [zero_base, +zero_bytes), as launch_init does)
 void launch_minmax(hipStream_t s, const float *x, uint64_t n, Ctl *ctl, uint32_t *partials, double valrel, int ncu,
                    void *zero_base, uint64_t zero_bytes);
@@ -293,6 +323,9 @@ struct QuantBufs {
     uint32_t *hist_sum;    // 2R, the replicas summed
     uint2 *stage;          // tiles * cap exception records
     uint32_t cap;
+    uint2 *pool;           // records past a tile's cap, taken in runs by atomic reservation
+    uint64_t pool_cap;     // records the pool holds
+    uint32_t *ovf_base;    // per tile: first pool record of its overflow run
     TileScan scan;         // exception count (0) and outlier count (1) per tile
 };
 void launch_quantize(hipStream_t s, const float *x, const Geom &g, const Layout &L, Ctl *ctl, const QuantBufs &b);
@@ -301,32 +334,35 @@ uint32_t quantize_tiles(const Geom &g);
 void launch_codebook(hipStream_t s, const Geom &g, const Layout &L, Ctl *ctl, const uint32_t *hist,
                      uint64_t *book, uint32_t *book32, uint8_t *archive, int eb_mode, double eb_param,
                      const TileScan &qscan,
-                     Ctl *hctl);
+                     Readback *rb);
 struct EncodeBufs {
     const uint16_t *codes;
     const uint64_t *book;
     const uint32_t *book32;
     const uint2 *stage;    // quantize staging
     uint32_t cap;
+    const uint2 *pool;     // quantize overflow pool
+    const uint32_t *ovf_base;
     TileScan qscan;        // offsets of the staged exceptions
     uint64_t *eflag;       // per encode tile: look-back state (zeroed before the launch)
     uint32_t n_tiles_q;
 };
-void launch_encode(hipStream_t s, const Geom &g, const Layout &L, Ctl *ctl, Ctl *hctl, const EncodeBufs &b,
+void launch_encode(hipStream_t s, const Geom &g, const Layout &L, Ctl *ctl, Readback *rb, const EncodeBufs &b,
                    uint8_t *archive, int ncu);
 uint32_t encode_tiles(const Geom &g);
 void launch_decode_tables(hipStream_t s, const Layout &L, const uint8_t *archive, uint32_t max_len_hdr,
-                          DecodeTables *tab, uint32_t *hstatus, uint32_t n_exc, uint32_t *unit_exc,
+                          DecodeTables *tab, Readback *rb, uint32_t n_exc, uint32_t *unit_exc,
                           uint32_t n_units);
 size_t decode_lds_bytes(const Layout &L);
+hipError_t decode_kernel_attributes();   // once per device, before the first decoding launch
 // Subchunks of 128 positions: launch_decode inflates into `qws` (u16 per
 // padded position) and launch_recon reconstructs from it; other subchunk
 // sizes decode in one kernel (qws unused).
 void launch_decode(hipStream_t s, const Geom &g, const Layout &L, const uint8_t *archive, uint64_t off_str,
                    uint64_t n_words, uint32_t n_exc, float h, DecodeTables *tab, float *out, bool trace,
-                   uint4 *qws, uint32_t *hstatus);
+                   uint4 *qws, Readback *rb, int ncu);
 void launch_recon(hipStream_t s, const Geom &g, const Layout &L, const uint8_t *archive, uint32_t n_exc, float h,
-                  const DecodeTables *tab, const uint4 *qws, const uint32_t *unit_exc, float *out, uint32_t *hstatus);
+                  const DecodeTables *tab, const uint4 *qws, const uint32_t *unit_exc, float *out, Readback *rb);
 // reconstruction units of 512 padded positions
 inline uint32_t recon_units(const Geom &g) { return (g.padded + (1u << kUnitShift) - 1) >> kUnitShift; }
 

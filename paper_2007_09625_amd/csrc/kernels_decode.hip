@@ -43,7 +43,7 @@ struct DecArgs {
     uint32_t win_words; // LDS stream-window words per wave
     uint32_t trace;     // record phase durations into tab->phase
     uint4 *qws;         // 128-position subchunks: 16 x 16 bytes of codes per subchunk, lane-interleaved
-    uint32_t *hstatus;  // status word in pinned host memory, read after the stream ends
+    Readback *rb;       // the call's readback block, read by the host after the stream ends
 };
 
 // Stream word i.  Indices past the end are clamped to the last word rather
@@ -461,7 +461,8 @@ __global__ __launch_bounds__(64 * kDecMaxWaves) void k_decode(DecArgs a) {
         const uint32_t max_len = a.tab->max_len < 63u ? a.tab->max_len : 63u;
         const uint32_t used = inflate(a, win, nwin, wlo, start, pa, S, wq + lane * a.qstride, s_lut, s_t, s_sorted,
                                       max_len, bad);
-        if (used != bits_s) bad = true;
+        // the subchunk must lie inside the stream and consume exactly its recorded bits
+        if (used != bits_s || start + bits_s > 32ull * a.n_words) bad = true;
     }
     if (a.trace) tm[3] = wall_clock64();
     __syncthreads();
@@ -546,7 +547,7 @@ __global__ __launch_bounds__(64 * kDecMaxWaves) void k_decode(DecArgs a) {
     }
     if (bad) {
         atomicOr(a.status, ST_ECORRUPT);
-        *a.hstatus = ST_ECORRUPT;
+        publish_status(a.rb, ST_ECORRUPT);
     }
     if (a.trace && active && lane == 0) {
         tm[6] = wall_clock64();
@@ -769,11 +770,12 @@ __global__ __launch_bounds__(64 * kInfMaxWaves) void k_inflate128(DecArgs a) {
         else
             used = inflate_codes<false, false>(a, win, ws.nwin, ws.wlo, ws.start, pa, dst, s_lut, s_lut2, b2, base2,
                                                last2, max_len, bad);
-        if (used != ws.bits) bad = true;
+        // the subchunk must lie inside the stream and consume exactly its recorded bits
+        if (used != ws.bits || ws.start + ws.bits > 32ull * a.n_words) bad = true;
     }
     if (bad) {
         atomicOr(a.status, ST_ECORRUPT);
-        *a.hstatus = ST_ECORRUPT;
+        publish_status(a.rb, ST_ECORRUPT);
     }
     if (a.trace && active && lane == 0) {
         const uint64_t t2 = wall_clock64();
@@ -793,7 +795,7 @@ struct ReconArgs {
     const DecodeTables *tab;
     float *out;
     uint32_t *status;
-    uint32_t *hstatus;          // status word in pinned host memory
+    Readback *rb;               // the call's readback block
     uint32_t n_exc, n_units, radius;
     float h;
 };
@@ -814,7 +816,7 @@ __device__ __forceinline__ uint32_t slot_lane(uint32_t slot) {
 // One unit: its lane piece d[] (deltas, outliers still 0) and code-0 mask,
 // records [rs, re) of the exception list.
 template <uint32_t NDIM>
-__device__ __forceinline__ void recon_unit(const ReconArgs &a, uint32_t u, uint32_t lane, int32_t (&d)[8],
+__device__ __forceinline__ void recon_unit(const ReconArgs &a, uint32_t u, uint32_t lane, uint32_t (&d)[8],
                                            uint32_t zmask, uint32_t rs, uint32_t re, bool &bad) {
     const Geom &g = a.g;
     const uint32_t P0 = u << kUnitShift;
@@ -838,37 +840,38 @@ __device__ __forceinline__ void recon_unit(const ReconArgs &a, uint32_t u, uint3
             if (!((zmask >> x) & 1u)) bad = true;
 #pragma unroll
             for (uint32_t k = 0; k < 8; k++)
-                if (k == x) d[k] = (int32_t)r.y;
+                if (k == x) d[k] = r.y;
         }
     }
     // every code 0 takes exactly one record (keys increase)
     if (wave_sum<uint32_t>(__popc(zmask)) != n_out) bad = true;
 
-    // inverse Lorenzo prediction: inclusive prefix sums along every axis
+    // inverse Lorenzo prediction: inclusive prefix sums along every axis,
+    // wrapping modulo 2^32 like the forward difference
 #pragma unroll
     for (uint32_t x = 1; x < 8; x++) d[x] += d[x - 1];
     if (NDIM == 3) {
 #pragma unroll
-        for (uint32_t x = 0; x < 8; x++) d[x] = (int32_t)stride8_scan(seg_scan<8>((uint32_t)d[x], lane), lane);
+        for (uint32_t x = 0; x < 8; x++) d[x] = stride8_scan(seg_scan<8>(d[x], lane), lane);
     } else if (NDIM == 2) {
         uint32_t ofe, efo;
-        row_swap16((uint32_t)d[7], ofe, efo);   // the left half-row's total, for the right half
-        const int32_t left = ((lane >> 4) & 1u) ? (int32_t)ofe : 0;
+        row_swap16(d[7], ofe, efo);   // the left half-row's total, for the right half
+        const uint32_t left = ((lane >> 4) & 1u) ? ofe : 0u;
 #pragma unroll
-        for (uint32_t x = 0; x < 8; x++) d[x] = (int32_t)seg_scan<16>((uint32_t)(d[x] + left), lane);
+        for (uint32_t x = 0; x < 8; x++) d[x] = seg_scan<16>(d[x] + left, lane);
     } else {
         // exclusive prefix of the lane totals within the block's quad
-        const uint32_t t = (uint32_t)d[7], q4 = lane & 3u;
+        const uint32_t t = d[7], q4 = lane & 3u;
         const uint32_t s1 = quad_shr1(t);
         const uint32_t i1 = t + (q4 >= 1 ? s1 : 0u);
         const uint32_t s2 = quad_shr2(i1);
-        const int32_t ex = (int32_t)(i1 + (q4 >= 2 ? s2 : 0u) - t);
+        const uint32_t ex = i1 + (q4 >= 2 ? s2 : 0u) - t;
 #pragma unroll
         for (uint32_t x = 0; x < 8; x++) d[x] += ex;
     }
     float f[8];
 #pragma unroll
-    for (uint32_t x = 0; x < 8; x++) f[x] = dequant(d[x], a.h);
+    for (uint32_t x = 0; x < 8; x++) f[x] = dequant((int32_t)d[x], a.h);
 
     // output index of the lane's first position and how many of its eight lie in the field
     uint64_t o0 = 0;
@@ -921,7 +924,7 @@ __device__ __forceinline__ void recon_unit(const ReconArgs &a, uint32_t u, uint3
 // copy of the block twice, so that the y and then the z prefix are in-lane
 // too: lane 8 z + x holds a y-column, then lane 8 y + x a z-column.  Rows of
 // the copy are 9 words apart (bank spread for the column reads).
-__device__ __forceinline__ void recon_block3(const ReconArgs &a, uint32_t u, uint32_t lane, int32_t (&d)[8],
+__device__ __forceinline__ void recon_block3(const ReconArgs &a, uint32_t u, uint32_t lane, uint32_t (&d)[8],
                                              uint32_t zmask, uint32_t rs, uint32_t re, lds_u32 *blk, bool &bad) {
     const Geom &g = a.g;
     const uint32_t P0 = u << kUnitShift;
@@ -946,7 +949,7 @@ __device__ __forceinline__ void recon_block3(const ReconArgs &a, uint32_t u, uin
                 if (!((zmask >> x) & 1u)) bad = true;
 #pragma unroll
                 for (uint32_t k = 0; k < 8; k++)
-                    if (k == x) d[k] = (int32_t)r.y;
+                    if (k == x) d[k] = r.y;
             }
         }
     }
@@ -957,31 +960,32 @@ __device__ __forceinline__ void recon_block3(const ReconArgs &a, uint32_t u, uin
         for (uint32_t x = 0; x < 8; x++) nz += (uint32_t)__popcll(__ballot((int)((zmask >> x) & 1u)));
         if (nz != n_out) bad = true;
     }
-    // x in-lane (lane = 8 z + y)
+    // x in-lane (lane = 8 z + y); the sums wrap modulo 2^32 like the
+    // forward difference
 #pragma unroll
     for (uint32_t x = 1; x < 8; x++) d[x] += d[x - 1];
     const uint32_t hi = lane >> 3, lo = lane & 7u;
 #pragma unroll
-    for (uint32_t x = 0; x < 8; x++) blk[72 * hi + 9 * lo + x] = (uint32_t)d[x];   // (z, y) = (hi, lo)
+    for (uint32_t x = 0; x < 8; x++) blk[72 * hi + 9 * lo + x] = d[x];   // (z, y) = (hi, lo)
     // a wave's LDS accesses complete in order; the barriers keep the compiler
     // from moving the column reads above the other lanes' writes
     __builtin_amdgcn_wave_barrier();
     // y: lane 8 z + x reads the column (z, ., x)
 #pragma unroll
-    for (uint32_t y = 0; y < 8; y++) d[y] = (int32_t)blk[72 * hi + 9 * y + lo];
+    for (uint32_t y = 0; y < 8; y++) d[y] = blk[72 * hi + 9 * y + lo];
 #pragma unroll
     for (uint32_t y = 1; y < 8; y++) d[y] += d[y - 1];
 #pragma unroll
-    for (uint32_t y = 0; y < 8; y++) blk[72 * hi + 9 * y + lo] = (uint32_t)d[y];
+    for (uint32_t y = 0; y < 8; y++) blk[72 * hi + 9 * y + lo] = d[y];
     __builtin_amdgcn_wave_barrier();
     // z: lane 8 y + x reads the column (., y, x)
 #pragma unroll
-    for (uint32_t z = 0; z < 8; z++) d[z] = (int32_t)blk[72 * z + 9 * hi + lo];
+    for (uint32_t z = 0; z < 8; z++) d[z] = blk[72 * z + 9 * hi + lo];
 #pragma unroll
     for (uint32_t z = 1; z < 8; z++) d[z] += d[z - 1];
     float f[8];
 #pragma unroll
-    for (uint32_t z = 0; z < 8; z++) f[z] = dequant(d[z], a.h);
+    for (uint32_t z = 0; z < 8; z++) f[z] = dequant((int32_t)d[z], a.h);
     // lane (y, x) = (hi, lo) holds the z-column
     const uint32_t Bx = u % g.nb[2], By = (u / g.nb[2]) % g.nb[1], Bz = u / (g.nb[2] * g.nb[1]);
     const uint32_t vx = min(8u, g.n[2] - 8 * Bx), vy = min(8u, g.n[1] - 8 * By), vz = min(8u, g.n[0] - 8 * Bz);
@@ -1022,17 +1026,17 @@ __global__ __launch_bounds__(64 * kReconWaves) void k_recon(ReconArgs a) {
     // group slot % 16 of subchunk 4 u + slot / 16, lane-interleaved by wave of 64 subchunks
     const uint4 q = a.codes[((uint64_t)(u >> 4) * 16 + (slot & 15u)) * 64 + (u & 15u) * 4 + (slot >> 4)];
     const uint32_t rs = a.unit_exc[u], re = a.unit_exc[u + 1];
-    const int32_t R = (int32_t)a.radius;
+    const uint32_t R = a.radius;
     const bool lv = (u << kUnitShift) + 8 * slot < a.g.padded;
-    int32_t d[8];
+    uint32_t d[8];   // wrapping deltas
     uint32_t zmask = 0;   // code 0: an outlier
     {
         const uint32_t w4[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
         for (uint32_t m = 0; m < 4; m++) {
             const uint32_t c0 = w4[m] & 0xFFFFu, c1 = w4[m] >> 16;
-            d[2 * m] = lv ? (int32_t)c0 - R : 0;
-            d[2 * m + 1] = lv ? (int32_t)c1 - R : 0;
+            d[2 * m] = lv ? c0 - R : 0u;
+            d[2 * m + 1] = lv ? c1 - R : 0u;
             zmask |= ((lv && c0 == 0) ? 1u : 0u) << (2 * m);
             zmask |= ((lv && c1 == 0) ? 1u : 0u) << (2 * m + 1);
         }
@@ -1042,7 +1046,7 @@ __global__ __launch_bounds__(64 * kReconWaves) void k_recon(ReconArgs a) {
     else recon_unit<NDIM>(a, u, lane, d, zmask, rs, re, bad);
     if (bad) {
         atomicOr(a.status, ST_ECORRUPT);
-        *a.hstatus = ST_ECORRUPT;
+        publish_status(a.rb, ST_ECORRUPT);
     }
 }
 
@@ -1068,9 +1072,19 @@ size_t decode_lds_bytes(const Layout &L) {
     return decode_lds_fixed(L) - sizeof(DecLds) + 4ull * decode_waves(L) * decode_win_words(L);
 }
 
+// Dynamic LDS limits of the decoding kernels, set once per device before any
+// launch (not between launches, so that a stream capture holds launches only).
+hipError_t decode_kernel_attributes() {
+    hipError_t e = hipFuncSetAttribute((const void *)k_inflate128, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)(4ull * kInfMaxWaves * kInfWin));
+    if (e != hipSuccess) return e;
+    return hipFuncSetAttribute((const void *)k_decode, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)kDecLdsLimit);
+}
+
 void launch_decode(hipStream_t s, const Geom &g, const Layout &L, const uint8_t *archive, uint64_t off_str,
                    uint64_t n_words, uint32_t n_exc, float h, DecodeTables *tab, float *out, bool trace,
-                   uint4 *qws, uint32_t *hstatus) {
+                   uint4 *qws, Readback *rb, int ncu) {
     DecArgs a;
     a.g = g;
     a.L = L;
@@ -1089,19 +1103,17 @@ void launch_decode(hipStream_t s, const Geom &g, const Layout &L, const uint8_t 
     a.win_words = decode_win_words(L);
     a.trace = trace ? 1u : 0u;
     a.qws = qws;
-    a.hstatus = hstatus;
+    a.rb = rb;
     if (a.wave_tasks == 0) return;
     if (L.sub_size == 128 && qws) {
         // codes only; launch_recon finishes
         a.win_words = kInfWin;
         // one workgroup per CU, waves spread evenly over the CUs
-        constexpr uint32_t kCus = 256;
-        uint32_t waves = (a.wave_tasks + kCus - 1) / kCus;
+        const uint32_t cus = ncu > 0 ? (uint32_t)ncu : 256u;
+        uint32_t waves = (a.wave_tasks + cus - 1) / cus;
         waves = waves < 1 ? 1 : (waves > kInfMaxWaves ? kInfMaxWaves : waves);
         const uint32_t blocks = (a.wave_tasks + waves - 1) / waves;
         const size_t lds = 4ull * waves * kInfWin;   // the windows (the tables are static)
-        (void)hipFuncSetAttribute((const void *)k_inflate128, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)(4ull * kInfMaxWaves * kInfWin));
         hipLaunchKernelGGL(k_inflate128, dim3(blocks), dim3(64 * waves), lds, s, a);
         return;
     }
@@ -1109,12 +1121,11 @@ void launch_decode(hipStream_t s, const Geom &g, const Layout &L, const uint8_t 
     const uint32_t waves = decode_waves(L);
     const uint32_t blocks = (a.wave_tasks + waves - 1) / waves;
     const size_t lds = decode_lds_bytes(L);
-    if (lds > 65536) (void)hipFuncSetAttribute((const void *)k_decode, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     hipLaunchKernelGGL(k_decode, dim3(blocks), dim3(64 * waves), lds, s, a);
 }
 
 void launch_recon(hipStream_t s, const Geom &g, const Layout &L, const uint8_t *archive, uint32_t n_exc, float h,
-                  const DecodeTables *tab, const uint4 *qws, const uint32_t *unit_exc, float *out, uint32_t *hstatus) {
+                  const DecodeTables *tab, const uint4 *qws, const uint32_t *unit_exc, float *out, Readback *rb) {
     ReconArgs a;
     a.g = g;
     a.codes = qws;
@@ -1123,7 +1134,7 @@ void launch_recon(hipStream_t s, const Geom &g, const Layout &L, const uint8_t *
     a.tab = tab;
     a.out = out;
     a.status = const_cast<uint32_t *>(&tab->status);
-    a.hstatus = hstatus;
+    a.rb = rb;
     a.n_exc = n_exc;
     a.n_units = recon_units(g);
     a.radius = L.radius;

@@ -40,14 +40,14 @@ struct EncArgs {
     Geom g;
     Layout L;
     Ctl *ctl;
-    Ctl *hctl;        // the host's readback block: errors found here are reported there too
+    Readback *rb;     // the call's readback block: errors found here are reported there too
     EncodeBufs b;
     uint8_t *archive;
     uint32_t n_tiles_e;
 };
 
 constexpr uint32_t kEncPer = kTile / 256;              // positions per thread
-constexpr uint32_t kBadStatus = ST_EINVAL | ST_ETOOSMALL | ST_EUNSUPPORTED | ST_EINTERNAL | ST_RETRY;
+constexpr uint32_t kBadStatus = ST_EINVAL | ST_ETOOSMALL | ST_EUNSUPPORTED | ST_EINTERNAL | ST_ENOMEM;
 
 template <bool WIDE> struct Codeword;
 template <> struct Codeword<false> {
@@ -114,7 +114,7 @@ __device__ __forceinline__ void flag_store(uint64_t *p, uint64_t v) {
 
 __device__ __forceinline__ void report_internal(const EncArgs &a) {
     atomicOr(&a.ctl->status, ST_EINTERNAL);
-    a.hctl->status = a.ctl->status | ST_EINTERNAL;
+    publish_status(a.rb, a.ctl->status | ST_EINTERNAL);
 }
 
 // Stream bit offset of tile t > 0 (one whole wave): predecessors are read 64
@@ -287,16 +287,21 @@ struct EncLds {
 
 // Staged exception records of quantize tile t -> archive, by one wave (the
 // records' offset: the segment totals before the tile's, plus its offset
-// inside its segment).
+// inside its segment).  Records past the tile's slot come from its run of
+// the overflow pool (this kernel does not run when the pool was too small).
 __device__ void copy_exceptions(const EncArgs &a, uint32_t t, uint32_t lane) {
-    uint32_t cnt = a.b.qscan.val[0][t];
-    if (cnt > a.b.cap) cnt = a.b.cap;   // overflowed: the host compresses again with full staging
+    const uint32_t cnt = a.b.qscan.val[0][t];
+    const uint32_t in_slot = cnt < a.b.cap ? cnt : a.b.cap;
     uint64_t part = 0;
     for (uint32_t i = lane; i < t / kSegTiles; i += 64) part += a.b.qscan.seg_total[0][i];
     const uint64_t off = wave_sum<uint64_t>(part) + a.b.qscan.excl[0][t];
     uint2 *dst = reinterpret_cast<uint2 *>(a.archive + a.L.off_exc) + off;
     const uint2 *src = a.b.stage + (uint64_t)t * a.b.cap;
-    for (uint32_t i = lane; i < cnt; i += 64) dst[i] = src[i];
+    for (uint32_t i = lane; i < in_slot; i += 64) dst[i] = src[i];
+    if (cnt > in_slot) {
+        const uint2 *ovf = a.b.pool + a.b.ovf_base[t];
+        for (uint32_t i = lane; i < cnt - in_slot; i += 64) dst[in_slot + i] = ovf[i];
+    }
 }
 
 template <bool WIDE>
@@ -458,13 +463,13 @@ void launch_seg_scan(hipStream_t s, const TileScan &S, const HistJob *hj) {
 
 uint32_t encode_tiles(const Geom &g) { return (uint32_t)((g.padded + kTile - 1) / kTile); }
 
-void launch_encode(hipStream_t s, const Geom &g, const Layout &L, Ctl *ctl, Ctl *hctl, const EncodeBufs &b,
+void launch_encode(hipStream_t s, const Geom &g, const Layout &L, Ctl *ctl, Readback *rb, const EncodeBufs &b,
                    uint8_t *archive, int ncu) {
     EncArgs a;
     a.g = g;
     a.L = L;
     a.ctl = ctl;
-    a.hctl = hctl;
+    a.rb = rb;
     a.b = b;
     a.archive = archive;
     a.n_tiles_e = encode_tiles(g);

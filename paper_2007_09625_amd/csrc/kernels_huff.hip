@@ -321,13 +321,13 @@ __global__ __launch_bounds__(kBookThreads) void k_codebook(const uint32_t *__res
                                                            uint64_t *__restrict__ book, uint32_t *__restrict__ book32,
                                                            uint8_t *archive, Layout L, Geom g, HeaderArgs hdr,
                                                            TileScan qscan,
-                                                           Ctl *hctl) {
+                                                           Readback *rb) {
     __shared__ BookLds s;
     __shared__ uint64_t s_red[4];
     const uint32_t tid = threadIdx.x, T = blockDim.x;
     const uint32_t ns = L.nsym;
     if (ctl->status & (ST_EINVAL | ST_EINTERNAL)) {
-        if (tid == 0) hctl->status = ctl->status;   // the host reads this block after the stream ends
+        if (tid == 0) publish_status(rb, ctl->status);   // the host reads this block after the stream ends
         return;
     }
     if (tid == 0) ctl->phase[0] = wall_clock64();
@@ -560,7 +560,6 @@ __global__ __launch_bounds__(kBookThreads) void k_codebook(const uint32_t *__res
     if (tid == 0) {
         ctl->phase[6] = wall_clock64();
         if (max_len > 64) atomicOr(&ctl->status, ST_EUNSUPPORTED);
-        if (ctl->exc_overflow) atomicOr(&ctl->status, ST_RETRY);
         const uint64_t total_bits = s.total_bits;
         const uint64_t n_words = (total_bits + 31) / 32;
         const uint32_t n_exc = (uint32_t)ctl->exc_total;
@@ -609,13 +608,14 @@ __global__ __launch_bounds__(kBookThreads) void k_codebook(const uint32_t *__res
     for (uint32_t i = tid; i < kHeaderBytes; i += T) {
         archive[i] = s.hdr[i];
         ctl->header[i] = s.hdr[i];
-        hctl->header[i] = s.hdr[i];
+        rb->header[i] = s.hdr[i];
     }
     if (tid == 0) {
         // the host's readback block (pinned host memory): final once this
         // kernel ends, since the encoding kernels add no status
-        hctl->archive_bytes = ctl->archive_bytes;
-        hctl->status = ctl->status;
+        rb->archive_bytes = ctl->archive_bytes;
+        rb->workspace_need = (ctl->status & ST_ENOMEM) ? L.ws_fixed + 8ull * ctl->pool_used : 0ull;
+        publish_status(rb, ctl->status);
     }
     for (uint32_t i = tid; i < ns; i += T) archive[L.off_len + i] = s.len[i];
     for (uint64_t i = L.off_len + ns + tid; i < L.off_chunk; i += T) archive[i] = 0;
@@ -625,7 +625,7 @@ __global__ __launch_bounds__(kBookThreads) void k_codebook(const uint32_t *__res
 
 void launch_codebook(hipStream_t st, const Geom &g, const Layout &L, Ctl *ctl, const uint32_t *hist, uint64_t *book,
                      uint32_t *book32, uint8_t *archive, int eb_mode, double eb_param, const TileScan &qscan,
-                     Ctl *hctl) {
+                     Readback *rb) {
     HeaderArgs h;
     h.dims[0] = g.n[0];
     h.dims[1] = g.n[1];
@@ -633,7 +633,7 @@ void launch_codebook(hipStream_t st, const Geom &g, const Layout &L, Ctl *ctl, c
     h.eb_param = eb_param;
     h.ndim = g.ndim;
     h.eb_mode = (uint32_t)eb_mode;
-    hipLaunchKernelGGL(k_codebook, dim3(1), dim3(kBookThreads), 0, st, hist, ctl, book, book32, archive, L, g, h, qscan, hctl);
+    hipLaunchKernelGGL(k_codebook, dim3(1), dim3(kBookThreads), 0, st, hist, ctl, book, book32, archive, L, g, h, qscan, rb);
 }
 
 // ---------------------------------------------------------------------------
@@ -645,7 +645,7 @@ void launch_codebook(hipStream_t st, const Geom &g, const Layout &L, Ctl *ctl, c
 // every adjacent pair of keys is checked to increase.
 // ---------------------------------------------------------------------------
 __device__ void exception_index(const uint2 *exc, uint32_t n_exc, uint32_t *unit_exc, uint32_t n_units,
-                                uint32_t *hstatus) {
+                                Readback *rb) {
     const uint32_t i = (blockIdx.x - 1) * blockDim.x + threadIdx.x;
     if (i <= n_units) {
         const uint64_t key = 2ull * ((uint64_t)i << kUnitShift);
@@ -656,9 +656,9 @@ __device__ void exception_index(const uint2 *exc, uint32_t n_exc, uint32_t *unit
         }
         unit_exc[i] = lo;
     }
-    if (i > 0 && i < n_exc && exc[i - 1].x >= exc[i].x) *hstatus = ST_ECORRUPT;
+    if (i > 0 && i < n_exc && exc[i - 1].x >= exc[i].x) publish_status(rb, ST_ECORRUPT);
     // with increasing keys, every record then lies in some unit
-    if (i + 1 == n_exc && ((exc[i].x >> 1) >> kUnitShift) >= n_units) *hstatus = ST_ECORRUPT;
+    if (i + 1 == n_exc && ((exc[i].x >> 1) >> kUnitShift) >= n_units) publish_status(rb, ST_ECORRUPT);
 }
 
 // Second-level table: the long-code prefixes are the top of the first
@@ -718,10 +718,10 @@ __device__ void build_lut2(const CanonScratch &c, DecodeTables *tab, const uint6
 }
 
 __global__ __launch_bounds__(kTableThreads) void k_decode_tables(const uint8_t *__restrict__ archive, Layout L,
-                                                                uint32_t max_len_hdr, DecodeTables *tab, uint32_t *hstatus,
+                                                                uint32_t max_len_hdr, DecodeTables *tab, Readback *rb,
                                                                 uint32_t n_exc, uint32_t *unit_exc, uint32_t n_units) {
     if (blockIdx.x > 0) {
-        exception_index(reinterpret_cast<const uint2 *>(archive + L.off_exc), n_exc, unit_exc, n_units, hstatus);
+        exception_index(reinterpret_cast<const uint2 *>(archive + L.off_exc), n_exc, unit_exc, n_units, rb);
         return;
     }
     __shared__ CanonScratch c;
@@ -742,7 +742,7 @@ __global__ __launch_bounds__(kTableThreads) void k_decode_tables(const uint8_t *
     }
     __syncthreads();
     if (s_bad) {
-        if (tid == 0) { tab->status = ST_ECORRUPT; tab->max_len = 0; *hstatus = ST_ECORRUPT; }
+        if (tid == 0) { tab->status = ST_ECORRUPT; tab->max_len = 0; publish_status(rb, ST_ECORRUPT); }
         return;
     }
     canonical_order(len, ns, c);
@@ -754,7 +754,7 @@ __global__ __launch_bounds__(kTableThreads) void k_decode_tables(const uint8_t *
         if (c.kraft == 1u || (!lone && c.n_used > 0 && c.kraft != 0u) || c.max_len != max_len_hdr || c.max_len > 63)
             st = ST_ECORRUPT;
         tab->status = st;
-        if (st) *hstatus = st;   // pinned host memory, read after the stream ends
+        if (st) publish_status(rb, st);   // the host reads this block after the stream ends
         tab->max_len = c.max_len;
     }
     for (uint32_t l = tid; l < 65; l += T) {
@@ -829,13 +829,13 @@ __global__ __launch_bounds__(kTableThreads) void k_decode_tables(const uint8_t *
 }
 
 void launch_decode_tables(hipStream_t st, const Layout &L, const uint8_t *archive, uint32_t max_len_hdr,
-                          DecodeTables *tab, uint32_t *hstatus, uint32_t n_exc, uint32_t *unit_exc,
+                          DecodeTables *tab, Readback *rb, uint32_t n_exc, uint32_t *unit_exc,
                           uint32_t n_units) {
     // workgroup 0 builds the tables; the others index the exception list
     const uint32_t idx_items = unit_exc ? (n_units + 1 > n_exc ? n_units + 1 : n_exc) : 0u;
     const uint32_t blocks = 1 + (idx_items + kTableThreads - 1) / kTableThreads;
     hipLaunchKernelGGL(k_decode_tables, dim3(blocks), dim3(kTableThreads), 0, st, archive, L, max_len_hdr, tab,
-                       hstatus, n_exc, unit_exc, n_units);
+                       rb, n_exc, unit_exc, n_units);
 }
 
 }  // namespace dqz

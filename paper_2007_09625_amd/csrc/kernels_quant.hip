@@ -69,6 +69,18 @@ void launch_init(hipStream_t s, Ctl *ctl, void *zero_base, uint64_t zero_bytes, 
     hipLaunchKernelGGL(k_init, dim3(blocks), dim3(256), 0, s, ctl, (uint32_t *)zero_base, words, eb_mode, eb);
 }
 
+// One thread: a readback block's status and archive size (the asynchronous
+// decompression's result before its kernels run; they overwrite it on damage).
+__global__ void k_publish(Readback *rb, uint32_t bits, uint64_t archive_bytes) {
+    rb->archive_bytes = archive_bytes;
+    rb->workspace_need = 0;
+    publish_status(rb, bits);
+}
+
+void launch_publish(hipStream_t s, Readback *rb, uint32_t bits, uint64_t archive_bytes) {
+    hipLaunchKernelGGL(k_publish, dim3(1), dim3(1), 0, s, rb, bits, archive_bytes);
+}
+
 __device__ __forceinline__ void key_acc(uint32_t u, uint32_t &lo, uint32_t &hi) {
     if ((u & 0x7F800000u) != 0x7F800000u) {   // finite
         const uint32_t k = f2key(u);
@@ -226,20 +238,44 @@ __device__ __forceinline__ uint32_t wave_base_in_tile(uint32_t wave_count, uint3
     return base;
 }
 
-__device__ __forceinline__ void put_exc(const QuantArgs &a, uint32_t tile, uint32_t idx, uint32_t key, uint32_t payload) {
+// Record idx of the tile (in stream order): the first `cap` go to the tile's
+// staging slot, the rest to its run of the overflow pool starting at `ovf`.
+__device__ __forceinline__ void put_exc(const QuantArgs &a, uint32_t tile, uint32_t idx, uint32_t key, uint32_t payload,
+                                        uint32_t ovf) {
+    uint2 rec;
+    rec.x = key;
+    rec.y = payload;
     if (idx < a.b.cap) {
-        uint2 rec;
-        rec.x = key;
-        rec.y = payload;
         a.b.stage[(uint64_t)tile * a.b.cap + idx] = rec;
+    } else {
+        const uint64_t j = (uint64_t)ovf + (idx - a.b.cap);
+        if (j < a.b.pool_cap) a.b.pool[j] = rec;
     }
+}
+
+// A tile with more records than its slot takes a run of the overflow pool
+// (one device atomic, on this rare path only); a pool too small for every
+// run is reported as ST_ENOMEM, with the records it needed in pool_used.
+// tile_count is the same for every thread, so the barrier is uniform.
+__device__ __forceinline__ uint32_t reserve_overflow(const QuantArgs &a, uint32_t tile, uint32_t tile_count,
+                                                     uint32_t *sh) {
+    if (tile_count <= a.b.cap) return 0u;
+    if (threadIdx.x == 0) {
+        const uint64_t n = tile_count - a.b.cap;
+        const uint64_t base = atomicAdd((unsigned long long *)&a.ctl->pool_used, (unsigned long long)n);
+        if (base + n > a.b.pool_cap) atomicOr(&a.ctl->status, ST_ENOMEM);
+        a.b.ovf_base[tile] = (uint32_t)base;
+        sh[12] = (uint32_t)base;
+    }
+    __syncthreads();
+    return sh[12];
 }
 
 // Tile epilogue shared by all dimensionalities: overflow flag, histogram
 // flush, and the wait-free scan of the record counts.
 __device__ __forceinline__ void tile_epilogue(const QuantArgs &a, uint32_t tile, uint32_t tile_count, uint32_t tile_out,
                                               uint32_t *sh_hist, uint64_t *sh64) {
-    if (threadIdx.x == 0 && tile_count > a.b.cap) a.ctl->exc_overflow = 1u;
+    (void)tile_count;
     __syncthreads();
     hist_flush(sh_hist, a.L.nsym, a.b.hist);
     tile_publish(a.b.scan, tile, tile_count, tile_out);
@@ -371,6 +407,7 @@ __global__ __launch_bounds__(256) void k_quant3d(QuantArgs a) {
 
     uint32_t tile_count, tile_out;
     const uint32_t base0 = wave_base_in_tile(wave_count, wave_out, s_misc, tile_count, tile_out);
+    const uint32_t ovf = reserve_overflow(a, tile, tile_count, s_misc);
     if (wave_count) {
         uint32_t base = base0;
         const uint64_t below = lanes_below(lane);
@@ -385,8 +422,8 @@ __global__ __launch_bounds__(256) void k_quant3d(QuantArgs a) {
                 if ((mo | mp) == 0) continue;
                 const uint32_t idx = base + __popcll(mo & below) + __popcll(mp & below);
                 const uint32_t pos = (uint32_t)(blk * 512 + z * 64 + lane);
-                if (o) put_exc(a, tile, idx, 2u * pos, (uint32_t)delta[j][z]);
-                if (p) put_exc(a, tile, idx + (o ? 1 : 0), 2u * pos + 1u, __float_as_uint(s_tile[z][ly][bxl * 8 + lx]));
+                if (o) put_exc(a, tile, idx, 2u * pos, (uint32_t)delta[j][z], ovf);
+                if (p) put_exc(a, tile, idx + (o ? 1 : 0), 2u * pos + 1u, __float_as_uint(s_tile[z][ly][bxl * 8 + lx]), ovf);
                 base += __popcll(mo) + __popcll(mp);
             }
         }
@@ -504,6 +541,7 @@ __global__ __launch_bounds__(256) void k_quant2d(QuantArgs a) {
     const uint32_t grp_off = (grp > 0 ? g0 : 0u) + (grp > 1 ? g1 : 0u) + (grp > 2 ? g2 : 0u);
     uint32_t tile_count, tile_out;
     const uint32_t base0 = wave_base_in_tile(wave_count, wave_out, s_misc, tile_count, tile_out);
+    const uint32_t ovf = reserve_overflow(a, tile, tile_count, s_misc);
     if (wave_count) {
         uint32_t base = base0 + grp_off;
         const uint64_t gmask = 0xFFFFull << (16 * grp);
@@ -515,8 +553,8 @@ __global__ __launch_bounds__(256) void k_quant2d(QuantArgs a) {
             if ((mo | mp) == 0) continue;
             const uint32_t idx = base + __popcll(mo & below) + __popcll(mp & below);
             const uint32_t pos = (uint32_t)(blk * 256 + y * 16 + lx);
-            if (o) put_exc(a, tile, idx, 2u * pos, (uint32_t)delta[y]);
-            if (p) put_exc(a, tile, idx + (o ? 1 : 0), 2u * pos + 1u, __float_as_uint(s_tile[y][bxl * 16 + lx]));
+            if (o) put_exc(a, tile, idx, 2u * pos, (uint32_t)delta[y], ovf);
+            if (p) put_exc(a, tile, idx + (o ? 1 : 0), 2u * pos + 1u, __float_as_uint(s_tile[y][bxl * 16 + lx]), ovf);
             base += __popcll(mo & gmask) + __popcll(mp & gmask);
         }
     }
@@ -622,14 +660,15 @@ __global__ __launch_bounds__(256) void k_quant1d(QuantArgs a) {
     const uint32_t wave_patch = wave_sum_xor(__popc(flags_p));
     uint32_t tile_count, tile_out;
     const uint32_t base0 = wave_base_in_tile(wave_count, wave_out, s_misc, tile_count, tile_out);
+    const uint32_t ovf = reserve_overflow(a, tile, tile_count, s_misc);
     (void)wave_patch;
     if (my_count) {
         uint32_t idx = base0 + incl - my_count;
 #pragma unroll
         for (uint32_t i = 0; i < 16; i++) {
             const uint32_t pos = (uint32_t)(p0 + 16 * t + i);
-            if ((flags_o >> i) & 1u) put_exc(a, tile, idx++, 2u * pos, (uint32_t)delta[i]);
-            if ((flags_p >> i) & 1u) put_exc(a, tile, idx++, 2u * pos + 1u, __float_as_uint(s_tile[16 * t + i]));
+            if ((flags_o >> i) & 1u) put_exc(a, tile, idx++, 2u * pos, (uint32_t)delta[i], ovf);
+            if ((flags_p >> i) & 1u) put_exc(a, tile, idx++, 2u * pos + 1u, __float_as_uint(s_tile[16 * t + i]), ovf);
         }
     }
     n_zero = wave_sum_xor(n_zero);

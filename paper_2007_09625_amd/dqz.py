@@ -20,9 +20,12 @@ DQZ_EB_ABS, DQZ_EB_VALREL = 0, 1
 DQZ_HEADER_BYTES = 128
 DQZ_DBG_CODES, DQZ_DBG_HISTOGRAM, DQZ_DBG_CODEBOOK, DQZ_DBG_PHASES = 1, 2, 3, 4
 
-EXPORTED = ("dqz_ctx_create", "dqz_ctx_destroy", "dqz_compress_bound", "dqz_compress", "dqz_archive_info",
-            "dqz_decompress", "dqz_status_str", "dqz_ctx_last_error", "dqz_debug_copy", "dqz_ctx_set_timing",
-            "dqz_stage_times")
+DQZ_INJECT_ALLOC_FAIL = 1
+
+EXPORTED = ("dqz_ctx_create", "dqz_ctx_destroy", "dqz_ctx_reserve", "dqz_ctx_workspace", "dqz_compress_bound",
+            "dqz_decompress_bound", "dqz_compress", "dqz_compress_async", "dqz_archive_info", "dqz_decompress",
+            "dqz_decompress_async", "dqz_status_str", "dqz_ctx_last_error", "dqz_debug_copy", "dqz_debug_inject",
+            "dqz_ctx_set_timing", "dqz_stage_times")
 DQZ_MAX_STAGES = 8
 COMPRESS_STAGES = ("init", "range_eb", "quantize", "quantize_scan", "codebook", "encode")
 DECOMPRESS_STAGES = ("decode_tables", "inflate", "reconstruct")
@@ -50,6 +53,16 @@ class dqz_params(ctypes.Structure):
                 ("sub_size", ctypes.c_uint32), ("chunk_subs", ctypes.c_uint32)]
 
 
+class dqz_result(ctypes.Structure):
+    """What an _async call reports (written by its kernels)."""
+    _fields_ = [("flags", ctypes.c_uint32), ("status", ctypes.c_int32), ("archive_bytes", ctypes.c_uint64),
+                ("workspace_need", ctypes.c_uint64), ("reserved", ctypes.c_uint64),
+                ("header", ctypes.c_uint8 * DQZ_HEADER_BYTES)]
+
+
+DQZ_RESULT_BYTES = ctypes.sizeof(dqz_result)
+
+
 def _load() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libdqz.so is not built ({LIB_PATH}); run __graft_entry__.build()")
@@ -59,10 +72,22 @@ def _load() -> ctypes.CDLL:
     import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     P, u64, i32 = ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int32
-    lib.dqz_ctx_create.argtypes = [ctypes.c_int, ctypes.POINTER(P)]
+    lib.dqz_ctx_create.argtypes = [ctypes.c_int, u64, ctypes.POINTER(P)]
     lib.dqz_ctx_create.restype = i32
     lib.dqz_ctx_destroy.argtypes = [P]
     lib.dqz_ctx_destroy.restype = None
+    lib.dqz_ctx_reserve.argtypes = [P, u64]
+    lib.dqz_ctx_reserve.restype = i32
+    lib.dqz_ctx_workspace.argtypes = [P, ctypes.POINTER(u64), ctypes.POINTER(u64)]
+    lib.dqz_ctx_workspace.restype = i32
+    lib.dqz_decompress_bound.argtypes = [P, u64, ctypes.POINTER(u64)]
+    lib.dqz_decompress_bound.restype = i32
+    lib.dqz_compress_async.argtypes = [P, P, ctypes.POINTER(dqz_shape), ctypes.POINTER(dqz_params), P, u64, P, P]
+    lib.dqz_compress_async.restype = i32
+    lib.dqz_decompress_async.argtypes = [P, P, u64, P, P, u64, P, P]
+    lib.dqz_decompress_async.restype = i32
+    lib.dqz_debug_inject.argtypes = [P, ctypes.c_int, ctypes.c_int]
+    lib.dqz_debug_inject.restype = i32
     lib.dqz_compress_bound.argtypes = [ctypes.POINTER(dqz_shape), ctypes.POINTER(dqz_params),
                                        ctypes.POINTER(u64), ctypes.POINTER(u64)]
     lib.dqz_compress_bound.restype = i32
@@ -124,6 +149,15 @@ def dqz_compress_bound(shape, params: dqz_params):
     return int(amax.value), int(ws.value)
 
 
+def dqz_decompress_bound(header: bytes) -> int:
+    ws = ctypes.c_uint64(0)
+    buf = ctypes.create_string_buffer(bytes(header), len(header))
+    st = lib.dqz_decompress_bound(buf, len(header), ctypes.byref(ws))
+    if st != DQZ_OK:
+        raise DqzError(st, f"dqz_decompress_bound: {lib.dqz_status_str(st).decode()}")
+    return int(ws.value)
+
+
 def dqz_archive_info(header: bytes):
     s, p = dqz_shape(), dqz_params()
     n, ab = ctypes.c_uint64(0), ctypes.c_uint64(0)
@@ -147,17 +181,32 @@ class Compressed:
 
 
 class Context:
-    """Owns one dqz_ctx (device scratch kept across calls)."""
+    """Owns one dqz_ctx (its device workspace is kept across calls).
 
-    def __init__(self, device: int = 0):
+    The tensor-level helpers (compress / decompress) reserve the workspace a
+    call needs before making it; the raw forwarders do not."""
+
+    def __init__(self, device: int = 0, workspace: int = 0):
         import torch  # device memory and streams only
         self._torch = torch
         self.device = device
         h = ctypes.c_void_p()
-        st = lib.dqz_ctx_create(device, ctypes.byref(h))
+        st = lib.dqz_ctx_create(device, int(workspace), ctypes.byref(h))
         if st != DQZ_OK:
             raise DqzError(st, f"dqz_ctx_create: {lib.dqz_status_str(st).decode()}")
         self.handle = h
+
+    def dqz_ctx_reserve(self, nbytes: int):
+        self._check(lib.dqz_ctx_reserve(self.handle, int(nbytes)), "dqz_ctx_reserve")
+
+    def dqz_ctx_workspace(self):
+        """(workspace bytes held, workspace the most recent call needed)"""
+        cap, need = ctypes.c_uint64(0), ctypes.c_uint64(0)
+        self._check(lib.dqz_ctx_workspace(self.handle, ctypes.byref(cap), ctypes.byref(need)), "dqz_ctx_workspace")
+        return int(cap.value), int(need.value)
+
+    def dqz_debug_inject(self, what: int, count: int):
+        self._check(lib.dqz_debug_inject(self.handle, int(what), int(count)), "dqz_debug_inject")
 
     def close(self):
         if getattr(self, "handle", None):
@@ -199,6 +248,21 @@ class Context:
         return lib.dqz_decompress(self.handle, ctypes.c_void_p(archive_ptr), int(archive_bytes), hb,
                                   ctypes.c_void_p(field_ptr), int(field_cap_elems), self._stream(stream))
 
+    def dqz_compress_async(self, field_ptr: int, shape, params: dqz_params, archive_ptr: int, archive_cap: int,
+                           result_ptr: int, stream=None) -> int:
+        """Enqueue only; the device writes a dqz_result at result_ptr."""
+        s = make_shape(shape)
+        return lib.dqz_compress_async(self.handle, ctypes.c_void_p(field_ptr), ctypes.byref(s), ctypes.byref(params),
+                                      ctypes.c_void_p(archive_ptr), int(archive_cap), ctypes.c_void_p(result_ptr),
+                                      self._stream(stream))
+
+    def dqz_decompress_async(self, archive_ptr: int, archive_bytes: int, header: bytes, field_ptr: int,
+                             field_cap_elems: int, result_ptr: int, stream=None) -> int:
+        hb = ctypes.create_string_buffer(bytes(header), DQZ_HEADER_BYTES)
+        return lib.dqz_decompress_async(self.handle, ctypes.c_void_p(archive_ptr), int(archive_bytes), hb,
+                                        ctypes.c_void_p(field_ptr), int(field_cap_elems),
+                                        ctypes.c_void_p(result_ptr), self._stream(stream))
+
     def dqz_ctx_set_timing(self, level):
         """0 off, 1 (or True) stage events, 2 also the decoding kernel's per-wave phase sums,
         timing_stage(which, stage): the two events around one stage only."""
@@ -228,7 +292,8 @@ class Context:
             raise DqzError(DQZ_EINVAL, "field must be a contiguous float32 CUDA tensor")
         params = make_params(eb, _mode(mode), radius, sub_size, chunk_subs)
         shape = tuple(field.shape)
-        bound, _ = dqz_compress_bound(shape, params)
+        bound, ws = dqz_compress_bound(shape, params)
+        self.dqz_ctx_reserve(ws)
         if out is None or out.numel() < bound:
             out = torch.empty(bound, dtype=torch.uint8, device=field.device)
         st, nbytes, hdr = self.dqz_compress(field.data_ptr(), shape, params, out.data_ptr(), out.numel(), stream)
@@ -245,6 +310,7 @@ class Context:
         if hdr is None:
             hdr = bytes(arc[:DQZ_HEADER_BYTES].cpu().numpy().tobytes())
         shape, _, n, _ = dqz_archive_info(hdr)
+        self.dqz_ctx_reserve(dqz_decompress_bound(hdr))
         if out is None:
             out = torch.empty(shape, dtype=torch.float32, device=arc.device)
         st = self.dqz_decompress(arc.data_ptr(), arc.numel(), hdr, out.data_ptr(), out.numel(), stream)

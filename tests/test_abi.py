@@ -57,7 +57,7 @@ def test_ctx_create_without_gpu_fails_cleanly(dqz):
     if torch.cuda.is_available():
         pytest.skip("GPU present")
     h = ctypes.c_void_p()
-    assert dqz.lib.dqz_ctx_create(0, ctypes.byref(h)) == dqz.DQZ_EHIP
+    assert dqz.lib.dqz_ctx_create(0, 1 << 20, ctypes.byref(h)) == dqz.DQZ_EHIP
     assert not h.value
 
 
@@ -115,3 +115,42 @@ def test_package_has_no_cpu_fallback():
     src = open(m.__file__).read()
     assert "import oracle" not in src and "from oracle" not in src
     assert "numpy" not in src.split("def dqz_debug_copy")[0]
+
+
+def test_workspace_bounds(dqz, orc):
+    """The compress workspace bound covers the worst case (every element an
+    outlier and a patch); the decompress bound parses the header and grows
+    with the field; both reject bad input."""
+    small = dqz.dqz_compress_bound((1000,), dqz.make_params(1e-4))[1]
+    big = dqz.dqz_compress_bound((100, 500, 500), dqz.make_params(1e-4))[1]
+    assert big > 16 * 25_000_000 > small > 16 * 1000
+    x = np.random.default_rng(4).standard_normal((20, 30, 40)).astype(np.float32)
+    arc = orc.compress(x, 1e-4)
+    ws = dqz.dqz_decompress_bound(arc[:128].tobytes())
+    assert ws >= 2 * x.size
+    empty = orc.compress(np.zeros(0, np.float32), 1e-4)
+    assert dqz.dqz_decompress_bound(empty[:128].tobytes()) == 0
+    bad = arc[:128].copy()
+    bad[0] ^= 1
+    with pytest.raises(dqz.DqzError) as e:
+        dqz.dqz_decompress_bound(bad.tobytes())
+    assert e.value.status == dqz.DQZ_ECORRUPT
+
+
+def test_result_struct_layout(dqz):
+    """dqz_result as declared in include/dqz.h: status at byte 4, sizes at 8 and
+    16, the header at 32 (the library checks the same layout at compile time)."""
+    r = dqz.dqz_result
+    assert r.status.offset == 4 and r.archive_bytes.offset == 8 and r.workspace_need.offset == 16
+    assert r.header.offset == 32 and dqz.DQZ_RESULT_BYTES == 160
+
+
+def test_null_context_arguments(dqz):
+    """Entry points reject a NULL context without touching the GPU."""
+    assert dqz.lib.dqz_ctx_reserve(None, 100) == dqz.DQZ_EINVAL
+    assert dqz.lib.dqz_ctx_workspace(None, None, None) == dqz.DQZ_EINVAL
+    assert dqz.lib.dqz_debug_inject(None, dqz.DQZ_INJECT_ALLOC_FAIL, 1) == dqz.DQZ_EINVAL
+    s = dqz.make_shape((100,))
+    p = dqz.make_params(1e-4)
+    assert dqz.lib.dqz_compress_async(None, None, ctypes.byref(s), ctypes.byref(p), None, 0, None, None) == dqz.DQZ_EINVAL
+    assert dqz.lib.dqz_decompress_async(None, None, 0, None, None, 0, None, None) == dqz.DQZ_EINVAL

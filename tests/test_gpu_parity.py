@@ -29,10 +29,15 @@ def _gpu_round_trip(ctx, x, eb, mode, **kw):
     return comp.archive.cpu().numpy(), comp.header, y.cpu().numpy()
 
 
-def _explain_mismatch(ctx, x, eb, mode, gpu_arc, ref_arc):
+def _explain_mismatch(ctx, x, eb, mode, gpu_arc, ref_arc, **kw):
     """Locate the first differing stage for the failure message."""
+    import torch
     from paper_2007_09625_amd import dqz
     lines = []
+    # the stage dumps hold the most recent compression: compress again (the
+    # round trip's decompression has overwritten them)
+    ctx.compress(torch.from_numpy(np.ascontiguousarray(x)).to("cuda:0"), eb, mode, **kw)
+    torch.cuda.synchronize()
     if gpu_arc.size != ref_arc.size:
         lines.append(f"archive sizes differ: gpu {gpu_arc.size} oracle {ref_arc.size}")
     else:
@@ -74,7 +79,7 @@ def _check(ctx, x, eb=1e-4, mode=1, **kw):
                                                "sub_size": okw.get("sub_size", 128),
                                                "chunk_subs": okw.get("chunk_subs", 64)})
     if not np.array_equal(gpu_arc, ref_arc):
-        pytest.fail("archive differs from the oracle\n" + _explain_mismatch(ctx, x, eb, mode, gpu_arc, ref_arc))
+        pytest.fail("archive differs from the oracle\n" + _explain_mismatch(ctx, x, eb, mode, gpu_arc, ref_arc, **kw))
     assert hdr == ref_arc[:128].tobytes()
     ref_y = oracle.decompress(ref_arc)
     assert y.shape == x.shape
@@ -286,3 +291,39 @@ def test_stage_timing_modes(ctx):
     assert np.array_equal(a1, a2)
     with pytest.raises(Exception):
         ctx.dqz_ctx_set_timing(0x100 | (2 << 4))
+
+
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+def test_parity_wraparound(ctx, ndim):
+    """Absolute eb 0.5 (prequantization is the identity on integers) on values
+    of magnitude near 1e9 with alternating signs: the mixed Lorenzo differences
+    (up to 2^ndim * 1e9) wrap modulo 2^32, every delta is an outlier record
+    with a wrapped payload, and the inverse prefix sums wrap back (Sec. 3.1.2;
+    the forward and inverse maps are bijections modulo 2^32)."""
+    rng = np.random.default_rng(40 + ndim)
+    shape = {1: (5000,), 2: (37, 45), 3: (11, 13, 17)}[ndim]
+    idx = np.indices(shape).sum(axis=0)
+    sign = np.where(idx % 2 == 0, 1.0, -1.0)
+    mag = 1e9 - 64.0 * rng.integers(0, 100, shape)      # multiples of 64: exact in fp32
+    x = (sign * mag).astype(np.float32)
+    x.ravel()[::7] = rng.integers(-300, 300, x.size)[::7].astype(np.float32)   # some in-cap codes
+    arc = _check(ctx, x, 0.5, 0)
+    assert au.header(arc)["n_out"] > x.size // 2
+
+
+@pytest.fixture(scope="module")
+def c3_field():
+    from synth import fields
+    return fields.workload("c3")
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("eb", [1e-4, 1e-3])
+def test_parity_full_size_c3(ctx, c3_field, eb):
+    """The 1D 280,953,867-element particle workload at full size (HACC shape,
+    Sec. 4.1): whole archive bytes and decompressed float bits against the
+    oracle, |x - x'| <= eb_abs on every element."""
+    arc = _check(ctx, c3_field, eb, 1)
+    h = au.header(arc)
+    print(f"c3 eb={eb}: {c3_field.nbytes / arc.size:.2f}x, {8 * arc.size / c3_field.size:.3f} bits/elem, "
+          f"outliers {h['n_out']}, patches {h['n_patch']}, max_len {h['max_len']}", flush=True)
