@@ -204,7 +204,8 @@ dqz_status dqz_decompress_async(dqz_ctx *ctx, const void *d_archive, uint64_t ar
                                 dqz_result *d_result, void *stream);
 
 const char *dqz_status_str(dqz_status status);
-/* Text of the last error on this context ("" if none). */
+/* Text of the last error on this context ("" if none); with ctx == NULL, why
+ * the most recent dqz_ctx_create on the calling thread failed. */
 const char *dqz_ctx_last_error(const dqz_ctx *ctx);
 
 /* Per-stage timing (the paper's per-kernel breakdown, Sec. 4.2).  `level` 0

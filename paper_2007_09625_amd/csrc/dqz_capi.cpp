@@ -166,6 +166,13 @@ hipError_t wait_stream(hipStream_t s) {
     }
 }
 
+// why the most recent dqz_ctx_create on this thread failed
+thread_local std::string g_create_error;
+dqz_status create_fail(dqz_status st, const std::string &why) {
+    g_create_error = why;
+    return st;
+}
+
 // readback status before the codebook kernel has written the block
 constexpr uint32_t kNoReadback = 0xFFFFFFFFu;
 
@@ -490,44 +497,50 @@ const char *dqz_status_str(dqz_status s) {
     }
 }
 
-const char *dqz_ctx_last_error(const dqz_ctx *ctx) { return ctx ? ctx->last_error.c_str() : ""; }
+const char *dqz_ctx_last_error(const dqz_ctx *ctx) { return ctx ? ctx->last_error.c_str() : g_create_error.c_str(); }
 
 dqz_status dqz_ctx_create(int device, uint64_t workspace_cap, dqz_ctx **out) {
-    if (!out) return DQZ_EINVAL;
+    g_create_error.clear();
+    if (!out) return create_fail(DQZ_EINVAL, "null output pointer");
     *out = nullptr;
     int count = 0;
-    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) {
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count <= 0) {
         (void)hipGetLastError();
-        return DQZ_EHIP;
+        return create_fail(DQZ_EHIP, std::string("hipGetDeviceCount: ") + hipGetErrorString(e));
     }
-    if (device < 0 || device >= count) return DQZ_EINVAL;
+    if (device < 0 || device >= count) return create_fail(DQZ_EINVAL, "no such device");
     dqz_ctx *ctx = new (std::nothrow) dqz_ctx;
-    if (!ctx) return DQZ_ENOMEM;
+    if (!ctx) return create_fail(DQZ_ENOMEM, "host allocation failed");
     ctx->device = device;
-    if (hipSetDevice(device) != hipSuccess) { delete ctx; return DQZ_EHIP; }
+    if ((e = hipSetDevice(device)) != hipSuccess) {
+        delete ctx;
+        return create_fail(DQZ_EHIP, std::string("hipSetDevice: ") + hipGetErrorString(e));
+    }
     int ncu = 0;
     if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && ncu > 0)
         ctx->ncu = ncu;
-    if (decode_kernel_attributes() != hipSuccess) {
+    if ((e = decode_kernel_attributes()) != hipSuccess) {
         (void)hipGetLastError();
         delete ctx;
-        return DQZ_EHIP;
+        return create_fail(DQZ_EHIP, std::string("decoding kernels' LDS attributes: ") + hipGetErrorString(e));
     }
-    if (hipHostMalloc((void **)&ctx->h_rb, sizeof(Readback), hipHostMallocDefault) != hipSuccess) {
+    if ((e = hipHostMalloc((void **)&ctx->h_rb, sizeof(Readback), hipHostMallocDefault)) != hipSuccess) {
         (void)hipGetLastError();
         delete ctx;
-        return DQZ_ENOMEM;
+        return create_fail(DQZ_ENOMEM, std::string("hipHostMalloc: ") + hipGetErrorString(e));
     }
-    if (hipHostGetDevicePointer((void **)&ctx->d_rb, ctx->h_rb, 0) != hipSuccess) {
+    if ((e = hipHostGetDevicePointer((void **)&ctx->d_rb, ctx->h_rb, 0)) != hipSuccess) {
         (void)hipGetLastError();
         (void)hipHostFree(ctx->h_rb);
         delete ctx;
-        return DQZ_EHIP;
+        return create_fail(DQZ_EHIP, std::string("hipHostGetDevicePointer: ") + hipGetErrorString(e));
     }
     if (workspace_cap && alloc_workspace(ctx, workspace_cap) != DQZ_OK) {
+        const std::string why = ctx->last_error;
         (void)hipHostFree(ctx->h_rb);
         delete ctx;
-        return DQZ_ENOMEM;
+        return create_fail(DQZ_ENOMEM, why);
     }
     *out = ctx;
     return DQZ_OK;

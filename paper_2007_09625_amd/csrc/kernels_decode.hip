@@ -1075,11 +1075,20 @@ size_t decode_lds_bytes(const Layout &L) {
 // Dynamic LDS limits of the decoding kernels, set once per device before any
 // launch (not between launches, so that a stream capture holds launches only).
 hipError_t decode_kernel_attributes() {
-    hipError_t e = hipFuncSetAttribute((const void *)k_inflate128, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)(4ull * kInfMaxWaves * kInfWin));
+    // the dynamic allowance is what the CU's LDS leaves beside the kernel's
+    // static arrays (the LDS tables of k_inflate128, the shared block of k_decode)
+    hipFuncAttributes fa;
+    hipError_t e = hipFuncGetAttributes(&fa, (const void *)k_inflate128);
     if (e != hipSuccess) return e;
+    const size_t inf_dyn = 4ull * kInfMaxWaves * kInfWin;
+    if (fa.sharedSizeBytes + inf_dyn > kDecLdsLimit) return hipErrorInvalidConfiguration;
+    e = hipFuncSetAttribute((const void *)k_inflate128, hipFuncAttributeMaxDynamicSharedMemorySize, (int)inf_dyn);
+    if (e != hipSuccess) return e;
+    e = hipFuncGetAttributes(&fa, (const void *)k_decode);
+    if (e != hipSuccess) return e;
+    if (fa.sharedSizeBytes > sizeof(DecLds)) return hipErrorInvalidConfiguration;   // decode_lds_bytes assumes it
     return hipFuncSetAttribute((const void *)k_decode, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)kDecLdsLimit);
+                               (int)(kDecLdsLimit - fa.sharedSizeBytes));
 }
 
 void launch_decode(hipStream_t s, const Geom &g, const Layout &L, const uint8_t *archive, uint64_t off_str,

@@ -193,7 +193,8 @@ class Context:
         h = ctypes.c_void_p()
         st = lib.dqz_ctx_create(device, int(workspace), ctypes.byref(h))
         if st != DQZ_OK:
-            raise DqzError(st, f"dqz_ctx_create: {lib.dqz_status_str(st).decode()}")
+            why = lib.dqz_ctx_last_error(None).decode()
+            raise DqzError(st, f"dqz_ctx_create: {lib.dqz_status_str(st).decode()} ({why})")
         self.handle = h
 
     def dqz_ctx_reserve(self, nbytes: int):
