@@ -180,6 +180,26 @@ dqz_status dqz_compress_async(dqz_ctx *ctx, const float *d_field, const dqz_shap
                               const dqz_params *params, void *d_archive, uint64_t archive_cap,
                               dqz_result *d_result, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * dqz_compress_async without a context.  The workspace is a fixed 128 MiB
+ * device array inside the library (one copy per GPU, resident until the
+ * process ends; its address is looked up on the first call on each device),
+ * so nothing is allocated, freed or set on the host side.  Runs on the
+ * calling thread's current HIP device; status, archive size and header
+ * arrive in *d_result as for dqz_compress_async.  DQZ_EUNSUPPORTED, before
+ * anything is enqueued, when the field's workspace (dqz_compress_bound's
+ * workspace less the exception overflow pool: about 3 bytes per element)
+ * exceeds the array -- fields of up to about 40 million elements fit;
+ * exception records past the tiles' staging slots use the rest of the array,
+ * and when they do not fit the device reports DQZ_ENOMEM in d_result.  Every
+ * call on one GPU shares that GPU's array: calls that overlap on one GPU
+ * (on different streams or threads, or with dqz_compress_async_static work
+ * still running) race and must be serialized by the caller.  The kernels
+ * clear what must start at zero themselves. */
+dqz_status dqz_compress_async_static(const float *d_field, const dqz_shape *shape, const dqz_params *params,
+                                     void *d_archive, uint64_t archive_cap, dqz_result *d_result, void *stream);
+
 /* Host-only: parse and validate a 128-byte header.  Any output may be NULL.
  * field_elems = product of the dims. */
 dqz_status dqz_archive_info(const void *h_header, uint64_t header_bytes, dqz_shape *shape,

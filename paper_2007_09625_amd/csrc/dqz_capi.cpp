@@ -13,6 +13,7 @@
 // fit returns DQZ_ENOMEM and reports the size that would have sufficed.
 #include "../../include/dqz.h"
 #include "dqz_internal.h"
+#include "dqz_host.h"
 
 #include <hip/hip_runtime.h>
 
@@ -26,6 +27,7 @@
 #include <string>
 
 using namespace dqz;
+using namespace dqz::host;
 
 static_assert(sizeof(dqz_result) == sizeof(Readback), "dqz_result mirrors the kernels' readback block");
 static_assert(offsetof(dqz_result, status) == offsetof(Readback, code), "dqz_result layout");
@@ -33,38 +35,8 @@ static_assert(offsetof(dqz_result, archive_bytes) == offsetof(Readback, archive_
 static_assert(offsetof(dqz_result, workspace_need) == offsetof(Readback, workspace_need), "dqz_result layout");
 static_assert(offsetof(dqz_result, header) == offsetof(Readback, header), "dqz_result layout");
 
-struct dqz_ctx {
-    int device = 0;
-    int ncu = 256;
-    void *ws = nullptr;        // device workspace
-    uint64_t ws_bytes = 0;
-    uint64_t last_need = 0;    // workspace the most recent call needed
-    Readback *h_rb = nullptr;  // readback block in pinned host memory, written by the kernels
-    Readback *d_rb = nullptr;  // the same block's device address
-    int inject_alloc_fail = 0; // test hook: workspace allocations that fail on purpose
-    std::string last_error;
-    // most recent compression, for the stage dumps (cleared by a decompression,
-    // whose scratch overlaps these buffers, and by a workspace reallocation)
-    bool last_valid = false;
-    uint16_t *last_codes = nullptr;
-    uint32_t *last_hist = nullptr;
-    uint64_t *last_book = nullptr;
-    uint64_t last_padded = 0;
-    uint32_t last_nsym = 0;
-    Ctl *last_ctl = nullptr;
-    DecodeTables *last_tab = nullptr;
-    // per-stage timing (events between kernels) and, at level 2, the decoding
-    // kernel's per-wave phase sums
-    bool timing = false;
-    bool trace = false;
-    hipEvent_t ev[2][DQZ_MAX_STAGES + 1] = {};
-    int n_ev[2] = {0, 0};
-    bool ev_rec[2][DQZ_MAX_STAGES + 1] = {};
-    int only_stage[2] = {-1, -1};   // >= 0: events only around this stage (-2: none)
-    bool ev_ready[2] = {false, false};
-};
-
-namespace {
+namespace dqz {
+namespace host {
 
 constexpr uint32_t kDefaultRadius = 512;
 constexpr uint32_t kDefaultSub = 128;
@@ -87,17 +59,7 @@ dqz_status hip_fail(dqz_ctx *ctx, hipError_t e, const char *what) {
     return fail(ctx, DQZ_EHIP, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-#define HIP_TRY(ctx, expr)                                   \
-    do {                                                     \
-        hipError_t e_ = (expr);                              \
-        if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
-    } while (0)
 
-struct Plan {
-    Geom g;
-    Layout L;
-    uint32_t tiles_q = 0, tiles_e = 0;
-};
 
 dqz_status make_geom(const dqz_shape *s, Geom &g, std::string &why) {
     if (!s) { why = "shape is NULL"; return DQZ_EINVAL; }
@@ -183,14 +145,6 @@ constexpr uint32_t kNoReadback = 0xFFFFFFFFu;
 // `fixed`) the exception overflow pool, which takes the rest of the
 // workspace.  Decompression: control block, tables, the decoded code array
 // and the per-unit exception index (over the compression buffers).
-struct WsLayout {
-    uint64_t ctl, tab, hist, zero_end;
-    uint64_t hist_sum, book, book32, parts;
-    uint64_t qval[2], qexcl[2], qseg_total[2];
-    uint64_t ovf_base, eflag;
-    uint64_t stage, codes, fixed, qws, unit_exc, total;
-    uint32_t n_segs_q;
-};
 
 WsLayout ws_layout(const Plan &P, bool compress) {
     WsLayout w;
@@ -235,7 +189,7 @@ WsLayout ws_layout(const Plan &P, bool compress) {
 
 // stage marks: mark(ctx, which, i) records event i of call kind `which`
 void mark(dqz_ctx *ctx, int which, int i, hipStream_t s) {
-    if (!ctx->timing) return;
+    if (!ctx || !ctx->timing) return;
     if (i == 0)
         for (int k = 0; k <= DQZ_MAX_STAGES; k++) ctx->ev_rec[which][k] = false;
     const int only = ctx->only_stage[which];
@@ -271,13 +225,6 @@ uint64_t rd_u64(const uint8_t *p, int off) {
 
 // Parse and validate a header; fills the plan (with the archive-dependent
 // counts) when `P` is non-NULL.
-struct HeaderInfo {
-    dqz_shape shape;
-    dqz_params params;
-    uint64_t nelem, n_exc, total_bits, archive_bytes, off_str, n_words;
-    uint32_t max_len;
-    float h;
-};
 
 dqz_status parse_header(const uint8_t *hb, uint64_t n, HeaderInfo &hi, Plan *P, std::string &why) {
     if (!hb || n < kHeaderBytes) { why = "header too short"; return DQZ_ECORRUPT; }
@@ -344,31 +291,41 @@ dqz_status alloc_workspace(dqz_ctx *ctx, uint64_t bytes) {
     return DQZ_OK;
 }
 
-// Validate the arguments of a compression and plan it (host only).
-dqz_status plan_compress(dqz_ctx *ctx, const float *d_field, const dqz_shape *shape, const dqz_params *params,
-                         const void *d_archive, uint64_t archive_cap, Plan &P, WsLayout &W) {
-    if (!params || !d_archive) return fail(ctx, DQZ_EINVAL, "null argument");
-    if (!(params->eb > 0.0) || !std::isfinite(params->eb)) return fail(ctx, DQZ_EINVAL, "eb must be finite and > 0");
-    if (params->eb_mode != DQZ_EB_ABS && params->eb_mode != DQZ_EB_VALREL) return fail(ctx, DQZ_EINVAL, "bad eb_mode");
-    std::string why;
+// Validate the arguments of a compression and plan it (host only); the
+// workspace size check is the caller's.
+dqz_status plan_compress_args(const float *d_field, const dqz_shape *shape, const dqz_params *params,
+                              const void *d_archive, uint64_t archive_cap, Plan &P, WsLayout &W, std::string &why) {
+    if (!params || !d_archive) { why = "null argument"; return DQZ_EINVAL; }
+    if (!(params->eb > 0.0) || !std::isfinite(params->eb)) { why = "eb must be finite and > 0"; return DQZ_EINVAL; }
+    if (params->eb_mode != DQZ_EB_ABS && params->eb_mode != DQZ_EB_VALREL) { why = "bad eb_mode"; return DQZ_EINVAL; }
     dqz_status st = make_geom(shape, P.g, why);
-    if (st != DQZ_OK) return fail(ctx, st, why);
-    if (P.g.nelem && !d_field) return fail(ctx, DQZ_EINVAL, "null field");
+    if (st != DQZ_OK) return st;
+    if (P.g.nelem && !d_field) { why = "null field"; return DQZ_EINVAL; }
     uint32_t radius, sub, csubs;
     fill_params(params, radius, sub, csubs);
-    if ((st = make_layout(P.g, radius, sub, csubs, P.L, why)) != DQZ_OK) return fail(ctx, st, why);
+    if ((st = make_layout(P.g, radius, sub, csubs, P.L, why)) != DQZ_OK) return st;
     if (params->eb_mode == DQZ_EB_ABS) {
         const double e = params->eb;
         const float h = (float)(2.0 * e), r = (float)(1.0 / (2.0 * e));
-        if (e < (double)FLT_MIN || !std::isfinite(h) || !(r >= FLT_MIN) || !std::isfinite(r))
-            return fail(ctx, DQZ_EINVAL, "eb out of the fp32 range");
+        if (e < (double)FLT_MIN || !std::isfinite(h) || !(r >= FLT_MIN) || !std::isfinite(r)) {
+            why = "eb out of the fp32 range";
+            return DQZ_EINVAL;
+        }
     }
     P.L.cap = archive_cap;
-    if (archive_cap < P.L.off_exc) return fail(ctx, DQZ_ETOOSMALL, "archive capacity below the fixed sections");
+    if (archive_cap < P.L.off_exc) { why = "archive capacity below the fixed sections"; return DQZ_ETOOSMALL; }
     P.tiles_q = quantize_tiles(P.g);
     P.tiles_e = encode_tiles(P.g);
     W = ws_layout(P, true);
     P.L.ws_fixed = W.fixed;
+    return DQZ_OK;
+}
+
+dqz_status plan_compress(dqz_ctx *ctx, const float *d_field, const dqz_shape *shape, const dqz_params *params,
+                         const void *d_archive, uint64_t archive_cap, Plan &P, WsLayout &W) {
+    std::string why;
+    const dqz_status st = plan_compress_args(d_field, shape, params, d_archive, archive_cap, P, W, why);
+    if (st != DQZ_OK) return fail(ctx, st, why);
     ctx->last_need = W.fixed;
     if (ctx->ws_bytes < W.fixed)
         return fail(ctx, DQZ_ENOMEM, "workspace too small: this field needs at least " + std::to_string(W.fixed) +
@@ -377,9 +334,12 @@ dqz_status plan_compress(dqz_ctx *ctx, const float *d_field, const dqz_shape *sh
 }
 
 // Enqueue the compression kernels; they write status, size and header to rb.
-void enqueue_compress(dqz_ctx *ctx, const float *d_field, const dqz_params *params, uint8_t *arc, const Plan &P,
-                      const WsLayout &W, Readback *rb, hipStream_t s) {
-    uint8_t *ws = reinterpret_cast<uint8_t *>(ctx->ws);
+// The workspace is [ws, ws + ws_bytes) on the stream's device (ws_bytes >=
+// W.fixed); `ctx` (may be NULL) takes the timing marks and the stage-dump
+// pointers.
+void enqueue_compress(dqz_ctx *ctx, uint8_t *ws, uint64_t ws_bytes, int ncu, const float *d_field,
+                      const dqz_params *params, uint8_t *arc, const Plan &P, const WsLayout &W, Readback *rb,
+                      hipStream_t s) {
     Ctl *ctl = reinterpret_cast<Ctl *>(ws + W.ctl);
     uint32_t *hist = reinterpret_cast<uint32_t *>(ws + W.hist);
     uint64_t *book = reinterpret_cast<uint64_t *>(ws + W.book);
@@ -393,7 +353,7 @@ void enqueue_compress(dqz_ctx *ctx, const float *d_field, const dqz_params *para
     qb.stage = reinterpret_cast<uint2 *>(ws + W.stage);
     qb.cap = kExcCap;
     qb.pool = reinterpret_cast<uint2 *>(ws + W.fixed);
-    qb.pool_cap = (ctx->ws_bytes - W.fixed) / 8;
+    qb.pool_cap = (ws_bytes - W.fixed) / 8;
     qb.ovf_base = reinterpret_cast<uint32_t *>(ws + W.ovf_base);
     TileScan &qs = qb.scan;
     for (int k = 0; k < 2; k++) {
@@ -416,13 +376,13 @@ void enqueue_compress(dqz_ctx *ctx, const float *d_field, const dqz_params *para
     eb.n_tiles_q = P.tiles_q;
     eb.eflag = reinterpret_cast<uint64_t *>(ws + W.eflag);
 
-    ctx->ev_ready[0] = false;
+    if (ctx) ctx->ev_ready[0] = false;
     mark(ctx, 0, 0, s);
     // value-range-relative mode: the range kernel also clears the scratch
     if (params->eb_mode != DQZ_EB_VALREL) launch_init(s, ctl, ws + W.hist, W.zero_end - W.hist, params->eb_mode, params->eb);
     mark(ctx, 0, 1, s);
     if (params->eb_mode == DQZ_EB_VALREL)
-        launch_minmax(s, d_field, P.g.nelem, ctl, parts, params->eb, ctx->ncu, ws + W.hist, W.zero_end - W.hist);
+        launch_minmax(s, d_field, P.g.nelem, ctl, parts, params->eb, ncu, ws + W.hist, W.zero_end - W.hist);
     mark(ctx, 0, 2, s);
     launch_quantize(s, d_field, P.g, P.L, ctl, qb);
     mark(ctx, 0, 3, s);
@@ -430,8 +390,9 @@ void enqueue_compress(dqz_ctx *ctx, const float *d_field, const dqz_params *para
     mark(ctx, 0, 4, s);
     launch_codebook(s, P.g, P.L, ctl, qb.hist_sum, book, book32, arc, params->eb_mode, params->eb, qs, rb);
     mark(ctx, 0, 5, s);
-    launch_encode(s, P.g, P.L, ctl, rb, eb, arc, ctx->ncu);
+    launch_encode(s, P.g, P.L, ctl, rb, eb, arc, ncu);
     mark(ctx, 0, 6, s);
+    if (!ctx) return;
     ctx->last_valid = true;
     ctx->last_codes = codes;
     ctx->last_hist = hist;
@@ -442,17 +403,25 @@ void enqueue_compress(dqz_ctx *ctx, const float *d_field, const dqz_params *para
     ctx->last_nsym = P.L.nsym;
 }
 
-// Validate a decompression and plan it (host only).
+// Validate a decompression and plan it (host only); the workspace size check
+// is the caller's.
+dqz_status plan_decompress_args(const uint8_t *hb, uint64_t archive_bytes, float *d_field, uint64_t field_cap_elems,
+                                HeaderInfo &hi, Plan &P, WsLayout &W, std::string &why) {
+    dqz_status st = parse_header(hb, kHeaderBytes, hi, &P, why);
+    if (st != DQZ_OK) return st;
+    if (hi.archive_bytes != archive_bytes) { why = "archive length differs from its header"; return DQZ_ECORRUPT; }
+    if (field_cap_elems < hi.nelem) { why = "field capacity too small"; return DQZ_ETOOSMALL; }
+    if (hi.nelem && !d_field) { why = "null field"; return DQZ_EINVAL; }
+    W = ws_layout(P, false);
+    return DQZ_OK;
+}
+
 dqz_status plan_decompress(dqz_ctx *ctx, const void *d_archive, uint64_t archive_bytes, const uint8_t *hb,
                            float *d_field, uint64_t field_cap_elems, HeaderInfo &hi, Plan &P, WsLayout &W) {
     std::string why;
-    dqz_status st = parse_header(hb, kHeaderBytes, hi, &P, why);
-    if (st != DQZ_OK) return fail(ctx, st, why);
-    if (hi.archive_bytes != archive_bytes) return fail(ctx, DQZ_ECORRUPT, "archive length differs from its header");
-    if (field_cap_elems < hi.nelem) return fail(ctx, DQZ_ETOOSMALL, "field capacity too small");
-    if (hi.nelem && !d_field) return fail(ctx, DQZ_EINVAL, "null field");
     (void)d_archive;
-    W = ws_layout(P, false);
+    const dqz_status st = plan_decompress_args(hb, archive_bytes, d_field, field_cap_elems, hi, P, W, why);
+    if (st != DQZ_OK) return fail(ctx, st, why);
     ctx->last_need = hi.nelem ? W.total : 0;
     if (hi.nelem && ctx->ws_bytes < W.total)
         return fail(ctx, DQZ_ENOMEM, "workspace too small: this archive needs " + std::to_string(W.total) +
@@ -460,26 +429,47 @@ dqz_status plan_decompress(dqz_ctx *ctx, const void *d_archive, uint64_t archive
     return DQZ_OK;
 }
 
-void enqueue_decompress(dqz_ctx *ctx, const uint8_t *arc, float *d_field, const HeaderInfo &hi, const Plan &P,
-                        const WsLayout &W, Readback *rb, hipStream_t s) {
-    uint8_t *ws = reinterpret_cast<uint8_t *>(ctx->ws);
+void enqueue_decompress(dqz_ctx *ctx, uint8_t *ws, int ncu, const uint8_t *arc, float *d_field, const HeaderInfo &hi,
+                        const Plan &P, const WsLayout &W, Readback *rb, hipStream_t s) {
     DecodeTables *tab = reinterpret_cast<DecodeTables *>(ws + W.tab);
-    ctx->last_valid = false;   // the decompression scratch overlaps the compression's
-    ctx->ev_ready[1] = false;
+    const bool trace = ctx && ctx->trace;
+    if (ctx) {
+        ctx->last_valid = false;   // the decompression scratch overlaps the compression's
+        ctx->ev_ready[1] = false;
+    }
     mark(ctx, 1, 0, s);
     const bool two_pass = P.L.sub_size == 128;
     uint4 *qws = two_pass ? reinterpret_cast<uint4 *>(ws + W.qws) : nullptr;
     uint32_t *unit_exc = two_pass ? reinterpret_cast<uint32_t *>(ws + W.unit_exc) : nullptr;
     launch_decode_tables(s, P.L, arc, hi.max_len, tab, rb, (uint32_t)hi.n_exc, unit_exc, recon_units(P.g));
     mark(ctx, 1, 1, s);
-    launch_decode(s, P.g, P.L, arc, hi.off_str, hi.n_words, (uint32_t)hi.n_exc, hi.h, tab, d_field, ctx->trace, qws,
-                  rb, ctx->ncu);
+    launch_decode(s, P.g, P.L, arc, hi.off_str, hi.n_words, (uint32_t)hi.n_exc, hi.h, tab, d_field, trace, qws, rb,
+                  ncu);
     mark(ctx, 1, 2, s);
     if (two_pass) launch_recon(s, P.g, P.L, arc, (uint32_t)hi.n_exc, hi.h, tab, qws, unit_exc, d_field, rb);
     mark(ctx, 1, 3, s);
 }
 
-}  // namespace
+}  // namespace host
+
+dqz_status compress_on_workspace(uint8_t *ws, uint64_t ws_bytes, int ncu, const float *d_field,
+                                 const dqz_shape *shape, const dqz_params *params, void *d_archive,
+                                 uint64_t archive_cap, Readback *d_result, hipStream_t stream, uint64_t *need) {
+    Plan P;
+    WsLayout W;
+    std::string why;
+    *need = 0;
+    const dqz_status st = plan_compress_args(d_field, shape, params, d_archive, archive_cap, P, W, why);
+    if (st != DQZ_OK) return st;
+    *need = W.fixed;
+    if (ws_bytes < W.fixed) return DQZ_EUNSUPPORTED;
+    enqueue_compress(nullptr, ws, ws_bytes, ncu, d_field, params, reinterpret_cast<uint8_t *>(d_archive), P, W,
+                     d_result, stream);
+    const hipError_t e = hipGetLastError();
+    return e == hipSuccess ? DQZ_OK : DQZ_EHIP;
+}
+
+}  // namespace dqz
 
 extern "C" {
 
@@ -615,7 +605,8 @@ dqz_status dqz_compress(dqz_ctx *ctx, const float *d_field, const dqz_shape *sha
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     ctx->h_rb->bits = kNoReadback;   // the codebook kernel overwrites it
     ctx->h_rb->code = 0;
-    enqueue_compress(ctx, d_field, params, reinterpret_cast<uint8_t *>(d_archive), P, W, ctx->d_rb, s);
+    enqueue_compress(ctx, reinterpret_cast<uint8_t *>(ctx->ws), ctx->ws_bytes, ctx->ncu, d_field, params,
+                     reinterpret_cast<uint8_t *>(d_archive), P, W, ctx->d_rb, s);
     HIP_TRY(ctx, hipGetLastError());
     HIP_TRY(ctx, wait_stream(s));
     ctx->ev_ready[0] = ctx->timing;
@@ -645,8 +636,8 @@ dqz_status dqz_compress_async(dqz_ctx *ctx, const float *d_field, const dqz_shap
     if (st != DQZ_OK) return st;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-    enqueue_compress(ctx, d_field, params, reinterpret_cast<uint8_t *>(d_archive), P, W,
-                     reinterpret_cast<Readback *>(d_result), s);
+    enqueue_compress(ctx, reinterpret_cast<uint8_t *>(ctx->ws), ctx->ws_bytes, ctx->ncu, d_field, params,
+                     reinterpret_cast<uint8_t *>(d_archive), P, W, reinterpret_cast<Readback *>(d_result), s);
     HIP_TRY(ctx, hipGetLastError());
     ctx->ev_ready[0] = false;
     return DQZ_OK;
@@ -689,7 +680,8 @@ dqz_status dqz_decompress(dqz_ctx *ctx, const void *d_archive, uint64_t archive_
     if (hi.nelem == 0) return DQZ_OK;
     ctx->h_rb->bits = 0;   // the decoding kernels set it on damage
     ctx->h_rb->code = 0;
-    enqueue_decompress(ctx, reinterpret_cast<const uint8_t *>(d_archive), d_field, hi, P, W, ctx->d_rb, s);
+    enqueue_decompress(ctx, reinterpret_cast<uint8_t *>(ctx->ws), ctx->ncu, reinterpret_cast<const uint8_t *>(d_archive),
+                       d_field, hi, P, W, ctx->d_rb, s);
     HIP_TRY(ctx, hipGetLastError());
     HIP_TRY(ctx, wait_stream(s));
     ctx->ev_ready[1] = ctx->timing;
@@ -714,7 +706,9 @@ dqz_status dqz_decompress_async(dqz_ctx *ctx, const void *d_archive, uint64_t ar
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     Readback *rb = reinterpret_cast<Readback *>(d_result);
     launch_publish(s, rb, 0u, hi.archive_bytes);   // the decoding kernels overwrite it on damage
-    if (hi.nelem) enqueue_decompress(ctx, reinterpret_cast<const uint8_t *>(d_archive), d_field, hi, P, W, rb, s);
+    if (hi.nelem)
+        enqueue_decompress(ctx, reinterpret_cast<uint8_t *>(ctx->ws), ctx->ncu, reinterpret_cast<const uint8_t *>(d_archive),
+                           d_field, hi, P, W, rb, s);
     HIP_TRY(ctx, hipGetLastError());
     ctx->ev_ready[1] = false;
     return DQZ_OK;

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/dqz.h"
+
 namespace dqz {
 
 constexpr uint32_t kHeaderBytes = 128;
@@ -363,6 +365,13 @@ void launch_decode(hipStream_t s, const Geom &g, const Layout &L, const uint8_t 
                    uint4 *qws, Readback *rb, int ncu);
 void launch_recon(hipStream_t s, const Geom &g, const Layout &L, const uint8_t *archive, uint32_t n_exc, float h,
                   const DecodeTables *tab, const uint4 *qws, const uint32_t *unit_exc, float *out, Readback *rb);
+// Compression on a caller-given workspace [ws, ws + ws_bytes) of the current
+// device, status and size into d_result (dqz_compress_async without a
+// context).  *need: the workspace the field needs (0 if the arguments are
+// invalid); DQZ_EUNSUPPORTED when ws_bytes is below it.
+dqz_status compress_on_workspace(uint8_t *ws, uint64_t ws_bytes, int ncu, const float *d_field,
+                                 const dqz_shape *shape, const dqz_params *params, void *d_archive,
+                                 uint64_t archive_cap, Readback *d_result, hipStream_t stream, uint64_t *need);
 // reconstruction units of 512 padded positions
 inline uint32_t recon_units(const Geom &g) { return (g.padded + (1u << kUnitShift) - 1) >> kUnitShift; }
 

@@ -23,7 +23,8 @@ DQZ_DBG_CODES, DQZ_DBG_HISTOGRAM, DQZ_DBG_CODEBOOK, DQZ_DBG_PHASES = 1, 2, 3, 4
 DQZ_INJECT_ALLOC_FAIL = 1
 
 EXPORTED = ("dqz_ctx_create", "dqz_ctx_destroy", "dqz_ctx_reserve", "dqz_ctx_workspace", "dqz_compress_bound",
-            "dqz_decompress_bound", "dqz_compress", "dqz_compress_async", "dqz_archive_info", "dqz_decompress",
+            "dqz_decompress_bound", "dqz_compress", "dqz_compress_async", "dqz_compress_async_static",
+            "dqz_archive_info", "dqz_decompress",
             "dqz_decompress_async", "dqz_status_str", "dqz_ctx_last_error", "dqz_debug_copy", "dqz_debug_inject",
             "dqz_ctx_set_timing", "dqz_stage_times")
 DQZ_MAX_STAGES = 8
@@ -84,6 +85,8 @@ def _load() -> ctypes.CDLL:
     lib.dqz_decompress_bound.restype = i32
     lib.dqz_compress_async.argtypes = [P, P, ctypes.POINTER(dqz_shape), ctypes.POINTER(dqz_params), P, u64, P, P]
     lib.dqz_compress_async.restype = i32
+    lib.dqz_compress_async_static.argtypes = [P, ctypes.POINTER(dqz_shape), ctypes.POINTER(dqz_params), P, u64, P, P]
+    lib.dqz_compress_async_static.restype = i32
     lib.dqz_decompress_async.argtypes = [P, P, u64, P, P, u64, P, P]
     lib.dqz_decompress_async.restype = i32
     lib.dqz_debug_inject.argtypes = [P, ctypes.c_int, ctypes.c_int]
@@ -147,6 +150,20 @@ def dqz_compress_bound(shape, params: dqz_params):
     if st != DQZ_OK:
         raise DqzError(st, f"dqz_compress_bound: {lib.dqz_status_str(st).decode()}")
     return int(amax.value), int(ws.value)
+
+
+def dqz_compress_async_static(field_ptr: int, shape, params: dqz_params, archive_ptr: int, archive_cap: int,
+                              result_ptr: int, stream=None) -> int:
+    """dqz_compress_async on the library's fixed per-GPU workspace (no context,
+    no allocation); the device writes a dqz_result at result_ptr.  `stream`: a
+    torch stream of the current device (None: its current stream)."""
+    import torch  # streams only
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    s = make_shape(shape)
+    return lib.dqz_compress_async_static(ctypes.c_void_p(field_ptr), ctypes.byref(s), ctypes.byref(params),
+                                         ctypes.c_void_p(archive_ptr), int(archive_cap), ctypes.c_void_p(result_ptr),
+                                         ctypes.c_void_p(stream.cuda_stream))
 
 
 def dqz_decompress_bound(header: bytes) -> int:
