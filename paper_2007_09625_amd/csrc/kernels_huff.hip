@@ -406,6 +406,21 @@ __global__ __launch_bounds__(kBookThreads) void k_codebook(const uint32_t *__res
         uint32_t la = 0, ib = 0, ic = 0, rounds = 0;
         for (;;) {
             if ((n - la) + (ic - ib) <= 1) break;
+            if (la == n) {
+                // Leaves used up: the internal queue is nondecreasing and every
+                // node made from now on weighs at least its last item, so the
+                // sequential algorithm pairs the queue front to back (oldest
+                // first on ties) with no weight comparison left: item x of
+                // [ib, ic + k - 2) gets parent ic + (x - ib) / 2 for the k =
+                // ic - ib items left, the last node made being the root.
+                const uint32_t k = ic - ib;
+                for (uint32_t x = ib + tid; x < ic + k - 2; x += T) s.parent_int[x] = (uint16_t)(ic + (x - ib) / 2);
+                ib = ic + k - 2;
+                ic += k - 1;
+                rounds += 32u - __clz(k - 1u);   // ceil(log2 k) levels: the bound on the depth
+                __syncthreads();
+                break;
+            }
             // T, from the first two items of each queue (lanes 0..3 read
             // them together)
             const uint32_t hv = lane < 2u ? ldc(s.leaf_w, la + lane) : ldc(s.int_w, ib + (lane & 1u));
