@@ -223,6 +223,63 @@ dqz_status dqz_decompress_async(dqz_ctx *ctx, const void *d_archive, uint64_t ar
                                 const void *h_header, float *d_field, uint64_t field_cap_elems,
                                 dqz_result *d_result, void *stream);
 
+/* Batched calls: many fields in one call (the paper compresses one field per
+ * launch sequence, Sec. 3; batching spreads a batch over concurrent lanes).
+ * dqz_ctx_set_lanes gives the context `lanes` concurrent lanes (HIP streams of
+ * default priority, 1..DQZ_MAX_LANES; 1 runs a batch on the caller's stream)
+ * and with DQZ_LANES_GRAPH captures each batch into a HIP graph, replayed with
+ * one launch while the same call (same pointers, shapes, parameters) repeats.
+ * It synchronizes the device and may create streams, events and graphs:
+ * call it at set-up, not while a batch of this context is in flight. */
+#define DQZ_MAX_LANES 8
+#define DQZ_LANES_GRAPH 1u
+dqz_status dqz_ctx_set_lanes(dqz_ctx *ctx, uint32_t lanes, uint32_t flags);
+
+/* Host-only: the workspace a batch of these fields needs on a context with
+ * `lanes` lanes (each lane holds the largest fixed layout among the fields
+ * assigned to it; what the context holds beyond the sum is split among the
+ * lanes as their exception overflow pools). */
+dqz_status dqz_batch_workspace(uint32_t n, const dqz_shape *shapes, const dqz_params *params, uint32_t lanes,
+                               uint64_t *workspace_bytes);
+
+/* Compress n fields: field i (d_fields[i], shapes[i], params[i]) into
+ * d_archives[i] (capacity archive_caps[i]); status, size and header of field
+ * i arrive in d_results[i] (device-visible memory, n entries, 8-byte
+ * aligned) as for dqz_compress_async.  Enqueues on `stream` and returns (the
+ * lanes fork from and join back into it).  Fields are assigned to lanes
+ * longest first, each to the least loaded lane; every archive is byte for
+ * byte the one dqz_compress writes for that field alone.  DQZ_ENOMEM when
+ * the workspace is below dqz_batch_workspace (dqz_ctx_workspace reports the
+ * need).  Host-side argument errors name the field in dqz_ctx_last_error. */
+dqz_status dqz_compress_batch(dqz_ctx *ctx, uint32_t n, const float *const *d_fields, const dqz_shape *shapes,
+                              const dqz_params *params, void *const *d_archives, const uint64_t *archive_caps,
+                              dqz_result *d_results, void *stream);
+
+/* Decompress n archives (Sec. 3.3 for each): archive i (d_archives[i],
+ * archive_bytes[i], its 128-byte header at h_headers + 128 i on the host)
+ * into d_fields[i] (capacity field_caps[i] floats); per-archive status in
+ * d_results[i].  Lanes and graphs as for dqz_compress_batch; each lane needs
+ * the largest dqz_decompress_bound among its archives. */
+dqz_status dqz_decompress_batch(dqz_ctx *ctx, uint32_t n, const void *const *d_archives,
+                                const uint64_t *archive_bytes, const void *h_headers, float *const *d_fields,
+                                const uint64_t *field_caps, dqz_result *d_results, void *stream);
+
+/* Autotuner for the deflate/inflate chunking (the paper sweeps the chunk
+ * size per dataset, Sec. 4.2 / its chunk-size table): for the shape class of
+ * this field (ndim, size octave, eb mode and decade, radius) pick sub_size in
+ * {128, 256, 512} and chunk_subs in {16, 64, 256} by compressing and
+ * decompressing the field with each (decompression timed with HIP events):
+ * the smallest archive among the candidates that decompress within
+ * (1 + tolerance) of the fastest.  The bit stream does not depend on the
+ * choice.  The choice is cached on the context; a later call for the same
+ * class returns it without measuring unless flags has DQZ_TUNE_FORCE.
+ * *out = base with sub_size and chunk_subs set.  Synchronizes `stream`; the
+ * workspace must hold the field's compression layout plus an archive bound,
+ * the field and 64 MiB (DQZ_ENOMEM otherwise). */
+#define DQZ_TUNE_FORCE 1u
+dqz_status dqz_tune(dqz_ctx *ctx, const float *d_field, const dqz_shape *shape, const dqz_params *base,
+                    double tolerance, uint32_t flags, dqz_params *out, void *stream);
+
 const char *dqz_status_str(dqz_status status);
 /* Text of the last error on this context ("" if none); with ctx == NULL, why
  * the most recent dqz_ctx_create on the calling thread failed. */

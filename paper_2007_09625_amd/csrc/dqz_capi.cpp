@@ -539,6 +539,17 @@ dqz_status dqz_ctx_create(int device, uint64_t workspace_cap, dqz_ctx **out) {
 void dqz_ctx_destroy(dqz_ctx *ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
+    if (!ctx->lanes.empty() || ctx->capture) (void)hipDeviceSynchronize();
+    for (int k = 0; k < 2; k++) {
+        if (ctx->graphs[k].exec) (void)hipGraphExecDestroy(ctx->graphs[k].exec);
+        if (ctx->graphs[k].graph) (void)hipGraphDestroy(ctx->graphs[k].graph);
+    }
+    for (auto &ln : ctx->lanes) {
+        (void)hipEventDestroy(ln.done);
+        (void)hipStreamDestroy(ln.stream);
+    }
+    if (ctx->fork) (void)hipEventDestroy(ctx->fork);
+    if (ctx->capture) (void)hipStreamDestroy(ctx->capture);
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->h_rb) (void)hipHostFree(ctx->h_rb);
     for (int k = 0; k < 2; k++)

@@ -9,6 +9,8 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <utility>
+#include <vector>
 
 namespace dqz {
 namespace host {
@@ -44,6 +46,20 @@ struct HeaderInfo {
     float h;
 };
 
+// One concurrent lane of a context: its own HIP stream (default priority)
+// and the event that joins it back to the caller's stream.
+struct Lane {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+};
+
+// A captured batch, replayed while the same call repeats.
+struct BatchGraph {
+    std::vector<uint64_t> key;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
 }  // namespace host
 }  // namespace dqz
 
@@ -76,6 +92,15 @@ struct dqz_ctx {
     bool ev_rec[2][DQZ_MAX_STAGES + 1] = {};
     int only_stage[2] = {-1, -1};   // >= 0: events only around this stage (-2: none)
     bool ev_ready[2] = {false, false};
+    // concurrent lanes for batched calls, the fork event, the capture stream
+    // and the cached batch graphs (compress, decompress)
+    std::vector<dqz::host::Lane> lanes;
+    hipEvent_t fork = nullptr;
+    hipStream_t capture = nullptr;
+    bool use_graph = false;
+    dqz::host::BatchGraph graphs[2];
+    // tuned parameters per shape class
+    std::vector<std::pair<uint64_t, dqz_params>> tuned;
 };
 
 namespace dqz {

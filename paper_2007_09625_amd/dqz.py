@@ -21,12 +21,16 @@ DQZ_HEADER_BYTES = 128
 DQZ_DBG_CODES, DQZ_DBG_HISTOGRAM, DQZ_DBG_CODEBOOK, DQZ_DBG_PHASES = 1, 2, 3, 4
 
 DQZ_INJECT_ALLOC_FAIL = 1
+DQZ_MAX_LANES = 8
+DQZ_LANES_GRAPH = 1
+DQZ_TUNE_FORCE = 1
 
 EXPORTED = ("dqz_ctx_create", "dqz_ctx_destroy", "dqz_ctx_reserve", "dqz_ctx_workspace", "dqz_compress_bound",
             "dqz_decompress_bound", "dqz_compress", "dqz_compress_async", "dqz_compress_async_static",
             "dqz_archive_info", "dqz_decompress",
             "dqz_decompress_async", "dqz_status_str", "dqz_ctx_last_error", "dqz_debug_copy", "dqz_debug_inject",
-            "dqz_ctx_set_timing", "dqz_stage_times")
+            "dqz_ctx_set_timing", "dqz_stage_times", "dqz_ctx_set_lanes", "dqz_batch_workspace", "dqz_compress_batch",
+            "dqz_decompress_batch", "dqz_tune")
 DQZ_MAX_STAGES = 8
 COMPRESS_STAGES = ("init", "range_eb", "quantize", "quantize_scan", "codebook", "encode")
 DECOMPRESS_STAGES = ("decode_tables", "inflate", "reconstruct")
@@ -87,6 +91,20 @@ def _load() -> ctypes.CDLL:
     lib.dqz_compress_async.restype = i32
     lib.dqz_compress_async_static.argtypes = [P, ctypes.POINTER(dqz_shape), ctypes.POINTER(dqz_params), P, u64, P, P]
     lib.dqz_compress_async_static.restype = i32
+    lib.dqz_ctx_set_lanes.argtypes = [P, ctypes.c_uint32, ctypes.c_uint32]
+    lib.dqz_ctx_set_lanes.restype = i32
+    lib.dqz_batch_workspace.argtypes = [ctypes.c_uint32, ctypes.POINTER(dqz_shape), ctypes.POINTER(dqz_params),
+                                        ctypes.c_uint32, ctypes.POINTER(u64)]
+    lib.dqz_batch_workspace.restype = i32
+    lib.dqz_compress_batch.argtypes = [P, ctypes.c_uint32, ctypes.POINTER(P), ctypes.POINTER(dqz_shape),
+                                       ctypes.POINTER(dqz_params), ctypes.POINTER(P), ctypes.POINTER(u64), P, P]
+    lib.dqz_compress_batch.restype = i32
+    lib.dqz_decompress_batch.argtypes = [P, ctypes.c_uint32, ctypes.POINTER(P), ctypes.POINTER(u64), P,
+                                         ctypes.POINTER(P), ctypes.POINTER(u64), P, P]
+    lib.dqz_decompress_batch.restype = i32
+    lib.dqz_tune.argtypes = [P, P, ctypes.POINTER(dqz_shape), ctypes.POINTER(dqz_params), ctypes.c_double,
+                             ctypes.c_uint32, ctypes.POINTER(dqz_params), P]
+    lib.dqz_tune.restype = i32
     lib.dqz_decompress_async.argtypes = [P, P, u64, P, P, u64, P, P]
     lib.dqz_decompress_async.restype = i32
     lib.dqz_debug_inject.argtypes = [P, ctypes.c_int, ctypes.c_int]
@@ -197,6 +215,15 @@ class Compressed:
         return int(self.archive.numel())
 
 
+@dataclass
+class BatchBuffers:
+    """Archive and result buffers of one batch (see Context.batch_buffers)."""
+    shapes: list
+    params: list
+    archives: list
+    results: object
+
+
 class Context:
     """Owns one dqz_ctx (its device workspace is kept across calls).
 
@@ -213,6 +240,7 @@ class Context:
             why = lib.dqz_ctx_last_error(None).decode()
             raise DqzError(st, f"dqz_ctx_create: {lib.dqz_status_str(st).decode()} ({why})")
         self.handle = h
+        self.lanes = 1
 
     def dqz_ctx_reserve(self, nbytes: int):
         self._check(lib.dqz_ctx_reserve(self.handle, int(nbytes)), "dqz_ctx_reserve")
@@ -333,6 +361,110 @@ class Context:
             out = torch.empty(shape, dtype=torch.float32, device=arc.device)
         st = self.dqz_decompress(arc.data_ptr(), arc.numel(), hdr, out.data_ptr(), out.numel(), stream)
         self._check(st, "dqz_decompress")
+        return out
+
+    # -- batched calls ------------------------------------------------------------------
+    def dqz_ctx_set_lanes(self, lanes: int, flags: int = 0):
+        self._check(lib.dqz_ctx_set_lanes(self.handle, int(lanes), int(flags)), "dqz_ctx_set_lanes")
+        self.lanes = int(lanes)
+
+    def batch_buffers(self, fields, ebs, mode="valrel", **kw) -> "BatchBuffers":
+        """Archive and result buffers for a batch of these fields (reusing them
+        keeps a captured batch graph valid across calls)."""
+        torch = self._torch
+        params = [make_params(eb, _mode(mode), kw.get("radius", 0), kw.get("sub_size", 0), kw.get("chunk_subs", 0))
+                  for eb in ebs]
+        shapes = [tuple(f.shape) for f in fields]
+        caps = [dqz_compress_bound(s, p)[0] for s, p in zip(shapes, params)]
+        arcs = [torch.empty(c, dtype=torch.uint8, device=f.device) for c, f in zip(caps, fields)]
+        res = torch.zeros(len(fields) * DQZ_RESULT_BYTES, dtype=torch.uint8, device=fields[0].device)
+        return BatchBuffers(shapes, params, arcs, res)
+
+    def compress_batch(self, fields, ebs, mode="valrel", buffers=None, reserve=True, stream=None, **kw):
+        """Compress several float32 CUDA tensors in one dqz_compress_batch call;
+        returns one Compressed per field."""
+        torch = self._torch
+        n = len(fields)
+        for f in fields:
+            if f.dtype != torch.float32 or not f.is_cuda or not f.is_contiguous():
+                raise DqzError(DQZ_EINVAL, "fields must be contiguous float32 CUDA tensors")
+        if buffers is None:
+            buffers = self.batch_buffers(fields, ebs, mode, **kw)
+        shapes = (dqz_shape * n)(*[make_shape(s) for s in buffers.shapes])
+        params = (dqz_params * n)(*buffers.params)
+        if reserve:
+            lanes = max(1, self.lanes)
+            need = ctypes.c_uint64(0)
+            st = lib.dqz_batch_workspace(n, shapes, params, lanes, ctypes.byref(need))
+            self._check(st, "dqz_batch_workspace")
+            self.dqz_ctx_reserve(int(need.value))
+        P = ctypes.c_void_p
+        fptr = (P * n)(*[f.data_ptr() for f in fields])
+        aptr = (P * n)(*[a.data_ptr() for a in buffers.archives])
+        caps = (ctypes.c_uint64 * n)(*[a.numel() for a in buffers.archives])
+        st = lib.dqz_compress_batch(self.handle, n, fptr, shapes, params, aptr, caps,
+                                    P(buffers.results.data_ptr()), self._stream(stream))
+        self._check(st, "dqz_compress_batch")
+        raw = buffers.results.cpu().numpy().tobytes()      # waits for the batch
+        res = [dqz_result.from_buffer_copy(raw[i * DQZ_RESULT_BYTES:(i + 1) * DQZ_RESULT_BYTES]) for i in range(n)]
+        short = [r.workspace_need for r in res if r.status == DQZ_ENOMEM]
+        if short and reserve:
+            # a lane's exception overflow pool was too small: give every lane
+            # the largest reported need on top and run the batch again
+            self.dqz_ctx_reserve(self.dqz_ctx_workspace()[0] + max(1, self.lanes) * max(short))
+            return self.compress_batch(fields, ebs, mode, buffers, False, stream, **kw)
+        out = []
+        for i, r in enumerate(res):
+            if r.status != DQZ_OK:
+                raise DqzError(r.status, f"dqz_compress_batch: field {i}: {lib.dqz_status_str(r.status).decode()}")
+            out.append(Compressed(buffers.archives[i][:r.archive_bytes], bytes(r.header)))
+        return out
+
+    def decompress_batch(self, comps, outs=None, reserve=True, stream=None):
+        """Decompress several Compressed archives in one dqz_decompress_batch call."""
+        torch = self._torch
+        n = len(comps)
+        hdrs = b"".join(c.header for c in comps)
+        shapes = [dqz_archive_info(c.header)[0] for c in comps]
+        if reserve:
+            # each lane holds the largest decompression layout of its fields
+            need = sum(sorted((dqz_decompress_bound(c.header) for c in comps), reverse=True)[:max(1, self.lanes)])
+            self.dqz_ctx_reserve(need)
+        if outs is None:
+            outs = [torch.empty(s, dtype=torch.float32, device=c.archive.device) for s, c in zip(shapes, comps)]
+        P = ctypes.c_void_p
+        aptr = (P * n)(*[c.archive.data_ptr() for c in comps])
+        abytes = (ctypes.c_uint64 * n)(*[c.archive.numel() for c in comps])
+        fptr = (P * n)(*[o.data_ptr() for o in outs])
+        fcap = (ctypes.c_uint64 * n)(*[o.numel() for o in outs])
+        res = torch.zeros(n * DQZ_RESULT_BYTES, dtype=torch.uint8, device=comps[0].archive.device)
+        hb = ctypes.create_string_buffer(hdrs, len(hdrs))
+        st = lib.dqz_decompress_batch(self.handle, n, aptr, abytes, hb, fptr, fcap, P(res.data_ptr()),
+                                      self._stream(stream))
+        if st == DQZ_ENOMEM and reserve:
+            self.dqz_ctx_reserve(self.dqz_ctx_workspace()[1])
+            st = lib.dqz_decompress_batch(self.handle, n, aptr, abytes, hb, fptr, fcap, P(res.data_ptr()),
+                                          self._stream(stream))
+        self._check(st, "dqz_decompress_batch")
+        raw = res.cpu().numpy().tobytes()
+        for i in range(n):
+            r = dqz_result.from_buffer_copy(raw[i * DQZ_RESULT_BYTES:(i + 1) * DQZ_RESULT_BYTES])
+            if r.status != DQZ_OK:
+                raise DqzError(r.status, f"dqz_decompress_batch: archive {i}: {lib.dqz_status_str(r.status).decode()}")
+        return outs
+
+    def tune(self, field, eb: float, mode="valrel", radius: int = 0, tolerance: float = 0.05, force: bool = False,
+             stream=None) -> dqz_params:
+        """dqz_tune: subchunk and chunk sizes for this field's shape class."""
+        p = make_params(eb, _mode(mode), radius)
+        s = make_shape(tuple(field.shape))
+        _, ws = dqz_compress_bound(tuple(field.shape), p)
+        amax = dqz_compress_bound(tuple(field.shape), p)[0]
+        self.dqz_ctx_reserve(ws + amax + 4 * field.numel() + (64 << 20) + 4096)
+        out = dqz_params()
+        st = lib.dqz_tune(self.handle, ctypes.c_void_p(field.data_ptr()), ctypes.byref(s), ctypes.byref(p),
+                          float(tolerance), DQZ_TUNE_FORCE if force else 0, ctypes.byref(out), self._stream(stream))
+        self._check(st, "dqz_tune")
         return out
 
 

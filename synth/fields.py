@@ -142,3 +142,51 @@ def workload(name: str, scale: float = 1.0) -> np.ndarray:
     if name == "c3":
         return particles1d(sc((C3_N,))[0])
     raise KeyError(name)
+
+
+C4_FIELDS = 64
+C4_EDGES = (64, 512)
+C4_EBS = (1e-2, 1e-3, 1e-4)
+
+
+class BatchWorkload:
+    """Uneven 3D fields for batched compression (Nyx-like mixed fields):
+    field 0 is a 512^3 log-normal density exp(2 g - 2) of a unit-variance
+    Kolmogorov GRF g (sigma = 2: heavy upper tail); fields 1.. have edges
+    drawn uniformly from [64, 512] and are boxes cut (with periodic wrap, at
+    seeded offsets) from one 512^3 Kolmogorov GRF, each with its own seeded
+    offset and scale.  Each field has a value-range-relative eb drawn from
+    {1e-2, 1e-3, 1e-4}.  ``scale`` < 1 shrinks every edge (tests)."""
+
+    def __init__(self, n: int = C4_FIELDS, seed: int = 4, scale: float = 1.0):
+        rng = np.random.default_rng(seed)
+        self.seed = seed
+        self.scale = scale
+        lo, hi = C4_EDGES
+        def sc(e):
+            return max(1, int(round(e * scale)))
+        self.pool_edge = sc(512)
+        self.shapes = [(sc(512),) * 3]
+        for _ in range(1, n):
+            self.shapes.append(tuple(sc(int(e)) for e in rng.integers(lo, hi + 1, size=3)))
+        self.ebs = [float(e) for e in rng.choice(np.array(C4_EBS), size=n)]
+        self.offsets = [tuple(int(o) for o in rng.integers(0, self.pool_edge, size=3)) for _ in range(n)]
+        self.affine = [(float(a), float(b)) for a, b in zip(rng.normal(0.0, 10.0, n), rng.uniform(0.5, 4.0, n))]
+        self._pool = None
+
+    def __len__(self):
+        return len(self.shapes)
+
+    def field(self, i: int) -> np.ndarray:
+        if i == 0:
+            g = grf(self.shapes[0], self.seed + 1000)
+            return np.exp(2.0 * g - 2.0).astype(np.float32)
+        if self._pool is None:
+            self._pool = grf((self.pool_edge,) * 3, self.seed + 2000).astype(np.float32)
+        idx = [(np.arange(n) + o) % self.pool_edge for n, o in zip(self.shapes[i], self.offsets[i])]
+        box = self._pool[np.ix_(*idx)]
+        a, b = self.affine[i]
+        return (box * np.float32(b) + np.float32(a)).astype(np.float32)
+
+    def elements(self) -> int:
+        return int(sum(int(np.prod(s)) for s in self.shapes))

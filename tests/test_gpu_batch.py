@@ -1,0 +1,125 @@
+"""Batched compression and decompression (many fields of uneven sizes and
+dimensionality in one call, spread over concurrent lanes, optionally one
+captured HIP graph) and the parameter autotuner.  Every archive must be the
+one the plain single-field call writes for that field (and the oracle's);
+every decompressed field the plain call's floats."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import archive_util as au
+
+pytestmark = pytest.mark.gpu
+
+
+def _fields():
+    from synth import fields
+    xs, ebs = [], []
+    shapes = [(20, 33, 47), (64, 64, 64), (9, 130, 70), (300, 410), (1, 1, 77), (100003,), (17, 18, 19),
+              (48, 96, 120), (5000,), (45, 70), (33, 65, 130), (3, 4100)]
+    rng = np.random.default_rng(77)
+    for k, sh in enumerate(shapes):
+        if len(sh) == 3:
+            x = fields.hurricane3d(sh, seed=100 + k)
+        elif len(sh) == 2:
+            x = fields.fourier2d(sh, seed=100 + k)
+        else:
+            x = fields.particles1d(sh[0], seed=100 + k, shuffle_block=256)
+        xs.append(x)
+        ebs.append(float(rng.choice([1e-2, 1e-3, 1e-4])))
+    return xs, ebs
+
+
+@pytest.fixture(scope="module")
+def batch_case():
+    import oracle
+    xs, ebs = _fields()
+    refs = [oracle.compress(x, eb) for x, eb in zip(xs, ebs)]
+    return xs, ebs, refs
+
+
+@pytest.mark.parametrize("lanes,graph", [(1, False), (3, False), (4, True)])
+def test_batch_compress_matches_plain_and_oracle(batch_case, lanes, graph):
+    import torch
+    from paper_2007_09625_amd import dqz
+    xs, ebs, refs = batch_case
+    ctx = dqz.Context(0)
+    ts = [torch.from_numpy(x).cuda() for x in xs]
+    plain = [ctx.compress(t, eb).archive.cpu().numpy() for t, eb in zip(ts, ebs)]
+    for p, r in zip(plain, refs):
+        assert np.array_equal(p, r)
+    ctx.dqz_ctx_set_lanes(lanes, dqz.DQZ_LANES_GRAPH if graph else 0)
+    for rep in range(2):   # with the graph: capture, then replay
+        comps = ctx.compress_batch(ts, ebs)
+        for i, (c, r) in enumerate(zip(comps, refs)):
+            assert np.array_equal(c.archive.cpu().numpy(), r), (rep, i)
+    ys = ctx.decompress_batch(comps)
+    for i, (y, r) in enumerate(zip(ys, refs)):
+        import oracle
+        assert np.array_equal(y.cpu().numpy().view(np.uint32), oracle.decompress(r).view(np.uint32)), i
+
+
+def test_batch_graph_replays_new_contents(batch_case):
+    """The captured batch graph replayed on new contents of the same buffers
+    (eager work and synchronizations between replays) gives the oracle's
+    archive for each content."""
+    import torch
+    import oracle
+    from paper_2007_09625_amd import dqz
+    from synth import fields
+    xs, ebs, _ = batch_case
+    sel = [0, 2, 6, 9]
+    ctx = dqz.Context(0)
+    ctx.dqz_ctx_set_lanes(3, dqz.DQZ_LANES_GRAPH)
+    ts = [torch.from_numpy(xs[i]).cuda() for i in sel]
+    bufs = ctx.batch_buffers(ts, [ebs[i] for i in sel])
+    for rep in range(3):
+        new = []
+        for j, i in enumerate(sel):
+            sh = xs[i].shape
+            x = (fields.hurricane3d(sh, seed=500 + 10 * rep + j) if len(sh) == 3
+                 else fields.fourier2d(sh, seed=500 + 10 * rep + j))
+            ts[j].copy_(torch.from_numpy(x))
+            new.append(x)
+        torch.cuda.synchronize()
+        comps = ctx.compress_batch(ts, [ebs[i] for i in sel], buffers=bufs)
+        for j, i in enumerate(sel):
+            assert np.array_equal(comps[j].archive.cpu().numpy(), oracle.compress(new[j], ebs[i])), (rep, j)
+        _ = sum(float(t.sum()) for t in ts)   # unrelated eager work between replays
+
+
+def test_batch_workspace_too_small(batch_case):
+    import torch
+    from paper_2007_09625_amd import dqz
+    xs, ebs, refs = batch_case
+    ctx = dqz.Context(0, workspace=1 << 20)
+    ctx.dqz_ctx_set_lanes(2, 0)
+    ts = [torch.from_numpy(x).cuda() for x in xs[:3]]
+    with pytest.raises(dqz.DqzError) as e:
+        ctx.compress_batch(ts, ebs[:3], reserve=False)
+    assert e.value.status == dqz.DQZ_ENOMEM
+    comps = ctx.compress_batch(ts, ebs[:3])    # reserves what it reported
+    for c, r in zip(comps, refs[:3]):
+        assert np.array_equal(c.archive.cpu().numpy(), r)
+
+
+def test_tuner_choice_is_cached_and_bit_exact():
+    import torch
+    import oracle
+    from paper_2007_09625_amd import dqz
+    from synth import fields
+    x = fields.hurricane3d((40, 96, 128), seed=9)
+    t = torch.from_numpy(x).cuda()
+    ctx = dqz.Context(0)
+    p = ctx.tune(t, 1e-2)
+    assert p.sub_size in (128, 256, 512) and p.chunk_subs in (16, 64, 256)
+    c = ctx.compress(t, 1e-2, sub_size=p.sub_size, chunk_subs=p.chunk_subs)
+    ref = oracle.compress(x, 1e-2, sub_size=p.sub_size, chunk_subs=p.chunk_subs)
+    assert np.array_equal(c.archive.cpu().numpy(), ref)
+    # the stream does not depend on the choice
+    base = au.sections(oracle.compress(x, 1e-2))
+    assert np.array_equal(au.sections(ref)["stream"], base["stream"])
+    y = fields.hurricane3d((40, 96, 130), seed=10)     # same shape class: cached choice
+    q = ctx.tune(torch.from_numpy(y).cuda(), 1e-2)
+    assert (q.sub_size, q.chunk_subs) == (p.sub_size, p.chunk_subs)
