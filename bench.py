@@ -42,6 +42,8 @@ WORKLOADS = {
     "c1": "2D 1800x3600 fp32, 64 Fourier modes (|k|^-2) + N(0,1e-3) noise",
     "c2": "3D 100x500x500 fp32, Kolmogorov Gaussian random field + Lamb-Oseen vortex",
     "c3": "1D 280,953,867 fp32 particle coordinates, sorted U[0,256) + N(0,0.05), 4096-blocks shuffled",
+    "c4": "64 uneven 3D fp32 fields (edges U[64,512], one 512^3 log-normal sigma=2), per-field valrel eb "
+          "in {1e-2,1e-3,1e-4}: batched against plain per-field calls",
 }
 
 # What bounds each stage's kernel: "hbm" kernels stream the field or the
@@ -138,6 +140,8 @@ def main() -> int:
     from paper_2007_09625_amd import dqz
     from synth import fields
 
+    if args.workload == "c4":
+        return bench_batch(args)
     desc = WORKLOADS[args.workload]
     x_host = fields.workload(args.workload)
     n = x_host.size
@@ -380,6 +384,145 @@ def main() -> int:
                                   "sample": f"the full workload field, median of 3 runs of one compress "
                                             f"({tc:.2f} s) + one decompress ({td:.2f} s), single-threaded C",
                                   "archive_identical_to_gpu": same}
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+def bench_batch(args) -> int:
+    """The batched workload: every field compressed and decompressed by plain
+    single-field calls (one after another, each ending in its readback), then
+    by dqz_compress_batch / dqz_decompress_batch over 1-4 lanes with the
+    batch captured in a HIP graph; the archives and floats of both paths
+    must be identical.  Parameters per shape class from dqz_tune (setup, not
+    timed).  Prints one JSON line."""
+    import numpy as np
+    import torch
+
+    from paper_2007_09625_amd import dqz
+    from synth import fields
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    w = fields.BatchWorkload()
+    xs = []
+    for i in range(len(w)):
+        xs.append(torch.from_numpy(w.field(i)).to(dev))
+        print(f"field {i} {w.shapes[i]} eb {w.ebs[i]}", file=sys.stderr, flush=True)
+    w._pool = None
+    gen_s = time.perf_counter() - t0
+    n_tot = sum(x.numel() for x in xs)
+    orig = 4.0 * n_tot
+    ctx = dqz.Context(0)
+    t0 = time.perf_counter()
+    tuned = [ctx.tune(x, eb) for x, eb in zip(xs, w.ebs)]
+    tune_s = time.perf_counter() - t0
+    kw = [dict(sub_size=p.sub_size, chunk_subs=p.chunk_subs) for p in tuned]
+    params = [dqz.make_params(eb, dqz.DQZ_EB_VALREL, 0, p.sub_size, p.chunk_subs) for eb, p in zip(w.ebs, tuned)]
+    bufs = None
+    stream = torch.cuda.current_stream(dev)
+
+    # plain path: the single-field calls, one after another, into the batch's
+    # own archive buffers
+    def plain_compress():
+        out = []
+        for i, x in enumerate(xs):
+            a = bufs.archives[i]
+            st, nb, hdr = ctx.dqz_compress(x.data_ptr(), tuple(x.shape), params[i], a.data_ptr(), a.numel(), stream)
+            ctx._check(st, "dqz_compress")
+            out.append((nb, hdr))
+        return out
+
+    def plain_decompress(meta, ys):
+        for i, (nb, hdr) in enumerate(meta):
+            st = ctx.dqz_decompress(bufs.archives[i].data_ptr(), nb, hdr, ys[i].data_ptr(), ys[i].numel(), stream)
+            ctx._check(st, "dqz_decompress")
+
+    ctx.dqz_ctx_set_lanes(1, 0)
+    bufs = ctx.batch_buffers(xs, w.ebs, **{})
+    bufs.params = params
+    for i, x in enumerate(xs):
+        ctx.dqz_ctx_reserve(dqz.dqz_compress_bound(tuple(x.shape), params[i])[1])
+    meta = plain_compress()                                   # warm-up
+    ys = [torch.empty_like(x) for x in xs]
+    for nb, hdr in meta:
+        ctx.dqz_ctx_reserve(dqz.dqz_decompress_bound(hdr))
+    plain_decompress(meta, ys)
+    torch.cuda.synchronize()
+    reps = max(1, min(args.steps, 3))
+    tpc, tpd = [], []
+    for _ in range(reps):
+        t = time.perf_counter()
+        meta = plain_compress()
+        tpc.append(time.perf_counter() - t)
+        t = time.perf_counter()
+        plain_decompress(meta, ys)
+        torch.cuda.synchronize()
+        tpd.append(time.perf_counter() - t)
+    plain_arcs = [bufs.archives[i][:nb].clone() for i, (nb, _) in enumerate(meta)]
+    plain_ys = [y.clone() for y in ys]
+    arc_bytes = sum(nb for nb, _ in meta)
+    torch.cuda.synchronize()
+
+    per_lanes = {}
+    best = None
+    for lanes in (1, 2, 3, 4):
+        ctx.dqz_ctx_set_lanes(lanes, dqz.DQZ_LANES_GRAPH)
+        comps = ctx.compress_batch(xs, w.ebs, buffers=bufs)     # reserves, captures the graph
+        outs = [torch.empty_like(x) for x in xs]
+        ctx.decompress_batch(comps, outs=outs)
+        tcs, tds = [], []
+        for _ in range(reps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            comps = ctx.compress_batch(xs, w.ebs, buffers=bufs)
+            tcs.append(time.perf_counter() - t)
+            t = time.perf_counter()
+            ctx.decompress_batch(comps, outs=outs)
+            torch.cuda.synchronize()
+            tds.append(time.perf_counter() - t)
+        same_a = all(c.archive.numel() == p.numel() and torch.equal(c.archive, p) for c, p in zip(comps, plain_arcs))
+        same_y = all(torch.equal(a.view(torch.int32), b.view(torch.int32)) for a, b in zip(outs, plain_ys))
+        tc, td = sorted(tcs)[len(tcs) // 2], sorted(tds)[len(tds) // 2]
+        per_lanes[lanes] = {"compress_s": round(tc, 5), "decompress_s": round(td, 5),
+                            "compress_GBps": round(orig / tc / 1e9, 2), "decompress_GBps": round(orig / td / 1e9, 2),
+                            "identical_archives": same_a, "identical_floats": same_y}
+        if not (same_a and same_y):
+            raise SystemExit(f"batched output differs from the plain calls at {lanes} lanes")
+        if best is None or tc + td < per_lanes[best]["compress_s"] + per_lanes[best]["decompress_s"]:
+            best = lanes
+        del outs
+    tpc_m, tpd_m = sorted(tpc)[len(tpc) // 2], sorted(tpd)[len(tpd) // 2]
+    b = per_lanes[best]
+    # error bound on every element of every field (outside the timed region)
+    worst = 0.0
+    for i, (x, y) in enumerate(zip(xs, plain_ys)):
+        eb_abs = float(np.frombuffer(meta[i][1][56:64], np.float64)[0])
+        fin = torch.isfinite(x)
+        err = (x.double() - y.double()).abs()[fin].max().item()
+        assert err <= eb_abs, f"field {i}: error bound violated"
+        worst = max(worst, err / eb_abs)
+    classes = {}
+    for sh, eb, p in zip(w.shapes, w.ebs, tuned):
+        classes[f"S{p.sub_size}/C{p.chunk_subs}"] = classes.get(f"S{p.sub_size}/C{p.chunk_subs}", 0) + 1
+    result = {
+        "metric": "batched compress+decompress aggregate GB/s (original bytes) against plain per-field calls",
+        "value": round(orig / (b["compress_s"] + b["decompress_s"]) / 1e9, 2),
+        "unit": "GB/s", "n_gpus": 1, "steps": reps, "warmup": 1,
+        "ms_per_step": round(1e3 * (b["compress_s"] + b["decompress_s"]), 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": WORKLOADS["c4"], "fields": len(xs), "elements": n_tot,
+                   "value_definition": "4N bytes of all fields / (batched compress + batched decompress time, "
+                                       "median of the timed repetitions)"},
+        "batched": {"lanes": best, "graph": True, **b},
+        "plain": {"compress_s": round(tpc_m, 5), "decompress_s": round(tpd_m, 5),
+                  "compress_GBps": round(orig / tpc_m / 1e9, 2), "decompress_GBps": round(orig / tpd_m / 1e9, 2)},
+        "speedup": {"compress": round(tpc_m / b["compress_s"], 3), "decompress": round(tpd_m / b["decompress_s"], 3)},
+        "per_lanes": per_lanes,
+        "ratio": round(orig / arc_bytes, 3),
+        "max_err_over_eb": round(worst, 6),
+        "tuner": {"choices": classes, "seconds": round(tune_s, 2)},
+        "generation_s": round(gen_s, 1),
+    }
     print(json.dumps(result), flush=True)
     return 0
 

@@ -45,13 +45,19 @@ def fourier2d(shape=C1_SHAPE, seed: int = 1, modes: int = 64, noise: float = 1e-
     return field.astype(np.float32)
 
 
-def grf(shape, seed: int, slope: float = -11.0 / 3.0) -> np.ndarray:
+def grf(shape, seed: int, slope: float = -11.0 / 3.0, workers: int = 0) -> np.ndarray:
     """Unit-variance Gaussian random field with power spectrum P(|k|) ~ |k|^slope
     (default: Kolmogorov E(k) ~ k^-5/3, i.e. P ~ k^-11/3 in 3D), by FFT
-    filtering of white noise.  float64 result."""
+    filtering of white noise.  float64 result.  ``workers`` > 0 takes the
+    transforms from scipy.fft with that many threads (same definition, other
+    rounding: a different array than the default)."""
     rng = np.random.default_rng(seed)
     white = rng.standard_normal(shape)
-    spec = np.fft.rfftn(white)
+    if workers > 0:
+        import scipy.fft as sfft
+        spec = sfft.rfftn(white, workers=workers)
+    else:
+        spec = np.fft.rfftn(white)
     freqs = [np.fft.fftfreq(n) for n in shape[:-1]] + [np.fft.rfftfreq(shape[-1])]
     k2 = np.zeros(spec.shape, dtype=np.float64)
     for ax, f in enumerate(freqs):
@@ -62,7 +68,10 @@ def grf(shape, seed: int, slope: float = -11.0 / 3.0) -> np.ndarray:
     filt = k2 ** (slope / 4.0)       # sqrt(P) = |k|^(slope/2) = (k^2)^(slope/4)
     filt.flat[0] = 0.0               # zero mean
     spec *= filt
-    field = np.fft.irfftn(spec, s=shape, axes=list(range(len(shape))))
+    if workers > 0:
+        field = sfft.irfftn(spec, s=shape, axes=list(range(len(shape))), workers=workers)
+    else:
+        field = np.fft.irfftn(spec, s=shape, axes=list(range(len(shape))))
     sd = field.std()
     if sd > 0:
         field /= sd
@@ -149,6 +158,19 @@ C4_EDGES = (64, 512)
 C4_EBS = (1e-2, 1e-3, 1e-4)
 
 
+def _wrap_take(a: np.ndarray, axis: int, start: int, n: int) -> np.ndarray:
+    """Elements start .. start + n - 1 of ``a`` along ``axis``, wrapping around."""
+    size = a.shape[axis]
+    start %= size
+    if start + n <= size:
+        return np.take(a, range(start, start + n), axis=axis) if n < size else a
+    head = [slice(None)] * a.ndim
+    tail = [slice(None)] * a.ndim
+    head[axis] = slice(start, size)
+    tail[axis] = slice(0, start + n - size)
+    return np.concatenate([a[tuple(head)], a[tuple(tail)]], axis=axis)
+
+
 class BatchWorkload:
     """Uneven 3D fields for batched compression (Nyx-like mixed fields):
     field 0 is a 512^3 log-normal density exp(2 g - 2) of a unit-variance
@@ -158,7 +180,7 @@ class BatchWorkload:
     offset and scale.  Each field has a value-range-relative eb drawn from
     {1e-2, 1e-3, 1e-4}.  ``scale`` < 1 shrinks every edge (tests)."""
 
-    def __init__(self, n: int = C4_FIELDS, seed: int = 4, scale: float = 1.0):
+    def __init__(self, n: int = C4_FIELDS, seed: int = 4, scale: float = 1.0, workers: int = 8):
         rng = np.random.default_rng(seed)
         self.seed = seed
         self.scale = scale
@@ -173,18 +195,20 @@ class BatchWorkload:
         self.offsets = [tuple(int(o) for o in rng.integers(0, self.pool_edge, size=3)) for _ in range(n)]
         self.affine = [(float(a), float(b)) for a, b in zip(rng.normal(0.0, 10.0, n), rng.uniform(0.5, 4.0, n))]
         self._pool = None
+        self.workers = workers
 
     def __len__(self):
         return len(self.shapes)
 
     def field(self, i: int) -> np.ndarray:
         if i == 0:
-            g = grf(self.shapes[0], self.seed + 1000)
+            g = grf(self.shapes[0], self.seed + 1000, workers=self.workers)
             return np.exp(2.0 * g - 2.0).astype(np.float32)
         if self._pool is None:
-            self._pool = grf((self.pool_edge,) * 3, self.seed + 2000).astype(np.float32)
-        idx = [(np.arange(n) + o) % self.pool_edge for n, o in zip(self.shapes[i], self.offsets[i])]
-        box = self._pool[np.ix_(*idx)]
+            self._pool = grf((self.pool_edge,) * 3, self.seed + 2000, workers=self.workers).astype(np.float32)
+        box = self._pool
+        for ax, (n, o) in enumerate(zip(self.shapes[i], self.offsets[i])):
+            box = _wrap_take(box, ax, o, n)
         a, b = self.affine[i]
         return (box * np.float32(b) + np.float32(a)).astype(np.float32)
 

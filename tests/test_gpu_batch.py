@@ -123,3 +123,49 @@ def test_tuner_choice_is_cached_and_bit_exact():
     y = fields.hurricane3d((40, 96, 130), seed=10)     # same shape class: cached choice
     q = ctx.tune(torch.from_numpy(y).cuda(), 1e-2)
     assert (q.sub_size, q.chunk_subs) == (p.sub_size, p.chunk_subs)
+
+
+@pytest.mark.timeout(900)
+def test_batch_full_size_c4():
+    """The 64-field batched workload at full size (uneven 3D fields, one
+    512^3 log-normal), in the configuration the benchmark times (tuned
+    parameters, 4 lanes, one captured graph): every field's archive equals
+    its plain single-field archive and every decompressed field the plain
+    call's floats; sampled fields (the log-normal one and two others) equal
+    the oracle's archive and floats; |x - x'| <= eb_abs on every element of
+    every field."""
+    import torch
+    import oracle
+    from paper_2007_09625_amd import dqz
+    from synth import fields
+    w = fields.BatchWorkload()
+    host = {}
+    sample = {0, 17, 42}
+    xs = []
+    for i in range(len(w)):
+        x = w.field(i)
+        if i in sample:
+            host[i] = x
+        xs.append(torch.from_numpy(x).cuda())
+    w._pool = None
+    ctx = dqz.Context(0)
+    tuned = [ctx.tune(x, eb) for x, eb in zip(xs, w.ebs)]
+    ctx.dqz_ctx_set_lanes(4, dqz.DQZ_LANES_GRAPH)
+    bufs = ctx.batch_buffers(xs, w.ebs)
+    bufs.params = [dqz.make_params(eb, dqz.DQZ_EB_VALREL, 0, p.sub_size, p.chunk_subs) for eb, p in zip(w.ebs, tuned)]
+    comps = ctx.compress_batch(xs, w.ebs, buffers=bufs)
+    ys = ctx.decompress_batch(comps)
+    for i, (x, c, y) in enumerate(zip(xs, comps, ys)):
+        p = tuned[i]
+        plain = ctx.compress(x, w.ebs[i], sub_size=p.sub_size, chunk_subs=p.chunk_subs)
+        assert plain.archive.numel() == c.archive.numel() and torch.equal(plain.archive, c.archive), i
+        py = ctx.decompress(plain)
+        assert torch.equal(py.view(torch.int32), y.view(torch.int32)), i
+        eb_abs = float(np.frombuffer(c.header[56:64], np.float64)[0])
+        fin = torch.isfinite(x)
+        assert (x.double() - y.double()).abs()[fin].max().item() <= eb_abs, i
+        if i in sample:
+            ref = oracle.compress(host[i], w.ebs[i], sub_size=p.sub_size, chunk_subs=p.chunk_subs)
+            assert np.array_equal(c.archive.cpu().numpy(), ref), i
+            assert np.array_equal(y.cpu().numpy().view(np.uint32), oracle.decompress(ref).view(np.uint32)), i
+        del plain, py
