@@ -78,6 +78,7 @@ typedef int32_t dqz_status;
 #define DQZ_EUNSUPPORTED (-5) /* valid request outside this build's limits */
 #define DQZ_EHIP (-6)         /* a HIP runtime call failed (message in dqz_ctx_last_error) */
 #define DQZ_EINTERNAL (-7)    /* a device-side ordering wait timed out (kernels exited; retry) */
+/* DQZ_EAGAIN (-8): see dqz_server_wait */
 
 #define DQZ_EB_ABS 0     /* eb is the absolute bound */
 #define DQZ_EB_VALREL 1  /* eb is relative to (max - min) of the finite values */
@@ -279,6 +280,70 @@ dqz_status dqz_decompress_batch(dqz_ctx *ctx, uint32_t n, const void *const *d_a
 #define DQZ_TUNE_FORCE 1u
 dqz_status dqz_tune(dqz_ctx *ctx, const float *d_field, const dqz_shape *shape, const dqz_params *base,
                     double tolerance, uint32_t flags, dqz_params *out, void *stream);
+
+/* Serving: continuous batching of compression and decompression requests on
+ * one GPU (the paper's kernels, Sec. 3, run per request; a served request's
+ * output is byte for byte what dqz_compress / dqz_decompress write for it).
+ * A server owns `slots` concurrent slots (each a HIP stream of default
+ * priority, an event and a pinned status block) and one resident device
+ * arena of `workspace_bytes` from which each admitted request gets its
+ * workspace; all of it is allocated by dqz_server_create, nothing per
+ * request.  One dispatcher thread admits requests in arrival order as soon as
+ * a slot is free and the request's footprint (input bytes + output capacity +
+ * workspace) fits `hbm_budget` beside the running requests' footprints (the
+ * head of the queue waits until it fits; a request runs alone if it exceeds
+ * the budget by itself), enqueues its kernels on the slot's stream and polls
+ * the slots' completion events, so requests that arrive while others run
+ * start as soon as a slot and memory free up and their kernels overlap the
+ * running ones.  A compression whose exception records overflow its
+ * workspace runs again first in line with the size the device reported.
+ * The caller owns every input and output buffer and keeps it valid until the
+ * request's completion has been collected with dqz_server_wait. */
+typedef struct dqz_server dqz_server;
+typedef struct {
+    uint32_t slots;            /* concurrent requests on the device, 1..DQZ_MAX_LANES */
+    uint32_t reserved;
+    uint64_t workspace_bytes;  /* resident device arena for the requests' workspaces */
+    uint64_t hbm_budget;       /* cap on the summed footprints of the running requests */
+} dqz_server_config;
+#define DQZ_REQ_COMPRESS 0u
+#define DQZ_REQ_DECOMPRESS 1u
+typedef struct {
+    uint32_t kind;             /* DQZ_REQ_COMPRESS or DQZ_REQ_DECOMPRESS */
+    uint32_t reserved;
+    const void *d_input;       /* compression: fp32 field; decompression: archive */
+    uint64_t input_bytes;      /* decompression: archive bytes */
+    void *d_output;            /* compression: archive buffer; decompression: field buffer */
+    uint64_t output_capacity;  /* bytes */
+    dqz_shape shape;           /* compression */
+    dqz_params params;         /* compression */
+    uint8_t header[DQZ_HEADER_BYTES];   /* decompression: host copy of the archive's header */
+} dqz_request;
+typedef struct {
+    int32_t status;            /* the request's dqz_status */
+    uint32_t reserved;
+    uint64_t output_bytes;     /* archive bytes (with DQZ_ETOOSMALL: the size needed) or field bytes */
+    uint64_t footprint;        /* device bytes it was admitted with */
+    double t_submit_us, t_admit_us, t_done_us;   /* server clock: submitted, admitted, completion seen */
+    uint8_t header[DQZ_HEADER_BYTES];   /* compression: the archive's header */
+} dqz_completion;
+typedef struct {
+    uint64_t submitted, admitted, completed, failed, retried;
+    uint64_t max_running;          /* most requests on the device at once */
+    uint64_t max_in_flight_bytes;  /* largest summed footprint of running requests */
+} dqz_server_stats;
+#define DQZ_EAGAIN (-8)   /* dqz_server_wait: not completed within the timeout */
+dqz_status dqz_server_create(int device, const dqz_server_config *cfg, dqz_server **out);
+/* Waits for every submitted request to complete, then frees the server. */
+void dqz_server_destroy(dqz_server *server);
+/* Validate (host only) and queue a request; *ticket names it.  DQZ_ENOMEM if
+ * its workspace exceeds the arena (it could never run); argument errors as
+ * for the single-field calls.  Thread-safe. */
+dqz_status dqz_server_submit(dqz_server *server, const dqz_request *req, uint64_t *ticket);
+/* Wait up to timeout_us (negative: without limit) for a request's completion
+ * and collect it (once per ticket); DQZ_EAGAIN on timeout.  Thread-safe. */
+dqz_status dqz_server_wait(dqz_server *server, uint64_t ticket, int64_t timeout_us, dqz_completion *out);
+dqz_status dqz_server_get_stats(dqz_server *server, dqz_server_stats *out);
 
 const char *dqz_status_str(dqz_status status);
 /* Text of the last error on this context ("" if none); with ctx == NULL, why

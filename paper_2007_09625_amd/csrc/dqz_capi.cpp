@@ -483,6 +483,7 @@ const char *dqz_status_str(dqz_status s) {
         case DQZ_EUNSUPPORTED: return "unsupported";
         case DQZ_EHIP: return "HIP runtime error";
         case DQZ_EINTERNAL: return "internal device error";
+        case DQZ_EAGAIN: return "not completed yet";
         default: return "unknown status";
     }
 }

@@ -16,6 +16,8 @@ LIB_PATH = os.path.join(HERE, "libdqz.so")
 
 DQZ_OK, DQZ_EINVAL, DQZ_ETOOSMALL, DQZ_ENOMEM, DQZ_ECORRUPT, DQZ_EUNSUPPORTED, DQZ_EHIP = 0, -1, -2, -3, -4, -5, -6
 DQZ_EINTERNAL = -7
+DQZ_EAGAIN = -8
+DQZ_REQ_COMPRESS, DQZ_REQ_DECOMPRESS = 0, 1
 DQZ_EB_ABS, DQZ_EB_VALREL = 0, 1
 DQZ_HEADER_BYTES = 128
 DQZ_DBG_CODES, DQZ_DBG_HISTOGRAM, DQZ_DBG_CODEBOOK, DQZ_DBG_PHASES = 1, 2, 3, 4
@@ -30,7 +32,8 @@ EXPORTED = ("dqz_ctx_create", "dqz_ctx_destroy", "dqz_ctx_reserve", "dqz_ctx_wor
             "dqz_archive_info", "dqz_decompress",
             "dqz_decompress_async", "dqz_status_str", "dqz_ctx_last_error", "dqz_debug_copy", "dqz_debug_inject",
             "dqz_ctx_set_timing", "dqz_stage_times", "dqz_ctx_set_lanes", "dqz_batch_workspace", "dqz_compress_batch",
-            "dqz_decompress_batch", "dqz_tune")
+            "dqz_decompress_batch", "dqz_tune", "dqz_server_create", "dqz_server_destroy", "dqz_server_submit",
+            "dqz_server_wait", "dqz_server_get_stats")
 DQZ_MAX_STAGES = 8
 COMPRESS_STAGES = ("init", "range_eb", "quantize", "quantize_scan", "codebook", "encode")
 DECOMPRESS_STAGES = ("decode_tables", "inflate", "reconstruct")
@@ -66,6 +69,28 @@ class dqz_result(ctypes.Structure):
 
 
 DQZ_RESULT_BYTES = ctypes.sizeof(dqz_result)
+
+
+class dqz_server_config(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("workspace_bytes", ctypes.c_uint64),
+                ("hbm_budget", ctypes.c_uint64)]
+
+
+class dqz_request(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("d_input", ctypes.c_void_p),
+                ("input_bytes", ctypes.c_uint64), ("d_output", ctypes.c_void_p), ("output_capacity", ctypes.c_uint64),
+                ("shape", dqz_shape), ("params", dqz_params), ("header", ctypes.c_uint8 * DQZ_HEADER_BYTES)]
+
+
+class dqz_completion(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("reserved", ctypes.c_uint32), ("output_bytes", ctypes.c_uint64),
+                ("footprint", ctypes.c_uint64), ("t_submit_us", ctypes.c_double), ("t_admit_us", ctypes.c_double),
+                ("t_done_us", ctypes.c_double), ("header", ctypes.c_uint8 * DQZ_HEADER_BYTES)]
+
+
+class dqz_server_stats(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_uint64) for k in ("submitted", "admitted", "completed", "failed", "retried",
+                                                "max_running", "max_in_flight_bytes")]
 
 
 def _load() -> ctypes.CDLL:
@@ -105,6 +130,16 @@ def _load() -> ctypes.CDLL:
     lib.dqz_tune.argtypes = [P, P, ctypes.POINTER(dqz_shape), ctypes.POINTER(dqz_params), ctypes.c_double,
                              ctypes.c_uint32, ctypes.POINTER(dqz_params), P]
     lib.dqz_tune.restype = i32
+    lib.dqz_server_create.argtypes = [ctypes.c_int, ctypes.POINTER(dqz_server_config), ctypes.POINTER(P)]
+    lib.dqz_server_create.restype = i32
+    lib.dqz_server_destroy.argtypes = [P]
+    lib.dqz_server_destroy.restype = None
+    lib.dqz_server_submit.argtypes = [P, ctypes.POINTER(dqz_request), ctypes.POINTER(u64)]
+    lib.dqz_server_submit.restype = i32
+    lib.dqz_server_wait.argtypes = [P, u64, ctypes.c_int64, ctypes.POINTER(dqz_completion)]
+    lib.dqz_server_wait.restype = i32
+    lib.dqz_server_get_stats.argtypes = [P, ctypes.POINTER(dqz_server_stats)]
+    lib.dqz_server_get_stats.restype = i32
     lib.dqz_decompress_async.argtypes = [P, P, u64, P, P, u64, P, P]
     lib.dqz_decompress_async.restype = i32
     lib.dqz_debug_inject.argtypes = [P, ctypes.c_int, ctypes.c_int]
@@ -466,6 +501,78 @@ class Context:
                           float(tolerance), DQZ_TUNE_FORCE if force else 0, ctypes.byref(out), self._stream(stream))
         self._check(st, "dqz_tune")
         return out
+
+
+class Server:
+    """One dqz_server: continuous batching of compression and decompression
+    requests (marshalling only; admission, launches and completion tracking
+    run in the library's dispatcher thread).  Buffers passed to submit_* must
+    stay alive until the request is collected with wait()."""
+
+    def __init__(self, device: int = 0, slots: int = 4, workspace: int = 1 << 30, budget: int = 64 << 30):
+        cfg = dqz_server_config(int(slots), 0, int(workspace), int(budget))
+        h = ctypes.c_void_p()
+        st = lib.dqz_server_create(int(device), ctypes.byref(cfg), ctypes.byref(h))
+        if st != DQZ_OK:
+            raise DqzError(st, f"dqz_server_create: {lib.dqz_status_str(st).decode()}")
+        self.handle = h
+        self._keep = {}
+
+    def submit_compress(self, field, eb: float, out, mode="valrel", radius: int = 0, sub_size: int = 0,
+                        chunk_subs: int = 0) -> int:
+        r = dqz_request()
+        r.kind = DQZ_REQ_COMPRESS
+        r.d_input = field.data_ptr()
+        r.d_output = out.data_ptr()
+        r.output_capacity = out.numel() * out.element_size()
+        r.shape = make_shape(tuple(field.shape))
+        r.params = make_params(eb, _mode(mode), radius, sub_size, chunk_subs)
+        return self._submit(r, (field, out))
+
+    def submit_decompress(self, archive, nbytes: int, header: bytes, out) -> int:
+        r = dqz_request()
+        r.kind = DQZ_REQ_DECOMPRESS
+        r.d_input = archive.data_ptr()
+        r.input_bytes = int(nbytes)
+        r.d_output = out.data_ptr()
+        r.output_capacity = out.numel() * out.element_size()
+        ctypes.memmove(r.header, bytes(header), DQZ_HEADER_BYTES)
+        return self._submit(r, (archive, out))
+
+    def _submit(self, r, keep) -> int:
+        t = ctypes.c_uint64(0)
+        st = lib.dqz_server_submit(self.handle, ctypes.byref(r), ctypes.byref(t))
+        if st != DQZ_OK:
+            raise DqzError(st, f"dqz_server_submit: {lib.dqz_status_str(st).decode()}")
+        self._keep[int(t.value)] = keep
+        return int(t.value)
+
+    def wait(self, ticket: int, timeout_us: int = -1) -> dqz_completion:
+        c = dqz_completion()
+        st = lib.dqz_server_wait(self.handle, int(ticket), int(timeout_us), ctypes.byref(c))
+        if st != DQZ_OK:
+            raise DqzError(st, f"dqz_server_wait: {lib.dqz_status_str(st).decode()}")
+        self._keep.pop(int(ticket), None)
+        return c
+
+    def stats(self) -> dict:
+        s = dqz_server_stats()
+        st = lib.dqz_server_get_stats(self.handle, ctypes.byref(s))
+        if st != DQZ_OK:
+            raise DqzError(st, "dqz_server_get_stats")
+        return {k: int(getattr(s, k)) for k, _ in dqz_server_stats._fields_}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib.dqz_server_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 _default = {}
