@@ -295,8 +295,9 @@ dqz_status dqz_tune(dqz_ctx *ctx, const float *d_field, const dqz_shape *shape, 
  * the budget by itself), enqueues its kernels on the slot's stream and polls
  * the slots' completion events, so requests that arrive while others run
  * start as soon as a slot and memory free up and their kernels overlap the
- * running ones.  A compression whose exception records overflow its
- * workspace runs again first in line with the size the device reported.
+ * running ones.  A compression gets its fixed workspace layout plus room for
+ * one exception record per element; one whose records overflow that runs
+ * again first in line with the size the device reported.
  * The caller owns every input and output buffer and keeps it valid until the
  * request's completion has been collected with dqz_server_wait. */
 typedef struct dqz_server dqz_server;
@@ -344,6 +345,40 @@ dqz_status dqz_server_submit(dqz_server *server, const dqz_request *req, uint64_
  * and collect it (once per ticket); DQZ_EAGAIN on timeout.  Thread-safe. */
 dqz_status dqz_server_wait(dqz_server *server, uint64_t ticket, int64_t timeout_us, dqz_completion *out);
 dqz_status dqz_server_get_stats(dqz_server *server, dqz_server_stats *out);
+
+/* Host path.  The paper's overall throughput counts the archive's trip to
+ * host memory (Sec. 4.2, its overall figures), and a field larger than the
+ * device memory is compressed block by block (the prediction blocks of
+ * Sec. 3.1.1 are independent).  dqz_stream_compress reads a field from host
+ * memory (pinned memory lets the copies overlap the kernels) in slabs: runs
+ * of the slowest axis about slab_bytes long whose extent is a multiple of the
+ * prediction block edge along it (32 in 1D, 16 in 2D, 8 in 3D), so every
+ * block lies in one slab.  Each slab becomes an ordinary archive compressed
+ * with an absolute bound (in the value-range-relative mode: eb times the
+ * whole field's finite range, found in a first pass over the slabs), written
+ * into h_container after a 128-byte container header and the slab offsets.
+ * The decompressed field is bit for bit what dqz_decompress gives for a
+ * whole-field archive compressed with that absolute bound.  Uploads, kernels
+ * and downloads of consecutive slabs overlap on three streams (`stream` and
+ * the context's two copy streams).  The workspace holds two slabs of input
+ * and archive plus one slab's compression workspace with one exception
+ * record per element (dqz_stream_workspace); DQZ_ENOMEM if smaller.
+ * Synchronous: returns when the container is complete in host memory. */
+dqz_status dqz_stream_workspace(const dqz_shape *shape, const dqz_params *params, uint64_t slab_bytes,
+                                uint64_t *workspace_bytes, uint64_t *container_max);
+dqz_status dqz_stream_compress(dqz_ctx *ctx, const float *h_field, const dqz_shape *shape, const dqz_params *params,
+                               uint64_t slab_bytes, void *h_container, uint64_t container_cap,
+                               uint64_t *container_bytes, void *stream);
+/* Host-only: parse and validate a container (and its slabs' headers): shape,
+ * slab count, the absolute bound, and the workspace dqz_stream_decompress
+ * needs.  Any output may be NULL.  DQZ_ECORRUPT for a bad container. */
+dqz_status dqz_stream_info(const void *h_container, uint64_t bytes, dqz_shape *shape, uint32_t *n_slabs,
+                           double *eb_abs, uint64_t *workspace_bytes);
+/* Decompress a container from host memory into the host field (capacity
+ * field_cap_elems floats), slab by slab with the copies overlapping the
+ * kernels (Sec. 3.3 per slab).  Synchronous. */
+dqz_status dqz_stream_decompress(dqz_ctx *ctx, const void *h_container, uint64_t bytes, float *h_field,
+                                 uint64_t field_cap_elems, void *stream);
 
 const char *dqz_status_str(dqz_status status);
 /* Text of the last error on this context ("" if none); with ctx == NULL, why

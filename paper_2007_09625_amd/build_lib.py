@@ -11,7 +11,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libdqz.so")
 
 SOURCES = ["kernels_quant.hip", "kernels_huff.hip", "kernels_encode.hip", "kernels_decode.hip", "dqz_static.hip",
-           "dqz_capi.cpp", "dqz_batch.cpp", "dqz_server.cpp"]
+           "dqz_capi.cpp", "dqz_batch.cpp", "dqz_server.cpp",
+           "dqz_stream.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-result"]

@@ -516,7 +516,7 @@ dqz_status dqz_ctx_create(int device, uint64_t workspace_cap, dqz_ctx **out) {
         delete ctx;
         return create_fail(DQZ_EHIP, std::string("decoding kernels' LDS attributes: ") + hipGetErrorString(e));
     }
-    if ((e = hipHostMalloc((void **)&ctx->h_rb, sizeof(Readback), hipHostMallocDefault)) != hipSuccess) {
+    if ((e = hipHostMalloc((void **)&ctx->h_rb, 3 * sizeof(Readback), hipHostMallocDefault)) != hipSuccess) {
         (void)hipGetLastError();
         delete ctx;
         return create_fail(DQZ_ENOMEM, std::string("hipHostMalloc: ") + hipGetErrorString(e));
@@ -527,8 +527,18 @@ dqz_status dqz_ctx_create(int device, uint64_t workspace_cap, dqz_ctx **out) {
         delete ctx;
         return create_fail(DQZ_EHIP, std::string("hipHostGetDevicePointer: ") + hipGetErrorString(e));
     }
+    if ((e = hipStreamCreateWithFlags(&ctx->copy_in, hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipStreamCreateWithFlags(&ctx->copy_out, hipStreamNonBlocking)) != hipSuccess) {
+        (void)hipGetLastError();
+        if (ctx->copy_in) (void)hipStreamDestroy(ctx->copy_in);
+        (void)hipHostFree(ctx->h_rb);
+        delete ctx;
+        return create_fail(DQZ_EHIP, std::string("hipStreamCreateWithFlags: ") + hipGetErrorString(e));
+    }
     if (workspace_cap && alloc_workspace(ctx, workspace_cap) != DQZ_OK) {
         const std::string why = ctx->last_error;
+        (void)hipStreamDestroy(ctx->copy_in);
+        (void)hipStreamDestroy(ctx->copy_out);
         (void)hipHostFree(ctx->h_rb);
         delete ctx;
         return create_fail(DQZ_ENOMEM, why);
@@ -551,6 +561,10 @@ void dqz_ctx_destroy(dqz_ctx *ctx) {
     }
     if (ctx->fork) (void)hipEventDestroy(ctx->fork);
     if (ctx->capture) (void)hipStreamDestroy(ctx->capture);
+    if (ctx->copy_in) (void)hipStreamSynchronize(ctx->copy_in);
+    if (ctx->copy_out) (void)hipStreamSynchronize(ctx->copy_out);
+    if (ctx->copy_in) (void)hipStreamDestroy(ctx->copy_in);
+    if (ctx->copy_out) (void)hipStreamDestroy(ctx->copy_out);
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->h_rb) (void)hipHostFree(ctx->h_rb);
     for (int k = 0; k < 2; k++)

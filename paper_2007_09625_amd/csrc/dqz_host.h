@@ -69,8 +69,11 @@ struct dqz_ctx {
     void *ws = nullptr;        // device workspace
     uint64_t ws_bytes = 0;
     uint64_t last_need = 0;    // workspace the most recent call needed
-    dqz::Readback *h_rb = nullptr;  // readback block in pinned host memory, written by the kernels
-    dqz::Readback *d_rb = nullptr;  // the same block's device address
+    // readback blocks in pinned host memory, written by the kernels: [0] for
+    // the single calls, [1], [2] for the two slabs in flight of a streaming call
+    dqz::Readback *h_rb = nullptr;
+    dqz::Readback *d_rb = nullptr;  // the same blocks' device address
+    hipStream_t copy_in = nullptr, copy_out = nullptr;   // streaming calls' copy streams
     int inject_alloc_fail = 0; // test hook: workspace allocations that fail on purpose
     std::string last_error;
     // most recent compression, for the stage dumps (cleared by a decompression,

@@ -319,6 +319,8 @@ void launch_publish(hipStream_t s, Readback *rb, uint32_t bits, uint64_t archive
 void launch_minmax(hipStream_t s, const float *x, uint64_t n, Ctl *ctl, uint32_t *partials, double valrel, int ncu,
                    void *zero_base, uint64_t zero_bytes);
 constexpr uint32_t kMinmaxMaxBlocks = 2048;
+// fold the control block's (min key, max key) into acc[0..1] (first: set it)
+void launch_range_fold(hipStream_t s, const Ctl *ctl, uint32_t *acc, bool first);
 struct QuantBufs {
     uint16_t *codes;
     uint32_t *hist;        // kHistReplicas * 2R

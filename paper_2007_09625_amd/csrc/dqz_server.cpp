@@ -331,10 +331,11 @@ dqz_status dqz_server_submit(dqz_server *sv, const dqz_request *req, uint64_t *t
         st = plan_compress_args(static_cast<const float *>(req->d_input), &req->shape, &req->params, req->d_output,
                                 req->output_capacity, j.P, j.W, why);
         if (st != DQZ_OK) return st;
-        // the fixed layout plus an eighth of it for exception records past the
-        // tiles' slots (a request that needs more runs again with what the
+        // the fixed layout plus room for exception records past the tiles'
+        // slots: one record per element, enough for every element an outlier
+        // (a request that also needs many patches runs again with what the
         // device reports)
-        j.ws_need = j.W.fixed + j.W.fixed / 8;
+        j.ws_need = j.W.fixed + 8ull * j.P.g.nelem;
         j.footprint = 4ull * j.P.g.nelem + req->output_capacity + j.ws_need;
     } else if (req->kind == DQZ_REQ_DECOMPRESS) {
         if (!req->d_input) return DQZ_EINVAL;

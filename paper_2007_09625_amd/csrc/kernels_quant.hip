@@ -197,6 +197,19 @@ void launch_minmax(hipStream_t s, const float *x, uint64_t n, Ctl *ctl, uint32_t
     hipLaunchKernelGGL(k_minmax_final, dim3(1), dim3(256), 0, s, partials, blocks, ctl, valrel);
 }
 
+// Range of a field compressed slab by slab: fold one slab's (min key, max
+// key), as the range kernels left them in the control block, into acc[0..1]
+// (the first slab initializes it).  One thread.
+__global__ void k_range_fold(const Ctl *ctl, uint32_t *acc, uint32_t first) {
+    const uint32_t lo = ctl->vmin_key, hi = ctl->vmax_key;
+    acc[0] = (first || lo < acc[0]) ? lo : acc[0];
+    acc[1] = (first || hi > acc[1]) ? hi : acc[1];
+}
+
+void launch_range_fold(hipStream_t s, const Ctl *ctl, uint32_t *acc, bool first) {
+    hipLaunchKernelGGL(k_range_fold, dim3(1), dim3(1), 0, s, ctl, acc, first ? 1u : 0u);
+}
+
 // ---------------------------------------------------------------------------
 // shared pieces of the quantize kernels
 // ---------------------------------------------------------------------------

@@ -33,7 +33,8 @@ EXPORTED = ("dqz_ctx_create", "dqz_ctx_destroy", "dqz_ctx_reserve", "dqz_ctx_wor
             "dqz_decompress_async", "dqz_status_str", "dqz_ctx_last_error", "dqz_debug_copy", "dqz_debug_inject",
             "dqz_ctx_set_timing", "dqz_stage_times", "dqz_ctx_set_lanes", "dqz_batch_workspace", "dqz_compress_batch",
             "dqz_decompress_batch", "dqz_tune", "dqz_server_create", "dqz_server_destroy", "dqz_server_submit",
-            "dqz_server_wait", "dqz_server_get_stats")
+            "dqz_server_wait", "dqz_server_get_stats", "dqz_stream_workspace", "dqz_stream_compress", "dqz_stream_info",
+            "dqz_stream_decompress")
 DQZ_MAX_STAGES = 8
 COMPRESS_STAGES = ("init", "range_eb", "quantize", "quantize_scan", "codebook", "encode")
 DECOMPRESS_STAGES = ("decode_tables", "inflate", "reconstruct")
@@ -130,6 +131,17 @@ def _load() -> ctypes.CDLL:
     lib.dqz_tune.argtypes = [P, P, ctypes.POINTER(dqz_shape), ctypes.POINTER(dqz_params), ctypes.c_double,
                              ctypes.c_uint32, ctypes.POINTER(dqz_params), P]
     lib.dqz_tune.restype = i32
+    lib.dqz_stream_workspace.argtypes = [ctypes.POINTER(dqz_shape), ctypes.POINTER(dqz_params), u64,
+                                         ctypes.POINTER(u64), ctypes.POINTER(u64)]
+    lib.dqz_stream_workspace.restype = i32
+    lib.dqz_stream_compress.argtypes = [P, P, ctypes.POINTER(dqz_shape), ctypes.POINTER(dqz_params), u64, P, u64,
+                                        ctypes.POINTER(u64), P]
+    lib.dqz_stream_compress.restype = i32
+    lib.dqz_stream_info.argtypes = [P, u64, ctypes.POINTER(dqz_shape), ctypes.POINTER(ctypes.c_uint32),
+                                    ctypes.POINTER(ctypes.c_double), ctypes.POINTER(u64)]
+    lib.dqz_stream_info.restype = i32
+    lib.dqz_stream_decompress.argtypes = [P, P, u64, P, u64, P]
+    lib.dqz_stream_decompress.restype = i32
     lib.dqz_server_create.argtypes = [ctypes.c_int, ctypes.POINTER(dqz_server_config), ctypes.POINTER(P)]
     lib.dqz_server_create.restype = i32
     lib.dqz_server_destroy.argtypes = [P]
@@ -217,6 +229,36 @@ def dqz_compress_async_static(field_ptr: int, shape, params: dqz_params, archive
     return lib.dqz_compress_async_static(ctypes.c_void_p(field_ptr), ctypes.byref(s), ctypes.byref(params),
                                          ctypes.c_void_p(archive_ptr), int(archive_cap), ctypes.c_void_p(result_ptr),
                                          ctypes.c_void_p(stream.cuda_stream))
+
+
+def dqz_stream_workspace(shape, params: dqz_params, slab_bytes: int):
+    """(workspace bytes, largest container) of a streaming compression."""
+    ws, cmax = ctypes.c_uint64(0), ctypes.c_uint64(0)
+    s = make_shape(shape)
+    st = lib.dqz_stream_workspace(ctypes.byref(s), ctypes.byref(params), int(slab_bytes), ctypes.byref(ws),
+                                  ctypes.byref(cmax))
+    if st != DQZ_OK:
+        raise DqzError(st, f"dqz_stream_workspace: {lib.dqz_status_str(st).decode()}")
+    return int(ws.value), int(cmax.value)
+
+
+def _host_ptr(a) -> int:
+    """Address of a host buffer: an ndarray (its .ctypes) or a CPU torch tensor."""
+    if hasattr(a, "data_ptr"):
+        return a.data_ptr()
+    return a.ctypes.data
+
+
+def dqz_stream_info(container):
+    """(shape tuple, slabs, absolute bound, workspace bytes) of a container in host memory."""
+    s, n, eb, ws = dqz_shape(), ctypes.c_uint32(0), ctypes.c_double(0), ctypes.c_uint64(0)
+    nbytes = container.nbytes if hasattr(container, "nbytes") and not hasattr(container, "data_ptr") \
+        else container.numel() * container.element_size()
+    st = lib.dqz_stream_info(ctypes.c_void_p(_host_ptr(container)), int(nbytes), ctypes.byref(s), ctypes.byref(n),
+                             ctypes.byref(eb), ctypes.byref(ws))
+    if st != DQZ_OK:
+        raise DqzError(st, f"dqz_stream_info: {lib.dqz_status_str(st).decode()}")
+    return tuple(int(s.dims[i]) for i in range(s.ndim)), int(n.value), float(eb.value), int(ws.value)
 
 
 def dqz_decompress_bound(header: bytes) -> int:
@@ -396,6 +438,42 @@ class Context:
             out = torch.empty(shape, dtype=torch.float32, device=arc.device)
         st = self.dqz_decompress(arc.data_ptr(), arc.numel(), hdr, out.data_ptr(), out.numel(), stream)
         self._check(st, "dqz_decompress")
+        return out
+
+    # -- host path ----------------------------------------------------------------------
+    def stream_compress(self, x, eb: float, mode="valrel", slab_bytes: int = 256 << 20, out=None, radius: int = 0,
+                        sub_size: int = 0, chunk_subs: int = 0, stream=None):
+        """Compress a host field (C-contiguous float32 numpy array or CPU torch
+        tensor, pinned for overlapped copies) slab by slab into a container in
+        host memory; returns the container (a prefix view of `out` if given)."""
+        import numpy as np
+        params = make_params(eb, _mode(mode), radius, sub_size, chunk_subs)
+        shape = tuple(x.shape)
+        ws, cmax = dqz_stream_workspace(shape, params, slab_bytes)
+        self.dqz_ctx_reserve(ws)
+        if out is None:
+            out = np.empty(cmax, dtype=np.uint8)
+        cap = out.nbytes if not hasattr(out, "data_ptr") else out.numel()
+        nbytes = ctypes.c_uint64(0)
+        st = lib.dqz_stream_compress(self.handle, ctypes.c_void_p(_host_ptr(x)), ctypes.byref(make_shape(shape)),
+                                     ctypes.byref(params), int(slab_bytes), ctypes.c_void_p(_host_ptr(out)), int(cap),
+                                     ctypes.byref(nbytes), self._stream(stream))
+        self._check(st, "dqz_stream_compress")
+        return out[:int(nbytes.value)]
+
+    def stream_decompress(self, container, out=None, stream=None):
+        """Decompress a container from host memory into a host field (numpy
+        float32 unless `out`, a float32 host array or CPU tensor, is given)."""
+        import numpy as np
+        shape, _, _, ws = dqz_stream_info(container)
+        self.dqz_ctx_reserve(ws)
+        if out is None:
+            out = np.empty(shape, dtype=np.float32)
+        cap = out.size if not hasattr(out, "data_ptr") else out.numel()
+        nbytes = container.nbytes if not hasattr(container, "data_ptr") else container.numel()
+        st = lib.dqz_stream_decompress(self.handle, ctypes.c_void_p(_host_ptr(container)), int(nbytes),
+                                       ctypes.c_void_p(_host_ptr(out)), int(cap), self._stream(stream))
+        self._check(st, "dqz_stream_decompress")
         return out
 
     # -- batched calls ------------------------------------------------------------------

@@ -214,3 +214,67 @@ class BatchWorkload:
 
     def elements(self) -> int:
         return int(sum(int(np.prod(s)) for s in self.shapes))
+
+
+C5_RATES = (50, 100, 200, 500, 1000, 2000)
+C5_RATES_SATURATION = (5000, 10000, 20000)   # past the configured range, until the server saturates
+
+
+class ServeWorkload:
+    """Request pool and Poisson request streams for serving: ``pool`` fields,
+    a third each 1D (n log-uniform in [1e5, 1e8]), 2D (edges log-uniform in
+    [64, 3600]) and 3D (edges log-uniform in [32, 256]), cut at seeded offsets
+    from one Kolmogorov GRF per dimensionality (1D of 2^27 points, 2D 3600^2,
+    3D 256^3; spectra k^-5/3, k^-8/3, k^-11/3).  ``scale`` < 1 shrinks the
+    size ranges (tests)."""
+
+    def __init__(self, pool: int = 48, seed: int = 5, scale: float = 1.0, workers: int = 8):
+        rng = np.random.default_rng(seed)
+        self.seed = seed
+        self.workers = workers
+        def lu(lo, hi):
+            return float(np.exp(rng.uniform(np.log(lo), np.log(hi))))
+        s = scale
+        self.src_shape = {1: (max(1024, int((1 << 27) * s)),), 2: (max(64, int(3600 * s)),) * 2,
+                          3: (max(32, int(256 * s)),) * 3}
+        self.shapes = []
+        for k in range(pool):
+            nd = 1 + k % 3
+            if nd == 1:
+                sh = (max(1, int(lu(1e5 * s, 1e8 * s))),)
+            elif nd == 2:
+                sh = tuple(max(1, int(lu(64 * s, 3600 * s))) for _ in range(2))
+            else:
+                sh = tuple(max(1, int(lu(32 * s, 256 * s))) for _ in range(3))
+            self.shapes.append(tuple(min(a, b) for a, b in zip(sh, self.src_shape[nd])))
+        self.offsets = [tuple(int(o) for o in rng.integers(0, 1 << 30, size=len(sh))) for sh in self.shapes]
+        self._src = {}
+
+    def __len__(self):
+        return len(self.shapes)
+
+    def field(self, i: int) -> np.ndarray:
+        sh = self.shapes[i]
+        nd = len(sh)
+        if nd not in self._src:
+            slope = {1: -5.0 / 3.0, 2: -8.0 / 3.0, 3: -11.0 / 3.0}[nd]
+            self._src[nd] = grf(self.src_shape[nd], self.seed + 100 * nd, slope=slope,
+                                workers=self.workers).astype(np.float32)
+        box = self._src[nd]
+        for ax, (n, o) in enumerate(zip(sh, self.offsets[i])):
+            box = _wrap_take(box, ax, o, n)
+        return np.ascontiguousarray(box)
+
+    def release_sources(self):
+        self._src = {}
+
+    def requests(self, rate: float, n: int, seed: int):
+        """n requests arriving as a Poisson process of the given rate: arrays
+        of arrival times (s), kinds (0 compress, 1 decompress), pool indices
+        and value-range-relative error bounds (log-uniform in [1e-5, 1e-2])."""
+        rng = np.random.default_rng([self.seed, int(rate), seed])
+        t = np.cumsum(rng.exponential(1.0 / rate, size=n))
+        kind = rng.integers(0, 2, size=n)
+        idx = rng.integers(0, len(self.shapes), size=n)
+        eb = np.exp(rng.uniform(np.log(1e-5), np.log(1e-2), size=n))
+        return t, kind, idx, eb

@@ -63,3 +63,53 @@ def stream_bits(words: np.ndarray, total_bits: int) -> np.ndarray:
     w = np.asarray(words, dtype=np.uint32)
     bits = ((w[:, None] >> np.arange(31, -1, -1, dtype=np.uint32)[None, :]) & 1).astype(np.uint8)
     return bits.ravel()[:total_bits]
+
+
+# -- streaming containers ('DQZS'): 128-byte header, (slabs + 1) u64 offsets,
+#    slab archives each 8-byte aligned --------------------------------------
+STREAM_MAGIC = 0x535A5144
+BLOCK_EDGE = {1: 32, 2: 16, 3: 8}
+
+
+def slab_rows(shape, slab_bytes):
+    """Slab extent along the slowest axis for a slab size in bytes."""
+    row = int(np.prod(shape[1:])) if len(shape) > 1 else 1
+    e = BLOCK_EDGE[len(shape)]
+    rows = slab_bytes // (4 * row) if row else shape[0]
+    rows = rows // e * e
+    return int(min(max(rows, e), shape[0]))
+
+
+def container_from_oracle(x, eb, mode, slab_bytes, radius=512, sub_size=128, chunk_subs=64):
+    """The container the streaming compression must write, built from the
+    oracle's archives of each slab (absolute bound: eb, or eb times the whole
+    field's finite range in the value-range-relative mode)."""
+    import oracle
+    x = np.ascontiguousarray(x, dtype=np.float32)
+    shape = x.shape
+    vmin, vmax, nfin = oracle.value_range(x)
+    eb_abs = oracle.eb_params(mode, eb, vmin, vmax, nfin)[0]
+    rows = slab_rows(shape, slab_bytes) if x.size else 0
+    n_slabs = -(-shape[0] // rows) if x.size else 0
+    arcs = [oracle.compress(x[k * rows:(k + 1) * rows], eb_abs, oracle.EB_ABS, radius=radius, sub_size=sub_size,
+                            chunk_subs=chunk_subs) for k in range(n_slabs)]
+    off = _a8(128 + 8 * (n_slabs + 1))
+    offsets = []
+    for a in arcs:
+        offsets.append(off)
+        off = _a8(off + a.size)
+    total = offsets[-1] + arcs[-1].size if arcs else _a8(128 + 8)
+    offsets.append(total)
+    dims = [1] * (3 - len(shape)) + list(shape)
+    h = bytearray(128)
+    struct.pack_into("<IHBB3QQII", h, 0, STREAM_MAGIC, 1, len(shape), mode, *dims, rows, n_slabs, radius)
+    struct.pack_into("<dd", h, 48, eb, eb_abs)
+    if mode == 1 and nfin:
+        struct.pack_into("<ff", h, 64, vmin, vmax)
+    struct.pack_into("<QQII", h, 72, x.size, total, sub_size, chunk_subs)
+    out = np.zeros(total, np.uint8)
+    out[:128] = np.frombuffer(bytes(h), np.uint8)
+    out[128:128 + 8 * len(offsets)] = np.frombuffer(np.array(offsets, np.uint64).tobytes(), np.uint8)
+    for o, a in zip(offsets, arcs):
+        out[o:o + a.size] = a
+    return out, arcs, eb_abs, rows

@@ -154,3 +154,33 @@ def test_null_context_arguments(dqz):
     p = dqz.make_params(1e-4)
     assert dqz.lib.dqz_compress_async(None, None, ctypes.byref(s), ctypes.byref(p), None, 0, None, None) == dqz.DQZ_EINVAL
     assert dqz.lib.dqz_decompress_async(None, None, 0, None, None, 0, None, None) == dqz.DQZ_EINVAL
+
+
+def test_stream_info_parses_containers_and_rejects_damage(dqz, orc):
+    """dqz_stream_info (host only) on containers built from the oracle's slab
+    archives: shape, slab count and absolute bound; damaged headers, offsets
+    and slab shapes are rejected."""
+    import archive_util as au
+    from synth import fields
+    x = fields.hurricane3d((37, 20, 30), seed=3)
+    c, arcs, eb_abs, rows = au.container_from_oracle(x, 1e-3, 1, slab_bytes=16 * 20 * 30 * 4)
+    assert rows == 16 and len(arcs) == 3
+    shape, n, eb, ws = dqz.dqz_stream_info(c)
+    assert shape == x.shape and n == 3 and eb == eb_abs and ws > 0
+    for off, val in ((0, 0x00), (6, 4), (32, 3), (40, 9), (80, 1)):
+        bad = c.copy()
+        bad[off] ^= val if val else 0xFF
+        with pytest.raises(dqz.DqzError) as e:
+            dqz.dqz_stream_info(bad)
+        assert e.value.status == dqz.DQZ_ECORRUPT
+    bad = c.copy()
+    bad[128 + 8] ^= 8                       # slab 1 starts elsewhere
+    with pytest.raises(dqz.DqzError):
+        dqz.dqz_stream_info(bad)
+    bad = c.copy()
+    o1 = int(np.frombuffer(c[136:144].tobytes(), np.uint64)[0])
+    bad[o1 + 8] ^= 1                        # slab 1's archive claims another extent
+    with pytest.raises(dqz.DqzError):
+        dqz.dqz_stream_info(bad)
+    with pytest.raises(dqz.DqzError):
+        dqz.dqz_stream_info(c[:-1])

@@ -131,14 +131,17 @@ def test_admission_by_footprint(case):
 
 
 def test_overflow_runs_again_with_reported_workspace():
-    """Every element an outlier: the exception records overflow the
-    request's first workspace; the server runs it again with the size the
-    device reported and the archive is the oracle's."""
+    """Every element an outlier and most of them patches too (values near
+    2^27 quantization steps: random deltas far outside the cap, and d° above
+    2^24 is not exact in fp32): about two exception records per element
+    overflow the request's first workspace (room for one per element); the
+    server runs it again with the size the device reported and the archive
+    is the oracle's."""
     import torch
     import oracle
     from paper_2007_09625_amd import dqz
     rng = np.random.default_rng(31)
-    x = (rng.standard_normal(20000) * 1e4).astype(np.float32)
+    x = rng.uniform(-2.6e5, 2.6e5, 20000).astype(np.float32)
     t = torch.from_numpy(x).cuda()
     sv = dqz.Server(0, slots=2, workspace=64 << 20, budget=1 << 30)
     bound, _ = dqz.dqz_compress_bound(tuple(x.shape), dqz.make_params(1e-3, dqz.DQZ_EB_ABS))
@@ -146,8 +149,11 @@ def test_overflow_runs_again_with_reported_workspace():
     c = sv.wait(sv.submit_compress(t, 1e-3, out, mode="abs"))
     stats = sv.stats()
     sv.close()
-    assert c.status == 0 and stats["retried"] >= 1
     ref = oracle.compress(x, 1e-3, oracle.EB_ABS)
+    import archive_util as au
+    h = au.header(ref)
+    assert h["n_out"] + h["n_patch"] > x.size          # more records than the first workspace holds
+    assert c.status == 0 and stats["retried"] >= 1
     assert np.array_equal(out[:c.output_bytes].cpu().numpy(), ref)
 
 
