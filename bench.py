@@ -44,6 +44,9 @@ WORKLOADS = {
     "c3": "1D 280,953,867 fp32 particle coordinates, sorted U[0,256) + N(0,0.05), 4096-blocks shuffled",
     "c4": "64 uneven 3D fp32 fields (edges U[64,512], one 512^3 log-normal sigma=2), per-field valrel eb "
           "in {1e-2,1e-3,1e-4}: batched against plain per-field calls",
+    "host": "host path: the 1D 280,953,867 and 3D 100x500x500 fields in pinned host memory, compressed slab by slab "
+            "into a host container and back (copies overlapped with the kernels), and the device path plus the "
+            "archive's copy to the host (overall)",
     "c5": "serving: Poisson streams (50-2000 req/s) of mixed compress/decompress requests over 1D (1e5-1e8), "
           "2D (64..3600 edges) and 3D (32..256 edges) Kolmogorov GRF inputs, valrel eb log-uniform 1e-5..1e-2",
 }
@@ -146,6 +149,8 @@ def main() -> int:
         return bench_batch(args)
     if args.workload == "c5":
         return bench_serve(args)
+    if args.workload == "host":
+        return bench_host(args)
     desc = WORKLOADS[args.workload]
     x_host = fields.workload(args.workload)
     n = x_host.size
@@ -646,6 +651,128 @@ def bench_serve(args) -> int:
                    "hbm_budget_GB": 64, "workspace_arena_GB": 4, "decompress_archives_eb": 1e-3},
         "sweep": sweep,
         "generation_s": round(gen_s, 1),
+    }
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+def bench_host(args) -> int:
+    """Host path.  For each field: (a) overall, the device path plus the
+    archive's trip over the host link (compress + archive to pinned host
+    memory; archive from the host + decompress; also with the decompressed
+    field copied to the host), warm, one call at a time,
+    (b) streaming from pinned host memory to a host container and back with
+    256 MB slabs (the field need not fit the device; here it does, for the
+    comparison).  Original bytes / wall time, median of the repetitions.
+    Prints one JSON line."""
+    import numpy as np
+    import torch
+
+    from paper_2007_09625_amd import dqz
+    from synth import fields
+
+    dev = torch.device("cuda:0")
+    reps = max(3, min(args.steps, 7))
+    out = {}
+    for name in ("c3", "c2"):
+        x_host = fields.workload(name)
+        n = x_host.size
+        orig = 4.0 * n
+        xp = torch.from_numpy(x_host).pin_memory()
+        x = xp.to(dev)
+        ctx = dqz.Context(0)
+        params = dqz.make_params(args.eb, dqz.DQZ_EB_VALREL)
+        bound, ws = dqz.dqz_compress_bound(tuple(x.shape), params)
+        ctx.dqz_ctx_reserve(ws)
+        arc = torch.empty(bound, dtype=torch.uint8, device=dev)
+        harc = torch.empty(bound, dtype=torch.uint8).pin_memory()
+        y = torch.empty_like(x)
+        yh = torch.empty_like(xp).pin_memory()
+        stream = torch.cuda.current_stream(dev)
+        tc, tcd, td, tdd, tdh = [], [], [], [], []
+        for r in range(reps + 1):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            st, nb, hdr = ctx.dqz_compress(x.data_ptr(), tuple(x.shape), params, arc.data_ptr(), bound, stream)
+            ctx._check(st, "dqz_compress")
+            t1 = time.perf_counter()
+            harc[:nb].copy_(arc[:nb])
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            ctx.dqz_ctx_reserve(dqz.dqz_decompress_bound(hdr))
+            t3 = time.perf_counter()
+            arc[:nb].copy_(harc[:nb])
+            torch.cuda.synchronize()
+            t4 = time.perf_counter()
+            st = ctx.dqz_decompress(arc.data_ptr(), nb, hdr, y.data_ptr(), y.numel(), stream)
+            ctx._check(st, "dqz_decompress")
+            t5 = time.perf_counter()
+            yh.copy_(y)
+            torch.cuda.synchronize()
+            t6 = time.perf_counter()
+            if r:
+                tcd.append(t1 - t)       # device path
+                tc.append(t2 - t)        # + archive to the host
+                td.append(t5 - t4)       # device path
+                tdd.append(t5 - t3)      # archive from the host + device path
+                tdh.append(t6 - t3)      # ... + field to the host
+        slab = 256 << 20
+        sws, cmax = dqz.dqz_stream_workspace(tuple(x.shape), params, slab)
+        ctx.dqz_ctx_reserve(sws)
+        cbuf = torch.empty(cmax, dtype=torch.uint8).pin_memory()
+        ts, tsd = [], []
+        c = None
+        for r in range(reps + 1):
+            t = time.perf_counter()
+            c = ctx.stream_compress(xp, args.eb, "valrel", slab_bytes=slab, out=cbuf)
+            t1 = time.perf_counter()
+            ctx.dqz_ctx_reserve(dqz.dqz_stream_info(c)[3])
+            t2 = time.perf_counter()
+            ctx.stream_decompress(c, out=yh)
+            t3 = time.perf_counter()
+            if r:
+                ts.append(t1 - t)
+                tsd.append(t3 - t2)
+        shape, n_slabs, eb_abs, _ = dqz.dqz_stream_info(c)
+        err = float((xp.double() - yh.double()).abs().max())
+        assert err <= eb_abs, f"{name}: error bound violated by the host path"
+        med = lambda v: sorted(v)[len(v) // 2]
+        out[name] = {
+            "elements": n, "archive_bytes": nb, "container_bytes": int(c.numel()), "slabs": n_slabs,
+            "device_compress_GBps": round(orig / med(tcd) / 1e9, 2),
+            "overall_compress_GBps": round(orig / med(tc) / 1e9, 2),
+            "device_decompress_GBps": round(orig / med(td) / 1e9, 2),
+            "overall_decompress_GBps": round(orig / med(tdd) / 1e9, 2),
+            "decompress_to_host_GBps": round(orig / med(tdh) / 1e9, 2),
+            "stream_compress_GBps": round(orig / med(ts) / 1e9, 2),
+            "stream_decompress_GBps": round(orig / med(tsd) / 1e9, 2),
+            "max_err_over_eb": round(err / eb_abs, 6),
+        }
+        print(f"{name}: {out[name]}", file=sys.stderr, flush=True)
+        del ctx, x, xp, arc, harc, y, yh, cbuf
+        torch.cuda.empty_cache()
+    # pinned host <-> device copy bandwidth for context
+    a = torch.empty(1 << 28, dtype=torch.float32).pin_memory()
+    d = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    bw = {}
+    for direction in ("h2d", "d2h"):
+        ts = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            (d.copy_(a) if direction == "h2d" else a.copy_(d))
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t)
+        bw[direction] = round(4.0 * a.numel() / sorted(ts)[1] / 1e9, 2)
+    result = {
+        "metric": "host path: overall (device path + archive copy) and streamed host-to-host compress/decompress GB/s",
+        "value": out["c3"]["stream_compress_GBps"], "unit": "GB/s", "n_gpus": 1, "steps": reps, "warmup": 1,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOADS["host"], "eb_valrel": args.eb, "slab_bytes": 256 << 20,
+                   "value_definition": "original bytes / wall time of the streamed compression of the 1D field "
+                                       "from pinned host memory into a pinned host container (median)"},
+        "fields": out, "pinned_copy_GBps": bw,
     }
     print(json.dumps(result), flush=True)
     return 0
