@@ -9,7 +9,7 @@ the HIP implementation.
 Functions follow the paper's steps:
   value_range / eb_params   -- value-range-relative error bound (footnote, Sec. 3.2.2)
   prequant                  -- prequantization (Sec. 3.1.2, Algorithm 2)
-  lorenzo_delta             -- 1-layer Lorenzo + zero padding layer (Sec. 3.1.1-3.1.2)
+  lorenzo_delta             -- 1- and 2-layer Lorenzo + zero padding layer (Sec. 3.1.1-3.1.2)
   lorenzo_reconstruct       -- cascading reconstruction (Algorithm 2, decompression)
   huffman_lengths           -- Huffman tree code lengths (Sec. 3.2.2)
   canonical_codes           -- canonical codebook (Sec. 3.2.3)
@@ -74,6 +74,9 @@ def _load():
     lib.orc_huffman_lengths.argtypes = [P, u32, P]
     lib.orc_canonical_codes.argtypes = [P, u32, P]
     lib.orc_compress.argtypes = [P, i32, P, f64, i32, u32, u32, u32, P, u64, P]
+    lib.orc_compress_layers.argtypes = [P, i32, P, f64, i32, u32, u32, u32, i32, P, u64, P]
+    lib.orc_lorenzo_delta_n.argtypes = [P, i32, P, i32, P]
+    lib.orc_lorenzo_reconstruct_n.argtypes = [P, i32, P, i32, P]
     lib.orc_compressed_size.argtypes = [P, i32, P, f64, i32, u32, u32, u32, P]
     lib.orc_decompress.argtypes = [P, u64, P, u64]
     lib.orc_stages.argtypes = [P, i32, P, f64, i32, u32, P, P, P, P]
@@ -117,20 +120,28 @@ def prequant(x: np.ndarray, r) -> np.ndarray:
     return out
 
 
-def lorenzo_delta(dq: np.ndarray) -> np.ndarray:
-    """delta = d° - p° per element (row-major, same shape), ndim = dq.ndim."""
+def lorenzo_delta(dq: np.ndarray, layers: int = 1) -> np.ndarray:
+    """delta = d° - p° per element (row-major, same shape), ndim = dq.ndim,
+    with the ``layers``-layer predictor."""
     dq = np.ascontiguousarray(dq, dtype=np.int32)
     out = np.empty(dq.shape, np.int32)
-    st = _load().orc_lorenzo_delta(_ptr(dq), dq.ndim, _ptr(_dims(dq.shape)), _ptr(out))
+    if layers == 1:
+        st = _load().orc_lorenzo_delta(_ptr(dq), dq.ndim, _ptr(_dims(dq.shape)), _ptr(out))
+    else:
+        st = _load().orc_lorenzo_delta_n(_ptr(dq), dq.ndim, _ptr(_dims(dq.shape)), int(layers), _ptr(out))
     if st != OK:
         raise OracleError(st, "lorenzo_delta")
     return out
 
 
-def lorenzo_reconstruct(delta: np.ndarray) -> np.ndarray:
+def lorenzo_reconstruct(delta: np.ndarray, layers: int = 1) -> np.ndarray:
     delta = np.ascontiguousarray(delta, dtype=np.int32)
     out = np.empty(delta.shape, np.int32)
-    st = _load().orc_lorenzo_reconstruct(_ptr(delta), delta.ndim, _ptr(_dims(delta.shape)), _ptr(out))
+    if layers == 1:
+        st = _load().orc_lorenzo_reconstruct(_ptr(delta), delta.ndim, _ptr(_dims(delta.shape)), _ptr(out))
+    else:
+        st = _load().orc_lorenzo_reconstruct_n(_ptr(delta), delta.ndim, _ptr(_dims(delta.shape)), int(layers),
+                                               _ptr(out))
     if st != OK:
         raise OracleError(st, "lorenzo_reconstruct")
     return out
@@ -155,21 +166,28 @@ def canonical_codes(lengths) -> np.ndarray:
 
 
 def compress(x: np.ndarray, eb: float, mode: int = EB_VALREL, radius: int = 512,
-             sub_size: int = 128, chunk_subs: int = 64) -> np.ndarray:
-    """Archive bytes (uint8) of ``x`` (float32, 1-3 dims)."""
+             sub_size: int = 128, chunk_subs: int = 64, layers: int = 1) -> np.ndarray:
+    """Archive bytes (uint8) of ``x`` (float32, 1-3 dims); ``layers`` = 2
+    takes the 2-layer Lorenzo predictor (recorded in the header)."""
     lib = _load()
     x = np.ascontiguousarray(x, dtype=np.float32)
     if x.ndim < 1 or x.ndim > 3:
         raise OracleError(EINVAL, "compress: ndim")
     dims = _dims(x.shape)
     size = np.zeros(1, np.uint64)
-    st = lib.orc_compressed_size(_ptr(x), x.ndim, _ptr(dims), float(eb), int(mode), radius, sub_size,
-                                 chunk_subs, _ptr(size))
+    if layers == 1:
+        st = lib.orc_compressed_size(_ptr(x), x.ndim, _ptr(dims), float(eb), int(mode), radius, sub_size,
+                                     chunk_subs, _ptr(size))
+    else:
+        dummy = np.zeros(1, np.uint8)
+        st = lib.orc_compress_layers(_ptr(x), x.ndim, _ptr(dims), float(eb), int(mode), radius, sub_size,
+                                     chunk_subs, int(layers), _ptr(dummy), 0, _ptr(size))
+        st = OK if st == ETOOSMALL else st
     if st != OK:
         raise OracleError(st, "compress (size)")
     out = np.zeros(int(size[0]), np.uint8)
-    st = lib.orc_compress(_ptr(x), x.ndim, _ptr(dims), float(eb), int(mode), radius, sub_size,
-                          chunk_subs, _ptr(out), out.size, _ptr(size))
+    st = lib.orc_compress_layers(_ptr(x), x.ndim, _ptr(dims), float(eb), int(mode), radius, sub_size,
+                                 chunk_subs, int(layers), _ptr(out), out.size, _ptr(size))
     if st != OK:
         raise OracleError(st, "compress")
     return out

@@ -15,7 +15,9 @@
  *   - prequantization d° = round(d / 2eb)      (Sec. 3.1.2, Algorithm 2)
  *   - chunking with a zero padding layer       (Sec. 3.1.1)
  *   - 1-layer Lorenzo predictor                (Sec. 3.1.2, "Lorenzo predictor
- *                                               with binomial coefficients")
+ *                                               with binomial coefficients"),
+ *     and its 2-layer form as an archive option (the same paragraph's
+ *     generalized n-layer predictor)
  *   - postquantization delta = d° - p°, cap    (Sec. 3.1.2, Algorithm 2)
  *   - outliers recorded verbatim               (Algorithm 2)
  *   - rehearsal + verbatim fallback (patches)  (Algorithm 1's watchdog)
@@ -298,6 +300,73 @@ int orc_lorenzo_reconstruct(const int32_t *delta, int ndim, const uint64_t *dims
 }
 
 /* ------------------------------------------------------------------ */
+/* Step 3, n layers: the generalized Lorenzo predictor with binomial      */
+/* coefficients (Sec. 3.1.2), in the same sign reading as the 1-layer     */
+/* predictor above: the neighbour k in {0..n}^3 \ {0} steps back has      */
+/* coefficient (-1)^(|k|+1) C(n,kz) C(n,ky) C(n,kx), which sums to 1 (unit */
+/* weight, as the paper requires).  A neighbour outside the point's own    */
+/* block (more steps back than the point lies into its block along some   */
+/* axis) reads the padding value 0.  Only n = 2 is used with this form;   */
+/* n = 1 keeps the explicit predictor above.                              */
+/* ------------------------------------------------------------------ */
+#define ORC_MAX_LAYERS 2
+
+static int64_t binomial(int n, int k)
+{
+    int64_t c = 1;
+    for (int i = 1; i <= k; i++) c = c * (n - k + i) / i;
+    return c;
+}
+
+static int64_t lorenzo_predict_n(const int32_t *dq, const geom_t *g, uint64_t z, uint64_t y, uint64_t x, int n)
+{
+    int64_t p = 0;
+    for (int kz = 0; kz <= n; kz++)
+        for (int ky = 0; ky <= n; ky++)
+            for (int kx = 0; kx <= n; kx++) {
+                if (kz == 0 && ky == 0 && kx == 0) continue;
+                /* the neighbour must lie in the same block */
+                if ((uint64_t)kz > z % g->b[0] || (uint64_t)ky > y % g->b[1] || (uint64_t)kx > x % g->b[2])
+                    continue;
+                int64_t v = dq[((z - (uint64_t)kz) * g->n[1] + (y - (uint64_t)ky)) * g->n[2] + (x - (uint64_t)kx)];
+                int64_t c = binomial(n, kz) * binomial(n, ky) * binomial(n, kx);
+                p += ((kz + ky + kx) % 2 == 1) ? c * v : -c * v; /* (-1)^(|k|+1) */
+            }
+    return p;
+}
+
+int orc_lorenzo_delta_n(const int32_t *dq, int ndim, const uint64_t *dims, int layers, int32_t *delta)
+{
+    geom_t g;
+    if (layers < 1 || layers > ORC_MAX_LAYERS) return ORC_EINVAL;
+    if (layers == 1) return orc_lorenzo_delta(dq, ndim, dims, delta);
+    if (make_geom(ndim, dims, &g) != ORC_OK) return ORC_EINVAL;
+    for (uint64_t z = 0; z < g.n[0]; z++)
+        for (uint64_t y = 0; y < g.n[1]; y++)
+            for (uint64_t x = 0; x < g.n[2]; x++) {
+                uint64_t i = (z * g.n[1] + y) * g.n[2] + x;
+                delta[i] = wrap32((int64_t)dq[i] - lorenzo_predict_n(dq, &g, z, y, x, layers));
+            }
+    return ORC_OK;
+}
+
+/* The cascading reconstruction of Algorithm 2 with the n-layer predictor. */
+int orc_lorenzo_reconstruct_n(const int32_t *delta, int ndim, const uint64_t *dims, int layers, int32_t *dq)
+{
+    geom_t g;
+    if (layers < 1 || layers > ORC_MAX_LAYERS) return ORC_EINVAL;
+    if (layers == 1) return orc_lorenzo_reconstruct(delta, ndim, dims, dq);
+    if (make_geom(ndim, dims, &g) != ORC_OK) return ORC_EINVAL;
+    for (uint64_t z = 0; z < g.n[0]; z++)
+        for (uint64_t y = 0; y < g.n[1]; y++)
+            for (uint64_t x = 0; x < g.n[2]; x++) {
+                uint64_t i = (z * g.n[1] + y) * g.n[2] + x;
+                dq[i] = wrap32((int64_t)delta[i] + lorenzo_predict_n(dq, &g, z, y, x, layers));
+            }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
 /* Step 5: Huffman code lengths (Sec. 3.2.2).  Reading of the tie rules: */
 /* leaves with nonzero frequency sorted by (frequency, symbol); the      */
 /* classic two-queue construction (sorted leaves, FIFO of merged nodes); */
@@ -451,6 +520,7 @@ enum {
     H_RADIUS = 44, H_EBPARAM = 48, H_EBABS = 56, H_H = 64, H_R = 68, H_VMIN = 72,
     H_VMAX = 76, H_NELEM = 80, H_NOUT = 88, H_NPATCH = 92, H_TOTBITS = 96,
     H_SUBSIZE = 104, H_CHUNKSUBS = 108, H_NCHUNKS = 112, H_MAXLEN = 116,
+    H_LAYERS = 117, /* Lorenzo layers - 1 (0: the 1-layer predictor) */
     H_ARCBYTES = 120
 };
 
@@ -506,12 +576,13 @@ static int check_params(uint32_t radius, uint32_t sub, uint32_t csubs)
 /* ------------------------------------------------------------------ */
 /* Compression: the whole pipeline, in the paper's order.              */
 /* ------------------------------------------------------------------ */
-int orc_compress(const float *xin, int ndim, const uint64_t *dims, double eb, int eb_mode,
-                 uint32_t radius, uint32_t sub, uint32_t csubs,
-                 uint8_t *out, uint64_t cap, uint64_t *out_bytes)
+int orc_compress_layers(const float *xin, int ndim, const uint64_t *dims, double eb, int eb_mode,
+                        uint32_t radius, uint32_t sub, uint32_t csubs, int layers,
+                        uint8_t *out, uint64_t cap, uint64_t *out_bytes)
 {
     geom_t g;
     int st;
+    if (layers < 1 || layers > ORC_MAX_LAYERS) return ORC_EINVAL;
     if ((st = make_geom(ndim, dims, &g)) != ORC_OK) return st;
     if ((st = check_params(radius, sub, csubs)) != ORC_OK) return st;
     if (g.padded >= (1ull << 31)) return ORC_EUNSUPPORTED;
@@ -540,7 +611,7 @@ int orc_compress(const float *xin, int ndim, const uint64_t *dims, double eb, in
     /* prequantization (whole field first: Algorithm 2's barrier) */
     orc_prequant(xin, N, r, dq);
     /* prediction + postquantization delta */
-    orc_lorenzo_delta(dq, ndim, dims, delta);
+    orc_lorenzo_delta_n(dq, ndim, dims, layers, delta);
 
     /* postquantization into codes, outliers and patches, in stream order */
     uint64_t n_exc = 0, n_out = 0, n_patch = 0, ns = 0;
@@ -604,6 +675,7 @@ int orc_compress(const float *xin, int ndim, const uint64_t *dims, double eb, in
     put_u32(out, H_CHUNKSUBS, csubs);
     put_u32(out, H_NCHUNKS, (uint32_t)L.n_chunks);
     put_u8(out, H_MAXLEN, (uint8_t)maxlen);
+    put_u8(out, H_LAYERS, (uint8_t)(layers - 1));
     put_u64(out, H_ARCBYTES, L.end);
 
     /* lengths */
@@ -637,6 +709,13 @@ int orc_compress(const float *xin, int ndim, const uint64_t *dims, double eb, in
 done:
     free(dq); free(delta); free(q); free(posv); free(exc); free(freq); free(len); free(code);
     return st;
+}
+
+int orc_compress(const float *xin, int ndim, const uint64_t *dims, double eb, int eb_mode,
+                 uint32_t radius, uint32_t sub, uint32_t csubs,
+                 uint8_t *out, uint64_t cap, uint64_t *out_bytes)
+{
+    return orc_compress_layers(xin, ndim, dims, eb, eb_mode, radius, sub, csubs, 1, out, cap, out_bytes);
 }
 
 /* Size of the archive orc_compress would write (runs the whole method). */
@@ -682,6 +761,8 @@ int orc_decompress(const uint8_t *arc, uint64_t nbytes, float *out, uint64_t cap
     uint64_t n_out = get_u32(arc, H_NOUT), n_patch = get_u32(arc, H_NPATCH);
     uint64_t total_bits = get_u64(arc, H_TOTBITS);
     int maxlen_hdr = get_u8(arc, H_MAXLEN);
+    int layers = get_u8(arc, H_LAYERS) + 1;
+    if (layers > ORC_MAX_LAYERS) return ORC_ECORRUPT;
     if (n_out > g.nelem || n_patch > g.nelem) return ORC_ECORRUPT;
     if (total_bits > 64ull * g.nelem) return ORC_ECORRUPT;
     layout_t L;
@@ -782,7 +863,7 @@ int orc_decompress(const uint8_t *arc, uint64_t nbytes, float *out, uint64_t cap
     }
     /* reversed dual-quantization: cascading Lorenzo reconstruction, then
      * d = d° * 2eb */
-    orc_lorenzo_reconstruct(delta, ndim, dims, dq);
+    orc_lorenzo_reconstruct_n(delta, ndim, dims, layers, dq);
     for (uint64_t i = 0; i < N; i++) out[i] = dequant(dq[i], h);
     /* patches: verbatim values */
     {

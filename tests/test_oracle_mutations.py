@@ -25,6 +25,9 @@ MUTATIONS = [
     ("bit order", "v |= 1u << (31 - (w->nbits & 31));", "v |= 1u << (w->nbits & 31);"),
     ("valrel scale", "e = eb * range;", "e = eb * range * 0.5;"),
     ("code bit order", "for (int i = len - 1; i >= 0; i--) bw_put_bit", "for (int i = 0; i < len; i++) bw_put_bit"),
+    ("2-layer sign", "p += ((kz + ky + kx) % 2 == 1) ? c * v : -c * v;", "p += ((kz + ky + kx) % 2 == 0) ? c * v : -c * v;"),
+    ("2-layer padding", "if ((uint64_t)kz > z % g->b[0] ||", "if ((uint64_t)kz >= z % g->b[0] ||"),
+    ("2-layer binomial", "for (int i = 1; i <= k; i++) c = c * (n - k + i) / i;", "for (int i = 1; i < k; i++) c = c * (n - k + i) / i;"),
 ]
 
 

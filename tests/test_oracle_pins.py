@@ -123,6 +123,94 @@ def test_lorenzo_inverse_equals_prefix_sums_with_wraparound(orc, shape, block):
 
 
 # --------------------------------------------------------------------------
+# 2-layer Lorenzo predictor (the generalized predictor of Sec. 3.1.2, n = 2)
+# --------------------------------------------------------------------------
+
+def test_lorenzo2_worked_examples(orc):
+    g = load_golden("lorenzo2_worked.txt")
+    assert orc.lorenzo_delta(np.array(g["dq_1d"], np.int32), 2).tolist() == g["delta_1d"]
+    d2 = np.array(g["dq_2d"], np.int32).reshape(3, 3)
+    assert orc.lorenzo_delta(d2, 2).ravel().tolist() == g["delta_2d"]
+    d3 = np.array(g["dq_3d"], np.int32).reshape(2, 2, 2)
+    assert orc.lorenzo_delta(d3, 2).ravel().tolist() == g["delta_3d"]
+
+
+@pytest.mark.parametrize("shape,block", [((70,), (32,)), ((37, 21), (16, 16)), ((11, 19, 13), (8, 8, 8))])
+def test_lorenzo2_constant_field_closed_form(orc, shape, block):
+    """Unit weight: a constant c gives delta = c * prod_axes a(i mod b) with
+    a(0) = 1, a(1) = -1, a(>=2) = 0 ((1 - S)^2 of a step that starts at the
+    block's padding)."""
+    c = 777
+    delta = orc.lorenzo_delta(np.full(shape, c, np.int32), 2)
+    want = np.full(shape, c, np.int64)
+    for ax, b in enumerate(block):
+        i = np.arange(shape[ax]) % b
+        a = np.where(i == 0, 1, np.where(i == 1, -1, 0))
+        sh = [1] * len(shape)
+        sh[ax] = shape[ax]
+        want = want * a.reshape(sh)
+    assert np.array_equal(delta.astype(np.int64), want)
+
+
+def test_lorenzo2_annihilates_fields_linear_along_an_axis(orc):
+    """(1 - S)^2 along an axis annihilates anything linear along it, whatever
+    the dependence on the other axes: delta = 0 at points two or more steps
+    into the block along that axis."""
+    rng = np.random.default_rng(21)
+    x = np.arange(90)
+    d1 = (17 + 5 * x).astype(np.int32)
+    assert np.all(orc.lorenzo_delta(d1, 2)[x % 32 >= 2] == 0)
+    ny, nx = 33, 40
+    g, h = rng.integers(-99, 99, ny), rng.integers(-99, 99, ny)
+    d2 = (g[:, None] + h[:, None] * np.arange(nx)[None, :]).astype(np.int32)     # linear in x
+    assert np.all(orc.lorenzo_delta(d2, 2)[:, np.arange(nx) % 16 >= 2] == 0)
+    d2t = np.ascontiguousarray(d2.T[:ny, :]) if nx >= ny else None                   # linear in y
+    assert np.all(orc.lorenzo_delta(d2t, 2)[np.arange(ny) % 16 >= 2, :] == 0)
+    nz, ny3, nx3 = 19, 10, 11
+    gg, hh = rng.integers(-99, 99, (ny3, nx3)), rng.integers(-99, 99, (ny3, nx3))
+    d3 = (gg[None] + hh[None] * np.arange(nz)[:, None, None]).astype(np.int32)      # linear in z
+    assert np.all(orc.lorenzo_delta(d3, 2)[np.arange(nz) % 8 >= 2] == 0)
+    assert np.any(orc.lorenzo_delta(d3, 2) != 0)
+
+
+@pytest.mark.parametrize("shape", [(100,), (35, 18), (9, 17, 10)])
+def test_lorenzo2_is_the_1layer_map_twice(orc, shape):
+    """The binomial 2-layer form equals the explicit 1-layer predictor's
+    delta map applied twice (each with the zero padding), mod 2^32."""
+    rng = np.random.default_rng(len(shape))
+    d = rng.integers(-2**31, 2**31, size=shape, dtype=np.int64).astype(np.int32)
+    assert np.array_equal(orc.lorenzo_delta(d, 2), orc.lorenzo_delta(orc.lorenzo_delta(d)))
+
+
+@pytest.mark.parametrize("shape,block", [((100,), (32,)), ((35, 18), (16, 16)), ((9, 17, 10), (8, 8, 8))])
+def test_lorenzo2_inverse_is_prefix_sums_twice_with_wraparound(orc, shape, block):
+    rng = np.random.default_rng(13)
+    dq = rng.integers(-2**31, 2**31, size=shape, dtype=np.int64).astype(np.int32)
+    delta = orc.lorenzo_delta(dq, 2)
+    assert np.array_equal(_blockwise_cumsum_inverse(_blockwise_cumsum_inverse(delta, block), block), dq)
+    assert np.array_equal(orc.lorenzo_reconstruct(delta, 2), dq)
+
+
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+def test_compress2_round_trip_within_bound(orc, ndim):
+    """Whole pipeline with the 2-layer predictor: the header records it, the
+    field comes back within the bound, and on a smooth field most points
+    need no outlier."""
+    from synth import fields
+    x = {1: lambda: fields.particles1d(20000, seed=1, shuffle_block=256),
+         2: lambda: fields.fourier2d((60, 90), seed=2),
+         3: lambda: fields.hurricane3d((20, 24, 28), seed=3)}[ndim]()
+    arc = orc.compress(x, 1e-3, orc.EB_VALREL, layers=2)
+    assert int(arc[117]) == 1
+    assert int(orc.compress(x, 1e-3, orc.EB_VALREL)[117]) == 0
+    y = orc.decompress(arc)
+    eb_abs = au.header(arc)["eb_abs"]
+    assert np.all(np.abs(x.astype(np.float64) - y.astype(np.float64)) <= eb_abs)
+    # same prequantized values as the 1-layer archive: the floats agree
+    assert np.array_equal(y.view(np.uint32), orc.decompress(orc.compress(x, 1e-3, orc.EB_VALREL)).view(np.uint32))
+
+
+# --------------------------------------------------------------------------
 # Prequantization (Sec. 3.1.2) and the error bound
 # --------------------------------------------------------------------------
 
