@@ -102,6 +102,10 @@ typedef struct {
     uint32_t radius;     /* code cap R: power of two in [1, 1024]; 2R quantization bins (default 512) */
     uint32_t sub_size;   /* positions per subchunk: power of two in [32, 1024] (default 128) */
     uint32_t chunk_subs; /* subchunks per chunk: power of two in [1, 65536] (default 64) */
+    uint32_t layers;     /* Lorenzo predictor layers, 1 or 2 (default 1): the generalized
+                            predictor with binomial coefficients of Sec. 3.1.2; recorded in
+                            the archive header (byte 117 = layers - 1) */
+    uint32_t reserved;   /* must be 0 */
 } dqz_params;
 
 /* What an _async call reports, written by its kernels into device-visible

@@ -228,10 +228,10 @@ dqz_status dqz_compress_batch(dqz_ctx *ctx, uint32_t n, const float *const *d_fi
         uint64_t sb[4];
         memcpy(sb, &shapes[i], sizeof(sb));
         key.insert(key.end(), sb, sb + 4);
-        uint64_t pb[3];
-        static_assert(sizeof(dqz_params) == 24, "params layout");
+        uint64_t pb[4];
+        static_assert(sizeof(dqz_params) == sizeof(pb), "params layout");
         memcpy(pb, &params[i], sizeof(pb));
-        key.insert(key.end(), pb, pb + 3);
+        key.insert(key.end(), pb, pb + 4);
     }
     key.push_back(reinterpret_cast<uintptr_t>(d_results));
     B.lane_of = assign_lanes(work, lanes);

@@ -105,8 +105,18 @@ dqz_status make_layout(const Geom &g, uint32_t radius, uint32_t sub, uint32_t cs
     L.off_sub = L.off_chunk + 8 * n_chunks;
     L.off_exc = align_up(L.off_sub + 2 * n_sub, 8);
     L.cap = 0;
-    L.pad = 0;
+    L.layers = 1;
     L.ws_fixed = 0;
+    return DQZ_OK;
+}
+
+dqz_status set_layers(const dqz_params *p, Layout &L, std::string &why) {
+    const uint32_t layers = p->layers ? p->layers : 1u;
+    if (layers > kMaxLayers || p->reserved) {
+        why = "layers must be 1 or 2 (and reserved 0)";
+        return DQZ_EINVAL;
+    }
+    L.layers = layers;
     return DQZ_OK;
 }
 
@@ -252,6 +262,9 @@ dqz_status parse_header(const uint8_t *hb, uint64_t n, HeaderInfo &hi, Plan *P, 
     hi.params.radius = radius;
     hi.params.sub_size = sub;
     hi.params.chunk_subs = csubs;
+    if (hb[117] + 1u > kMaxLayers || hb[118] || hb[119]) { why = "bad predictor layers"; return DQZ_ECORRUPT; }
+    pl.L.layers = hb[117] + 1u;
+    hi.params.layers = pl.L.layers;
     hi.nelem = rd_u64(hb, 80);
     if (hi.nelem != pl.g.nelem) { why = "element count mismatch"; return DQZ_ECORRUPT; }
     const uint64_t n_out = rd_u32(hb, 88), n_patch = rd_u32(hb, 92);
@@ -304,6 +317,7 @@ dqz_status plan_compress_args(const float *d_field, const dqz_shape *shape, cons
     uint32_t radius, sub, csubs;
     fill_params(params, radius, sub, csubs);
     if ((st = make_layout(P.g, radius, sub, csubs, P.L, why)) != DQZ_OK) return st;
+    if ((st = set_layers(params, P.L, why)) != DQZ_OK) return st;
     if (params->eb_mode == DQZ_EB_ABS) {
         const double e = params->eb;
         const float h = (float)(2.0 * e), r = (float)(1.0 / (2.0 * e));
@@ -598,6 +612,7 @@ dqz_status dqz_compress_bound(const dqz_shape *shape, const dqz_params *params, 
     uint32_t radius, sub, csubs;
     fill_params(params, radius, sub, csubs);
     if ((st = make_layout(P.g, radius, sub, csubs, P.L, why)) != DQZ_OK) return st;
+    if ((st = set_layers(params, P.L, why)) != DQZ_OK) return st;
     P.tiles_q = quantize_tiles(P.g);
     P.tiles_e = encode_tiles(P.g);
     // every element an outlier and a patch (16 bytes) and a 64-bit code

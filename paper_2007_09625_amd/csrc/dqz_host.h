@@ -120,6 +120,8 @@ dqz_status hip_fail(dqz_ctx *ctx, hipError_t e, const char *what);
 dqz_status make_geom(const dqz_shape *s, Geom &g, std::string &why);
 dqz_status make_layout(const Geom &g, uint32_t radius, uint32_t sub, uint32_t csubs, Layout &L, std::string &why);
 void fill_params(const dqz_params *p, uint32_t &radius, uint32_t &sub, uint32_t &csubs);
+// Lorenzo layers from the parameters into the layout (DQZ_EINVAL unless 0, 1, 2)
+dqz_status set_layers(const dqz_params *p, Layout &L, std::string &why);
 hipError_t wait_stream(hipStream_t s);
 WsLayout ws_layout(const Plan &P, bool compress);
 const char *status_message(dqz_status st);

@@ -22,6 +22,7 @@ constexpr uint32_t kMaxRadius = 1024;      // codebook kernel keeps 2R <= 2048 s
 constexpr uint32_t kMaxSyms = 2 * kMaxRadius;
 constexpr uint16_t kNoSymbol = 0xFFFF;     // code slot of a padded position outside the field
 constexpr uint32_t kDecodeWaveSubs = 64;   // subchunks decoded by one wave (one per lane)
+constexpr uint32_t kMaxLayers = 2;         // Lorenzo predictor layers the kernels implement
 
 // Device status bits (Ctl::status); status_code maps them to a dqz_status.
 enum : uint32_t {
@@ -81,7 +82,7 @@ struct Layout {
     uint32_t sub_size, chunk_subs;
     uint32_t radius, nsym;
     uint32_t sub_shift;    // log2(sub_size)
-    uint32_t pad;
+    uint32_t layers;       // Lorenzo predictor layers (1 or 2)
     uint64_t ws_fixed;     // compression workspace bytes before the exception overflow pool
 };
 

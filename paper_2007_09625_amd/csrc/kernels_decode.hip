@@ -484,6 +484,7 @@ __global__ __launch_bounds__(64 * kDecMaxWaves) void k_decode(DecArgs a) {
     if (active) {
         const Geom &g = a.g;
         const float h = a.h;
+        const bool layers2 = a.L.layers == 2;   // each axis's prefix sum twice
         auto qat = [&](uint64_t loc) -> uint16_t { return wq[(loc >> sh) * a.qstride + (loc & (S - 1))]; };
         if (g.ndim == 3) {
             const uint32_t ly = lane / 8, lx = lane % 8;
@@ -491,14 +492,19 @@ __global__ __launch_bounds__(64 * kDecMaxWaves) void k_decode(DecArgs a) {
             for (uint32_t blk = bfirst; blk <= blast; blk++) {
                 const uint64_t base = (uint64_t)blk * 512 - P0;
                 uint32_t v[8];
-                uint32_t run = 0;
+                uint32_t run = 0, run2 = 0;
 #pragma unroll
                 for (uint32_t z = 0; z < 8; z++) {
                     run += slot_delta(a, qat(base + z * 64 + lane), e0, xp, bad);
-                    v[z] = run;
+                    run2 += run;
+                    v[z] = layers2 ? run2 : run;
                 }
 #pragma unroll
                 for (uint32_t z = 0; z < 8; z++) v[z] = seg_scan<8>(stride8_scan(v[z], lane), lane);
+                if (layers2) {
+#pragma unroll
+                    for (uint32_t z = 0; z < 8; z++) v[z] = seg_scan<8>(stride8_scan(v[z], lane), lane);
+                }
                 const uint32_t Bx = blk % g.nb[2], By = (blk / g.nb[2]) % g.nb[1], Bz = blk / (g.nb[2] * g.nb[1]);
                 const uint32_t x = Bx * 8 + lx, y = By * 8 + ly;
 #pragma unroll
@@ -517,10 +523,12 @@ __global__ __launch_bounds__(64 * kDecMaxWaves) void k_decode(DecArgs a) {
                 const uint64_t base = (uint64_t)blk * 256 - P0;
                 const uint32_t Bx = blk % g.nb[2], By = blk / g.nb[2];
                 const uint32_t x = Bx * 16 + lx;
-                uint32_t col = 0;
+                uint32_t col = 0, col2 = 0;
                 for (uint32_t y = 0; y < 16; y++) {
                     if (ok) col += slot_delta(a, qat(base + y * 16 + lx), e0, xp, bad);
-                    const uint32_t t = seg_scan<16>(col, lane);
+                    col2 += col;
+                    uint32_t t = seg_scan<16>(layers2 ? col2 : col, lane);
+                    if (layers2) t = seg_scan<16>(t, lane);
                     const uint32_t yy = By * 16 + y;
                     if (ok && x < g.n[2] && yy < g.n[1]) a.out[(uint64_t)yy * g.n[2] + x] = dequant((int32_t)t, h);
                 }
@@ -529,7 +537,8 @@ __global__ __launch_bounds__(64 * kDecMaxWaves) void k_decode(DecArgs a) {
             for (uint64_t off = 0; P0 + off < P1; off += 64) {
                 const uint64_t loc = off + lane;
                 const uint64_t p = P0 + loc;
-                const uint32_t t = seg_scan<32>((p < P1) ? slot_delta(a, qat(loc), e0, xp, bad) : 0u, lane);
+                uint32_t t = seg_scan<32>((p < P1) ? slot_delta(a, qat(loc), e0, xp, bad) : 0u, lane);
+                if (layers2) t = seg_scan<32>(t, lane);
                 if (p < g.nelem) a.out[p] = dequant((int32_t)t, h);
             }
         }
@@ -815,7 +824,7 @@ __device__ __forceinline__ uint32_t slot_lane(uint32_t slot) {
 
 // One unit: its lane piece d[] (deltas, outliers still 0) and code-0 mask,
 // records [rs, re) of the exception list.
-template <uint32_t NDIM>
+template <uint32_t NDIM, uint32_t LAYERS>
 __device__ __forceinline__ void recon_unit(const ReconArgs &a, uint32_t u, uint32_t lane, uint32_t (&d)[8],
                                            uint32_t zmask, uint32_t rs, uint32_t re, bool &bad) {
     const Geom &g = a.g;
@@ -846,28 +855,41 @@ __device__ __forceinline__ void recon_unit(const ReconArgs &a, uint32_t u, uint3
     // every code 0 takes exactly one record (keys increase)
     if (wave_sum<uint32_t>(__popc(zmask)) != n_out) bad = true;
 
-    // inverse Lorenzo prediction: inclusive prefix sums along every axis,
-    // wrapping modulo 2^32 like the forward difference
+    // inverse Lorenzo prediction: inclusive prefix sums along every axis
+    // (LAYERS times each), wrapping modulo 2^32 like the forward difference
 #pragma unroll
-    for (uint32_t x = 1; x < 8; x++) d[x] += d[x - 1];
-    if (NDIM == 3) {
+    for (uint32_t l = 0; l < LAYERS; l++) {
 #pragma unroll
-        for (uint32_t x = 0; x < 8; x++) d[x] = stride8_scan(seg_scan<8>(d[x], lane), lane);
-    } else if (NDIM == 2) {
-        uint32_t ofe, efo;
-        row_swap16(d[7], ofe, efo);   // the left half-row's total, for the right half
-        const uint32_t left = ((lane >> 4) & 1u) ? ofe : 0u;
+        for (uint32_t x = 1; x < 8; x++) d[x] += d[x - 1];
+        if (NDIM == 3) {
 #pragma unroll
-        for (uint32_t x = 0; x < 8; x++) d[x] = seg_scan<16>(d[x] + left, lane);
-    } else {
-        // exclusive prefix of the lane totals within the block's quad
-        const uint32_t t = d[7], q4 = lane & 3u;
-        const uint32_t s1 = quad_shr1(t);
-        const uint32_t i1 = t + (q4 >= 1 ? s1 : 0u);
-        const uint32_t s2 = quad_shr2(i1);
-        const uint32_t ex = i1 + (q4 >= 2 ? s2 : 0u) - t;
+            for (uint32_t x = 0; x < 8; x++) d[x] = seg_scan<8>(d[x], lane);
+        } else if (NDIM == 2) {
+            uint32_t ofe, efo;
+            row_swap16(d[7], ofe, efo);   // the left half-row's total, for the right half
+            const uint32_t left = ((lane >> 4) & 1u) ? ofe : 0u;
 #pragma unroll
-        for (uint32_t x = 0; x < 8; x++) d[x] += ex;
+            for (uint32_t x = 0; x < 8; x++) d[x] += left;
+        } else {
+            // exclusive prefix of the lane totals within the block's quad
+            const uint32_t t = d[7], q4 = lane & 3u;
+            const uint32_t s1 = quad_shr1(t);
+            const uint32_t i1 = t + (q4 >= 1 ? s1 : 0u);
+            const uint32_t s2 = quad_shr2(i1);
+            const uint32_t ex = i1 + (q4 >= 2 ? s2 : 0u) - t;
+#pragma unroll
+            for (uint32_t x = 0; x < 8; x++) d[x] += ex;
+        }
+    }
+#pragma unroll
+    for (uint32_t l = 0; l < LAYERS; l++) {
+        if (NDIM == 3) {
+#pragma unroll
+            for (uint32_t x = 0; x < 8; x++) d[x] = stride8_scan(d[x], lane);
+        } else if (NDIM == 2) {
+#pragma unroll
+            for (uint32_t x = 0; x < 8; x++) d[x] = seg_scan<16>(d[x], lane);
+        }
     }
     float f[8];
 #pragma unroll
@@ -924,6 +946,7 @@ __device__ __forceinline__ void recon_unit(const ReconArgs &a, uint32_t u, uint3
 // copy of the block twice, so that the y and then the z prefix are in-lane
 // too: lane 8 z + x holds a y-column, then lane 8 y + x a z-column.  Rows of
 // the copy are 9 words apart (bank spread for the column reads).
+template <uint32_t LAYERS>
 __device__ __forceinline__ void recon_block3(const ReconArgs &a, uint32_t u, uint32_t lane, uint32_t (&d)[8],
                                              uint32_t zmask, uint32_t rs, uint32_t re, lds_u32 *blk, bool &bad) {
     const Geom &g = a.g;
@@ -961,9 +984,11 @@ __device__ __forceinline__ void recon_block3(const ReconArgs &a, uint32_t u, uin
         if (nz != n_out) bad = true;
     }
     // x in-lane (lane = 8 z + y); the sums wrap modulo 2^32 like the
-    // forward difference
+    // forward difference; LAYERS prefix sums along each axis
 #pragma unroll
-    for (uint32_t x = 1; x < 8; x++) d[x] += d[x - 1];
+    for (uint32_t l = 0; l < LAYERS; l++)
+#pragma unroll
+        for (uint32_t x = 1; x < 8; x++) d[x] += d[x - 1];
     const uint32_t hi = lane >> 3, lo = lane & 7u;
 #pragma unroll
     for (uint32_t x = 0; x < 8; x++) blk[72 * hi + 9 * lo + x] = d[x];   // (z, y) = (hi, lo)
@@ -974,7 +999,9 @@ __device__ __forceinline__ void recon_block3(const ReconArgs &a, uint32_t u, uin
 #pragma unroll
     for (uint32_t y = 0; y < 8; y++) d[y] = blk[72 * hi + 9 * y + lo];
 #pragma unroll
-    for (uint32_t y = 1; y < 8; y++) d[y] += d[y - 1];
+    for (uint32_t l = 0; l < LAYERS; l++)
+#pragma unroll
+        for (uint32_t y = 1; y < 8; y++) d[y] += d[y - 1];
 #pragma unroll
     for (uint32_t y = 0; y < 8; y++) blk[72 * hi + 9 * y + lo] = d[y];
     __builtin_amdgcn_wave_barrier();
@@ -982,7 +1009,9 @@ __device__ __forceinline__ void recon_block3(const ReconArgs &a, uint32_t u, uin
 #pragma unroll
     for (uint32_t z = 0; z < 8; z++) d[z] = blk[72 * z + 9 * hi + lo];
 #pragma unroll
-    for (uint32_t z = 1; z < 8; z++) d[z] += d[z - 1];
+    for (uint32_t l = 0; l < LAYERS; l++)
+#pragma unroll
+        for (uint32_t z = 1; z < 8; z++) d[z] += d[z - 1];
     float f[8];
 #pragma unroll
     for (uint32_t z = 0; z < 8; z++) f[z] = dequant((int32_t)d[z], a.h);
@@ -1015,7 +1044,7 @@ __device__ __forceinline__ void recon_block3(const ReconArgs &a, uint32_t u, uin
 }
 
 // One unit per wave.
-template <uint32_t NDIM>
+template <uint32_t NDIM, uint32_t LAYERS>
 __global__ __launch_bounds__(64 * kReconWaves) void k_recon(ReconArgs a) {
     __shared__ uint32_t s_blk[kReconWaves][576];   // 3D: the block, rows 9 words apart
     if (a.tab->status) return;   // the inflate kernel did not run
@@ -1042,8 +1071,8 @@ __global__ __launch_bounds__(64 * kReconWaves) void k_recon(ReconArgs a) {
         }
     }
     bool bad = false;
-    if (NDIM == 3) recon_block3(a, u, lane, d, zmask, rs, re, (lds_u32 *)s_blk[w], bad);
-    else recon_unit<NDIM>(a, u, lane, d, zmask, rs, re, bad);
+    if (NDIM == 3) recon_block3<LAYERS>(a, u, lane, d, zmask, rs, re, (lds_u32 *)s_blk[w], bad);
+    else recon_unit<NDIM, LAYERS>(a, u, lane, d, zmask, rs, re, bad);
     if (bad) {
         atomicOr(a.status, ST_ECORRUPT);
         publish_status(a.rb, ST_ECORRUPT);
@@ -1150,9 +1179,16 @@ void launch_recon(hipStream_t s, const Geom &g, const Layout &L, const uint8_t *
     a.h = h;
     if (a.n_units == 0) return;
     const uint32_t blocks = (a.n_units + kReconWaves - 1) / kReconWaves;
-    if (g.ndim == 3) hipLaunchKernelGGL(k_recon<3>, dim3(blocks), dim3(64 * kReconWaves), 0, s, a);
-    else if (g.ndim == 2) hipLaunchKernelGGL(k_recon<2>, dim3(blocks), dim3(64 * kReconWaves), 0, s, a);
-    else hipLaunchKernelGGL(k_recon<1>, dim3(blocks), dim3(64 * kReconWaves), 0, s, a);
+    const dim3 grid(blocks), block(64 * kReconWaves);
+    if (L.layers == 2) {
+        if (g.ndim == 3) hipLaunchKernelGGL((k_recon<3, 2>), grid, block, 0, s, a);
+        else if (g.ndim == 2) hipLaunchKernelGGL((k_recon<2, 2>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_recon<1, 2>), grid, block, 0, s, a);
+    } else {
+        if (g.ndim == 3) hipLaunchKernelGGL((k_recon<3, 1>), grid, block, 0, s, a);
+        else if (g.ndim == 2) hipLaunchKernelGGL((k_recon<2, 1>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_recon<1, 1>), grid, block, 0, s, a);
+    }
 }
 
 }  // namespace dqz

@@ -615,6 +615,7 @@ __global__ __launch_bounds__(kBookThreads) void k_codebook(const uint32_t *__res
         put_le(hb, 108, L.chunk_subs, 4);
         put_le(hb, 112, L.n_chunks, 4);
         put_le(hb, 116, max_len, 1);
+        put_le(hb, 117, L.layers - 1, 1);
         put_le(hb, 120, end, 8);
     }
     __syncthreads();

@@ -303,6 +303,7 @@ __device__ __forceinline__ void tile_epilogue(const QuantArgs &a, uint32_t tile,
 constexpr uint32_t kT3 = 8;           // blocks per 3D tile
 constexpr uint32_t kRow3 = 8 * kT3 + 8;   // LDS row pitch (floats), padded against bank conflicts
 
+template <uint32_t LAYERS>
 __global__ __launch_bounds__(256) void k_quant3d(QuantArgs a) {
     extern __shared__ uint32_t sh_hist[];
     __shared__ float s_tile[8][8][kRow3];
@@ -372,14 +373,30 @@ __global__ __launch_bounds__(256) void k_quant3d(QuantArgs a) {
         for (uint32_t z = 0; z < 8; z++) v[z] = s_tile[z][ly][bxl * 8 + lx];
 #pragma unroll
         for (uint32_t z = 0; z < 8; z++) d[z] = prequant(v[z], r);
+        // (LAYERS layers: each axis's difference taken LAYERS times, the
+        // padding being 0 at every step, which is the binomial form)
         uint32_t t[8];
 #pragma unroll
         for (uint32_t z = 0; z < 8; z++) t[z] = (uint32_t)d[z] - (z ? (uint32_t)d[z - 1] : 0u);   // padding layer is 0
+#pragma unroll
+        for (uint32_t l = 1; l < LAYERS; l++)
+#pragma unroll
+            for (uint32_t z = 7; z > 0; z--) t[z] -= t[z - 1];
         uint32_t up[8];
 #pragma unroll
-        for (uint32_t z = 0; z < 8; z++) up[z] = __shfl_up(t[z], 8, 64);
+        for (uint32_t l = 0; l < LAYERS; l++) {
 #pragma unroll
-        for (uint32_t z = 0; z < 8; z++) t[z] -= ly > 0 ? up[z] : 0u;
+            for (uint32_t z = 0; z < 8; z++) up[z] = __shfl_up(t[z], 8, 64);
+#pragma unroll
+            for (uint32_t z = 0; z < 8; z++) t[z] -= ly > 0 ? up[z] : 0u;
+        }
+#pragma unroll
+        for (uint32_t l = 1; l < LAYERS; l++) {
+#pragma unroll
+            for (uint32_t z = 0; z < 8; z++) up[z] = __shfl_up(t[z], 1, 64);
+#pragma unroll
+            for (uint32_t z = 0; z < 8; z++) t[z] -= lx > 0 ? up[z] : 0u;
+        }
 #pragma unroll
         for (uint32_t z = 0; z < 8; z++) up[z] = __shfl_up(t[z], 1, 64);
 #pragma unroll
@@ -454,6 +471,7 @@ __global__ __launch_bounds__(256) void k_quant3d(QuantArgs a) {
 // ---------------------------------------------------------------------------
 constexpr uint32_t kT2 = 16;
 
+template <uint32_t LAYERS>
 __global__ __launch_bounds__(256) void k_quant2d(QuantArgs a) {
     extern __shared__ uint32_t sh_hist[];
     __shared__ float s_tile[16][16 * kT2];
@@ -498,6 +516,7 @@ __global__ __launch_bounds__(256) void k_quant2d(QuantArgs a) {
     uint32_t n_zero = 0;   // codes of delta 0 (bin R), added once per wave
     const bool col_ok = blk_ok && gx < nx;
     int32_t prev = 0;   // d° of (y-1) in this column; padding row is 0
+    uint32_t prev_e = 0;   // the first layer's y difference of (y-1) (2 layers)
 #pragma unroll
     for (uint32_t y0h = 0; y0h < 16; y0h += 8) {
         // eight rows at a time: LDS reads, prequantization and the x
@@ -512,6 +531,18 @@ __global__ __launch_bounds__(256) void k_quant2d(QuantArgs a) {
 #pragma unroll
         for (uint32_t k = 0; k < 8; k++) t[k] = (uint32_t)d[k] - (uint32_t)(k ? d[k - 1] : prev);
         prev = d[7];
+        if (LAYERS == 2) {
+            // the y difference again (its padding row is 0 too), then x twice
+            const uint32_t last = t[7];
+#pragma unroll
+            for (uint32_t k = 7; k > 0; k--) t[k] -= t[k - 1];
+            t[0] -= prev_e;
+            prev_e = last;
+#pragma unroll
+            for (uint32_t k = 0; k < 8; k++) up[k] = __shfl_up(t[k], 1, 64);
+#pragma unroll
+            for (uint32_t k = 0; k < 8; k++) t[k] -= lx > 0 ? up[k] : 0u;
+        }
 #pragma unroll
         for (uint32_t k = 0; k < 8; k++) up[k] = __shfl_up(t[k], 1, 64);
 #pragma unroll
@@ -581,6 +612,7 @@ __global__ __launch_bounds__(256) void k_quant2d(QuantArgs a) {
 // 16 consecutive points [16t, 16t + 16), half a block; the first point of an
 // odd thread takes its neighbour from the previous lane.
 // ---------------------------------------------------------------------------
+template <uint32_t LAYERS>
 __global__ __launch_bounds__(256) void k_quant1d(QuantArgs a) {
     extern __shared__ uint32_t sh_hist[];
     __shared__ float s_tile[kTile];
@@ -615,17 +647,28 @@ __global__ __launch_bounds__(256) void k_quant1d(QuantArgs a) {
     int32_t d[16];
 #pragma unroll
     for (uint32_t i = 0; i < 16; i++) d[i] = prequant(s_tile[16 * t + i], r);
-    const uint32_t nb_prev = __shfl_up((uint32_t)d[15], 1, 64);
+    // backward differences inside the 32-blocks (a thread holds half a block;
+    // an odd thread continues the previous one's half), LAYERS times
+    uint32_t e[16];
+    {
+        const uint32_t nb_prev = __shfl_up((uint32_t)d[15], 1, 64);
+#pragma unroll
+        for (uint32_t i = 0; i < 16; i++) e[i] = (uint32_t)d[i] - (i > 0 ? (uint32_t)d[i - 1] : ((t & 1u) ? nb_prev : 0u));
+#pragma unroll
+        for (uint32_t l = 1; l < LAYERS; l++) {
+            const uint32_t e_prev = __shfl_up(e[15], 1, 64);
+#pragma unroll
+            for (uint32_t i = 15; i > 0; i--) e[i] -= e[i - 1];
+            e[0] -= (t & 1u) ? e_prev : 0u;
+        }
+    }
     int32_t delta[16];
     uint32_t flags_o = 0, flags_p = 0, my_count = 0;
     uint32_t n_zero = 0;   // codes of delta 0 (bin R), added once per wave
     uint16_t q[16];
 #pragma unroll
     for (uint32_t i = 0; i < 16; i++) {
-        uint32_t pred = 0;
-        if (i > 0) pred = (uint32_t)d[i - 1];
-        else if (t & 1u) pred = nb_prev;      // lane t-1 is in the same wave (t odd)
-        const int32_t del = (int32_t)((uint32_t)d[i] - pred);
+        const int32_t del = (int32_t)e[i];   // lane t-1 is in the same wave (t odd)
         delta[i] = del;
         const uint64_t pos = p0 + 16 * t + i;
         const bool real = pos < n;
@@ -708,13 +751,16 @@ void launch_quantize(hipStream_t s, const float *x, const Geom &g, const Layout 
     const size_t lds = sizeof(uint32_t) * L.nsym;
     if (g.ndim == 3) {
         a.tiles_per_row = (g.nb[2] + kT3 - 1) / kT3;
-        hipLaunchKernelGGL(k_quant3d, dim3(a.n_tiles), dim3(256), lds, s, a);
+        if (L.layers == 2) hipLaunchKernelGGL(k_quant3d<2>, dim3(a.n_tiles), dim3(256), lds, s, a);
+        else hipLaunchKernelGGL(k_quant3d<1>, dim3(a.n_tiles), dim3(256), lds, s, a);
     } else if (g.ndim == 2) {
         a.tiles_per_row = (g.nb[2] + kT2 - 1) / kT2;
-        hipLaunchKernelGGL(k_quant2d, dim3(a.n_tiles), dim3(256), lds, s, a);
+        if (L.layers == 2) hipLaunchKernelGGL(k_quant2d<2>, dim3(a.n_tiles), dim3(256), lds, s, a);
+        else hipLaunchKernelGGL(k_quant2d<1>, dim3(a.n_tiles), dim3(256), lds, s, a);
     } else {
         a.tiles_per_row = 1;
-        hipLaunchKernelGGL(k_quant1d, dim3(a.n_tiles), dim3(256), lds, s, a);
+        if (L.layers == 2) hipLaunchKernelGGL(k_quant1d<2>, dim3(a.n_tiles), dim3(256), lds, s, a);
+        else hipLaunchKernelGGL(k_quant1d<1>, dim3(a.n_tiles), dim3(256), lds, s, a);
     }
 }
 

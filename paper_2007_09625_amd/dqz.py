@@ -59,7 +59,8 @@ class dqz_shape(ctypes.Structure):
 
 class dqz_params(ctypes.Structure):
     _fields_ = [("eb", ctypes.c_double), ("eb_mode", ctypes.c_int32), ("radius", ctypes.c_uint32),
-                ("sub_size", ctypes.c_uint32), ("chunk_subs", ctypes.c_uint32)]
+                ("sub_size", ctypes.c_uint32), ("chunk_subs", ctypes.c_uint32), ("layers", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
 
 class dqz_result(ctypes.Structure):
@@ -192,13 +193,14 @@ def make_shape(shape) -> dqz_shape:
 
 
 def make_params(eb: float, mode: int = DQZ_EB_VALREL, radius: int = 0, sub_size: int = 0,
-                chunk_subs: int = 0) -> dqz_params:
+                chunk_subs: int = 0, layers: int = 0) -> dqz_params:
     p = dqz_params()
     p.eb = float(eb)
     p.eb_mode = int(mode)
     p.radius = int(radius)
     p.sub_size = int(sub_size)
     p.chunk_subs = int(chunk_subs)
+    p.layers = int(layers)
     return p
 
 
@@ -408,12 +410,15 @@ class Context:
 
     # -- tensor-level helpers ---------------------------------------------------------
     def compress(self, field, eb: float, mode="valrel", radius: int = 0, sub_size: int = 0, chunk_subs: int = 0,
-                 out=None, stream=None) -> Compressed:
-        """Compress a float32 CUDA tensor (1-3 dims, contiguous)."""
+                 out=None, stream=None, layers: int = 0) -> Compressed:
+        """Compress a float32 CUDA tensor (1-3 dims, contiguous; a 4-dim one
+        is compressed as 3D with its two slowest axes merged)."""
         torch = self._torch
         if field.dtype != torch.float32 or not field.is_cuda or not field.is_contiguous():
             raise DqzError(DQZ_EINVAL, "field must be a contiguous float32 CUDA tensor")
-        params = make_params(eb, _mode(mode), radius, sub_size, chunk_subs)
+        if field.dim() == 4:
+            field = field.view(field.shape[0] * field.shape[1], field.shape[2], field.shape[3])
+        params = make_params(eb, _mode(mode), radius, sub_size, chunk_subs, layers)
         shape = tuple(field.shape)
         bound, ws = dqz_compress_bound(shape, params)
         self.dqz_ctx_reserve(ws)
@@ -442,12 +447,12 @@ class Context:
 
     # -- host path ----------------------------------------------------------------------
     def stream_compress(self, x, eb: float, mode="valrel", slab_bytes: int = 256 << 20, out=None, radius: int = 0,
-                        sub_size: int = 0, chunk_subs: int = 0, stream=None):
+                        sub_size: int = 0, chunk_subs: int = 0, stream=None, layers: int = 0):
         """Compress a host field (C-contiguous float32 numpy array or CPU torch
         tensor, pinned for overlapped copies) slab by slab into a container in
         host memory; returns the container (a prefix view of `out` if given)."""
         import numpy as np
-        params = make_params(eb, _mode(mode), radius, sub_size, chunk_subs)
+        params = make_params(eb, _mode(mode), radius, sub_size, chunk_subs, layers)
         shape = tuple(x.shape)
         ws, cmax = dqz_stream_workspace(shape, params, slab_bytes)
         self.dqz_ctx_reserve(ws)
@@ -485,8 +490,8 @@ class Context:
         """Archive and result buffers for a batch of these fields (reusing them
         keeps a captured batch graph valid across calls)."""
         torch = self._torch
-        params = [make_params(eb, _mode(mode), kw.get("radius", 0), kw.get("sub_size", 0), kw.get("chunk_subs", 0))
-                  for eb in ebs]
+        params = [make_params(eb, _mode(mode), kw.get("radius", 0), kw.get("sub_size", 0), kw.get("chunk_subs", 0),
+                              kw.get("layers", 0)) for eb in ebs]
         shapes = [tuple(f.shape) for f in fields]
         caps = [dqz_compress_bound(s, p)[0] for s, p in zip(shapes, params)]
         arcs = [torch.empty(c, dtype=torch.uint8, device=f.device) for c, f in zip(caps, fields)]
@@ -597,14 +602,14 @@ class Server:
         self._keep = {}
 
     def submit_compress(self, field, eb: float, out, mode="valrel", radius: int = 0, sub_size: int = 0,
-                        chunk_subs: int = 0) -> int:
+                        chunk_subs: int = 0, layers: int = 0) -> int:
         r = dqz_request()
         r.kind = DQZ_REQ_COMPRESS
         r.d_input = field.data_ptr()
         r.d_output = out.data_ptr()
         r.output_capacity = out.numel() * out.element_size()
         r.shape = make_shape(tuple(field.shape))
-        r.params = make_params(eb, _mode(mode), radius, sub_size, chunk_subs)
+        r.params = make_params(eb, _mode(mode), radius, sub_size, chunk_subs, layers)
         return self._submit(r, (field, out))
 
     def submit_decompress(self, archive, nbytes: int, header: bytes, out) -> int:

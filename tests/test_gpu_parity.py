@@ -77,7 +77,8 @@ def _check(ctx, x, eb=1e-4, mode=1, **kw):
     okw = {k: v for k, v in kw.items()}
     ref_arc = oracle.compress(x, eb, mode, **{"radius": okw.get("radius", 512),
                                                "sub_size": okw.get("sub_size", 128),
-                                               "chunk_subs": okw.get("chunk_subs", 64)})
+                                               "chunk_subs": okw.get("chunk_subs", 64),
+                                               "layers": okw.get("layers", 1) or 1})
     if not np.array_equal(gpu_arc, ref_arc):
         pytest.fail("archive differs from the oracle\n" + _explain_mismatch(ctx, x, eb, mode, gpu_arc, ref_arc, **kw))
     assert hdr == ref_arc[:128].tobytes()
@@ -327,3 +328,65 @@ def test_parity_full_size_c3(ctx, c3_field, eb):
     h = au.header(arc)
     print(f"c3 eb={eb}: {c3_field.nbytes / arc.size:.2f}x, {8 * arc.size / c3_field.size:.3f} bits/elem, "
           f"outliers {h['n_out']}, patches {h['n_patch']}, max_len {h['max_len']}", flush=True)
+
+
+# --------------------------------------------------------------------------
+# The 2-layer Lorenzo predictor (the generalized predictor of Sec. 3.1.2)
+# --------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape", [(8, 8, 8), (9, 17, 70), (33, 65, 130), (45, 70), (200, 600), (3, 4100),
+                                   (33,), (100003,)], ids=str)
+@pytest.mark.parametrize("eb", [1e-4, 1e-2])
+def test_parity_two_layers(ctx, shape, eb):
+    from synth import fields
+    if len(shape) == 3:
+        x = fields.hurricane3d(shape, seed=sum(shape))
+    elif len(shape) == 2:
+        x = fields.fourier2d(shape, seed=sum(shape))
+    else:
+        x = fields.particles1d(shape[0], seed=shape[0] % 97, shuffle_block=512)
+    arc = _check(ctx, x, eb, 1, layers=2)
+    assert int(arc[117]) == 1
+
+
+@pytest.mark.parametrize("sub_size,chunk_subs", [(32, 1), (256, 128), (512, 2)])
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+def test_parity_two_layers_other_subchunks(ctx, sub_size, chunk_subs, ndim):
+    """Subchunk sizes other than 128 decode in the one-kernel decoder."""
+    from synth import fields
+    x = {1: lambda: fields.particles1d(70001, seed=8, shuffle_block=128),
+         2: lambda: fields.fourier2d((100, 130), seed=9),
+         3: lambda: fields.hurricane3d((17, 45, 70), seed=10)}[ndim]()
+    _check(ctx, x, 1e-4, 1, sub_size=sub_size, chunk_subs=chunk_subs, layers=2)
+
+
+@pytest.mark.parametrize("ndim", [1, 2, 3])
+def test_parity_two_layers_wraparound(ctx, ndim):
+    rng = np.random.default_rng(50 + ndim)
+    shape = {1: (5000,), 2: (37, 45), 3: (11, 13, 17)}[ndim]
+    idx = np.indices(shape).sum(axis=0)
+    x = (np.where(idx % 2 == 0, 1.0, -1.0) * (1e9 - 64.0 * rng.integers(0, 100, shape))).astype(np.float32)
+    _check(ctx, x, 0.5, 0, layers=2)
+
+
+def test_four_dimensional_field_flattened(ctx):
+    """A 4D field (QMCPACK-like, Sec. 4.1's dataset table) is compressed as
+    3D with its two slowest axes merged."""
+    import torch
+    import oracle
+    from synth import fields
+    x4 = fields.hurricane3d((12, 23, 23), seed=4).reshape(3, 4, 23, 23)
+    t = torch.from_numpy(x4).cuda()
+    c = ctx.compress(t, 1e-4)
+    ref = oracle.compress(x4.reshape(12, 23, 23), 1e-4)
+    assert np.array_equal(c.archive.cpu().numpy(), ref)
+    y = ctx.decompress(c, out=torch.empty_like(t).view(12, 23, 23))
+    assert np.array_equal(y.cpu().numpy().view(np.uint32), oracle.decompress(ref).view(np.uint32))
+
+
+def test_parity_two_layers_full_size_3d(ctx):
+    from synth import fields
+    x = fields.workload("c2")
+    arc = _check(ctx, x, 1e-4, 1, layers=2)
+    h = au.header(arc)
+    print(f"c2 2-layer eb=1e-4: {x.nbytes / arc.size:.3f}x, outliers {h['n_out']}, max_len {h['max_len']}")
