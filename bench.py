@@ -47,6 +47,8 @@ WORKLOADS = {
     "host": "host path: the 1D 280,953,867 and 3D 100x500x500 fields in pinned host memory, compressed slab by slab "
             "into a host container and back (copies overlapped with the kernels), and the device path plus the "
             "archive's copy to the host (overall)",
+    "predictors": "the 1-layer (default) against the 2-layer Lorenzo predictor on the 2D 1800x3600, 3D 100x500x500 "
+                  "and 1D 280,953,867 fields at valrel 1e-4 and 1e-3: ratio and device-path throughput",
     "c5": "serving: Poisson streams (50-2000 req/s) of mixed compress/decompress requests over 1D (1e5-1e8), "
           "2D (64..3600 edges) and 3D (32..256 edges) Kolmogorov GRF inputs, valrel eb log-uniform 1e-5..1e-2",
 }
@@ -151,6 +153,8 @@ def main() -> int:
         return bench_serve(args)
     if args.workload == "host":
         return bench_host(args)
+    if args.workload == "predictors":
+        return bench_predictors(args)
     desc = WORKLOADS[args.workload]
     x_host = fields.workload(args.workload)
     n = x_host.size
@@ -774,6 +778,71 @@ def bench_host(args) -> int:
                                        "from pinned host memory into a pinned host container (median)"},
         "fields": out, "pinned_copy_GBps": bw,
     }
+    print(json.dumps(result), flush=True)
+    return 0
+
+
+def bench_predictors(args) -> int:
+    """Ratio and throughput of the 2-layer Lorenzo predictor against the
+    paper's 1-layer default (warm, median of the repetitions, device path).
+    Prints one JSON line."""
+    import numpy as np
+    import torch
+
+    from paper_2007_09625_amd import dqz
+    from synth import fields
+
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    reps = max(5, args.steps)
+    out = {}
+    for name in ("c1", "c2", "c3"):
+        x = torch.from_numpy(fields.workload(name)).to(dev)
+        n = x.numel()
+        ctx = dqz.Context(0)
+        for eb in (1e-4, 1e-3):
+            for layers in (1, 2):
+                params = dqz.make_params(eb, dqz.DQZ_EB_VALREL, 0, 0, 0, layers)
+                bound, ws = dqz.dqz_compress_bound(tuple(x.shape), params)
+                ctx.dqz_ctx_reserve(ws)
+                arc = torch.empty(bound, dtype=torch.uint8, device=dev)
+                y = torch.empty_like(x)
+                tc, td = [], []
+                for r in range(reps + 1):
+                    t = time.perf_counter()
+                    st, nb, hdr = ctx.dqz_compress(x.data_ptr(), tuple(x.shape), params, arc.data_ptr(), bound,
+                                                   stream)
+                    ctx._check(st, "dqz_compress")
+                    t1 = time.perf_counter()
+                    ctx.dqz_ctx_reserve(dqz.dqz_decompress_bound(hdr))
+                    t2 = time.perf_counter()
+                    st = ctx.dqz_decompress(arc.data_ptr(), nb, hdr, y.data_ptr(), y.numel(), stream)
+                    ctx._check(st, "dqz_decompress")
+                    t3 = time.perf_counter()
+                    if r:
+                        tc.append(t1 - t)
+                        td.append(t3 - t2)
+                eb_abs = float(np.frombuffer(hdr[56:64], np.float64)[0])
+                err = float((x.double() - y.double()).abs().max())
+                assert err <= eb_abs
+                med = lambda v: sorted(v)[len(v) // 2]
+                out[f"{name}/eb{eb:g}/layers{layers}"] = {
+                    "ratio": round(4.0 * n / nb, 4), "bits_per_elem": round(8.0 * nb / n, 4),
+                    "outliers": int(np.frombuffer(hdr[88:92], np.uint32)[0]),
+                    "compress_GBps": round(4.0 * n / med(tc) / 1e9, 2),
+                    "decompress_GBps": round(4.0 * n / med(td) / 1e9, 2)}
+                print(f"{name} eb {eb} layers {layers}: {out[f'{name}/eb{eb:g}/layers{layers}']}",
+                      file=sys.stderr, flush=True)
+                del arc, y
+        del ctx, x
+        torch.cuda.empty_cache()
+    result = {"metric": "compression ratio and device-path GB/s, 1-layer against 2-layer Lorenzo",
+              "value": out["c2/eb0.0001/layers2"]["ratio"], "unit": "ratio", "n_gpus": 1, "steps": reps,
+              "warmup": 1, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+              "dtype": "f32", "data": "synthetic",
+              "config": {"workload": WORKLOADS["predictors"],
+                         "value_definition": "ratio of the 3D field at valrel 1e-4 with the 2-layer predictor"},
+              "cases": out}
     print(json.dumps(result), flush=True)
     return 0
 
