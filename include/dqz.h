@@ -422,7 +422,10 @@ dqz_status dqz_stage_times(dqz_ctx *ctx, int which, double *us, int *n_stages);
  *   DQZ_DBG_HISTOGRAM  u32[2R]
  *   DQZ_DBG_CODEBOOK   u64[2R], (length << 56) | canonical code
  *   DQZ_DBG_PHASES     u64[32], phase timestamps of the one-workgroup kernels and
- *                      decoding-wave durations (recorded at timing level 2)
+ *                      decoding-wave durations (recorded at timing level 2);
+ *                      also readable after a dqz_decompress (until a
+ *                      reallocation or a batched or streaming call), the
+ *                      entries of the other kind of call then meaningless
  * `bytes` must equal the buffer's size. */
 #define DQZ_DBG_CODES 1
 #define DQZ_DBG_HISTOGRAM 2

@@ -245,6 +245,7 @@ dqz_status dqz_compress_batch(dqz_ctx *ctx, uint32_t n, const float *const *d_fi
     key.push_back(ctx->ws_bytes);
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     ctx->last_valid = false;
+    ctx->phases_valid = false;
     ctx->ev_ready[0] = false;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     uint8_t *ws = reinterpret_cast<uint8_t *>(ctx->ws);
@@ -309,6 +310,7 @@ dqz_status dqz_decompress_batch(dqz_ctx *ctx, uint32_t n, const void *const *d_a
     key.push_back(ctx->ws_bytes);
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     ctx->last_valid = false;
+    ctx->phases_valid = false;
     ctx->ev_ready[1] = false;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
     uint8_t *ws = reinterpret_cast<uint8_t *>(ctx->ws);
@@ -435,6 +437,7 @@ dqz_status dqz_tune(dqz_ctx *ctx, const float *d_field, const dqz_shape *shape, 
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     ctx->last_valid = false;
+    ctx->phases_valid = false;
     if (result != DQZ_OK) return result;
     double fastest = 1e300;
     for (const Cand &c : cands) fastest = std::min(fastest, c.us);

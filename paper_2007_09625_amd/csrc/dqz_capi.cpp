@@ -301,6 +301,7 @@ dqz_status alloc_workspace(dqz_ctx *ctx, uint64_t bytes) {
     ctx->ws = p;
     ctx->ws_bytes = bytes;
     ctx->last_valid = false;
+    ctx->phases_valid = false;
     return DQZ_OK;
 }
 
@@ -408,6 +409,7 @@ void enqueue_compress(dqz_ctx *ctx, uint8_t *ws, uint64_t ws_bytes, int ncu, con
     mark(ctx, 0, 6, s);
     if (!ctx) return;
     ctx->last_valid = true;
+    ctx->phases_valid = true;
     ctx->last_codes = codes;
     ctx->last_hist = hist;
     ctx->last_book = book;
@@ -449,6 +451,9 @@ void enqueue_decompress(dqz_ctx *ctx, uint8_t *ws, int ncu, const uint8_t *arc, 
     const bool trace = ctx && ctx->trace;
     if (ctx) {
         ctx->last_valid = false;   // the decompression scratch overlaps the compression's
+        ctx->phases_valid = true;
+        ctx->last_ctl = reinterpret_cast<Ctl *>(ws + W.ctl);
+        ctx->last_tab = tab;
         ctx->ev_ready[1] = false;
     }
     mark(ctx, 1, 0, s);
@@ -798,7 +803,9 @@ dqz_status dqz_stage_times(dqz_ctx *ctx, int which, double *us, int *n_stages) {
 
 dqz_status dqz_debug_copy(dqz_ctx *ctx, int what, void *h_dst, uint64_t bytes) {
     if (!ctx || !h_dst) return DQZ_EINVAL;
-    if (!ctx->last_valid)
+    if (what == DQZ_DBG_PHASES && !ctx->phases_valid)
+        return fail(ctx, DQZ_EINVAL, "no call on this context since its last reallocation or batched call");
+    if (what != DQZ_DBG_PHASES && !ctx->last_valid)
         return fail(ctx, DQZ_EINVAL, "no compression on this context since its last decompression or reallocation");
     const void *src = nullptr;
     uint64_t need = 0;

@@ -86,6 +86,8 @@ struct dqz_ctx {
     uint32_t last_nsym = 0;
     dqz::Ctl *last_ctl = nullptr;
     dqz::DecodeTables *last_tab = nullptr;
+    // the phase marks of the most recent single call on ws (either kind) are readable
+    bool phases_valid = false;
     // per-stage timing (events between kernels) and, at level 2, the decoding
     // kernel's per-wave phase sums
     bool timing = false;

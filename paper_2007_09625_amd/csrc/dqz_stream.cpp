@@ -284,6 +284,7 @@ dqz_status dqz_stream_compress(dqz_ctx *ctx, const float *h_field, const dqz_sha
     if (container_cap < idx_end) return fail(ctx, DQZ_ETOOSMALL, "container capacity below its index");
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     ctx->last_valid = false;
+    ctx->phases_valid = false;
     hipStream_t cs = reinterpret_cast<hipStream_t>(stream);
     uint8_t *ws = reinterpret_cast<uint8_t *>(ctx->ws);
     uint8_t *out = reinterpret_cast<uint8_t *>(h_container);
@@ -502,6 +503,7 @@ dqz_status dqz_stream_decompress(dqz_ctx *ctx, const void *h_container, uint64_t
     if (!ct.sg.n_slabs) return DQZ_OK;
     HIP_TRY(ctx, hipSetDevice(ctx->device));
     ctx->last_valid = false;
+    ctx->phases_valid = false;
     hipStream_t cs = reinterpret_cast<hipStream_t>(stream);
     uint8_t *ws = reinterpret_cast<uint8_t *>(ctx->ws);
     const uint64_t o_arc[2] = {o_arc0, o_arc1}, o_out[2] = {o_out0, o_out1};

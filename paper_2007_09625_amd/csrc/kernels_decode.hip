@@ -1054,7 +1054,8 @@ __global__ __launch_bounds__(64 * kReconWaves) void k_recon(ReconArgs a) {
     const uint32_t slot = unit_slot<NDIM>(lane);
     // group slot % 16 of subchunk 4 u + slot / 16, lane-interleaved by wave of 64 subchunks
     const uint4 q = a.codes[((uint64_t)(u >> 4) * 16 + (slot & 15u)) * 64 + (u & 15u) * 4 + (slot >> 4)];
-    const uint32_t rs = a.unit_exc[u], re = a.unit_exc[u + 1];
+    // (clamped: a damaged list leaves the index meaningless, never out of range)
+    const uint32_t re = min(a.unit_exc[u + 1], a.n_exc), rs = min(a.unit_exc[u], re);
     const uint32_t R = a.radius;
     const bool lv = (u << kUnitShift) + 8 * slot < a.g.padded;
     uint32_t d[8];   // wrapping deltas

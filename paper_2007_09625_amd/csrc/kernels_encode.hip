@@ -414,18 +414,19 @@ __device__ __forceinline__ void enc_tile(const EncArgs &a, uint32_t t, uint32_t 
     }
 }
 
-// One kernel per codeword width, both launched: the width is a device value
-// (the longest code; over 24 bits is common at larger error bounds, where
-// rare symbols get long codes), and the one that does not apply returns at
-// once.  Apart, the 32-bit path needs few enough registers for eight
-// workgroups per CU.
-template <bool WIDE>
+// Both codeword widths in one kernel: the width is a device value (the
+// longest code; over 24 bits is common at larger error bounds, where rare
+// symbols get long codes), taken uniformly by every workgroup.  The
+// launch reserves the larger of the two LDS layouts; the 32-bit path keeps
+// its speed at the 64-bit path's register count (measured), and no second
+// launch that returns at once is needed.
 __global__ __launch_bounds__(256) void k_enc_stream(EncArgs a) {
     extern __shared__ uint64_t s_dyn[];
     __shared__ EncLds S;
-    if ((a.ctl->status & kBadStatus) || (a.ctl->max_len > 24) != WIDE) return;
+    if (a.ctl->status & kBadStatus) return;
     uint32_t *s_words = reinterpret_cast<uint32_t *>(s_dyn);   // PackWords<WIDE>::n, then nsym codewords
-    enc_tile<WIDE>(a, blockIdx.x, s_words, s_dyn + book_offset_u64(WIDE), S);
+    if (a.ctl->max_len > 24) enc_tile<true>(a, blockIdx.x, s_words, s_dyn + book_offset_u64(true), S);
+    else enc_tile<false>(a, blockIdx.x, s_words, s_dyn + book_offset_u64(false), S);
 }
 
 // One workgroup per segment: exclusive prefix of the tile values inside
@@ -476,8 +477,8 @@ void launch_encode(hipStream_t s, const Geom &g, const Layout &L, Ctl *ctl, Read
     const uint32_t grid = a.n_tiles_e > b.n_tiles_q ? a.n_tiles_e : b.n_tiles_q;
     if (grid == 0) return;
     (void)ncu;
-    hipLaunchKernelGGL(k_enc_stream<false>, dim3(grid), dim3(256), enc_lds_bytes(false, L.nsym), s, a);
-    hipLaunchKernelGGL(k_enc_stream<true>, dim3(grid), dim3(256), enc_lds_bytes(true, L.nsym), s, a);
+    const size_t lds32 = enc_lds_bytes(false, L.nsym), lds64 = enc_lds_bytes(true, L.nsym);
+    hipLaunchKernelGGL(k_enc_stream, dim3(grid), dim3(256), lds32 > lds64 ? lds32 : lds64, s, a);
 }
 
 }  // namespace dqz

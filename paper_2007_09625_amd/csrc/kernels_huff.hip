@@ -23,7 +23,8 @@
 namespace dqz {
 
 constexpr uint32_t kBookThreads = 256;
-constexpr uint32_t kTableThreads = 1024;   // decoding tables: one workgroup fills the 8192-entry table
+constexpr uint32_t kTableThreads = 1024;   // decoding tables: threads per workgroup
+constexpr uint32_t kTableGroups = 8;       // workgroups that share the lookup tables' slots
 
 template <uint32_t D>
 __device__ __forceinline__ uint64_t xor_lane64(uint64_t v, uint32_t lane) {
@@ -268,13 +269,12 @@ struct BookLds {
     uint32_t merged_w[kMaxSyms];
     uint16_t parent_leaf[kMaxSyms];
     uint16_t parent_int[kMaxSyms];
-    uint16_t round_start[kMaxSyms + 1];
     uint8_t depth_int[kMaxSyms];
     uint8_t len[kMaxSyms];
     uint32_t hist[kMaxSyms];
     uint8_t hdr[kHeaderBytes];
     uint32_t n;
-    uint32_t nl[2], ni[2];
+    uint32_t ic_end, rounds;   // nodes made, merge rounds (for the other waves)
     unsigned long long total_bits;
 };
 
@@ -317,6 +317,135 @@ __device__ __forceinline__ void wave_count_le2(const uint32_t *A, uint32_t ma, c
 // reads go out together
 __device__ __forceinline__ uint32_t ldc(const uint32_t *A, uint32_t i) { return A[i < kMaxSyms ? i : kMaxSyms - 1]; }
 
+// Merges the ascending key sequences a and b (one key per lane each, 64
+// each) in registers: afterwards a holds merged positions 0..63 and b
+// positions 64..127, in lane order.  Bitonic: a followed by b reversed is
+// bitonic; one in-lane compare splits it into two bitonic halves, each
+// sorted by six cross-lane half-cleaners.
+__device__ __forceinline__ void wave_merge128(uint64_t &a, uint64_t &b, uint32_t lane) {
+    const uint64_t br = __shfl(b, (int)(63u - lane), 64);
+    uint64_t lo = a < br ? a : br, hi = a < br ? br : a;
+#define DQZ_HALF_CLEAN(D)                                                   \
+    {                                                                        \
+        const uint64_t pl = xor_lane64<D>(lo, lane), ph = xor_lane64<D>(hi, lane); \
+        const bool low = (lane & (D)) == 0;                                  \
+        lo = (low == (pl < lo)) ? pl : lo;                                   \
+        hi = (low == (ph < hi)) ? ph : hi;                                   \
+    }
+    DQZ_HALF_CLEAN(32)
+    DQZ_HALF_CLEAN(16)
+    DQZ_HALF_CLEAN(8)
+    DQZ_HALF_CLEAN(4)
+    DQZ_HALF_CLEAN(2)
+    DQZ_HALF_CLEAN(1)
+#undef DQZ_HALF_CLEAN
+    a = lo;
+    b = hi;
+}
+
+// The merge rounds of the two-queue construction, in one wave (no barrier):
+// leaf_w[0, n) ascending; internal nodes are appended to int_w (nondecreasing
+// by construction) and parents recorded in parent_leaf / parent_int.  A round
+// takes every item no heavier than T, the sum of the two lightest available
+// items: nodes made later weigh at least T (and lose ties to leaves and to
+// older nodes), so those items are exactly the next ones the sequential
+// algorithm would merge, in the stable merge of the two queues (leaf first
+// on equal weight), paired in order.  The merged order is built 64 positions
+// at a time: the next 64 items of each queue, keyed (weight, queue, index),
+// merged in registers; the first 64 results are the next 64 positions.
+__device__ void wave_rounds(BookLds &s, uint32_t n, Ctl *ctl, uint32_t lane) {
+    constexpr uint32_t kNone = 0xFFFFFFFFu;   // no item (weights stay below 2^31)
+    uint32_t la = 0, ib = 0, ic = 0, rounds = 0;
+    for (;;) {
+        if ((n - la) + (ic - ib) <= 1) break;
+        if (la == n) {
+            // Leaves used up: the internal queue is nondecreasing and every
+            // node made from now on weighs at least its last item, so the
+            // sequential algorithm pairs the queue front to back (oldest first
+            // on ties) with no weight comparison left: item x of
+            // [ib, ic + k - 2) gets parent ic + (x - ib) / 2 for the k = ic - ib
+            // items left, the last node made being the root.
+            const uint32_t k = ic - ib;
+            for (uint32_t x = ib + lane; x < ic + k - 2; x += 64) s.parent_int[x] = (uint16_t)(ic + (x - ib) / 2);
+            ib = ic + k - 2;
+            ic += k - 1;
+            rounds += 32u - __clz(k - 1u);   // ceil(log2 k) levels: the bound on the depth
+            break;
+        }
+        const uint32_t lw = la + lane < n ? s.leaf_w[la + lane] : kNone;
+        const uint32_t iw = ib + lane < ic ? s.int_w[ib + lane] : kNone;
+        // T, from the first two items of each queue
+        const uint32_t l0 = (uint32_t)__builtin_amdgcn_readlane((int)lw, 0);
+        const uint32_t l1 = (uint32_t)__builtin_amdgcn_readlane((int)lw, 1);
+        const uint32_t i0 = (uint32_t)__builtin_amdgcn_readlane((int)iw, 0);
+        const uint32_t i1 = (uint32_t)__builtin_amdgcn_readlane((int)iw, 1);
+        uint32_t Tw;
+        {
+            uint32_t a = 0, b = 0, t = 0;
+#pragma unroll
+            for (int q = 0; q < 2; q++) {
+                const uint32_t lv = a == 0 ? l0 : l1, iv = b == 0 ? i0 : i1;
+                const bool leaf = la + a < n && (ib + b >= ic || lv <= iv);
+                t += leaf ? lv : iv;
+                a += leaf ? 1u : 0u;
+                b += leaf ? 0u : 1u;
+            }
+            Tw = t;
+        }
+        // items of weight <= T: prefixes of both sorted queues (beyond the
+        // windows by 64-way probes)
+        uint32_t nl = (uint32_t)__popcll(__ballot(la + lane < n && lw <= Tw));
+        uint32_t ni = (uint32_t)__popcll(__ballot(ib + lane < ic && iw <= Tw));
+        uint32_t lastl, lasti;
+        if (nl == 64 || ni == 64) {
+            wave_count_le2(s.leaf_w + la, n - la, s.int_w + ib, ic - ib, Tw, lane, nl, ni, lastl, lasti);
+        } else {
+            lastl = nl ? (uint32_t)__builtin_amdgcn_readlane((int)lw, (int)(nl - 1)) : 0u;
+            lasti = ni ? (uint32_t)__builtin_amdgcn_readlane((int)iw, (int)(ni - 1)) : 0u;
+        }
+        if ((nl + ni) & 1u) {   // odd: the last item of the merged order waits
+            const bool int_last = ni > 0 && (nl == 0 || lasti >= lastl);
+            if (int_last) ni--; else nl--;
+        }
+        if (nl + ni < 2) {   // cannot happen for sorted queues: stop rather than spin
+            if (lane == 0) atomicOr(&ctl->status, ST_EINTERNAL);
+            break;
+        }
+        const uint32_t m = nl + ni;
+        uint32_t i = 0, j = 0;   // leaves and internals placed so far this round
+        for (uint32_t d = 0; d < m; d += 64) {
+            const uint32_t wl = d == 0 ? lw : (i + lane < nl ? s.leaf_w[la + i + lane] : kNone);
+            const uint32_t wi = d == 0 ? iw : (j + lane < ni ? s.int_w[ib + j + lane] : kNone);
+            // key: weight, then queue (leaf first), then position in the queue
+            uint64_t ka = i + lane < nl ? ((uint64_t)wl << 7) | lane : ~0ull;
+            uint64_t kb = j + lane < ni ? ((uint64_t)wi << 7) | 64u | lane : ~0ull;
+            wave_merge128(ka, kb, lane);
+            const uint32_t cnt = m - d < 64 ? m - d : 64u;   // even
+            const bool mine = lane < cnt;
+            const bool is_leaf = (ka & 64u) == 0;
+            const uint32_t k = (uint32_t)(ka & 63u), w = (uint32_t)(ka >> 7);
+            const uint32_t node = ic + ((d + lane) >> 1);
+            if (mine) {
+                if (is_leaf) s.parent_leaf[la + i + k] = (uint16_t)node;
+                else s.parent_int[ib + j + k] = (uint16_t)node;
+            }
+            const uint32_t wp = xor_lane32<1>(w, lane);
+            if (mine && !(lane & 1u)) s.int_w[node] = w + wp;
+            const uint32_t leaves = (uint32_t)__popcll(__ballot(mine && is_leaf));
+            i += leaves;
+            j += cnt - leaves;
+        }
+        la += nl;
+        ib += ni;
+        ic += m / 2;
+        rounds++;
+    }
+    if (lane == 0) {
+        s.ic_end = ic;
+        s.rounds = rounds;
+    }
+}
+
 __global__ __launch_bounds__(kBookThreads) void k_codebook(const uint32_t *__restrict__ hist, Ctl *ctl,
                                                            uint64_t *__restrict__ book, uint32_t *__restrict__ book32,
                                                            uint8_t *archive, Layout L, Geom g, HeaderArgs hdr,
@@ -351,7 +480,7 @@ __global__ __launch_bounds__(kBookThreads) void k_codebook(const uint32_t *__res
         fm = wave_max<uint32_t>(fm);
         if (lane_id() == 0) s.wave_fmax[tid / 64] = fm;
     }
-    if (tid == 0) { s.n = 0; s.total_bits = 0; s.nl[0] = s.nl[1] = s.ni[0] = s.ni[1] = 0; }
+    if (tid == 0) { s.n = 0; s.total_bits = 0; s.ic_end = 0; s.rounds = 0; }
     __syncthreads();
     // exception totals from the quantize tiles' segment totals
     {
@@ -395,121 +524,9 @@ __global__ __launch_bounds__(kBookThreads) void k_codebook(const uint32_t *__res
     if (n == 1) {
         if (tid == 0) s.len[s.leaf_sym[0]] = 1;
     } else if (n > 1) {
-        // rounds of the two-queue construction; every thread tracks the queue
-        // state (la: next leaf, ib: next unmerged internal, ic: internals made).
-        // A round takes every item no heavier than T, the sum of the two
-        // lightest available items: nodes made later weigh at least T (and
-        // lose ties to leaves and to older nodes), so those items are exactly
-        // the next ones the sequential algorithm would merge, in the stable
-        // merge of the two queues (leaf first on equal weight), paired in order.
-        const uint32_t lane = lane_id();
-        uint32_t la = 0, ib = 0, ic = 0, rounds = 0;
-        for (;;) {
-            if ((n - la) + (ic - ib) <= 1) break;
-            if (la == n) {
-                // Leaves used up: the internal queue is nondecreasing and every
-                // node made from now on weighs at least its last item, so the
-                // sequential algorithm pairs the queue front to back (oldest
-                // first on ties) with no weight comparison left: item x of
-                // [ib, ic + k - 2) gets parent ic + (x - ib) / 2 for the k =
-                // ic - ib items left, the last node made being the root.
-                const uint32_t k = ic - ib;
-                for (uint32_t x = ib + tid; x < ic + k - 2; x += T) s.parent_int[x] = (uint16_t)(ic + (x - ib) / 2);
-                ib = ic + k - 2;
-                ic += k - 1;
-                rounds += 32u - __clz(k - 1u);   // ceil(log2 k) levels: the bound on the depth
-                __syncthreads();
-                break;
-            }
-            // T, from the first two items of each queue (lanes 0..3 read
-            // them together)
-            const uint32_t hv = lane < 2u ? ldc(s.leaf_w, la + lane) : ldc(s.int_w, ib + (lane & 1u));
-            const uint32_t l0 = (uint32_t)__builtin_amdgcn_readlane((int)hv, 0);
-            const uint32_t l1 = (uint32_t)__builtin_amdgcn_readlane((int)hv, 1);
-            const uint32_t i0 = (uint32_t)__builtin_amdgcn_readlane((int)hv, 2);
-            const uint32_t i1 = (uint32_t)__builtin_amdgcn_readlane((int)hv, 3);
-            uint32_t Tw;
-            {
-                uint32_t a = 0, b = 0, t = 0;
-#pragma unroll
-                for (int q = 0; q < 2; q++) {
-                    const uint32_t lw = a == 0 ? l0 : l1, iw = b == 0 ? i0 : i1;
-                    const bool leaf = la + a < n && (ib + b >= ic || lw <= iw);
-                    t += leaf ? lw : iw;
-                    a += leaf ? 1u : 0u;
-                    b += leaf ? 0u : 1u;
-                }
-                Tw = t;
-            }
-            // items of weight <= T: prefixes of both sorted queues (each wave
-            // finds them itself, so no barrier is needed)
-            uint32_t nl, ni, lastl, lasti;
-            wave_count_le2(s.leaf_w + la, n - la, s.int_w + ib, ic - ib, Tw, lane, nl, ni, lastl, lasti);
-            if ((nl + ni) & 1u) {   // odd: the last item of the merged order waits
-                const bool int_last = ni > 0 && (nl == 0 || lasti >= lastl);
-                if (int_last) ni--; else nl--;
-            }
-            if (nl + ni < 2) {   // cannot happen for sorted queues: stop rather than spin
-                if (tid == 0) atomicOr(&ctl->status, ST_EINTERNAL);
-                break;
-            }
-            // the round's items in the stable merge of the two queues (leaf
-            // first on equal weight), paired in order: thread tid takes merged
-            // positions [d0, d0 + c), c even, found by a merge-path split
-            // (4-way search over the shorter queue), then makes their nodes
-            const uint32_t m = nl + ni;
-            const uint32_t c = 2 * ((m + 2 * kBookThreads - 1) / (2 * kBookThreads));
-            const uint32_t d0 = tid * c;
-            if (d0 < m) {
-                // i leaves + (d0 - i) internals precede position d0: the largest
-                // i with leaf[i-1] <= int[d0-i] (or no such comparison)
-                uint32_t lo = d0 > ni ? d0 - ni : 0u, hi = d0 < nl ? d0 : nl;
-                while (lo < hi) {
-                    const uint32_t span = hi - lo;
-                    uint32_t p[3];
-                    bool ok[3];
-#pragma unroll
-                    for (int k = 0; k < 3; k++) p[k] = lo + (span * (k + 1) + 3) / 4;
-                    uint32_t lv[3], iv[3];
-#pragma unroll
-                    for (int k = 0; k < 3; k++) {
-                        lv[k] = ldc(s.leaf_w, la + p[k] - 1);
-                        iv[k] = ldc(s.int_w, ib + d0 - p[k]);
-                    }
-#pragma unroll
-                    for (int k = 0; k < 3; k++) ok[k] = d0 - p[k] >= ni || lv[k] <= iv[k];
-                    if (ok[2]) lo = p[2];
-                    else if (ok[1]) { lo = p[1]; hi = p[2] - 1; }
-                    else if (ok[0]) { lo = p[0]; hi = p[1] - 1; }
-                    else hi = p[0] - 1;
-                }
-                uint32_t i = lo, j = d0 - lo;
-                const uint32_t d1 = d0 + c < m ? d0 + c : m;
-                for (uint32_t r = d0; r < d1; r += 2) {
-                    // one node from merged positions r, r + 1 (m is even)
-                    const uint32_t L0 = ldc(s.leaf_w, la + i), L1 = ldc(s.leaf_w, la + i + 1);
-                    const uint32_t I0 = ldc(s.int_w, ib + j), I1 = ldc(s.int_w, ib + j + 1);
-                    const uint16_t node = (uint16_t)(ic + r / 2);
-                    const bool f0 = i < nl && (j >= ni || L0 <= I0);
-                    const uint32_t w0 = f0 ? L0 : I0;
-                    if (f0) s.parent_leaf[la + i] = node; else s.parent_int[ib + j] = node;
-                    i += f0 ? 1u : 0u;
-                    j += f0 ? 0u : 1u;
-                    const uint32_t Lh = f0 ? L1 : L0, Ih = f0 ? I0 : I1;
-                    const bool f1 = i < nl && (j >= ni || Lh <= Ih);
-                    const uint32_t w1 = f1 ? Lh : Ih;
-                    if (f1) s.parent_leaf[la + i] = node; else s.parent_int[ib + j] = node;
-                    i += f1 ? 1u : 0u;
-                    j += f1 ? 0u : 1u;
-                    s.int_w[ic + r / 2] = w0 + w1;
-                }
-            }
-            la += nl;
-            ib += ni;
-            ic += (nl + ni) / 2;
-            rounds++;
-            __syncthreads();   // the new nodes' weights, for the next round
-        }
+        if (tid < 64) wave_rounds(s, n, ctl, tid);
+        __syncthreads();
+        const uint32_t ic = s.ic_end, rounds = s.rounds;
         if (tid == 0) { ctl->phase[3] = wall_clock64(); ctl->phase[8] = rounds; }
         // depths of the internal nodes by pointer jumping: the root is the last
         // node made; a node's depth is the length of its parent chain, doubled
@@ -653,16 +670,17 @@ void launch_codebook(hipStream_t st, const Geom &g, const Layout &L, Ctl *ctl, c
 }
 
 // ---------------------------------------------------------------------------
-// D0: archive code lengths -> canonical decoding tables (workgroup 0).
-// Validates that the lengths describe a complete prefix code (or one symbol
-// of length 1).  The other workgroups index the exception list by
+// D0: archive code lengths -> canonical decoding tables (the first
+// kTableGroups workgroups, each ordering the codes and filling a share of
+// the lookup tables).  Workgroup 0 validates that the lengths describe a
+// complete prefix code (or one symbol of length 1).  The other workgroups
+// index the exception list by
 // reconstruction unit (512 padded positions): unit_exc[u] is the first
 // record at or after the unit's first position, found by binary search, and
 // every adjacent pair of keys is checked to increase.
 // ---------------------------------------------------------------------------
 __device__ void exception_index(const uint2 *exc, uint32_t n_exc, uint32_t *unit_exc, uint32_t n_units,
-                                Readback *rb) {
-    const uint32_t i = (blockIdx.x - 1) * blockDim.x + threadIdx.x;
+                                Readback *rb, uint32_t i) {
     if (i <= n_units) {
         const uint64_t key = 2ull * ((uint64_t)i << kUnitShift);
         uint32_t lo = 0, hi = n_exc;
@@ -702,7 +720,10 @@ __device__ void build_limits(const CanonScratch &c, uint64_t *lim) {
         lim[l] = (l == 0) ? 0ull : (l == 64 ? ~0ull : ((c.first_code[l] + c.count[l]) << (64 - l)));
 }
 
-__device__ void build_lut2(const CanonScratch &c, DecodeTables *tab, const uint64_t *lim) {
+// Entries [part * ceil(n / parts), ...) of the second level (workgroup
+// `part` of `parts`; part 0 also stores the table's parameters).
+__device__ void build_lut2(const CanonScratch &c, DecodeTables *tab, const uint64_t *lim, uint32_t part,
+                           uint32_t parts) {
     const uint32_t tid = threadIdx.x, T = blockDim.x;
     const uint32_t max_len = c.max_len;
     // codes of <= kLutBits bits fill [0, V0) of the prefixes; no long codes: V0 = 2^kLutBits
@@ -711,12 +732,13 @@ __device__ void build_lut2(const CanonScratch &c, DecodeTables *tab, const uint6
     uint32_t b = 7;
     while (b > 1 && (n_long << b) > kLut2Max) b--;
     const uint32_t n2 = (n_long << b) < kLut2Max ? (n_long << b) : kLut2Max;
-    if (tid == 0) {
+    if (part == 0 && tid == 0) {
         tab->lut2_v0 = V0;
         tab->lut2_bits = b;
         tab->lut2_n = n2;
     }
-    for (uint32_t j = tid; j < n2; j += T) {
+    const uint32_t per = (n2 + parts - 1) / parts, j1 = (part + 1) * per < n2 ? (part + 1) * per : n2;
+    for (uint32_t j = part * per + tid; j < j1; j += T) {
         const uint64_t wv = (uint64_t)((V0 << b) + j) << (64 - kLutBits - b);
         const uint32_t l = long_code_len(lim, wv, max_len);
         uint32_t e = 0;
@@ -736,15 +758,21 @@ __device__ void build_lut2(const CanonScratch &c, DecodeTables *tab, const uint6
 __global__ __launch_bounds__(kTableThreads) void k_decode_tables(const uint8_t *__restrict__ archive, Layout L,
                                                                 uint32_t max_len_hdr, DecodeTables *tab, Readback *rb,
                                                                 uint32_t n_exc, uint32_t *unit_exc, uint32_t n_units) {
-    if (blockIdx.x > 0) {
-        exception_index(reinterpret_cast<const uint2 *>(archive + L.off_exc), n_exc, unit_exc, n_units, rb);
+    if (blockIdx.x >= kTableGroups) {
+        exception_index(reinterpret_cast<const uint2 *>(archive + L.off_exc), n_exc, unit_exc, n_units, rb,
+                        (blockIdx.x - kTableGroups) * blockDim.x + threadIdx.x);
         return;
     }
+    // each table workgroup orders the codes itself and fills its share of
+    // both lookup levels; workgroup 0 also stores the validation result and
+    // the canonical arrays
+    const uint32_t part = blockIdx.x;
     __shared__ CanonScratch c;
     __shared__ uint8_t len[kMaxSyms];
     __shared__ uint32_t s_bad;
     const uint32_t tid = threadIdx.x, T = blockDim.x, ns = L.nsym;
-    if (tid == 0) {
+    if (tid == 0) s_bad = 0;
+    if (part == 0 && tid == 0) {
         s_bad = 0;
         tab->phase[0] = wall_clock64();
         tab->phase[3] = 0;
@@ -758,11 +786,11 @@ __global__ __launch_bounds__(kTableThreads) void k_decode_tables(const uint8_t *
     }
     __syncthreads();
     if (s_bad) {
-        if (tid == 0) { tab->status = ST_ECORRUPT; tab->max_len = 0; publish_status(rb, ST_ECORRUPT); }
+        if (part == 0 && tid == 0) { tab->status = ST_ECORRUPT; tab->max_len = 0; publish_status(rb, ST_ECORRUPT); }
         return;
     }
     canonical_order(len, ns, c);
-    if (tid == 0) {
+    if (part == 0 && tid == 0) {
         tab->phase[1] = wall_clock64();
         // Kraft: the code space must be exactly filled (or a lone symbol of length 1)
         const bool lone = c.n_used == 1 && c.count[1] == 1;
@@ -773,16 +801,18 @@ __global__ __launch_bounds__(kTableThreads) void k_decode_tables(const uint8_t *
         if (st) publish_status(rb, st);   // the host reads this block after the stream ends
         tab->max_len = c.max_len;
     }
-    for (uint32_t l = tid; l < 65; l += T) {
-        tab->first_code[l] = c.first_code[l];
-        tab->count[l] = c.count[l];
-        tab->first_index[l] = c.first_index[l];
-        // codes of length <= l occupy [0, limit) of the left-aligned code space
-        tab->limit[l] = (l == 0) ? 0ull : (l == 64 ? ~0ull : ((c.first_code[l] + c.count[l]) << (64 - l)));
-    }
-    for (uint32_t i = tid; i < ns; i += T) {
-        const uint64_t k = c.key[i];
-        tab->sorted[i] = (k == ~0ull) ? 0 : (uint16_t)(k & 0xFFFF);
+    if (part == 0) {
+        for (uint32_t l = tid; l < 65; l += T) {
+            tab->first_code[l] = c.first_code[l];
+            tab->count[l] = c.count[l];
+            tab->first_index[l] = c.first_index[l];
+            // codes of length <= l occupy [0, limit) of the left-aligned code space
+            tab->limit[l] = (l == 0) ? 0ull : (l == 64 ? ~0ull : ((c.first_code[l] + c.count[l]) << (64 - l)));
+        }
+        for (uint32_t i = tid; i < ns; i += T) {
+            const uint64_t k = c.key[i];
+            tab->sorted[i] = (k == ~0ull) ? 0 : (uint16_t)(k & 0xFFFF);
+        }
     }
     // the left-aligned limits (the long-code searches below read them)
     build_limits(c, c.xch);
@@ -803,12 +833,14 @@ __global__ __launch_bounds__(kTableThreads) void k_decode_tables(const uint8_t *
     }
     // the shortest length after a long-code prefix (computed once per
     // workgroup for the prefixes, which are the top of the table)
-    constexpr uint32_t kPer = (1u << kLutBits) / kTableThreads;
-    static_assert(kPer * kTableThreads == (1u << kLutBits), "table slots per thread");
+    constexpr uint32_t kSlots = (1u << kLutBits) / kTableGroups;   // this workgroup's: [part * kSlots, ...)
+    constexpr uint32_t kPer = kSlots / kTableThreads;
+    static_assert(kPer * kTableThreads * kTableGroups == (1u << kLutBits), "table slots per thread");
+    const uint32_t v0 = part * kSlots;
     uint32_t slot_len[kPer];
 #pragma unroll
     for (uint32_t i = 0; i < kPer; i++) {
-        const uint32_t v = tid + kTableThreads * i;
+        const uint32_t v = v0 + tid + kTableThreads * i;
         uint32_t l = 1;
 #pragma unroll
         for (uint32_t k = 1; k <= kLutBits; k++) l += (lim[k] <= v) ? 1u : 0u;
@@ -817,7 +849,7 @@ __global__ __launch_bounds__(kTableThreads) void k_decode_tables(const uint8_t *
     uint64_t key[kPer];
 #pragma unroll
     for (uint32_t i = 0; i < kPer; i++) {
-        const uint32_t v = tid + kTableThreads * i, l = slot_len[i];
+        const uint32_t v = v0 + tid + kTableThreads * i, l = slot_len[i];
         int32_t b = 0;
 #pragma unroll
         for (uint32_t k = 1; k <= kLutBits; k++) b = (l == k) ? base[k] : b;
@@ -826,7 +858,7 @@ __global__ __launch_bounds__(kTableThreads) void k_decode_tables(const uint8_t *
     }
 #pragma unroll
     for (uint32_t i = 0; i < kPer; i++) {
-        const uint32_t v = tid + kTableThreads * i, l = slot_len[i];
+        const uint32_t v = v0 + tid + kTableThreads * i, l = slot_len[i];
         uint32_t e = 0;
         if (l <= kLutBits) {
             e = (l << 11) | (uint32_t)(key[i] & 0x7FF);
@@ -839,17 +871,18 @@ __global__ __launch_bounds__(kTableThreads) void k_decode_tables(const uint8_t *
     __syncthreads();
     // the second-level table (its limits, in the sort exchange buffer, were
     // built before the first level)
-    build_lut2(c, tab, c.xch);
+    build_lut2(c, tab, c.xch, part, kTableGroups);
     __syncthreads();
-    if (tid == 0) tab->phase[2] = wall_clock64();
+    if (part == 0 && tid == 0) tab->phase[2] = wall_clock64();
 }
 
 void launch_decode_tables(hipStream_t st, const Layout &L, const uint8_t *archive, uint32_t max_len_hdr,
                           DecodeTables *tab, Readback *rb, uint32_t n_exc, uint32_t *unit_exc,
                           uint32_t n_units) {
-    // workgroup 0 builds the tables; the others index the exception list
+    // the first kTableGroups workgroups build the tables; the others index
+    // the exception list
     const uint32_t idx_items = unit_exc ? (n_units + 1 > n_exc ? n_units + 1 : n_exc) : 0u;
-    const uint32_t blocks = 1 + (idx_items + kTableThreads - 1) / kTableThreads;
+    const uint32_t blocks = kTableGroups + (idx_items + kTableThreads - 1) / kTableThreads;
     hipLaunchKernelGGL(k_decode_tables, dim3(blocks), dim3(kTableThreads), 0, st, archive, L, max_len_hdr, tab,
                        rb, n_exc, unit_exc, n_units);
 }

@@ -292,6 +292,14 @@ def test_stage_timing_modes(ctx):
     assert np.array_equal(a1, a2)
     with pytest.raises(Exception):
         ctx.dqz_ctx_set_timing(0x100 | (2 << 4))
+    # level 2: the decoding waves' phase sums, readable after the decompression
+    ctx.dqz_ctx_set_timing(2)
+    c = ctx.compress(x, 1e-4)
+    y = ctx.decompress(c)
+    ph = ctx.dqz_debug_copy(dqz.DQZ_DBG_PHASES, 256).view(np.uint64)
+    ctx.dqz_ctx_set_timing(0)
+    assert ph[24] <= ph[25] and ph[26] > 0 and ph[27] > 0
+    assert np.array_equal(y.cpu().numpy().view(np.uint32), ctx.decompress(c).cpu().numpy().view(np.uint32))
 
 
 @pytest.mark.parametrize("ndim", [1, 2, 3])
