@@ -47,6 +47,22 @@ struct EncArgs {
 };
 
 constexpr uint32_t kEncPer = kTile / 256;              // positions per thread
+
+// The control-block fields the encoder reads, loaded once at the start (the
+// codebook kernel wrote them; nothing in this launch changes them).
+struct EncCtl {
+    uint32_t status, max_len;
+    uint64_t total_bits, off_str, n_words;
+};
+__device__ __forceinline__ EncCtl load_enc_ctl(const Ctl *ctl) {
+    EncCtl c;
+    c.status = ctl->status;
+    c.max_len = ctl->max_len;
+    c.total_bits = ctl->total_bits;
+    c.off_str = ctl->off_str;
+    c.n_words = ctl->n_words;
+    return c;
+}
 constexpr uint32_t kBadStatus = ST_EINVAL | ST_ETOOSMALL | ST_EUNSUPPORTED | ST_EINTERNAL | ST_ENOMEM;
 
 template <bool WIDE> struct Codeword;
@@ -189,7 +205,8 @@ __device__ __forceinline__ void pack_run(const EncArgs &a, uint64_t p0, uint64_t
                                          uint32_t excl, const uint16_t (&q)[PER],
                                          const typename Codeword<WIDE>::T *s_book,
                                          uint32_t *s_words, uint64_t tile_start, bool last_run,
-                                         const uint32_t *s_carry_in, uint32_t *s_carry_out, const uint32_t *s_head) {
+                                         const uint32_t *s_carry_in, uint32_t *s_carry_out, const uint32_t *s_head,
+                                         const EncCtl &cc) {
     typedef Codeword<WIDE> CW;
     const uint32_t tid = threadIdx.x;
     const uint64_t my0 = p0 + (uint64_t)PER * tid;
@@ -246,7 +263,7 @@ __device__ __forceinline__ void pack_run(const EncArgs &a, uint64_t p0, uint64_t
         if (fill) atomicOr(&s_words[w], (uint32_t)(acc >> 32));
     }
     __syncthreads();
-    uint32_t *stream = reinterpret_cast<uint32_t *>(a.archive + a.ctl->off_str);
+    uint32_t *stream = reinterpret_cast<uint32_t *>(a.archive + cc.off_str);
     const uint64_t W0 = base >> 5;
     const uint32_t tail = (lead + run_bits) & 31u;   // bits used in the last word (0: it is full)
     for (uint32_t i = tid; i < nwords; i += 256) {
@@ -259,7 +276,7 @@ __device__ __forceinline__ void pack_run(const EncArgs &a, uint64_t p0, uint64_t
             }
             v |= *s_head >> tail;
         }
-        if (32ull * (W0 + i) >= tile_start && W0 + i < a.ctl->n_words) stream[W0 + i] = v;
+        if (32ull * (W0 + i) >= tile_start && W0 + i < cc.n_words) stream[W0 + i] = v;
     }
 }
 
@@ -304,9 +321,11 @@ __device__ void copy_exceptions(const EncArgs &a, uint32_t t, uint32_t lane) {
     }
 }
 
+// q: the tile's codes (RUNS runs of PER per thread, loaded by the caller)
 template <bool WIDE>
 __device__ __forceinline__ void enc_tile(const EncArgs &a, uint32_t t, uint32_t *s_words, uint64_t *s_book_raw,
-                                         EncLds &S) {
+                                         EncLds &S, const EncCtl &cc,
+                                         const uint16_t (&q)[WIDE ? kRuns64 : 1][kEncPer / (WIDE ? kRuns64 : 1)]) {
     typedef Codeword<WIDE> CW;
     typedef typename CW::T Entry;
     constexpr uint32_t RUNS = WIDE ? kRuns64 : 1;
@@ -319,11 +338,8 @@ __device__ __forceinline__ void enc_tile(const EncArgs &a, uint32_t t, uint32_t 
         if (w == 0 && t < a.b.n_tiles_q) copy_exceptions(a, t, lane);
         return;
     }
-    // the tile's codes, the codebook and (wave 1) the codes just after the
-    // tile are all in flight together
-    uint16_t q[RUNS][PER];
-#pragma unroll
-    for (uint32_t r = 0; r < RUNS; r++) load_codes(a, p0 + r * (kTile / RUNS) + (uint64_t)PER * tid, q[r]);
+    // the codebook and (wave 1) the codes just after the tile in flight
+    // together (the tile's codes are already on their way)
     uint32_t after = kNoSymbol;
     {
         const uint64_t pn = p0 + kTile + lane;
@@ -379,7 +395,7 @@ __device__ __forceinline__ void enc_tile(const EncArgs &a, uint32_t t, uint32_t 
         if (tid == 0) {
             S.G = G;
             // the stream ends where the codebook's total says
-            if (t + 1 == a.n_tiles_e && G + tile_bits != a.ctl->total_bits) report_internal(a);
+            if (t + 1 == a.n_tiles_e && G + tile_bits != cc.total_bits) report_internal(a);
         }
     } else if (w == 1) {
         const uint32_t hb = stream_head<WIDE>(a, s_book, p0 + kTile, after);
@@ -409,7 +425,7 @@ __device__ __forceinline__ void enc_tile(const EncArgs &a, uint32_t t, uint32_t 
         if (r) __syncthreads();   // the word buffer is reused
         pack_run<WIDE, PER>(a, p0 + r * (kTile / RUNS), base, (uint32_t)tot[r], excl[r], q[r], s_book, s_words, G,
                             r + 1 == RUNS, r ? &S.carry[(r - 1) & 1] : nullptr,
-                            r + 1 < RUNS ? &S.carry[r & 1] : nullptr, &S.head);
+                            r + 1 < RUNS ? &S.carry[r & 1] : nullptr, &S.head, cc);
         base += tot[r];
     }
 }
@@ -423,10 +439,27 @@ __device__ __forceinline__ void enc_tile(const EncArgs &a, uint32_t t, uint32_t 
 __global__ __launch_bounds__(256) void k_enc_stream(EncArgs a) {
     extern __shared__ uint64_t s_dyn[];
     __shared__ EncLds S;
-    if (a.ctl->status & kBadStatus) return;
+    const EncCtl cc = load_enc_ctl(a.ctl);
+    const uint32_t t = blockIdx.x, tid = threadIdx.x;
+    const uint64_t p0 = (uint64_t)t * kTile;
+    const bool coder = t < a.n_tiles_e;
+    // the tile's codes in the 32-bit path's order go out together with the
+    // control fields (the common case; the 64-bit path loads its own order)
+    uint16_t q32[1][kEncPer];
+    if (coder) load_codes(a, p0 + (uint64_t)kEncPer * tid, q32[0]);
+    if (cc.status & kBadStatus) return;
     uint32_t *s_words = reinterpret_cast<uint32_t *>(s_dyn);   // PackWords<WIDE>::n, then nsym codewords
-    if (a.ctl->max_len > 24) enc_tile<true>(a, blockIdx.x, s_words, s_dyn + book_offset_u64(true), S);
-    else enc_tile<false>(a, blockIdx.x, s_words, s_dyn + book_offset_u64(false), S);
+    if (cc.max_len > 24) {
+        constexpr uint32_t PER = kEncPer / kRuns64;
+        uint16_t q64[kRuns64][PER];
+        if (coder) {
+#pragma unroll
+            for (uint32_t r = 0; r < kRuns64; r++) load_codes(a, p0 + r * (kTile / kRuns64) + (uint64_t)PER * tid, q64[r]);
+        }
+        enc_tile<true>(a, t, s_words, s_dyn + book_offset_u64(true), S, cc, q64);
+    } else {
+        enc_tile<false>(a, t, s_words, s_dyn + book_offset_u64(false), S, cc, q32);
+    }
 }
 
 // One workgroup per segment: exclusive prefix of the tile values inside
