@@ -322,12 +322,13 @@ __device__ __forceinline__ uint32_t ldc(const uint32_t *A, uint32_t i) { return 
 // positions 64..127, in lane order.  Bitonic: a followed by b reversed is
 // bitonic; one in-lane compare splits it into two bitonic halves, each
 // sorted by six cross-lane half-cleaners.
-__device__ __forceinline__ void wave_merge128(uint64_t &a, uint64_t &b, uint32_t lane) {
-    const uint64_t br = __shfl(b, (int)(63u - lane), 64);
-    uint64_t lo = a < br ? a : br, hi = a < br ? br : a;
+template <typename K>
+__device__ __forceinline__ void wave_merge128(K &a, K &b, uint32_t lane) {
+    const K br = __shfl(b, (int)(63u - lane), 64);
+    K lo = a < br ? a : br, hi = a < br ? br : a;
 #define DQZ_HALF_CLEAN(D)                                                   \
     {                                                                        \
-        const uint64_t pl = xor_lane64<D>(lo, lane), ph = xor_lane64<D>(hi, lane); \
+        const K pl = xor_lane_t<D>(lo, lane), ph = xor_lane_t<D>(hi, lane);  \
         const bool low = (lane & (D)) == 0;                                  \
         lo = (low == (pl < lo)) ? pl : lo;                                   \
         hi = (low == (ph < hi)) ? ph : hi;                                   \
@@ -352,7 +353,10 @@ __device__ __forceinline__ void wave_merge128(uint64_t &a, uint64_t &b, uint32_t
 // algorithm would merge, in the stable merge of the two queues (leaf first
 // on equal weight), paired in order.  The merged order is built 64 positions
 // at a time: the next 64 items of each queue, keyed (weight, queue, index),
-// merged in registers; the first 64 results are the next 64 positions.
+// merged in registers; the first 64 results are the next 64 positions.  K:
+// 32-bit keys when every weight (at most the total count) is below 2^25,
+// else 64-bit.
+template <typename K>
 __device__ void wave_rounds(BookLds &s, uint32_t n, Ctl *ctl, uint32_t lane) {
     constexpr uint32_t kNone = 0xFFFFFFFFu;   // no item (weights stay below 2^31)
     uint32_t la = 0, ib = 0, ic = 0, rounds = 0;
@@ -417,9 +421,9 @@ __device__ void wave_rounds(BookLds &s, uint32_t n, Ctl *ctl, uint32_t lane) {
             const uint32_t wl = d == 0 ? lw : (i + lane < nl ? s.leaf_w[la + i + lane] : kNone);
             const uint32_t wi = d == 0 ? iw : (j + lane < ni ? s.int_w[ib + j + lane] : kNone);
             // key: weight, then queue (leaf first), then position in the queue
-            uint64_t ka = i + lane < nl ? ((uint64_t)wl << 7) | lane : ~0ull;
-            uint64_t kb = j + lane < ni ? ((uint64_t)wi << 7) | 64u | lane : ~0ull;
-            wave_merge128(ka, kb, lane);
+            K ka = i + lane < nl ? ((K)wl << 7) | lane : (K)~(K)0;
+            K kb = j + lane < ni ? ((K)wi << 7) | 64u | lane : (K)~(K)0;
+            wave_merge128<K>(ka, kb, lane);
             const uint32_t cnt = m - d < 64 ? m - d : 64u;   // even
             const bool mine = lane < cnt;
             const bool is_leaf = (ka & 64u) == 0;
@@ -524,7 +528,10 @@ __global__ __launch_bounds__(kBookThreads) void k_codebook(const uint32_t *__res
     if (n == 1) {
         if (tid == 0) s.len[s.leaf_sym[0]] = 1;
     } else if (n > 1) {
-        if (tid < 64) wave_rounds(s, n, ctl, tid);
+        if (tid < 64) {
+            if (g.nelem < (1ull << 25)) wave_rounds<uint32_t>(s, n, ctl, tid);   // weights sum to the count of values
+            else wave_rounds<uint64_t>(s, n, ctl, tid);
+        }
         __syncthreads();
         const uint32_t ic = s.ic_end, rounds = s.rounds;
         if (tid == 0) { ctl->phase[3] = wall_clock64(); ctl->phase[8] = rounds; }
