@@ -535,7 +535,41 @@ def bench_batch(args) -> int:
         "max_err_over_eb": round(worst, 6),
         "tuner": {"choices": classes, "seconds": round(tune_s, 2)},
         "generation_s": round(gen_s, 1),
+        "cpu_baseline": None,
     }
+    if not args.no_cpu_baseline:
+        # the oracle over a bounded sample (fields 1.. up to about 1.6e8 values,
+        # some 20 s of single-core work), fields spread over the host cores
+        # (the oracle's C calls release the interpreter lock)
+        from concurrent.futures import ThreadPoolExecutor
+
+        import oracle
+        sample, tot = [], 0
+        for i in range(1, len(xs)):
+            if tot >= 160_000_000:
+                break
+            sample.append(i)
+            tot += xs[i].numel()
+        hosts = {i: xs[i].cpu().numpy() for i in sample}
+        workers = min(16, os.cpu_count() or 1, len(sample))
+
+        def round_trip(i):
+            ref = oracle.compress(hosts[i], w.ebs[i], oracle.EB_VALREL, 512, params[i].sub_size or 128,
+                                  params[i].chunk_subs or 64)
+            oracle.decompress(ref)
+            nb = meta[i][0]
+            return ref.size == nb and np.array_equal(ref, plain_arcs[i][:nb].cpu().numpy())
+
+        t = time.perf_counter()
+        with ThreadPoolExecutor(max_workers=workers) as pool:
+            same = list(pool.map(round_trip, sample))
+        tcpu = time.perf_counter() - t
+        result["cpu_baseline"] = {
+            "value": round(4.0 * tot / tcpu / 1e9, 4), "unit": "GB/s", "cores": workers, "kind": "oracle",
+            "cpu_model": cpu_model(),
+            "sample": f"fields {sample[0]}-{sample[-1]} ({tot} values), one compress + one decompress each, "
+                      f"{workers} fields at a time on host threads ({tcpu:.1f} s)",
+            "archives_identical_to_gpu": all(same)}
     print(json.dumps(result), flush=True)
     return 0
 

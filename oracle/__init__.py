@@ -20,6 +20,7 @@ from __future__ import annotations
 import ctypes
 import os
 import subprocess
+import threading
 
 import numpy as np
 
@@ -42,7 +43,7 @@ class OracleError(RuntimeError):
 def build() -> str:
     """Compile the oracle with gcc (no FMA contraction, no fast-math)."""
     os.makedirs(os.path.dirname(_LIB_PATH), exist_ok=True)
-    tmp = _LIB_PATH + ".tmp"
+    tmp = f"{_LIB_PATH}.{os.getpid()}.{threading.get_ident()}.tmp"
     cmd = ["gcc", "-O2", "-std=gnu99", "-Wall", "-ffp-contract=off", "-fno-fast-math",
            "-shared", "-fPIC", "-o", tmp, _SRC, "-lm"]
     subprocess.run(cmd, check=True)
@@ -51,12 +52,20 @@ def build() -> str:
 
 
 _lib = None
+_lib_lock = threading.Lock()
 
 
 def _load():
     global _lib
     if _lib is not None:
         return _lib
+    with _lib_lock:   # callers on several host threads build and bind it once
+        if _lib is None:
+            _lib = _bind()
+    return _lib
+
+
+def _bind():
     path = os.environ.get("DQZ_ORACLE_LIB")   # a deliberately mutated build (mutation tests)
     if not path:
         path = _LIB_PATH
@@ -80,7 +89,6 @@ def _load():
     lib.orc_compressed_size.argtypes = [P, i32, P, f64, i32, u32, u32, u32, P]
     lib.orc_decompress.argtypes = [P, u64, P, u64]
     lib.orc_stages.argtypes = [P, i32, P, f64, i32, u32, P, P, P, P]
-    _lib = lib
     return lib
 
 
