@@ -146,23 +146,6 @@ __device__ __forceinline__ uint64_t lanes_below(uint32_t lane) {
     return lane == 0 ? 0ull : (~0ull >> (64u - lane));
 }
 
-template <typename T>
-__device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-template <typename T>
-__device__ __forceinline__ T wave_max(T v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        T o = __shfl_xor(v, off, 64);
-        v = o > v ? o : v;
-    }
-    return v;
-}
-
 // Value of lane (lane ^ D) within the wave: DPP quad permutes for D = 1, 2,
 // row shifts for 4, a row rotate for 8, the row-pair and half-wave swaps
 // for 16 and 32 (all in the VALU, no LDS round trip).
@@ -184,6 +167,55 @@ __device__ __forceinline__ uint32_t xor_lane32(uint32_t v, uint32_t lane) {
     const auto p = __builtin_amdgcn_permlane32_swap(v, v, false, false);
     return (lane & 32u) ? p[0] : p[1];
 }
+template <uint32_t D>
+__device__ __forceinline__ uint64_t xor_lane64(uint64_t v, uint32_t lane) {
+    const uint32_t lo = xor_lane32<D>((uint32_t)v, lane), hi = xor_lane32<D>((uint32_t)(v >> 32), lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+template <uint32_t D>
+__device__ __forceinline__ uint32_t xor_lane_t(uint32_t v, uint32_t lane) { return xor_lane32<D>(v, lane); }
+template <uint32_t D>
+__device__ __forceinline__ uint64_t xor_lane_t(uint64_t v, uint32_t lane) { return xor_lane64<D>(v, lane); }
+
+// Sum and maximum over the 64 lanes (32- or 64-bit), by those exchanges.
+// Every wave helper here is called by whole waves (all 64 lanes active).
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+    const uint32_t lane = lane_id();
+    v += xor_lane_t<32>(v, lane);
+    v += xor_lane_t<16>(v, lane);
+    v += xor_lane_t<8>(v, lane);
+    v += xor_lane_t<4>(v, lane);
+    v += xor_lane_t<2>(v, lane);
+    v += xor_lane_t<1>(v, lane);
+    return v;
+}
+template <typename T>
+__device__ __forceinline__ T wave_max(T v) {
+    const uint32_t lane = lane_id();
+    T o;
+    o = xor_lane_t<32>(v, lane); v = o > v ? o : v;
+    o = xor_lane_t<16>(v, lane); v = o > v ? o : v;
+    o = xor_lane_t<8>(v, lane); v = o > v ? o : v;
+    o = xor_lane_t<4>(v, lane); v = o > v ? o : v;
+    o = xor_lane_t<2>(v, lane); v = o > v ? o : v;
+    o = xor_lane_t<1>(v, lane); v = o > v ? o : v;
+    return v;
+}
+
+// DPP move that yields 0 where the source lane lies outside the 16-lane row
+// or the destination row is masked off (CTRL: row_shr:n = 0x110 + n,
+// row_bcast:15 = 0x142 (lane 15 of each row into the next row),
+// row_bcast:31 = 0x143 (lane 31 into rows 2 and 3)).
+template <uint32_t CTRL, uint32_t ROWS = 0xF>
+__device__ __forceinline__ uint32_t dpp_zero(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xF, false);
+}
+template <uint32_t CTRL, uint32_t ROWS = 0xF>
+__device__ __forceinline__ uint64_t dpp_zero(uint64_t v) {
+    return ((uint64_t)dpp_zero<CTRL, ROWS>((uint32_t)(v >> 32)) << 32) | dpp_zero<CTRL, ROWS>((uint32_t)v);
+}
+
 // Sum over the 64 lanes through those exchanges (no LDS round trip).
 __device__ __forceinline__ uint32_t wave_sum_xor(uint32_t v) {
     const uint32_t lane = lane_id();
@@ -205,15 +237,17 @@ __device__ __forceinline__ uint32_t xcd_tile(uint32_t wg, uint32_t n) {
     return x * q + (x < r ? x : r) + k;
 }
 
-// Inclusive prefix sum over the 64 lanes.
+// Inclusive prefix sum over the 64 lanes (32- or 64-bit): a scan inside each
+// 16-lane row by row shifts, then each row's total carried into the rows
+// after it by the two row broadcasts; all in the VALU.
 template <typename T>
 __device__ __forceinline__ T wave_incl_scan(T v) {
-    const uint32_t lane = lane_id();
-#pragma unroll
-    for (int off = 1; off < 64; off <<= 1) {
-        T o = __shfl_up(v, off, 64);
-        if (lane >= (uint32_t)off) v += o;
-    }
+    v += dpp_zero<0x111>(v);
+    v += dpp_zero<0x112>(v);
+    v += dpp_zero<0x114>(v);
+    v += dpp_zero<0x118>(v);
+    v += dpp_zero<0x142, 0xA>(v);
+    v += dpp_zero<0x143, 0xC>(v);
     return v;
 }
 

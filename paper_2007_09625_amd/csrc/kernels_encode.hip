@@ -161,10 +161,14 @@ __device__ uint64_t look_back(const EncArgs &a, const uint64_t *flags, uint32_t 
     }
 }
 
-template <typename T>
-__device__ __forceinline__ T wave_or(T v) {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v |= __shfl_xor(v, off, 64);
+__device__ __forceinline__ uint32_t wave_or(uint32_t v) {
+    const uint32_t lane = lane_id();
+    v |= xor_lane32<32>(v, lane);
+    v |= xor_lane32<16>(v, lane);
+    v |= xor_lane32<8>(v, lane);
+    v |= xor_lane32<4>(v, lane);
+    v |= xor_lane32<2>(v, lane);
+    v |= xor_lane32<1>(v, lane);
     return v;
 }
 
@@ -182,8 +186,8 @@ __device__ uint32_t stream_head(const EncArgs &a, const typename Codeword<WIDE>:
         const uint32_t start = off + incl - len;
         uint32_t part = 0;
         if (len && start < 32u) part = (uint32_t)(((CW::code(e) << (64u - len)) >> start) >> 32);
-        word |= wave_or<uint32_t>(part);
-        off += (uint32_t)__shfl(incl, 63, 64);
+        word |= wave_or(part);
+        off += (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
         p += 64;
         if (off >= 32u || p >= a.g.padded) return word;
         c = p + lane < a.g.padded ? a.b.codes[p + lane] : kNoSymbol;

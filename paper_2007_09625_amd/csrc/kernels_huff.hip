@@ -26,15 +26,6 @@ constexpr uint32_t kBookThreads = 256;
 constexpr uint32_t kTableThreads = 1024;   // decoding tables: threads per workgroup
 constexpr uint32_t kTableGroups = 8;       // workgroups that share the lookup tables' slots
 
-template <uint32_t D>
-__device__ __forceinline__ uint64_t xor_lane64(uint64_t v, uint32_t lane) {
-    const uint32_t lo = xor_lane32<D>((uint32_t)v, lane), hi = xor_lane32<D>((uint32_t)(v >> 32), lane);
-    return ((uint64_t)hi << 32) | lo;
-}
-template <uint32_t D>
-__device__ __forceinline__ uint32_t xor_lane_t(uint32_t v, uint32_t lane) { return xor_lane32<D>(v, lane); }
-template <uint32_t D>
-__device__ __forceinline__ uint64_t xor_lane_t(uint64_t v, uint32_t lane) { return xor_lane64<D>(v, lane); }
 template <typename K>
 __device__ __forceinline__ K xor_lane(K v, uint32_t lane, uint32_t d) {   // d a compile-time constant
     switch (d) {
@@ -224,12 +215,16 @@ __device__ void canonical_order(const uint8_t *len, uint32_t ns, CanonScratch &c
         c.count[l] = cl;
         const uint32_t incl = wave_incl_scan<uint32_t>(cl);
         c.first_index[l] = incl - cl;
+        // (the same doubling steps as a prefix sum: row shifts by 1, 2, 4, 8
+        // weighted 2^k, then the row broadcasts weighted by the distance
+        // from the broadcast lane)
         uint64_t S = cl;
-#pragma unroll
-        for (uint32_t k = 1; k < 64; k <<= 1) {
-            const uint64_t o = __shfl_up(S, k, 64);
-            if (tid >= k) S += o << k;
-        }
+        S += dpp_zero<0x111>(S) << 1;
+        S += dpp_zero<0x112>(S) << 2;
+        S += dpp_zero<0x114>(S) << 4;
+        S += dpp_zero<0x118>(S) << 8;
+        S += dpp_zero<0x142, 0xA>(S) << ((tid & 15u) + 1u);
+        S += dpp_zero<0x143, 0xC>(S) << ((tid - 31u) & 63u);
         if (l + 1 <= 64) c.first_code[l + 1] = S << 1;
         if (tid == 0) c.first_code[1] = 0;
         // Kraft: S_l = sum_{j<=l} count_j 2^(l-j) may not exceed 2^l at any l
@@ -376,8 +371,11 @@ __device__ void wave_rounds(BookLds &s, uint32_t n, Ctl *ctl, uint32_t lane) {
             rounds += 32u - __clz(k - 1u);   // ceil(log2 k) levels: the bound on the depth
             break;
         }
-        const uint32_t lw = la + lane < n ? s.leaf_w[la + lane] : kNone;
-        const uint32_t iw = ib + lane < ic ? s.int_w[ib + lane] : kNone;
+        // both queue windows requested together (clamped reads, the lanes
+        // past a queue's end then set to kNone)
+        const uint32_t lw_raw = ldc(s.leaf_w, la + lane), iw_raw = ldc(s.int_w, ib + lane);
+        const uint32_t lw = la + lane < n ? lw_raw : kNone;
+        const uint32_t iw = ib + lane < ic ? iw_raw : kNone;
         // T, from the first two items of each queue
         const uint32_t l0 = (uint32_t)__builtin_amdgcn_readlane((int)lw, 0);
         const uint32_t l1 = (uint32_t)__builtin_amdgcn_readlane((int)lw, 1);
@@ -418,8 +416,10 @@ __device__ void wave_rounds(BookLds &s, uint32_t n, Ctl *ctl, uint32_t lane) {
         const uint32_t m = nl + ni;
         uint32_t i = 0, j = 0;   // leaves and internals placed so far this round
         for (uint32_t d = 0; d < m; d += 64) {
-            const uint32_t wl = d == 0 ? lw : (i + lane < nl ? s.leaf_w[la + i + lane] : kNone);
-            const uint32_t wi = d == 0 ? iw : (j + lane < ni ? s.int_w[ib + j + lane] : kNone);
+            const uint32_t wl_raw = d == 0 ? lw : ldc(s.leaf_w, la + i + lane);
+            const uint32_t wi_raw = d == 0 ? iw : ldc(s.int_w, ib + j + lane);
+            const uint32_t wl = d == 0 ? lw : (i + lane < nl ? wl_raw : kNone);
+            const uint32_t wi = d == 0 ? iw : (j + lane < ni ? wi_raw : kNone);
             // key: weight, then queue (leaf first), then position in the queue
             K ka = i + lane < nl ? ((K)wl << 7) | lane : (K)~(K)0;
             K kb = j + lane < ni ? ((K)wi << 7) | 64u | lane : (K)~(K)0;

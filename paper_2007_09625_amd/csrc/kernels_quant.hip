@@ -128,12 +128,8 @@ __global__ __launch_bounds__(256) void k_minmax(const float *__restrict__ x, uin
     } else {
         for (uint64_t j = tid; j < n; j += stride) key_acc(u[j], lo, hi);
     }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        const uint32_t a = __shfl_xor(lo, off, 64), b = __shfl_xor(hi, off, 64);
-        lo = a < lo ? a : lo;
-        hi = b > hi ? b : hi;
-    }
+    lo = ~wave_max<uint32_t>(~lo);
+    hi = wave_max<uint32_t>(hi);
     __shared__ uint32_t s_lo[4], s_hi[4];
     const uint32_t w = threadIdx.x / 64;
     if (lane_id() == 0) { s_lo[w] = lo; s_hi[w] = hi; }
@@ -157,12 +153,8 @@ __global__ __launch_bounds__(256) void k_minmax_final(const uint32_t *partials, 
         lo = a < lo ? a : lo;
         hi = b > hi ? b : hi;
     }
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) {
-        const uint32_t a = __shfl_xor(lo, off, 64), b = __shfl_xor(hi, off, 64);
-        lo = a < lo ? a : lo;
-        hi = b > hi ? b : hi;
-    }
+    lo = ~wave_max<uint32_t>(~lo);
+    hi = wave_max<uint32_t>(hi);
     __shared__ uint32_t s_lo[4], s_hi[4];
     const uint32_t w = threadIdx.x / 64;
     if (lane_id() == 0) { s_lo[w] = lo; s_hi[w] = hi; }
@@ -711,7 +703,7 @@ __global__ __launch_bounds__(256) void k_quant1d(QuantArgs a) {
         }
     }
     const uint32_t incl = wave_incl_scan<uint32_t>(my_count);
-    const uint32_t wave_count = __shfl(incl, 63, 64);
+    const uint32_t wave_count = (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
     const uint32_t wave_out = wave_sum_xor(__popc(flags_o));
     const uint32_t wave_patch = wave_sum_xor(__popc(flags_p));
     uint32_t tile_count, tile_out;
