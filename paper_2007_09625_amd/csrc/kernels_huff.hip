@@ -23,8 +23,8 @@
 namespace dqz {
 
 constexpr uint32_t kBookThreads = 256;
-constexpr uint32_t kTableThreads = 1024;   // decoding tables: threads per workgroup
-constexpr uint32_t kTableGroups = 8;       // workgroups that share the lookup tables' slots
+constexpr uint32_t kTableThreads = 512;    // decoding tables: threads per workgroup
+constexpr uint32_t kTableGroups = 16;      // workgroups that share the lookup tables' slots
 
 template <typename K>
 __device__ __forceinline__ K xor_lane(K v, uint32_t lane, uint32_t d) {   // d a compile-time constant
