@@ -21,6 +21,7 @@ namespace dqz {
 // LDS-typed pointers: every access through them is a ds_* instruction (a
 // generic pointer could be merged with a global one into a flat access)
 typedef __attribute__((address_space(3))) uint16_t lds_u16;
+typedef __attribute__((address_space(3))) int16_t lds_i16;
 typedef __attribute__((address_space(3))) uint32_t lds_u32;
 
 constexpr uint32_t kDecMaxWaves = 2;   // waves per workgroup (they share the lookup table)
@@ -645,7 +646,7 @@ __device__ __forceinline__ bool sub128_full(const Geom &g, uint32_t pa) {
 template <bool ALLREAL, bool WHOLE>
 __device__ __forceinline__ uint32_t inflate_codes(const DecArgs &a, const lds_u32 *win, uint32_t nwin, uint64_t wlo,
                                                   uint64_t start, uint32_t pa, uint4 *dst, const lds_u16 *lut,
-                                                  const lds_u16 *lut2, uint32_t b2, uint32_t base2, uint32_t last2,
+                                                  const lds_u16 *lut2, uint32_t b2, uint32_t base2,
                                                   uint32_t max_len, bool &bad) {
     const uint64_t sw = start >> 5;   // the lane's first stream word
     // window index of word sw + kr is relw + kr; a lane outside the window
@@ -666,6 +667,7 @@ __device__ __forceinline__ uint32_t inflate_codes(const DecArgs &a, const lds_u3
     if (o) { w0 = word(0); w1 = word(1); nxt = word(2); kk = relw + 2; }
     else { w0 = 0; w1 = word(0); nxt = word(1); kk = relw + 1; }
     const lds_u32 *wp = win + kk;   // window word kk (stepped with kk)
+    const uint32_t lut2_at = (uint32_t)(size_t)lut2 - 2u * base2;   // LDS byte address of entry "prefix 0"
     uint32_t nb = (32u - o) & 31u;
     uint32_t rmask = ~0u;
     for (uint32_t g = 0; g < 16; g++) {
@@ -675,10 +677,17 @@ __device__ __forceinline__ uint32_t inflate_codes(const DecArgs &a, const lds_u3
         for (uint32_t j = 0; j < 8; j++) {
             const bool real = ALLREAL || ((rmask >> ((g & 3u) * 8 + j)) & 1u);
             const uint32_t peek = __builtin_amdgcn_alignbit(w0, w1, nb);
-            const uint32_t e1 = lut[peek >> (32 - kLutBits)];   // zero-extended
-            const uint32_t v2 = (peek >> (32 - kLutBits - b2)) - base2;
-            const uint32_t e2 = lut2[v2 < last2 ? v2 : last2];
-            const uint32_t e = e1 < 0x8000u ? e1 : e2;
+            // first level read sign-extended: its long-prefix entries
+            // (0x8000 | length) come out negative
+            const int32_t e1s = reinterpret_cast<const lds_i16 *>(lut)[peek >> (32 - kLutBits)];
+            const uint32_t e1 = (uint32_t)e1s;
+            // second level, read at every step: base2 is folded into the LDS
+            // byte address, so a prefix below the long-code range (whose
+            // entry is never used) reads some other LDS word, or zero past
+            // the allocation; LDS reads cannot fault
+            const uint32_t e2 = *reinterpret_cast<const lds_u16 *>(
+                (size_t)(lut2_at + ((peek >> (32 - kLutBits - b2)) << 1)));
+            const uint32_t e = e1s >= 0 ? e1 : e2;
             uint32_t len = e >> 11, sym = e & 0x7FFu;
             const bool other = real && len == 0;   // longer than the second level, or no code
             if (__builtin_expect(__any((int)other), 0)) {
@@ -719,7 +728,7 @@ __device__ __forceinline__ uint32_t inflate_codes(const DecArgs &a, const lds_u3
             w0 = adv ? w1 : w0;
             w1 = adv ? nxt : w1;
             nb = (uint32_t)nn & 31u;
-            wp += adv ? 1 : 0;
+            wp = adv ? wp + 1 : wp;
             if (WHOLE) {
                 nxt = *wp;
             } else {
@@ -764,21 +773,20 @@ __global__ __launch_bounds__(64 * kInfMaxWaves) void k_inflate128(DecArgs a) {
     if (has) {
         const uint32_t pa = (uint32_t)((sub0 + lane) << 7);
         const uint32_t max_len = a.tab->max_len < 63u ? a.tab->max_len : 63u;
-        // second level: width, first index and last entry (an empty table
-        // keeps one zero entry, read by short codes only)
+        // second level: width and first index (an empty table keeps one
+        // zero entry; short codes' speculative reads land anywhere in LDS)
         const uint32_t b2 = a.tab->lut2_bits, base2 = a.tab->lut2_v0 << b2;
-        const uint32_t last2 = a.tab->lut2_n ? a.tab->lut2_n - 1 : 0u;
         uint4 *dst = a.qws + sub0 * 16 + lane;   // lane-interleaved groups
         uint32_t used;
         if (ws.whole && __all((int)sub128_full(a.g, pa)))
             used = inflate_codes<true, true>(a, win, ws.nwin, ws.wlo, ws.start, pa, dst, s_lut, s_lut2, b2, base2,
-                                             last2, max_len, bad);
+                                             max_len, bad);
         else if (ws.whole)
             used = inflate_codes<false, true>(a, win, ws.nwin, ws.wlo, ws.start, pa, dst, s_lut, s_lut2, b2, base2,
-                                              last2, max_len, bad);
+                                              max_len, bad);
         else
             used = inflate_codes<false, false>(a, win, ws.nwin, ws.wlo, ws.start, pa, dst, s_lut, s_lut2, b2, base2,
-                                               last2, max_len, bad);
+                                               max_len, bad);
         // the subchunk must lie inside the stream and consume exactly its recorded bits
         if (used != ws.bits || ws.start + ws.bits > 32ull * a.n_words) bad = true;
     }
