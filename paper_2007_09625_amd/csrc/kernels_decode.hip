@@ -593,6 +593,7 @@ __global__ __launch_bounds__(64 * kDecMaxWaves) void k_decode(DecArgs a) {
 constexpr uint32_t kInfMaxWaves = 14; // waves per inflate workgroup, at most (they share the lookup tables)
 constexpr uint32_t kInfWin = 2432;    // LDS stream-window words per wave (9.5 KiB)
 constexpr uint32_t kReconWaves = 8;   // units (one per wave) per reconstruction workgroup (8 measured best against 2, 4, 16)
+constexpr uint32_t kScatterMin = 4;   // 1D/2D units with more records than this scatter them through LDS
 
 // Both lookup-table levels into LDS: 16-byte copies, eight of a thread's
 // loads in flight (the tables are 256-byte aligned, the second level starts
@@ -832,32 +833,73 @@ __device__ __forceinline__ uint32_t slot_lane(uint32_t slot) {
 
 // One unit: its lane piece d[] (deltas, outliers still 0) and code-0 mask,
 // records [rs, re) of the exception list.
+// The unit's records of one kind (outliers or patches) scattered into the
+// wave's LDS buffer: buf[rel] their values, buf[512 ..) a bitmap of their
+// positions; records load one per lane, 64 at a time.  Returns the lane's
+// eight position bits (slot = the lane's piece of eight positions).
+template <bool PATCH>
+__device__ __forceinline__ uint32_t scatter_records(const ReconArgs &a, uint32_t rs, uint32_t re, uint32_t P0,
+                                                    uint32_t lane, uint32_t slot, lds_u32 *buf, bool &bad,
+                                                    uint32_t &n_kind) {
+    if (lane < 16) buf[512 + lane] = 0u;   // (one wave: its LDS operations take effect in order)
+    for (uint32_t base = rs; base < re; base += 64) {
+        const uint32_t i = base + lane;
+        if (i < re) {
+            const uint2 r = a.exc[i];
+            const uint32_t rel = (r.x >> 1) - P0;
+            if (rel >= 512u) {
+                if (!PATCH) bad = true;   // reported once
+            } else if ((r.x & 1u) == (PATCH ? 1u : 0u)) {
+                buf[rel] = r.y;
+                __hip_atomic_fetch_or(&buf[512 + (rel >> 5)], 1u << (rel & 31u), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+                n_kind++;
+            }
+        }
+    }
+    return (buf[512 + (slot >> 2)] >> ((slot & 3u) * 8u)) & 0xFFu;
+}
+
 template <uint32_t NDIM, uint32_t LAYERS>
 __device__ __forceinline__ void recon_unit(const ReconArgs &a, uint32_t u, uint32_t lane, uint32_t (&d)[8],
-                                           uint32_t zmask, uint32_t rs, uint32_t re, bool &bad) {
+                                           uint32_t zmask, uint32_t rs, uint32_t re, lds_u32 *buf, bool &bad) {
     const Geom &g = a.g;
     const uint32_t P0 = u << kUnitShift;
     if (rs > re || re > a.n_exc) {
         bad = true;
         rs = re = 0;
     }
-    // outlier deltas (records are wave-uniform); patches come last
+    // outlier deltas; patches come last.  A unit with more than a few records
+    // scatters them through the LDS buffer (records one per lane), the others
+    // walk theirs as wave-uniform scalar loads
+    const uint32_t slot = unit_slot<NDIM>(lane);
+    const bool scatter = re - rs > kScatterMin;   // uniform
     uint32_t n_out = 0;
-    for (uint32_t i = rs; i < re; i++) {
-        const uint2 r = a.exc[i];
-        const uint32_t rel = (r.x >> 1) - P0;
-        if (rel >= 512u) {
-            bad = true;
-            continue;
-        }
-        if (r.x & 1u) continue;
-        n_out++;
-        const uint32_t x = rel & 7u;
-        if (lane == slot_lane<NDIM>(rel >> 3)) {
-            if (!((zmask >> x) & 1u)) bad = true;
+    if (scatter) {
+        const uint32_t m = scatter_records<false>(a, rs, re, P0, lane, slot, buf, bad, n_out);
+        if (m & ~zmask) bad = true;   // an outlier record on a code that is not 0
+        if (m) {
 #pragma unroll
             for (uint32_t k = 0; k < 8; k++)
-                if (k == x) d[k] = r.y;
+                if ((m >> k) & 1u) d[k] = buf[8 * slot + k];
+        }
+        n_out = wave_sum<uint32_t>(n_out);
+    } else {
+        for (uint32_t i = rs; i < re; i++) {
+            const uint2 r = a.exc[i];
+            const uint32_t rel = (r.x >> 1) - P0;
+            if (rel >= 512u) {
+                bad = true;
+                continue;
+            }
+            if (r.x & 1u) continue;
+            n_out++;
+            const uint32_t x = rel & 7u;
+            if (lane == slot_lane<NDIM>(rel >> 3)) {
+                if (!((zmask >> x) & 1u)) bad = true;
+#pragma unroll
+                for (uint32_t k = 0; k < 8; k++)
+                    if (k == x) d[k] = r.y;
+            }
         }
     }
     // every code 0 takes exactly one record (keys increase)
@@ -925,17 +967,28 @@ __device__ __forceinline__ void recon_unit(const ReconArgs &a, uint32_t u, uint3
         cnt = g.nelem > o0 ? (g.nelem - o0 < 8 ? (uint32_t)(g.nelem - o0) : 8u) : 0u;
     }
     // patches replace the lane's values before they are stored
-    for (uint32_t i = rs; i < re; i++) {
-        const uint2 r = a.exc[i];
-        if (!(r.x & 1u)) continue;
-        const uint32_t rel = (r.x >> 1) - P0;
-        if (rel >= 512u) continue;   // reported above
-        const uint32_t x = rel & 7u;
-        if (lane == slot_lane<NDIM>(rel >> 3)) {
-            if (x >= cnt) bad = true;   // a patch outside the field
+    if (scatter) {
+        uint32_t n_patch = 0;
+        const uint32_t m = scatter_records<true>(a, rs, re, P0, lane, slot, buf, bad, n_patch);
+        if (m >> cnt) bad = true;   // a patch outside the field
+        if (m) {
 #pragma unroll
             for (uint32_t k = 0; k < 8; k++)
-                if (k == x) f[k] = __uint_as_float(r.y);
+                if ((m >> k) & 1u) f[k] = __uint_as_float(buf[8 * slot + k]);
+        }
+    } else {
+        for (uint32_t i = rs; i < re; i++) {
+            const uint2 r = a.exc[i];
+            if (!(r.x & 1u)) continue;
+            const uint32_t rel = (r.x >> 1) - P0;
+            if (rel >= 512u) continue;   // reported above
+            const uint32_t x = rel & 7u;
+            if (lane == slot_lane<NDIM>(rel >> 3)) {
+                if (x >= cnt) bad = true;   // a patch outside the field
+#pragma unroll
+                for (uint32_t k = 0; k < 8; k++)
+                    if (k == x) f[k] = __uint_as_float(r.y);
+            }
         }
     }
     float *o = a.out + o0;
@@ -1054,7 +1107,7 @@ __device__ __forceinline__ void recon_block3(const ReconArgs &a, uint32_t u, uin
 // One unit per wave.
 template <uint32_t NDIM, uint32_t LAYERS>
 __global__ __launch_bounds__(64 * kReconWaves) void k_recon(ReconArgs a) {
-    __shared__ uint32_t s_blk[kReconWaves][576];   // 3D: the block, rows 9 words apart
+    __shared__ uint32_t s_blk[kReconWaves][576];   // 3D: the block, rows 9 words apart; 1D/2D: the records
     if (a.tab->status) return;   // the inflate kernel did not run
     const uint32_t lane = lane_id(), w = __builtin_amdgcn_readfirstlane(threadIdx.x / 64);
     const uint32_t u = blockIdx.x * kReconWaves + w;
@@ -1081,7 +1134,7 @@ __global__ __launch_bounds__(64 * kReconWaves) void k_recon(ReconArgs a) {
     }
     bool bad = false;
     if (NDIM == 3) recon_block3<LAYERS>(a, u, lane, d, zmask, rs, re, (lds_u32 *)s_blk[w], bad);
-    else recon_unit<NDIM, LAYERS>(a, u, lane, d, zmask, rs, re, bad);
+    else recon_unit<NDIM, LAYERS>(a, u, lane, d, zmask, rs, re, (lds_u32 *)s_blk[w], bad);
     if (bad) {
         atomicOr(a.status, ST_ECORRUPT);
         publish_status(a.rb, ST_ECORRUPT);
