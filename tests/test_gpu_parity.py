@@ -398,3 +398,24 @@ def test_parity_two_layers_full_size_3d(ctx):
     arc = _check(ctx, x, 1e-4, 1, layers=2)
     h = au.header(arc)
     print(f"c2 2-layer eb=1e-4: {x.nbytes / arc.size:.3f}x, outliers {h['n_out']}, max_len {h['max_len']}")
+
+
+@pytest.mark.parametrize("ndim", [1, 2])
+def test_parity_record_density_per_unit(ctx, ndim):
+    """Units of 512 positions with 0 to 35 spikes each (about two outliers
+    per spike: from no records to well over 64 in one unit), and in every
+    fifth unit a run of values near 3000 whose rounding makes patches:
+    exercises both ways reconstruction takes a unit's exception records (a
+    scalar walk for a few, the per-lane LDS scatter for more) and the
+    boundary between them."""
+    rng = np.random.default_rng(11 + ndim)
+    n_units = 96
+    x = (np.float32(3.0) + np.cumsum(rng.standard_normal(512 * n_units) * 1e-3)).astype(np.float32)
+    for u in range(n_units):
+        pos = 512 * u + rng.choice(512, size=u % 36, replace=False)
+        x[pos] += np.float32(50.0)
+        if u % 5 == 0:
+            x[512 * u + 100:512 * u + 164] += np.float32(2997.0)
+    if ndim == 2:
+        x = x.reshape(96, 512)   # 16x16 blocks: a unit is two of them
+    _check(ctx, x, 3.3e-4, 0)
