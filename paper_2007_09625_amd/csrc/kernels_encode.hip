@@ -195,7 +195,8 @@ __device__ uint32_t stream_head(const EncArgs &a, const typename Codeword<WIDE>:
 }
 
 // One packing run: PER consecutive positions per thread from padded position
-// p0 + PER * tid, codes q[], the run's first bit at stream bit
+// p0 + PER * tid, codes q[] (their codewords pre[] when PRE, else looked up
+// again), the run's first bit at stream bit
 // `base`, the thread's bits at base + excl.  Codewords are built MSB-first
 // in a 64-bit register (current word in bits 63..32); words wholly inside
 // the thread's bit range are stored plainly into the LDS word buffer, the
@@ -204,9 +205,10 @@ __device__ uint32_t stream_head(const EncArgs &a, const typename Codeword<WIDE>:
 // before the tile (its owner completes it), and a last word left partial,
 // which is carried into the tile's next run or, after the last run,
 // completed with `head` (the next 32 stream bits) when the tile owns it.
-template <bool WIDE, uint32_t PER>
+template <bool WIDE, uint32_t PER, bool PRE>
 __device__ __forceinline__ void pack_run(const EncArgs &a, uint64_t p0, uint64_t base, uint32_t run_bits,
                                          uint32_t excl, const uint16_t (&q)[PER],
+                                         const typename Codeword<WIDE>::T (&pre)[PER],
                                          const typename Codeword<WIDE>::T *s_book,
                                          uint32_t *s_words, uint64_t tile_start, bool last_run,
                                          const uint32_t *s_carry_in, uint32_t *s_carry_out, const uint32_t *s_head,
@@ -229,7 +231,7 @@ __device__ __forceinline__ void pack_run(const EncArgs &a, uint64_t p0, uint64_t
     // position reads entry 0 and counts as an empty codeword)
     typename CW::T ent[PER];
 #pragma unroll
-    for (uint32_t i = 0; i < PER; i++) ent[i] = s_book[q[i] != kNoSymbol ? q[i] : 0u];
+    for (uint32_t i = 0; i < PER; i++) ent[i] = PRE ? pre[i] : s_book[q[i] != kNoSymbol ? q[i] : 0u];
     __syncthreads();
     {
         const uint32_t bit = lead + excl;
@@ -369,10 +371,11 @@ __device__ __forceinline__ void enc_tile(const EncArgs &a, uint32_t t, uint32_t 
     // subchunk), the runs' scans and the tile's bit count
     uint32_t bits[RUNS], excl[RUNS];
     uint64_t tot[RUNS];
+    Entry keep[RUNS][PER];   // the 32-bit path keeps its codewords for the packing
 #pragma unroll
     for (uint32_t r = 0; r < RUNS; r++) {
         bits[r] = 0;
-        Entry ent[PER];
+        Entry (&ent)[PER] = keep[r];
 #pragma unroll
         for (uint32_t i = 0; i < PER; i++) ent[i] = s_book[q[r][i] != kNoSymbol ? q[r][i] : 0u];
 #pragma unroll
@@ -427,9 +430,9 @@ __device__ __forceinline__ void enc_tile(const EncArgs &a, uint32_t t, uint32_t 
 #pragma unroll
     for (uint32_t r = 0; r < RUNS; r++) {
         if (r) __syncthreads();   // the word buffer is reused
-        pack_run<WIDE, PER>(a, p0 + r * (kTile / RUNS), base, (uint32_t)tot[r], excl[r], q[r], s_book, s_words, G,
-                            r + 1 == RUNS, r ? &S.carry[(r - 1) & 1] : nullptr,
-                            r + 1 < RUNS ? &S.carry[r & 1] : nullptr, &S.head, cc);
+        pack_run<WIDE, PER, !WIDE>(a, p0 + r * (kTile / RUNS), base, (uint32_t)tot[r], excl[r], q[r], keep[r],
+                                   s_book, s_words, G, r + 1 == RUNS, r ? &S.carry[(r - 1) & 1] : nullptr,
+                                   r + 1 < RUNS ? &S.carry[r & 1] : nullptr, &S.head, cc);
         base += tot[r];
     }
 }
